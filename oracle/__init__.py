@@ -1,0 +1,282 @@
+"""Python view of the CPU oracle (``oracle.c``): a plain FP64 reference for the
+SpMV / CG path of arXiv 2304.09511.
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's CPU
+baseline use it.  It shares no code with the GPU library and never imports it.
+Inputs come from ``workloads`` (structure and values only).
+
+Functions take and return numpy arrays; the index base is 0 and all ranges are
+half-open, as in the loops of Algorithms 1-3.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+OK, NOT_CONVERGED, INDEX_RANGE, UNSORTED, DUPLICATE, BREAKDOWN, NONFINITE = 0, 1, -2, -3, -4, -8, -9
+NPARAM = 4931
+NFEAT = 8
+NCLASS = 3
+
+
+def build(out: str | None = None, src: str | None = None) -> str:
+    """Compile the oracle with gcc (no fast-math, no FP contraction)."""
+    out = out or _LIB_PATH
+    cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+           "-o", out, src or _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    return out
+
+
+_lib = None
+
+
+class use_library:
+    """Context manager: route every call through another build of the oracle
+    (used by the tests that plant mistakes in a copy of the source)."""
+
+    def __init__(self, path: str):
+        self.path = path
+
+    def __enter__(self):
+        global _lib
+        self.saved = _lib
+        _lib = _bind(C.CDLL(self.path))
+        return self
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self.saved
+        return False
+
+
+def _load(path: str | None = None):
+    global _lib
+    if path is not None:
+        return _bind(C.CDLL(path))
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            build()
+        _lib = _bind(C.CDLL(_LIB_PATH))
+    return _lib
+
+
+P = C.c_void_p
+I64 = C.c_int64
+D = C.c_double
+
+
+def _bind(lib):
+    sig = {
+        "orc_coo_spmv": (None, [I64, I64, P, P, P, P, P]),
+        "orc_coo_spmv_f32": (None, [I64, I64, P, P, P, P, P]),
+        "orc_csr_spmv": (None, [I64, P, P, P, P, P]),
+        "orc_dia_spmv": (None, [I64, I64, I64, P, P, P, P]),
+        "orc_coo_check": (C.c_int, [I64, I64, I64, P, P]),
+        "orc_csr_check": (C.c_int, [I64, I64, I64, P, P]),
+        "orc_coo_sort": (None, [I64, I64, I64, P, P, P]),
+        "orc_coo_to_csr": (None, [I64, I64, P, P]),
+        "orc_csr_to_coo": (None, [I64, P, P]),
+        "orc_dia_offsets": (I64, [I64, I64, I64, P, P, P]),
+        "orc_coo_to_dia": (None, [I64, I64, P, P, P, I64, P, P]),
+        "orc_dia_nnz": (I64, [I64, I64, I64, P, P]),
+        "orc_dia_slots": (I64, [I64, I64, I64, P]),
+        "orc_dia_to_coo": (None, [I64, I64, I64, P, P, P, P, P]),
+        "orc_dot": (D, [I64, P, P]),
+        "orc_cg": (C.c_int, [I64, I64, P, P, P, P, P, D, I64, P, P]),
+        "orc_mixed_ir": (C.c_int, [I64, I64, P, P, P, P, P, D, D, I64, I64, P, P]),
+        "orc_features": (None, [I64, I64, I64, P, P, P]),
+        "orc_mlp_nparam": (I64, []),
+        "orc_mlp_forward": (None, [P, P, I64, P]),
+        "orc_mlp_loss_grad": (D, [P, P, P, I64, P]),
+        "orc_adam_step": (None, [I64, P, P, P, P, D, I64, D, D, D]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+# ----------------------------------------------------------------- SpMV
+def coo_spmv(nrows, ai, aj, av, x):
+    """Algorithm 1 over all stored entries, y cleared first: y = A x (FP64)."""
+    ai, aj, av, x = _i32(ai), _i32(aj), _f64(av), _f64(x)
+    y = np.empty(nrows, np.float64)
+    _load().orc_coo_spmv(nrows, ai.shape[0], _p(ai), _p(aj), _p(av), _p(x), _p(y))
+    return y
+
+
+def coo_spmv_f32(nrows, ai, aj, av, x):
+    """Algorithm 1 in float arithmetic (float products, float accumulation)."""
+    ai, aj, av, x = _i32(ai), _i32(aj), _f32(av), _f32(x)
+    y = np.empty(nrows, np.float32)
+    _load().orc_coo_spmv_f32(nrows, ai.shape[0], _p(ai), _p(aj), _p(av), _p(x), _p(y))
+    return y
+
+
+def csr_spmv(irp, aj, av, x):
+    """Algorithm 2: per-row sums assigned to y."""
+    irp, aj, av, x = _i32(irp), _i32(aj), _f64(av), _f64(x)
+    nrows = irp.shape[0] - 1
+    y = np.empty(nrows, np.float64)
+    _load().orc_csr_spmv(nrows, _p(irp), _p(aj), _p(av), _p(x), _p(y))
+    return y
+
+
+def dia_spmv(nrows, ncols, doff, av_dia, x):
+    """Algorithm 3 with N = ncols; av_dia is diagonal-major [ndiag][nrows]."""
+    doff, av_dia, x = _i32(doff), _f64(av_dia), _f64(x)
+    y = np.empty(nrows, np.float64)
+    _load().orc_dia_spmv(nrows, ncols, doff.shape[0], _p(doff), _p(av_dia), _p(x), _p(y))
+    return y
+
+
+# ----------------------------------------------------------- conversions
+def coo_check(nrows, ncols, ai, aj) -> int:
+    ai, aj = _i32(ai), _i32(aj)
+    return int(_load().orc_coo_check(nrows, ncols, ai.shape[0], _p(ai), _p(aj)))
+
+
+def csr_check(nrows, ncols, irp, aj) -> int:
+    irp, aj = _i32(irp), _i32(aj)
+    return int(_load().orc_csr_check(nrows, ncols, aj.shape[0], _p(irp), _p(aj)))
+
+
+def coo_sort(nrows, ncols, ai, aj, av):
+    """Triples sorted by (row, col), stably.  Returns new arrays."""
+    ai, aj, av = _i32(ai).copy(), _i32(aj).copy(), _f64(av).copy()
+    _load().orc_coo_sort(nrows, ncols, ai.shape[0], _p(ai), _p(aj), _p(av))
+    return ai, aj, av
+
+
+def coo_to_csr(nrows, ai):
+    ai = _i32(ai)
+    irp = np.empty(nrows + 1, np.int32)
+    _load().orc_coo_to_csr(nrows, ai.shape[0], _p(ai), _p(irp))
+    return irp
+
+
+def csr_to_coo(irp):
+    irp = _i32(irp)
+    nrows = irp.shape[0] - 1
+    ai = np.empty(int(irp[-1]) if nrows >= 0 else 0, np.int32)
+    _load().orc_csr_to_coo(nrows, _p(irp), _p(ai))
+    return ai
+
+
+def dia_offsets(nrows, ncols, ai, aj):
+    ai, aj = _i32(ai), _i32(aj)
+    buf = np.empty(max(nrows + ncols - 1, 1), np.int32)
+    nd = _load().orc_dia_offsets(nrows, ncols, ai.shape[0], _p(ai), _p(aj), _p(buf))
+    return buf[:nd].copy()
+
+
+def coo_to_dia(nrows, ncols, ai, aj, av):
+    """(doff, av_dia[ndiag*nrows]) of a sorted COO matrix."""
+    ai, aj, av = _i32(ai), _i32(aj), _f64(av)
+    doff = dia_offsets(nrows, ncols, ai, aj)
+    av_dia = np.empty(doff.shape[0] * nrows, np.float64)
+    _load().orc_coo_to_dia(nrows, ai.shape[0], _p(ai), _p(aj), _p(av), doff.shape[0],
+                           _p(doff), _p(av_dia))
+    return doff, av_dia
+
+
+def dia_slots(nrows, ncols, doff) -> int:
+    doff = _i32(doff)
+    return int(_load().orc_dia_slots(nrows, ncols, doff.shape[0], _p(doff)))
+
+
+def dia_to_coo(nrows, ncols, doff, av_dia):
+    doff, av_dia = _i32(doff), _f64(av_dia)
+    nd = doff.shape[0]
+    lib = _load()
+    nnz = int(lib.orc_dia_nnz(nrows, ncols, nd, _p(doff), _p(av_dia)))
+    ai = np.empty(nnz, np.int32)
+    aj = np.empty(nnz, np.int32)
+    av = np.empty(nnz, np.float64)
+    lib.orc_dia_to_coo(nrows, ncols, nd, _p(doff), _p(av_dia), _p(ai), _p(aj), _p(av))
+    return ai, aj, av
+
+
+# ------------------------------------------------------------------ CG
+def dot(a, b) -> float:
+    a, b = _f64(a), _f64(b)
+    return float(_load().orc_dot(a.shape[0], _p(a), _p(b)))
+
+
+def cg(n, ai, aj, av, b, x0=None, tol=1e-9, maxit=10000):
+    """Unpreconditioned CG.  Returns (status, x, iters, rel_resid, true_rel_resid)."""
+    ai, aj, av, b = _i32(ai), _i32(aj), _f64(av), _f64(b)
+    x = np.zeros(n, np.float64) if x0 is None else _f64(x0).copy()
+    iters = np.zeros(1, np.int64)
+    out = np.zeros(2, np.float64)
+    st = _load().orc_cg(n, ai.shape[0], _p(ai), _p(aj), _p(av), _p(b), _p(x), tol, maxit,
+                        _p(iters), _p(out))
+    return int(st), x, int(iters[0]), float(out[0]), float(out[1])
+
+
+def mixed_ir(n, ai, aj, av, b, x0=None, tol=1e-10, inner_rtol=1e-4, inner_maxit=10000,
+             max_outer=20):
+    """FP64-outer / FP32-inner refinement.
+    Returns (status, x, corrections, inner_iters_total, true_rel_resid)."""
+    ai, aj, av, b = _i32(ai), _i32(aj), _f64(av), _f64(b)
+    x = np.zeros(n, np.float64) if x0 is None else _f64(x0).copy()
+    counts = np.zeros(2, np.int64)
+    out = np.zeros(1, np.float64)
+    st = _load().orc_mixed_ir(n, ai.shape[0], _p(ai), _p(aj), _p(av), _p(b), _p(x), tol,
+                              inner_rtol, inner_maxit, max_outer, _p(counts), _p(out))
+    return int(st), x, int(counts[0]), int(counts[1]), float(out[0])
+
+
+# ------------------------------------------------------------ selector
+def features(nrows, ncols, ai, aj):
+    ai, aj = _i32(ai), _i32(aj)
+    f = np.empty(NFEAT, np.float64)
+    _load().orc_features(nrows, ncols, ai.shape[0], _p(ai), _p(aj), _p(f))
+    return f
+
+
+def mlp_forward(w, X):
+    w, X = _f64(w), _f64(X).reshape(-1, NFEAT)
+    z = np.empty((X.shape[0], NCLASS), np.float64)
+    _load().orc_mlp_forward(_p(w), _p(X), X.shape[0], _p(z))
+    return z
+
+
+def mlp_loss_grad(w, X, labels):
+    w, X, labels = _f64(w), _f64(X).reshape(-1, NFEAT), _i32(labels)
+    g = np.empty(NPARAM, np.float64)
+    loss = _load().orc_mlp_loss_grad(_p(w), _p(X), _p(labels), X.shape[0], _p(g))
+    return float(loss), g
+
+
+def adam_step(w, m, v, g, lr, t, b1=0.9, b2=0.999, eps=1e-8):
+    """In place on float64 arrays w, m, v."""
+    for a in (w, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    g = _f64(g)
+    _load().orc_adam_step(w.shape[0], _p(w), _p(m), _p(v), _p(g), lr, t, b1, b2, eps)

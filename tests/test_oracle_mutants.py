@@ -1,0 +1,94 @@
+"""Planted mistakes: each test compiles a copy of the oracle with one plausible
+error (a dropped term, a wrong sign or index, a transposed operand) and checks
+that at least one pin of ``test_oracle`` fails against it.  Every mutant stays
+inside its arrays, so a caught mistake is an assertion, never a crash."""
+import os
+
+import pytest
+
+import oracle as orc
+import test_oracle as pins
+
+SRC = os.path.join(os.path.dirname(orc.__file__), "oracle.c")
+
+# (name, original text, mutated text, pins that must catch it)
+MUTANTS = [
+    ("coo_transposed_operand",
+     "y[ai[k]] += av[k] * x[aj[k]];\n}\n\n/* Algorithm 1 with float",
+     "y[ai[k]] += av[k] * x[ai[k]];\n}\n\n/* Algorithm 1 with float",
+     [lambda: pins.test_spmv_integer_bruteforce((7, 3), 0.6)]),
+    ("coo_no_clear",
+     "        y[i] = 0.0;\n    for (int64_t k = 0; k < nnz; ++k)\n        y[ai[k]] += av[k] * x[aj[k]];",
+     "        y[i] = y[i];\n    for (int64_t k = 0; k < nnz; ++k)\n        y[ai[k]] += av[k] * x[aj[k]];",
+     [pins.test_coo_spmv_overwrites_y_and_empty_rows_are_zero]),
+    ("csr_wrong_column",
+     "sum += av[j] * x[aj[j]];",
+     "sum += av[j] * x[aj[j] > 0 ? aj[j] - 1 : 0];",
+     [lambda: pins.test_spmv_integer_bruteforce((17, 17), 0.6)]),
+    ("dia_bound_nrows",
+     "if (k >= 0 && k < ncols)\n                sum += av[j * nrows + i] * x[k];",
+     "if (k >= 0 && k < nrows)\n                sum += av[j * nrows + i] * x[k];",
+     [pins.test_dia_bound_uses_ncols_for_rectangular]),
+    ("dia_row_major_layout",
+     "sum += av[j * nrows + i] * x[k];",
+     "sum += av[i * ndiag + j] * x[k];",
+     [lambda: pins.test_stencil_integer_x_all_formats_bit_identical(7)]),
+    ("csr_pointer_shift",
+     "irp[ai[k] + 1]++;",
+     "irp[ai[k]]++;",
+     [lambda: pins.test_stencil_csr_and_dia_closed_forms(4)]),
+    ("dia_offset_sign",
+     "doff[nd++] = (int32_t)(s - (nrows - 1));",
+     "doff[nd++] = (int32_t)((nrows - 1) - s);",
+     [lambda: pins.test_stencil_csr_and_dia_closed_forms(4)]),
+    ("cg_residual_sign",
+     "r[i] -= alpha * q[i];\n            rho_new",
+     "r[i] += alpha * q[i];\n            rho_new",
+     [lambda: pins.test_cg_small_spd_matches_solve(12, 2)]),
+    ("cg_beta_inverted",
+     "double beta = rho_new / rho;",
+     "double beta = rho / rho_new;",
+     [lambda: pins.test_cg_small_spd_matches_solve(30, 3)]),
+    ("cg_no_direction_update",
+     "p[i] = r[i] + beta * p[i];\n            rho = rho_new;",
+     "p[i] = r[i] + 0.0 * beta * p[i];\n            rho = rho_new;",
+     [pins.test_cg_diagonal_distinct_eigenvalues_iteration_count,
+      lambda: pins.test_cg_stencil_recovers_ones_within_kappa_bound(8, 1e-9)]),
+    ("mixed_missing_scale",
+     "x[i] += rn * (double)d[i];",
+     "x[i] += (double)d[i];",
+     [lambda: pins.test_mixed_refinement_reaches_fp64_residual(8)]),
+    ("features_variance_not_normalised",
+     "var = nrows ? var / (double)nrows : 0.0;",
+     "var = var;",
+     [lambda: pins.test_features_stencil_closed_form(5)]),
+    ("mlp_relu_derivative_dropped",
+     "dh2[k] = a2[k] > 0.0 ? g : 0.0;",
+     "dh2[k] = g;",
+     [pins.test_mlp_gradient_matches_finite_differences]),
+    ("mlp_w2_transposed",
+     "s += h1[j] * w[OFF_W2 + j * NH + k];",
+     "s += h1[j] * w[OFF_W2 + k * NH + j];",
+     [pins.test_mlp_gradient_matches_finite_differences]),
+    ("adam_no_bias_correction",
+     "double mh = m[i] / c1, vh = v[i] / c2;",
+     "double mh = m[i], vh = v[i];",
+     [pins.test_adam_first_step_is_signed_lr]),
+]
+
+
+@pytest.mark.parametrize("name,old,new,catchers", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_planted_mistake_is_caught(tmp_path, name, old, new, catchers):
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation site for {name} not unique"
+    mutant_src = tmp_path / f"{name}.c"
+    mutant_src.write_text(src.replace(old, new))
+    lib = orc.build(out=str(tmp_path / f"{name}.so"), src=str(mutant_src))
+    caught = 0
+    with orc.use_library(lib):
+        for pin in catchers:
+            try:
+                pin()
+            except AssertionError:
+                caught += 1
+    assert caught >= 1, f"no pin caught the planted mistake {name}"
