@@ -1,0 +1,299 @@
+/*
+ * mxs.h -- C ABI of libmxs, an MI355X (gfx950) library for sparse
+ * matrix-vector multiplication y = A*x over the COO, CSR and DIA storage
+ * formats and the conjugate-gradient loop that calls it, after
+ * "Morpheus unleashed: Fast cross-platform SpMV on emerging architectures"
+ * (arXiv 2304.09511).
+ *
+ * General conventions
+ *   - Every call returns an mxs_status; no C++ exception crosses the ABI.
+ *   - Pointers to matrix arrays and vectors are DEVICE pointers unless the
+ *     argument description says "host".
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls marked [async] only enqueue work on `stream`; calls marked
+ *     [syncs] wait for `stream` before returning because they hand a value
+ *     back to the host.  Device faults surface as MXS_ERR_HIP at the next
+ *     call that synchronises.
+ *   - Indices are int32 and 0-based; ranges are half-open, as in the loops
+ *     of Algorithms 1-3 (Section III-B).  Counts of entries or slots are
+ *     int64.
+ *   - Values are FP64 (double) or FP32 (float), fixed per matrix by its
+ *     mxs_dtype; vectors passed with a matrix have that matrix's dtype.
+ *   - A call that fails validation leaves its outputs untouched.
+ *   - Memory: the library allocates device memory only for the arrays a
+ *     handle owns (copies made without MXS_BORROW, analysis plans) and for
+ *     temporaries of conversions, checks and feature extraction; all of it
+ *     is freed by mxs_destroy or before the call returns.  Outputs and CG
+ *     workspaces are allocated by the caller.
+ */
+#ifndef MXS_H
+#define MXS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MXS_OK = 0,
+    MXS_NOT_CONVERGED = 1,       /* iteration cap reached; the result is valid */
+    MXS_ERR_INVALID_ARG = -1,    /* null pointer, negative size, aliasing, bad enum */
+    MXS_ERR_INDEX_RANGE = -2,    /* an index outside its dimension, bad row pointers */
+    MXS_ERR_UNSORTED = -3,       /* order required and not met (borrowed arrays, DIA offsets) */
+    MXS_ERR_DUPLICATE = -4,      /* the same (row, col) stored twice */
+    MXS_ERR_DIA_TOO_SPARSE = -5, /* DIA would store more than 8 slots per non-zero */
+    MXS_ERR_OUT_OF_MEMORY = -6,
+    MXS_ERR_HIP = -7,            /* a HIP runtime error, including device faults */
+    MXS_ERR_BREAKDOWN = -8,      /* CG: p.Ap <= 0 or not finite (A not SPD) */
+    MXS_ERR_NONFINITE = -9,      /* NaN or Inf in a CG right-hand side or start vector */
+    MXS_ERR_UNSUPPORTED = -10    /* operation not defined for this format/dtype/shape */
+} mxs_status;
+
+typedef enum { MXS_COO = 0, MXS_CSR = 1, MXS_DIA = 2 } mxs_format;
+typedef enum { MXS_F64 = 0, MXS_F32 = 1 } mxs_dtype;
+
+/* Opaque host-side handle of a sparse matrix in one storage format. */
+typedef struct mxs_mat_s *mxs_mat;
+
+/* Creation flags. */
+#define MXS_BORROW 1u /* reference the caller's arrays instead of copying them;
+                         they must stay alive and unchanged until mxs_destroy */
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char *mxs_status_string(mxs_status s);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t mxs_version(void);
+
+/* ------------------------------------------------------------------------
+ * Containers (Section III-B: COO, CSR, DIA; typed for double and float as
+ * in Section VI-A's containers).  All three validate their input on the
+ * device and therefore [syncs].
+ * --------------------------------------------------------------------- */
+
+/* COO (Section III-B): entry k is (ai[k], aj[k], av[k]), k in [0, nnz).
+ * The paper's COO imposes no order.  The handle holds the canonical form:
+ * sorted by (row, col), which the COO kernel requires.  Unsorted input is
+ * sorted on the device into the handle's own copy; with MXS_BORROW it is
+ * refused with MXS_ERR_UNSORTED.  Errors: MXS_ERR_INDEX_RANGE for an index
+ * outside [0,nrows) x [0,ncols), MXS_ERR_DUPLICATE for a repeated
+ * (row, col).  nnz = 0 is legal (A = 0). */
+mxs_status mxs_coo_create(mxs_mat *out, int32_t nrows, int32_t ncols, int64_t nnz,
+                          const int32_t *ai, const int32_t *aj, const void *av,
+                          mxs_dtype dtype, unsigned flags, void *stream);
+
+/* CSR (Section III-B): irp[nrows+1] row pointers with irp[0] = 0 and
+ * irp[nrows] = nnz, non-decreasing; aj[nnz], av[nnz].  The paper imposes
+ * no order within a row; this library requires strictly ascending columns
+ * within a row (MXS_ERR_UNSORTED otherwise, MXS_ERR_DUPLICATE for a
+ * repeat), which makes conversions exact.  Bad row pointers or columns:
+ * MXS_ERR_INDEX_RANGE. */
+mxs_status mxs_csr_create(mxs_mat *out, int32_t nrows, int32_t ncols, int64_t nnz,
+                          const int32_t *irp, const int32_t *aj, const void *av,
+                          mxs_dtype dtype, unsigned flags, void *stream);
+
+/* DIA (Section III-B, Algorithm 3): ndiag offsets doff[d] (strictly
+ * ascending, each in [-(nrows-1), ncols-1]) and values stored
+ * DIAGONAL-MAJOR: av[d*nrows + i] multiplies x[i + doff[d]] in row i
+ * (row-aligned, as av(i,j) in Algorithm 3; the paper keeps av(i,j)
+ * row-major, this layout transposes it so that consecutive rows are
+ * consecutive in memory).  Slots with i + doff[d] outside [0, ncols) are
+ * never read.  Errors: MXS_ERR_INDEX_RANGE (offset out of range),
+ * MXS_ERR_UNSORTED (offsets not strictly ascending). */
+mxs_status mxs_dia_create(mxs_mat *out, int32_t nrows, int32_t ncols, int32_t ndiag,
+                          const int32_t *doff, const void *av, mxs_dtype dtype,
+                          unsigned flags, void *stream);
+
+/* Frees what the handle owns (waits for its pending work first).  A NULL
+ * handle is accepted. */
+mxs_status mxs_destroy(mxs_mat A);
+
+/* Host copies of a handle's shape.  Any output pointer may be NULL.  nnz is
+ * the stored-entry count (COO, CSR) or the in-range slot count (DIA). */
+mxs_status mxs_info(mxs_mat A, mxs_format *fmt, mxs_dtype *dtype, int32_t *nrows,
+                    int32_t *ncols, int64_t *nnz, int32_t *ndiag);
+
+/* Device pointers of the canonical arrays (owned by the handle or borrowed):
+ * COO (ai, aj, av); CSR (irp, aj, av); DIA (doff, NULL, av).  Read-only. */
+mxs_status mxs_arrays(mxs_mat A, const int32_t **idx0, const int32_t **idx1,
+                      const void **vals);
+
+/* ------------------------------------------------------------------------
+ * Format conversion (the runtime switching of Sections I-II)
+ * --------------------------------------------------------------------- */
+
+/* Sizes of the arrays mxs_convert will write for `dst` [syncs]:
+ *   dst COO/CSR: *count = number of entries (for DIA sources, the in-range
+ *                slots whose value is not +0.0 or -0.0); *ndiag = 0.
+ *   dst DIA:     *ndiag = number of distinct offsets j - i, *count =
+ *                ndiag*nrows (length of av).  Refused with
+ *                MXS_ERR_DIA_TOO_SPARSE when ndiag*nrows > 8*nnz.
+ * count or ndiag may be NULL. */
+mxs_status mxs_convert_size(mxs_mat src, mxs_format dst, int64_t *count, int32_t *ndiag,
+                            void *stream);
+
+/* Writes `src` in format `dst` into caller-allocated device arrays and
+ * returns a new handle that BORROWS them [syncs]:
+ *   dst COO: idx0 = ai[count], idx1 = aj[count], vals = av[count]
+ *   dst CSR: idx0 = irp[nrows+1], idx1 = aj[count], vals = av[count]
+ *   dst DIA: idx0 = doff[ndiag], idx1 unused (may be NULL), vals = av[count]
+ * with sizes from mxs_convert_size.  Output is canonical: rows ascending,
+ * columns ascending within a row, DIA offsets ascending with +0.0 in slots
+ * that hold no entry.  Values are moved, never recomputed: bit-exact. */
+mxs_status mxs_convert(mxs_mat src, mxs_format dst, int32_t *idx0, int32_t *idx1, void *vals,
+                       mxs_mat *out, void *stream);
+
+/* Same structure, values rounded to nearest (even) in `dtype` into
+ * caller-allocated `vals` (as many values as src stores) [async].  The new handle borrows src's
+ * index arrays and `vals`: destroy it before src. */
+mxs_status mxs_cast(mxs_mat src, mxs_dtype dtype, void *vals, mxs_mat *out, void *stream);
+
+/* ------------------------------------------------------------------------
+ * SpMV (Algorithms 1-3)
+ * --------------------------------------------------------------------- */
+
+/* Builds the format's execution plan [syncs]: CSR row blocks of bounded
+ * non-zero count (a single long row gets a block of its own), COO tile
+ * carries.  Idempotent.  mxs_spmv runs it on first use if not called. */
+mxs_status mxs_optimize(mxs_mat A, void *stream);
+
+/* y = A*x, overwriting y[nrows]; x has ncols entries [async].  Entry-wise
+ * the result is sum over stored (i, j, v) of v*x[j] (Algorithm 1 with y
+ * cleared first, which is what Algorithms 2 and 3 compute).  Summation
+ * order differs from a sequential loop; results are deterministic (no
+ * floating-point atomics).  x and y must not overlap (MXS_ERR_INVALID_ARG).
+ * Rows without entries get 0. */
+mxs_status mxs_spmv(mxs_mat A, const void *x, void *y, void *stream);
+
+/* Dot product a.b of n values of `dtype`, accumulated in FP64, written to
+ * the device double *result [async].  Deterministic. */
+mxs_status mxs_dot(int64_t n, mxs_dtype dtype, const void *a, const void *b, double *result,
+                   void *stream);
+
+/* y = alpha*x + beta*y over n values of `dtype` [async]. */
+mxs_status mxs_axpby(int64_t n, mxs_dtype dtype, double alpha, const void *x, double beta,
+                     void *y, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Conjugate gradients: HPCG's solver with the preconditioner disabled
+ * (Section VII-D), and an FP32-inner / FP64-outer refinement built on it.
+ * --------------------------------------------------------------------- */
+
+typedef struct {
+    double rtol;         /* FP64 CG: stop when ||r_k|| <= rtol*||r_0|| (recursive r).
+                            Mixed: stop when ||b - A x|| <= rtol*||b|| (FP64). */
+    int64_t maxit;       /* FP64 CG: iteration cap.  Mixed: cap per inner solve. */
+    int32_t mixed;       /* 0: FP64 CG on A.  1: refinement with FP32 inner CG on A32. */
+    int32_t max_outer;   /* mixed: at most this many corrections */
+    double inner_rtol;   /* mixed: inner solves stop at ||r|| <= inner_rtol*||r_0|| */
+    int32_t check_every; /* host reads the device convergence flag every this many
+                            iterations (>= 1); iterations past convergence are no-ops */
+    int32_t timing;      /* 1: time SpMV, dot and vector-update kernels with events */
+} mxs_cg_opts;
+
+typedef struct {
+    int64_t iters;         /* FP64: CG iterations (loop SpMVs).  Mixed: total inner iterations */
+    int64_t outer_iters;   /* mixed: corrections applied; FP64: 0 */
+    double rel_resid;      /* FP64: ||r_k||/||r_0|| (recursive).  Mixed: ||b-Ax||/||b|| */
+    double true_rel_resid; /* ||b - A x||/||b|| from an FP64 SpMV at exit */
+    double t_spmv_ms;      /* timing = 1: summed kernel times per class; else 0 */
+    double t_dot_ms;
+    double t_axpy_ms;
+} mxs_cg_result;
+
+/* Bytes of device workspace mxs_cg_solve needs for A (n = nrows). */
+mxs_status mxs_cg_workspace_size(mxs_mat A, int32_t mixed, size_t *bytes);
+
+/* Solves A x = b (A square, symmetric positive definite, FP64) [syncs].
+ * x holds x0 on entry and the solution on exit; b and x are FP64 device
+ * vectors of nrows entries.  With opts->mixed = 1, A32 must be an FP32
+ * handle of the same matrix (e.g. from mxs_cast) used by the inner solves.
+ * Returns MXS_OK on convergence, MXS_NOT_CONVERGED at the cap (x valid),
+ * MXS_ERR_BREAKDOWN when p.Ap <= 0 (x holds the last iterate),
+ * MXS_ERR_NONFINITE for NaN/Inf in b or x0, MXS_ERR_INVALID_ARG for a
+ * non-square A or a workspace smaller than mxs_cg_workspace_size. */
+mxs_status mxs_cg_solve(mxs_mat A, mxs_mat A32, const double *b, double *x,
+                        const mxs_cg_opts *opts, mxs_cg_result *res, void *workspace,
+                        size_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * HPCG problem setup (Section VII-D: Poisson on a regular 3-D grid)
+ * --------------------------------------------------------------------- */
+
+/* Number of stored entries of the n^3 stencil with `points` = 7 or 27. */
+int64_t mxs_stencil_nnz(int32_t n, int32_t points);
+
+/* Writes the n^3 stencil as canonical COO [async]: grid point (x,y,z) is
+ * row x + n*y + n*n*z; an entry for every neighbour inside the grid
+ * (27-point: all of {-1,0,1}^3; 7-point: the centre and the six faces),
+ * `diag` on the diagonal and `offdiag` elsewhere.  ai, aj, av hold
+ * mxs_stencil_nnz(n, points) entries; av has `dtype`. */
+mxs_status mxs_stencil_coo(int32_t n, int32_t points, double diag, double offdiag,
+                           int32_t *ai, int32_t *aj, void *av, mxs_dtype dtype, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Format selection (the run-first tuner of Section VII-D and the dynamic
+ * selection named as further work in Section IX): matrix features and a
+ * small MLP 8-64-64-3 (FP32) with its training step.
+ * --------------------------------------------------------------------- */
+
+#define MXS_NFEAT 8
+#define MXS_MLP_NPARAM 4931
+
+/* Eight features of A's stored entries into host out[8] [syncs]:
+ *   0 rows, 1 nnz, 2 mean row length, 3 population variance of row lengths,
+ *   4 max row length, 5 number of distinct diagonals j-i,
+ *   6 DIA fill ratio nnz/(ndiag*rows), 7 max |j-i| / ncols.
+ * For a DIA handle the features are those of its non-zero slots. */
+mxs_status mxs_features(mxs_mat A, double out[8], void *stream);
+
+/* Network input from raw features [async]: X[s][f] = (t(raw[s][f]) - mu[f]) / sd[f]
+ * with t = log1p for features 0-5 and identity for 6-7.  raw is FP64
+ * [n][8], X, mu and sd are FP32. */
+mxs_status mxs_mlp_inputs(const double *raw, int32_t n, const float *mu, const float *sd,
+                          float *X, void *stream);
+
+/* Normalisation statistics of a training set [async]: mu[f], sd[f] are the
+ * mean and population standard deviation over the n samples of t(raw[s][f])
+ * (t as in mxs_mlp_inputs), accumulated in FP64; sd is replaced by 1 where
+ * it is 0. */
+mxs_status mxs_mlp_norm_stats(const double *raw, int32_t n, float *mu, float *sd,
+                              void *stream);
+
+/* Logits[n][3] of the MLP with parameters w[MXS_MLP_NPARAM] laid out as
+ * W1[8][64], b1[64], W2[64][64], b2[64], W3[64][3], b3[3] (row-major,
+ * input index first), ReLU hidden layers [async]. */
+mxs_status mxs_mlp_forward(const float *w, const float *X, int32_t n, float *logits,
+                           void *stream);
+
+/* fmt_out[s] = argmax over formats f with feasible[s*3+f] != 0 of the
+ * logits (feasible may be NULL: all allowed); -1 if none is feasible [async]. */
+mxs_status mxs_mlp_predict(const float *w, const float *X, int32_t n, const uint8_t *feasible,
+                           int32_t *fmt_out, void *stream);
+
+/* Bytes of device workspace for mxs_mlp_grad / mxs_mlp_train_step with n
+ * samples (per-sample activations and deltas, then the gradient). */
+size_t mxs_mlp_workspace_size(int32_t n);
+
+/* Mean softmax cross-entropy over n samples (labels in {0,1,2}) into the
+ * device float *loss and its gradient grad[MXS_MLP_NPARAM] [async].
+ * Deterministic. */
+mxs_status mxs_mlp_grad(const float *w, const float *X, const int32_t *labels, int32_t n,
+                        float *grad, float *loss, void *workspace, size_t bytes, void *stream);
+
+/* One Adam step (Kingma and Ba 2015) at step t >= 1 on w, m, v [async]. */
+mxs_status mxs_mlp_adam(float *w, float *m, float *v, const float *grad, float lr, int32_t t,
+                        float beta1, float beta2, float eps, void *stream);
+
+/* mxs_mlp_grad followed by mxs_mlp_adam (beta1 0.9, beta2 0.999, eps 1e-8) [async]. */
+mxs_status mxs_mlp_train_step(float *w, float *m, float *v, const float *X,
+                              const int32_t *labels, int32_t n, float lr, int32_t t,
+                              float *loss, void *workspace, size_t bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MXS_H */

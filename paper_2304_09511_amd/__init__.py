@@ -1,0 +1,441 @@
+"""Python binding of libmxs: SpMV in COO / CSR / DIA and CG on MI355X (gfx950),
+after arXiv 2304.09511 ("Morpheus unleashed").
+
+Argument marshalling only: every step runs in the HIP library.  Device memory
+belongs to torch tensors; the stream is torch's current stream.  Import works
+without a GPU (so host-side validation can be tested); ``load()`` raises if
+the built library is missing -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+__all__ = [
+    "MxsError", "load", "lib_path", "Matrix", "spmv", "dot", "axpby", "cg_solve", "stencil",
+    "features", "mlp_inputs", "mlp_norm_stats", "mlp_forward", "mlp_predict", "mlp_grad",
+    "mlp_adam", "mlp_train_step", "COO", "CSR", "DIA", "F64", "F32", "NPARAM",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = os.path.join(_HERE, "libmxs.so")
+
+COO, CSR, DIA = 0, 1, 2
+F64, F32 = 0, 1
+BORROW = 1
+NPARAM = 4931
+FORMATS = {"coo": COO, "csr": CSR, "dia": DIA}
+FORMAT_NAMES = {COO: "coo", CSR: "csr", DIA: "dia"}
+
+STATUS = {
+    0: "MXS_OK", 1: "MXS_NOT_CONVERGED", -1: "MXS_ERR_INVALID_ARG", -2: "MXS_ERR_INDEX_RANGE",
+    -3: "MXS_ERR_UNSORTED", -4: "MXS_ERR_DUPLICATE", -5: "MXS_ERR_DIA_TOO_SPARSE",
+    -6: "MXS_ERR_OUT_OF_MEMORY", -7: "MXS_ERR_HIP", -8: "MXS_ERR_BREAKDOWN",
+    -9: "MXS_ERR_NONFINITE", -10: "MXS_ERR_UNSUPPORTED",
+}
+
+
+class MxsError(RuntimeError):
+    def __init__(self, status: int, where: str = ""):
+        self.status = status
+        super().__init__(f"{where}: {STATUS.get(status, status)}")
+
+
+def lib_path() -> str:
+    return _LIB
+
+
+class CgOpts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("maxit", C.c_int64), ("mixed", C.c_int32),
+                ("max_outer", C.c_int32), ("inner_rtol", C.c_double),
+                ("check_every", C.c_int32), ("timing", C.c_int32)]
+
+
+class CgResult(C.Structure):
+    _fields_ = [("iters", C.c_int64), ("outer_iters", C.c_int64), ("rel_resid", C.c_double),
+                ("true_rel_resid", C.c_double), ("t_spmv_ms", C.c_double),
+                ("t_dot_ms", C.c_double), ("t_axpy_ms", C.c_double)]
+
+
+_lib = None
+P, I32, I64, U32, D, F, SZ = (C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_double,
+                              C.c_float, C.c_size_t)
+
+_SIGS = {
+    "mxs_status_string": (C.c_char_p, [I32]),
+    "mxs_version": (I32, []),
+    "mxs_coo_create": (I32, [P, I32, I32, I64, P, P, P, I32, U32, P]),
+    "mxs_csr_create": (I32, [P, I32, I32, I64, P, P, P, I32, U32, P]),
+    "mxs_dia_create": (I32, [P, I32, I32, I32, P, P, I32, U32, P]),
+    "mxs_destroy": (I32, [P]),
+    "mxs_info": (I32, [P, P, P, P, P, P, P]),
+    "mxs_arrays": (I32, [P, P, P, P]),
+    "mxs_convert_size": (I32, [P, I32, P, P, P]),
+    "mxs_convert": (I32, [P, I32, P, P, P, P, P]),
+    "mxs_cast": (I32, [P, I32, P, P, P]),
+    "mxs_optimize": (I32, [P, P]),
+    "mxs_spmv": (I32, [P, P, P, P]),
+    "mxs_dot": (I32, [I64, I32, P, P, P, P]),
+    "mxs_axpby": (I32, [I64, I32, D, P, D, P, P]),
+    "mxs_cg_workspace_size": (I32, [P, I32, P]),
+    "mxs_cg_solve": (I32, [P, P, P, P, P, P, P, SZ, P]),
+    "mxs_stencil_nnz": (I64, [I32, I32]),
+    "mxs_stencil_coo": (I32, [I32, I32, D, D, P, P, P, I32, P]),
+    "mxs_features": (I32, [P, P, P]),
+    "mxs_mlp_inputs": (I32, [P, I32, P, P, P, P]),
+    "mxs_mlp_norm_stats": (I32, [P, I32, P, P, P]),
+    "mxs_mlp_forward": (I32, [P, P, I32, P, P]),
+    "mxs_mlp_predict": (I32, [P, P, I32, P, P, P]),
+    "mxs_mlp_workspace_size": (SZ, [I32]),
+    "mxs_mlp_grad": (I32, [P, P, P, I32, P, P, P, SZ, P]),
+    "mxs_mlp_adam": (I32, [P, P, P, P, F, I32, F, F, F, P]),
+    "mxs_mlp_train_step": (I32, [P, P, P, P, P, I32, F, I32, P, P, SZ, P]),
+}
+
+
+def load(path: str | None = None):
+    """Loads libmxs.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or _LIB
+    if not os.path.exists(p):
+        raise RuntimeError(f"{p} is missing: build it with `python -m paper_2304_09511_amd.build` "
+                           "(or __graft_entry__.build()); there is no fallback path")
+    lib = C.CDLL(p)
+    for name, (res, args) in _SIGS.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _check(st: int, where: str, ok=(0,)):
+    if st not in ok:
+        raise MxsError(st, where)
+    return st
+
+
+# --------------------------------------------------------------- tensors
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise TypeError("device tensor required")
+    if not t.is_contiguous():
+        raise TypeError("contiguous tensor required")
+    return C.c_void_p(t.data_ptr())
+
+
+def _dtype_code(t):
+    torch = _torch()
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32
+    raise TypeError(f"values must be float64 or float32, got {t.dtype}")
+
+
+def _torch_dtype(code):
+    torch = _torch()
+    return torch.float64 if code == F64 else torch.float32
+
+
+def _dev(a, dtype=None, device="cuda"):
+    """numpy or tensor -> contiguous device tensor."""
+    torch = _torch()
+    if isinstance(a, np.ndarray):
+        a = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        a = a.to(dtype)
+    return a.to(device).contiguous()
+
+
+# --------------------------------------------------------------- matrices
+class Matrix:
+    """A libmxs handle plus the tensors whose memory it borrows."""
+
+    def __init__(self, handle, keep=()):
+        self._h = handle
+        self._keep = list(keep)
+        lib = load()
+        fmt, dt, nr, nc, nnz, nd = (C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(),
+                                    C.c_int64(), C.c_int32())
+        _check(lib.mxs_info(handle, C.byref(fmt), C.byref(dt), C.byref(nr), C.byref(nc),
+                            C.byref(nnz), C.byref(nd)), "mxs_info")
+        self.format, self.dtype = fmt.value, dt.value
+        self.nrows, self.ncols, self.nnz, self.ndiag = nr.value, nc.value, nnz.value, nd.value
+
+    # -- construction
+    @classmethod
+    def coo(cls, nrows, ncols, ai, aj, av, borrow=False):
+        torch = _torch()
+        ai, aj, av = _dev(ai, torch.int32), _dev(aj, torch.int32), _dev(av)
+        h = C.c_void_p()
+        _check(load().mxs_coo_create(C.byref(h), nrows, ncols, ai.numel(), _ptr(ai), _ptr(aj),
+                                     _ptr(av), _dtype_code(av), BORROW if borrow else 0,
+                                     _stream()), "mxs_coo_create")
+        return cls(h, (ai, aj, av) if borrow else ())
+
+    @classmethod
+    def csr(cls, nrows, ncols, irp, aj, av, borrow=False):
+        torch = _torch()
+        irp, aj, av = _dev(irp, torch.int32), _dev(aj, torch.int32), _dev(av)
+        h = C.c_void_p()
+        _check(load().mxs_csr_create(C.byref(h), nrows, ncols, aj.numel(), _ptr(irp), _ptr(aj),
+                                     _ptr(av), _dtype_code(av), BORROW if borrow else 0,
+                                     _stream()), "mxs_csr_create")
+        return cls(h, (irp, aj, av) if borrow else ())
+
+    @classmethod
+    def dia(cls, nrows, ncols, doff, av, borrow=False):
+        """av is diagonal-major: av[d*nrows + i] multiplies x[i + doff[d]]."""
+        torch = _torch()
+        doff, av = _dev(doff, torch.int32), _dev(av)
+        h = C.c_void_p()
+        _check(load().mxs_dia_create(C.byref(h), nrows, ncols, doff.numel(), _ptr(doff),
+                                     _ptr(av), _dtype_code(av), BORROW if borrow else 0,
+                                     _stream()), "mxs_dia_create")
+        return cls(h, (doff, av) if borrow else ())
+
+    @classmethod
+    def from_workload(cls, coo, fmt="coo", dtype=None):
+        """A workloads.Coo uploaded as COO and converted to `fmt` on the device."""
+        av = coo.av if dtype is None else coo.av.astype(dtype)
+        A = cls.coo(coo.nrows, coo.ncols, coo.ai, coo.aj, av)
+        if FORMATS.get(fmt, fmt) == COO:
+            return A
+        B = A.convert(fmt)
+        A.close()
+        return B
+
+    # -- queries
+    @property
+    def handle(self):
+        return self._h
+
+    def arrays_ptr(self):
+        i0, i1, v = C.c_void_p(), C.c_void_p(), C.c_void_p()
+        _check(load().mxs_arrays(self._h, C.byref(i0), C.byref(i1), C.byref(v)), "mxs_arrays")
+        return i0.value, i1.value, v.value
+
+    def convert_size(self, fmt):
+        cnt, nd = C.c_int64(), C.c_int32()
+        _check(load().mxs_convert_size(self._h, FORMATS.get(fmt, fmt), C.byref(cnt), C.byref(nd),
+                                       _stream()), "mxs_convert_size")
+        return cnt.value, nd.value
+
+    def convert(self, fmt):
+        """Converts into freshly allocated tensors; returns the new Matrix."""
+        torch = _torch()
+        f = FORMATS.get(fmt, fmt)
+        cnt, nd = self.convert_size(f)
+        dev = "cuda"
+        vals = torch.empty(max(cnt, 0), dtype=_torch_dtype(self.dtype), device=dev)
+        if f == COO:
+            i0 = torch.empty(cnt, dtype=torch.int32, device=dev)
+            i1 = torch.empty(cnt, dtype=torch.int32, device=dev)
+        elif f == CSR:
+            i0 = torch.empty(self.nrows + 1, dtype=torch.int32, device=dev)
+            i1 = torch.empty(cnt, dtype=torch.int32, device=dev)
+        else:
+            i0 = torch.empty(nd, dtype=torch.int32, device=dev)
+            i1 = None
+        h = C.c_void_p()
+        _check(load().mxs_convert(self._h, f, _ptr(i0) if i0.numel() else None,
+                                  _ptr(i1) if i1 is not None and i1.numel() else None,
+                                  _ptr(vals) if vals.numel() else None, C.byref(h), _stream()),
+               "mxs_convert")
+        return Matrix(h, [t for t in (i0, i1, vals) if t is not None])
+
+    def cast(self, dtype):
+        torch = _torch()
+        code = F32 if dtype in (F32, torch.float32, np.float32, "f32") else F64
+        n = self.ndiag * self.nrows if self.format == DIA else self.nnz
+        vals = torch.empty(n, dtype=_torch_dtype(code), device="cuda")
+        h = C.c_void_p()
+        _check(load().mxs_cast(self._h, code, _ptr(vals) if n else None, C.byref(h), _stream()),
+               "mxs_cast")
+        return Matrix(h, [vals, self])
+
+    def export(self):
+        """Copies of the canonical arrays as CPU numpy arrays: COO (ai, aj, av),
+        CSR (irp, aj, av), DIA (doff, av)."""
+        B = self.convert(self.format)
+        out = [t.cpu().numpy() for t in B._keep]
+        B.close()
+        return tuple(out)
+
+    def optimize(self):
+        _check(load().mxs_optimize(self._h, _stream()), "mxs_optimize")
+        return self
+
+    def close(self):
+        if self._h is not None and _lib is not None:
+            _check(_lib.mxs_destroy(self._h), "mxs_destroy")
+        self._h = None
+        self._keep = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# --------------------------------------------------------------- operations
+def spmv(A: Matrix, x, y=None):
+    """y = A x on the device (y allocated when not given)."""
+    torch = _torch()
+    if y is None:
+        y = torch.empty(A.nrows, dtype=x.dtype, device=x.device)
+    if _dtype_code(x) != A.dtype or _dtype_code(y) != A.dtype:
+        raise TypeError("x and y must have the matrix's dtype")
+    if x.numel() != A.ncols or y.numel() != A.nrows:
+        raise ValueError("vector lengths do not match the matrix")
+    _check(load().mxs_spmv(A.handle, _ptr(x), _ptr(y), _stream()), "mxs_spmv")
+    return y
+
+
+def dot(a, b):
+    """a.b accumulated in FP64, as a device scalar tensor."""
+    torch = _torch()
+    out = torch.empty(1, dtype=torch.float64, device=a.device)
+    _check(load().mxs_dot(a.numel(), _dtype_code(a), _ptr(a), _ptr(b), _ptr(out), _stream()),
+           "mxs_dot")
+    return out
+
+
+def axpby(alpha, x, beta, y):
+    _check(load().mxs_axpby(x.numel(), _dtype_code(x), alpha, _ptr(x), beta, _ptr(y), _stream()),
+           "mxs_axpby")
+    return y
+
+
+def cg_workspace(A: Matrix, mixed=False):
+    torch = _torch()
+    n = C.c_size_t()
+    _check(load().mxs_cg_workspace_size(A.handle, 1 if mixed else 0, C.byref(n)),
+           "mxs_cg_workspace_size")
+    return torch.empty(max(n.value, 1), dtype=torch.uint8, device="cuda")
+
+
+def cg_solve(A: Matrix, b, x0=None, rtol=1e-9, maxit=10000, mixed=False, A32=None,
+             inner_rtol=1e-4, max_outer=20, check_every=16, timing=False, workspace=None):
+    """Solves A x = b.  Returns (status, x, CgResult as a dict)."""
+    torch = _torch()
+    x = torch.zeros_like(b) if x0 is None else x0.clone()
+    ws = workspace if workspace is not None else cg_workspace(A, mixed)
+    o = CgOpts(rtol, maxit, 1 if mixed else 0, max_outer, inner_rtol, check_every,
+               1 if timing else 0)
+    r = CgResult()
+    st = load().mxs_cg_solve(A.handle, A32.handle if A32 is not None else None, _ptr(b), _ptr(x),
+                             C.byref(o), C.byref(r), _ptr(ws), ws.numel(), _stream())
+    _check(st, "mxs_cg_solve", ok=(0, 1, -8))
+    res = {k: getattr(r, k) for k, _ in CgResult._fields_}
+    return st, x, res
+
+
+def stencil(n, points=27, diag=None, offdiag=-1.0, dtype=F64, fmt="coo"):
+    """The HPCG stencil generated on the device, as a Matrix in `fmt`."""
+    torch = _torch()
+    diag = (26.0 if points == 27 else 6.0) if diag is None else diag
+    lib = load()
+    nnz = lib.mxs_stencil_nnz(n, points)
+    ai = torch.empty(nnz, dtype=torch.int32, device="cuda")
+    aj = torch.empty(nnz, dtype=torch.int32, device="cuda")
+    av = torch.empty(nnz, dtype=_torch_dtype(dtype), device="cuda")
+    _check(lib.mxs_stencil_coo(n, points, diag, offdiag, _ptr(ai), _ptr(aj), _ptr(av), dtype,
+                               _stream()), "mxs_stencil_coo")
+    A = Matrix.coo(n ** 3, n ** 3, ai, aj, av, borrow=True)
+    if FORMATS.get(fmt, fmt) == COO:
+        return A
+    B = A.convert(fmt)
+    A.close()
+    return B
+
+
+def features(A: Matrix):
+    out = (C.c_double * 8)()
+    _check(load().mxs_features(A.handle, out, _stream()), "mxs_features")
+    return np.array(out[:], dtype=np.float64)
+
+
+# --------------------------------------------------------------- selector MLP
+def mlp_norm_stats(raw):
+    torch = _torch()
+    mu = torch.empty(8, dtype=torch.float32, device="cuda")
+    sd = torch.empty(8, dtype=torch.float32, device="cuda")
+    _check(load().mxs_mlp_norm_stats(_ptr(raw), raw.shape[0], _ptr(mu), _ptr(sd), _stream()),
+           "mxs_mlp_norm_stats")
+    return mu, sd
+
+
+def mlp_inputs(raw, mu, sd):
+    torch = _torch()
+    X = torch.empty(raw.shape[0], 8, dtype=torch.float32, device="cuda")
+    _check(load().mxs_mlp_inputs(_ptr(raw), raw.shape[0], _ptr(mu), _ptr(sd), _ptr(X),
+                                 _stream()), "mxs_mlp_inputs")
+    return X
+
+
+def mlp_forward(w, X):
+    torch = _torch()
+    z = torch.empty(X.shape[0], 3, dtype=torch.float32, device="cuda")
+    _check(load().mxs_mlp_forward(_ptr(w), _ptr(X), X.shape[0], _ptr(z), _stream()),
+           "mxs_mlp_forward")
+    return z
+
+
+def mlp_predict(w, X, feasible=None):
+    torch = _torch()
+    out = torch.empty(X.shape[0], dtype=torch.int32, device="cuda")
+    _check(load().mxs_mlp_predict(_ptr(w), _ptr(X), X.shape[0], _ptr(feasible), _ptr(out),
+                                  _stream()), "mxs_mlp_predict")
+    return out
+
+
+def mlp_workspace(n):
+    torch = _torch()
+    return torch.empty(load().mxs_mlp_workspace_size(n), dtype=torch.uint8, device="cuda")
+
+
+def mlp_grad(w, X, labels, workspace=None):
+    torch = _torch()
+    n = X.shape[0]
+    ws = workspace if workspace is not None else mlp_workspace(n)
+    g = torch.empty(NPARAM, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    _check(load().mxs_mlp_grad(_ptr(w), _ptr(X), _ptr(labels), n, _ptr(g), _ptr(loss), _ptr(ws),
+                               ws.numel(), _stream()), "mxs_mlp_grad")
+    return loss, g
+
+
+def mlp_adam(w, m, v, g, lr, t, b1=0.9, b2=0.999, eps=1e-8):
+    _check(load().mxs_mlp_adam(_ptr(w), _ptr(m), _ptr(v), _ptr(g), lr, t, b1, b2, eps,
+                               _stream()), "mxs_mlp_adam")
+
+
+def mlp_train_step(w, m, v, X, labels, lr, t, workspace=None):
+    torch = _torch()
+    n = X.shape[0]
+    ws = workspace if workspace is not None else mlp_workspace(n)
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    _check(load().mxs_mlp_train_step(_ptr(w), _ptr(m), _ptr(v), _ptr(X), _ptr(labels), n, lr, t,
+                                     _ptr(loss), _ptr(ws), ws.numel(), _stream()),
+           "mxs_mlp_train_step")
+    return loss

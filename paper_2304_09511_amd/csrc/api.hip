@@ -1,0 +1,507 @@
+// The C ABI of libmxs (declared in mxs.h): argument validation, handle
+// lifecycle and dispatch to the kernels.  Validation that needs no device
+// data runs before any HIP call, so invalid arguments are reported without
+// touching the GPU.  No C++ exception crosses the ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstring>
+#include <new>
+
+#include "common.h"
+
+using namespace mxs;
+
+namespace {
+
+hipStream_t S(void *stream) { return (hipStream_t)stream; }
+
+bool valid_dtype(mxs_dtype t) { return t == MXS_F64 || t == MXS_F32; }
+bool valid_format(mxs_format f) { return f == MXS_COO || f == MXS_CSR || f == MXS_DIA; }
+
+template <typename F>
+mxs_status guarded(F &&f)
+{
+    try {
+        return f();
+    } catch (const std::bad_alloc &) {
+        return MXS_ERR_OUT_OF_MEMORY;
+    } catch (...) {
+        return MXS_ERR_HIP;
+    }
+}
+
+void release(mxs_mat_s *A)
+{
+    if (!A) return;
+    for (void *p : A->owned)
+        if (p) (void)hipFree(p);
+    delete A;
+}
+
+// Copies `bytes` from a caller array into memory the handle owns.
+mxs_status own_copy(mxs_mat_s *A, const void *src, size_t bytes, void **dst, hipStream_t s)
+{
+    *dst = nullptr;
+    if (bytes == 0) return MXS_OK;
+    MXS_HIP(hipMalloc(dst, bytes));
+    A->owned.push_back(*dst);
+    MXS_HIP(hipMemcpyAsync(*dst, src, bytes, hipMemcpyDeviceToDevice, s));
+    return MXS_OK;
+}
+
+int64_t value_count(const mxs_mat_s *A)
+{
+    return A->fmt == MXS_DIA ? (int64_t)A->ndiag * A->nrows : A->nnz;
+}
+
+mxs_status ensure_plan(mxs_mat_s *A, hipStream_t s)
+{
+    if (A->optimized) return MXS_OK;
+    std::lock_guard<std::mutex> lk(A->mu);
+    return build_plan(A, s);
+}
+
+bool overlaps(const void *a, size_t na, const void *b, size_t nb)
+{
+    const char *x = (const char *)a, *y = (const char *)b;
+    return na && nb && x < y + nb && y < x + na;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *mxs_status_string(mxs_status s)
+{
+    switch (s) {
+    case MXS_OK: return "MXS_OK";
+    case MXS_NOT_CONVERGED: return "MXS_NOT_CONVERGED";
+    case MXS_ERR_INVALID_ARG: return "MXS_ERR_INVALID_ARG";
+    case MXS_ERR_INDEX_RANGE: return "MXS_ERR_INDEX_RANGE";
+    case MXS_ERR_UNSORTED: return "MXS_ERR_UNSORTED";
+    case MXS_ERR_DUPLICATE: return "MXS_ERR_DUPLICATE";
+    case MXS_ERR_DIA_TOO_SPARSE: return "MXS_ERR_DIA_TOO_SPARSE";
+    case MXS_ERR_OUT_OF_MEMORY: return "MXS_ERR_OUT_OF_MEMORY";
+    case MXS_ERR_HIP: return "MXS_ERR_HIP";
+    case MXS_ERR_BREAKDOWN: return "MXS_ERR_BREAKDOWN";
+    case MXS_ERR_NONFINITE: return "MXS_ERR_NONFINITE";
+    case MXS_ERR_UNSUPPORTED: return "MXS_ERR_UNSUPPORTED";
+    }
+    return "MXS_UNKNOWN_STATUS";
+}
+
+int32_t mxs_version(void) { return 10000; }
+
+// ---------------------------------------------------------------------------
+// Containers
+// ---------------------------------------------------------------------------
+mxs_status mxs_coo_create(mxs_mat *out, int32_t nrows, int32_t ncols, int64_t nnz,
+                          const int32_t *ai, const int32_t *aj, const void *av, mxs_dtype dtype,
+                          unsigned flags, void *stream)
+{
+    if (!out || nrows < 0 || ncols < 0 || nnz < 0 || !valid_dtype(dtype) ||
+        (flags & ~MXS_BORROW))
+        return MXS_ERR_INVALID_ARG;
+    if (nnz > 0 && (!ai || !aj || !av)) return MXS_ERR_INVALID_ARG;
+    if (nnz > INT32_MAX) return MXS_ERR_UNSUPPORTED;
+    return guarded([&] {
+        hipStream_t s = S(stream);
+        mxs_mat_s *A = new mxs_mat_s;
+        A->fmt = MXS_COO;
+        A->dtype = dtype;
+        A->nrows = nrows;
+        A->ncols = ncols;
+        A->nnz = nnz;
+        MXS_HIP(hipGetDevice(&A->device));
+        mxs_status st = MXS_OK;
+        if (flags & MXS_BORROW) {
+            A->idx0 = ai;
+            A->idx1 = aj;
+            A->vals = av;
+        } else {
+            void *p0, *p1, *p2;
+            if ((st = own_copy(A, ai, sizeof(int32_t) * nnz, &p0, s)) != MXS_OK ||
+                (st = own_copy(A, aj, sizeof(int32_t) * nnz, &p1, s)) != MXS_OK ||
+                (st = own_copy(A, av, dsize(dtype) * nnz, &p2, s)) != MXS_OK)
+                return release(A), st;
+            A->idx0 = (const int32_t *)p0;
+            A->idx1 = (const int32_t *)p1;
+            A->vals = p2;
+        }
+        st = check_coo(A, s);
+        if (st == MXS_ERR_UNSORTED && !(flags & MXS_BORROW)) {
+            st = sort_coo(nrows, ncols, nnz, (int32_t *)A->idx0, (int32_t *)A->idx1,
+                          (void *)A->vals, dtype, s);
+            if (st == MXS_OK) st = check_coo(A, s);
+        }
+        if (st != MXS_OK) return release(A), st;
+        *out = A;
+        return MXS_OK;
+    });
+}
+
+mxs_status mxs_csr_create(mxs_mat *out, int32_t nrows, int32_t ncols, int64_t nnz,
+                          const int32_t *irp, const int32_t *aj, const void *av, mxs_dtype dtype,
+                          unsigned flags, void *stream)
+{
+    if (!out || nrows < 0 || ncols < 0 || nnz < 0 || !valid_dtype(dtype) ||
+        (flags & ~MXS_BORROW) || !irp)
+        return MXS_ERR_INVALID_ARG;
+    if (nnz > 0 && (!aj || !av)) return MXS_ERR_INVALID_ARG;
+    if (nnz > INT32_MAX) return MXS_ERR_UNSUPPORTED;
+    return guarded([&] {
+        hipStream_t s = S(stream);
+        mxs_mat_s *A = new mxs_mat_s;
+        A->fmt = MXS_CSR;
+        A->dtype = dtype;
+        A->nrows = nrows;
+        A->ncols = ncols;
+        A->nnz = nnz;
+        MXS_HIP(hipGetDevice(&A->device));
+        mxs_status st = MXS_OK;
+        if (flags & MXS_BORROW) {
+            A->idx0 = irp;
+            A->idx1 = aj;
+            A->vals = av;
+        } else {
+            void *p0, *p1, *p2;
+            if ((st = own_copy(A, irp, sizeof(int32_t) * ((size_t)nrows + 1), &p0, s)) != MXS_OK ||
+                (st = own_copy(A, aj, sizeof(int32_t) * nnz, &p1, s)) != MXS_OK ||
+                (st = own_copy(A, av, dsize(dtype) * nnz, &p2, s)) != MXS_OK)
+                return release(A), st;
+            A->idx0 = (const int32_t *)p0;
+            A->idx1 = (const int32_t *)p1;
+            A->vals = p2;
+        }
+        if ((st = check_csr(A, s)) != MXS_OK) return release(A), st;
+        *out = A;
+        return MXS_OK;
+    });
+}
+
+mxs_status mxs_dia_create(mxs_mat *out, int32_t nrows, int32_t ncols, int32_t ndiag,
+                          const int32_t *doff, const void *av, mxs_dtype dtype, unsigned flags,
+                          void *stream)
+{
+    if (!out || nrows < 0 || ncols < 0 || ndiag < 0 || !valid_dtype(dtype) ||
+        (flags & ~MXS_BORROW))
+        return MXS_ERR_INVALID_ARG;
+    if (ndiag > 0 && (!doff || (nrows > 0 && !av))) return MXS_ERR_INVALID_ARG;
+    if ((int64_t)ndiag > (int64_t)nrows + ncols - 1 && ndiag > 0) return MXS_ERR_INDEX_RANGE;
+    return guarded([&] {
+        hipStream_t s = S(stream);
+        mxs_mat_s *A = new mxs_mat_s;
+        A->fmt = MXS_DIA;
+        A->dtype = dtype;
+        A->nrows = nrows;
+        A->ncols = ncols;
+        A->ndiag = ndiag;
+        MXS_HIP(hipGetDevice(&A->device));
+        mxs_status st = MXS_OK;
+        if (flags & MXS_BORROW) {
+            A->idx0 = doff;
+            A->vals = av;
+        } else {
+            void *p0, *p2;
+            if ((st = own_copy(A, doff, sizeof(int32_t) * ndiag, &p0, s)) != MXS_OK ||
+                (st = own_copy(A, av, dsize(dtype) * (size_t)ndiag * nrows, &p2, s)) != MXS_OK)
+                return release(A), st;
+            A->idx0 = (const int32_t *)p0;
+            A->vals = p2;
+        }
+        if ((st = check_dia(A, s)) != MXS_OK || (st = dia_slot_count(A, &A->nnz, s)) != MXS_OK)
+            return release(A), st;
+        *out = A;
+        return MXS_OK;
+    });
+}
+
+mxs_status mxs_destroy(mxs_mat A)
+{
+    if (!A) return MXS_OK;
+    return guarded([&] {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipSetDevice(A->device);
+        const hipError_t e = hipDeviceSynchronize();
+        release(A);
+        (void)hipSetDevice(dev);
+        return from_hip(e);
+    });
+}
+
+mxs_status mxs_info(mxs_mat A, mxs_format *fmt, mxs_dtype *dtype, int32_t *nrows, int32_t *ncols,
+                    int64_t *nnz, int32_t *ndiag)
+{
+    if (!A) return MXS_ERR_INVALID_ARG;
+    if (fmt) *fmt = A->fmt;
+    if (dtype) *dtype = A->dtype;
+    if (nrows) *nrows = A->nrows;
+    if (ncols) *ncols = A->ncols;
+    if (nnz) *nnz = A->nnz;
+    if (ndiag) *ndiag = A->ndiag;
+    return MXS_OK;
+}
+
+mxs_status mxs_arrays(mxs_mat A, const int32_t **idx0, const int32_t **idx1, const void **vals)
+{
+    if (!A) return MXS_ERR_INVALID_ARG;
+    if (idx0) *idx0 = A->idx0;
+    if (idx1) *idx1 = A->idx1;
+    if (vals) *vals = A->vals;
+    return MXS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Conversion
+// ---------------------------------------------------------------------------
+mxs_status mxs_convert_size(mxs_mat src, mxs_format dst, int64_t *count, int32_t *ndiag,
+                            void *stream)
+{
+    if (!src || !valid_format(dst)) return MXS_ERR_INVALID_ARG;
+    return guarded([&] {
+        int64_t c = 0;
+        int32_t nd = 0;
+        mxs_status st = convert_size(src, dst, &c, &nd, S(stream));
+        if (st != MXS_OK) return st;
+        if (count) *count = c;
+        if (ndiag) *ndiag = nd;
+        return MXS_OK;
+    });
+}
+
+mxs_status mxs_convert(mxs_mat src, mxs_format dst, int32_t *idx0, int32_t *idx1, void *vals,
+                       mxs_mat *out, void *stream)
+{
+    if (!src || !valid_format(dst) || !out) return MXS_ERR_INVALID_ARG;
+    return guarded([&] {
+        hipStream_t s = S(stream);
+        int64_t count = 0;
+        int32_t nd = 0;
+        mxs_status st = convert_size(src, dst, &count, &nd, s);
+        if (st != MXS_OK) return st;
+        const bool need0 = dst == MXS_CSR || (dst == MXS_COO && count > 0) || (dst == MXS_DIA && nd > 0);
+        const bool need1 = dst != MXS_DIA && count > 0;
+        if ((need0 && !idx0) || (need1 && !idx1) || (count > 0 && !vals))
+            return MXS_ERR_INVALID_ARG;
+        if ((st = convert(src, dst, idx0, idx1, vals, count, nd, s)) != MXS_OK) return st;
+        mxs_mat_s *B = new mxs_mat_s;
+        B->fmt = dst;
+        B->dtype = src->dtype;
+        B->nrows = src->nrows;
+        B->ncols = src->ncols;
+        B->device = src->device;
+        B->idx0 = idx0;
+        B->idx1 = dst == MXS_DIA ? nullptr : idx1;
+        B->vals = vals;
+        if (dst == MXS_DIA) {
+            B->ndiag = nd;
+            if ((st = dia_slot_count(B, &B->nnz, s)) != MXS_OK) return release(B), st;
+        } else {
+            B->nnz = count;
+        }
+        MXS_HIP(hipStreamSynchronize(s));
+        *out = B;
+        return MXS_OK;
+    });
+}
+
+mxs_status mxs_cast(mxs_mat src, mxs_dtype dtype, void *vals, mxs_mat *out, void *stream)
+{
+    if (!src || !valid_dtype(dtype) || !out) return MXS_ERR_INVALID_ARG;
+    const int64_t n = value_count(src);
+    if (n > 0 && !vals) return MXS_ERR_INVALID_ARG;
+    return guarded([&] {
+        mxs_status st = cast_values(src->vals, src->dtype, vals, dtype, n, S(stream));
+        if (st != MXS_OK) return st;
+        mxs_mat_s *B = new mxs_mat_s;
+        B->fmt = src->fmt;
+        B->dtype = dtype;
+        B->nrows = src->nrows;
+        B->ncols = src->ncols;
+        B->nnz = src->nnz;
+        B->ndiag = src->ndiag;
+        B->device = src->device;
+        B->idx0 = src->idx0;
+        B->idx1 = src->idx1;
+        B->vals = vals;
+        *out = B;
+        return MXS_OK;
+    });
+}
+
+// ---------------------------------------------------------------------------
+// SpMV and BLAS-1
+// ---------------------------------------------------------------------------
+mxs_status mxs_optimize(mxs_mat A, void *stream)
+{
+    if (!A) return MXS_ERR_INVALID_ARG;
+    return guarded([&] { return ensure_plan(A, S(stream)); });
+}
+
+mxs_status mxs_spmv(mxs_mat A, const void *x, void *y, void *stream)
+{
+    if (!A) return MXS_ERR_INVALID_ARG;
+    const size_t es = dsize(A->dtype);
+    if ((A->ncols > 0 && !x) || (A->nrows > 0 && !y)) return MXS_ERR_INVALID_ARG;
+    if (overlaps(x, es * A->ncols, y, es * A->nrows)) return MXS_ERR_INVALID_ARG;
+    return guarded([&] {
+        hipStream_t s = S(stream);
+        mxs_status st = ensure_plan(A, s);
+        if (st != MXS_OK) return st;
+        return spmv_launch(A, x, y, nullptr, nullptr, s);
+    });
+}
+
+mxs_status mxs_dot(int64_t n, mxs_dtype dtype, const void *a, const void *b, double *result,
+                   void *stream)
+{
+    if (n < 0 || !valid_dtype(dtype) || !result || (n > 0 && (!a || !b)))
+        return MXS_ERR_INVALID_ARG;
+    return guarded([&] { return dot_launch(n, dtype, a, b, result, S(stream)); });
+}
+
+mxs_status mxs_axpby(int64_t n, mxs_dtype dtype, double alpha, const void *x, double beta, void *y,
+                     void *stream)
+{
+    if (n < 0 || !valid_dtype(dtype) || (n > 0 && (!x || !y))) return MXS_ERR_INVALID_ARG;
+    return guarded([&] { return axpby_launch(n, dtype, alpha, x, beta, y, S(stream)); });
+}
+
+// ---------------------------------------------------------------------------
+// CG
+// ---------------------------------------------------------------------------
+mxs_status mxs_cg_workspace_size(mxs_mat A, int32_t mixed, size_t *bytes)
+{
+    if (!A || !bytes) return MXS_ERR_INVALID_ARG;
+    *bytes = cg_workspace_bytes(A->nrows, mixed ? 1 : 0, 0, 0);
+    return MXS_OK;
+}
+
+mxs_status mxs_cg_solve(mxs_mat A, mxs_mat A32, const double *b, double *x, const mxs_cg_opts *opts,
+                        mxs_cg_result *res, void *workspace, size_t workspace_bytes, void *stream)
+{
+    if (!A || !opts || !res || A->dtype != MXS_F64 || A->nrows != A->ncols)
+        return MXS_ERR_INVALID_ARG;
+    if (A->nrows > 0 && (!b || !x || !workspace)) return MXS_ERR_INVALID_ARG;
+    if (overlaps(b, 8 * (size_t)A->nrows, x, 8 * (size_t)A->nrows)) return MXS_ERR_INVALID_ARG;
+    if (opts->mixed && (!A32 || A32->dtype != MXS_F32 || A32->nrows != A->nrows ||
+                        A32->ncols != A->ncols))
+        return MXS_ERR_INVALID_ARG;
+    if (!(opts->rtol >= 0.0) || opts->maxit < 0 || (opts->mixed && opts->max_outer < 0))
+        return MXS_ERR_INVALID_ARG;
+    if (workspace_bytes < cg_workspace_bytes(A->nrows, opts->mixed ? 1 : 0, 0, 0))
+        return MXS_ERR_INVALID_ARG;
+    return guarded([&] {
+        hipStream_t s = S(stream);
+        mxs_status st = ensure_plan(A, s);
+        if (st == MXS_OK && opts->mixed) st = ensure_plan(A32, s);
+        if (st != MXS_OK) return st;
+        if (A->nrows == 0) {
+            *res = mxs_cg_result{0, 0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            return MXS_OK;
+        }
+        return cg_solve(A, opts->mixed ? A32 : nullptr, b, x, opts, res, workspace,
+                        workspace_bytes, s);
+    });
+}
+
+// ---------------------------------------------------------------------------
+// Problem setup
+// ---------------------------------------------------------------------------
+int64_t mxs_stencil_nnz(int32_t n, int32_t points)
+{
+    if (n < 0) return -1;
+    const int64_t m = n;
+    if (points == 27) return (3 * m - 2) * (3 * m - 2) * (3 * m - 2) * (m > 0);
+    if (points == 7) return m * m * m + 6 * (m - 1) * m * m * (m > 0);
+    return -1;
+}
+
+mxs_status mxs_stencil_coo(int32_t n, int32_t points, double diag, double offdiag, int32_t *ai,
+                           int32_t *aj, void *av, mxs_dtype dtype, void *stream)
+{
+    if (n < 0 || (points != 7 && points != 27) || !valid_dtype(dtype)) return MXS_ERR_INVALID_ARG;
+    const int64_t nnz = mxs_stencil_nnz(n, points);
+    if ((int64_t)n * n * n > INT32_MAX || nnz > INT32_MAX) return MXS_ERR_UNSUPPORTED;
+    if (nnz > 0 && (!ai || !aj || !av)) return MXS_ERR_INVALID_ARG;
+    return guarded([&] { return stencil_coo(n, points, diag, offdiag, ai, aj, av, dtype, S(stream)); });
+}
+
+// ---------------------------------------------------------------------------
+// Format selection
+// ---------------------------------------------------------------------------
+mxs_status mxs_features(mxs_mat A, double out[8], void *stream)
+{
+    if (!A || !out) return MXS_ERR_INVALID_ARG;
+    return guarded([&] { return features(A, out, S(stream)); });
+}
+
+mxs_status mxs_mlp_inputs(const double *raw, int32_t n, const float *mu, const float *sd, float *X,
+                          void *stream)
+{
+    if (n < 0 || (n > 0 && (!raw || !mu || !sd || !X))) return MXS_ERR_INVALID_ARG;
+    return guarded([&] { return mlp_inputs(raw, n, mu, sd, X, S(stream)); });
+}
+
+mxs_status mxs_mlp_norm_stats(const double *raw, int32_t n, float *mu, float *sd, void *stream)
+{
+    if (n < 0 || !mu || !sd || (n > 0 && !raw)) return MXS_ERR_INVALID_ARG;
+    return guarded([&] { return mlp_norm_stats(raw, n, mu, sd, S(stream)); });
+}
+
+mxs_status mxs_mlp_forward(const float *w, const float *X, int32_t n, float *logits, void *stream)
+{
+    if (n < 0 || !w || (n > 0 && (!X || !logits))) return MXS_ERR_INVALID_ARG;
+    return guarded([&] { return mlp_forward(w, X, n, logits, S(stream)); });
+}
+
+mxs_status mxs_mlp_predict(const float *w, const float *X, int32_t n, const uint8_t *feasible,
+                           int32_t *fmt_out, void *stream)
+{
+    if (n < 0 || !w || (n > 0 && (!X || !fmt_out))) return MXS_ERR_INVALID_ARG;
+    return guarded([&] { return mlp_predict(w, X, n, feasible, fmt_out, S(stream)); });
+}
+
+size_t mxs_mlp_workspace_size(int32_t n)
+{
+    // per-sample scratch, then (for mxs_mlp_train_step) the gradient
+    return (mlp_ws_bytes(n) + 255) / 256 * 256 + sizeof(float) * MXS_MLP_NPARAM;
+}
+
+mxs_status mxs_mlp_grad(const float *w, const float *X, const int32_t *labels, int32_t n,
+                        float *grad, float *loss, void *workspace, size_t bytes, void *stream)
+{
+    if (n < 0 || !w || !grad || !loss || (n > 0 && (!X || !labels || !workspace)))
+        return MXS_ERR_INVALID_ARG;
+    if (n > 0 && bytes < mlp_ws_bytes(n)) return MXS_ERR_INVALID_ARG;
+    return guarded([&] { return mlp_grad(w, X, labels, n, grad, loss, workspace, S(stream)); });
+}
+
+mxs_status mxs_mlp_adam(float *w, float *m, float *v, const float *grad, float lr, int32_t t,
+                        float beta1, float beta2, float eps, void *stream)
+{
+    if (!w || !m || !v || !grad || t < 1) return MXS_ERR_INVALID_ARG;
+    return guarded([&] { return mlp_adam(w, m, v, grad, lr, t, beta1, beta2, eps, S(stream)); });
+}
+
+mxs_status mxs_mlp_train_step(float *w, float *m, float *v, const float *X, const int32_t *labels,
+                              int32_t n, float lr, int32_t t, float *loss, void *workspace,
+                              size_t bytes, void *stream)
+{
+    if (!w || !m || !v || !loss || t < 1 || n < 0 || (n > 0 && (!X || !labels || !workspace)))
+        return MXS_ERR_INVALID_ARG;
+    if (bytes < mxs_mlp_workspace_size(n)) return MXS_ERR_INVALID_ARG;
+    return guarded([&] {
+        hipStream_t s = S(stream);
+        const size_t off = (mlp_ws_bytes(n) + 255) / 256 * 256;
+        float *grad = (float *)((char *)workspace + off);
+        mxs_status st = mlp_grad(w, X, labels, n, grad, loss, workspace, s);
+        if (st != MXS_OK) return st;
+        return mlp_adam(w, m, v, grad, lr, t, 0.9f, 0.999f, 1e-8f, s);
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,551 @@
+// BLAS-1 and the conjugate-gradient driver: HPCG's solver with the
+// preconditioner disabled (Section VII-D), plus FP32-inner / FP64-outer
+// iterative refinement built on the same kernels.
+//
+// Scalars live on the device (CgState).  One CG iteration is three kernels:
+//   1. q = A p with p.q fused into the SpMV epilogue; its last workgroup
+//      computes alpha = rho / p.q (CSR, DIA; COO adds one dot kernel)
+//   2. x += alpha p, r -= alpha q with r.r fused; its last workgroup tests
+//      convergence and computes beta
+//   3. p = r + beta p
+// Every kernel returns at entry once the device flag `done` is set, so the
+// host enqueues iterations in batches and reads the flag once per batch.
+// Reductions are two-level in fixed order: results are deterministic.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "common.h"
+
+namespace mxs {
+
+constexpr int kVNT = 256;
+constexpr int64_t kVecGridMax = 2048;
+
+static uint32_t vec_grid(int64_t n)
+{
+    return (uint32_t)std::clamp<int64_t>((n + kVNT * 4 - 1) / (kVNT * 4), 1, kVecGridMax);
+}
+
+#define VEC_LOOP(i, n)                                                         \
+    for (int64_t i = (int64_t)blockIdx.x * kVNT + threadIdx.x; i < (n); \
+         i += (int64_t)gridDim.x * kVNT)
+
+struct Aux {
+    double norm2[2]; // scratch results of norm kernels
+    unsigned ticket;
+    int nonfinite;
+};
+
+// ---------------------------------------------------------------------------
+// Dot and axpby
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kVNT) void dot_kernel(int64_t n, const T *__restrict__ a,
+                                                   const T *__restrict__ b, double *partials,
+                                                   unsigned *ticket, double *result)
+{
+    __shared__ double red[kVNT / kWave];
+    double s = 0.0;
+    VEC_LOOP(i, n) s += (double)a[i] * (double)b[i];
+    const double bs = block_sum<kVNT>(s, red);
+    double tot;
+    if (last_block_total<kVNT>(bs, blockIdx.x, gridDim.x, partials, ticket, red, &tot) &&
+        threadIdx.x == 0)
+        *result = tot;
+}
+
+mxs_status dot_launch(int64_t n, mxs_dtype t, const void *a, const void *b, double *result,
+                      hipStream_t s)
+{
+    const uint32_t g = vec_grid(n);
+    char *tmp = nullptr;
+    MXS_HIP(hipMallocAsync((void **)&tmp, 256 + sizeof(double) * g, s));
+    unsigned *ticket = (unsigned *)tmp;
+    double *parts = (double *)(tmp + 256);
+    mxs_status st = fill_bytes0(ticket, 4, s);
+    if (st != MXS_OK) return st;
+    if (t == MXS_F64)
+        dot_kernel<double><<<g, kVNT, 0, s>>>(n, (const double *)a, (const double *)b, parts, ticket,
+                                              result);
+    else
+        dot_kernel<float><<<g, kVNT, 0, s>>>(n, (const float *)a, (const float *)b, parts, ticket,
+                                             result);
+    MXS_HIP(hipGetLastError());
+    MXS_HIP(hipFreeAsync(tmp, s));
+    return MXS_OK;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kVNT) void axpby_kernel(int64_t n, T alpha, const T *__restrict__ x,
+                                                     T beta, T *__restrict__ y)
+{
+    if (beta == T(0)) {
+        VEC_LOOP(i, n) y[i] = alpha * x[i];
+    } else {
+        VEC_LOOP(i, n) y[i] = alpha * x[i] + beta * y[i];
+    }
+}
+
+mxs_status axpby_launch(int64_t n, mxs_dtype t, double alpha, const void *x, double beta, void *y,
+                        hipStream_t s)
+{
+    if (n == 0) return MXS_OK;
+    if (t == MXS_F64)
+        axpby_kernel<double><<<vec_grid(n), kVNT, 0, s>>>(n, alpha, (const double *)x, beta,
+                                                          (double *)y);
+    else
+        axpby_kernel<float><<<vec_grid(n), kVNT, 0, s>>>(n, (float)alpha, (const float *)x,
+                                                         (float)beta, (float *)y);
+    return launch_status();
+}
+
+// ---------------------------------------------------------------------------
+// CG kernels
+// ---------------------------------------------------------------------------
+__global__ void cg_state_init(CgState *st, double rtol, long long maxit)
+{
+    st->rho0 = st->rho = st->sigma = st->alpha = st->beta = st->rr = 0.0;
+    st->rtol = rtol;
+    st->iters = 0;
+    st->maxit = maxit;
+    st->done = 0;
+    st->status = (int)MXS_NOT_CONVERGED;
+    st->ticket = 0u;
+    st->nonfinite = 0;
+}
+
+// r = b - q (q = A x0), p = r, rho0 = r.r; NaN/Inf in b or x0 stops the solve.
+__global__ __launch_bounds__(kVNT) void cg_start_kernel(int64_t n, const double *__restrict__ b,
+                                                        const double *__restrict__ x,
+                                                        const double *__restrict__ q,
+                                                        double *__restrict__ r,
+                                                        double *__restrict__ p, double *partials,
+                                                        CgState *st)
+{
+    __shared__ double red[kVNT / kWave];
+    double s = 0.0;
+    int bad = 0;
+    VEC_LOOP(i, n)
+    {
+        const double bi = b[i], xi = x[i];
+        if (!__builtin_isfinite(bi) || !__builtin_isfinite(xi)) bad = 1;
+        const double ri = bi - q[i];
+        r[i] = ri;
+        p[i] = ri;
+        s += ri * ri;
+    }
+    if (bad) atomicOr(&st->nonfinite, 1);
+    const double bs = block_sum<kVNT>(s, red);
+    double tot;
+    if (last_block_total<kVNT>(bs, blockIdx.x, gridDim.x, partials, &st->ticket, red, &tot) &&
+        threadIdx.x == 0) {
+        if (__hip_atomic_load(&st->nonfinite, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) {
+            st->status = (int)MXS_ERR_NONFINITE;
+            st->done = 1;
+        } else {
+            st->rho0 = st->rho = st->rr = tot;
+            if (tot == 0.0) {
+                st->status = (int)MXS_OK;
+                st->done = 1;
+            }
+        }
+    }
+}
+
+// After r.r of the new residual: converged, capped, or beta for the next p.
+__device__ __forceinline__ void cg_finish_rho(CgState *st, double rr)
+{
+    st->rr = rr;
+    if (sqrt(rr) <= st->rtol * sqrt(st->rho0)) {
+        st->status = (int)MXS_OK;
+        st->done = 1;
+    } else if (st->iters >= st->maxit) {
+        st->status = (int)MXS_NOT_CONVERGED;
+        st->done = 1;
+    } else {
+        st->beta = rr / st->rho;
+    }
+    st->rho = rr;
+}
+
+// x += alpha p; r -= alpha q; with FUSED, r.r and the convergence test.
+template <typename T, bool FUSED>
+__global__ __launch_bounds__(kVNT) void cg_xr_kernel(int64_t n, T *__restrict__ x,
+                                                     T *__restrict__ r, const T *__restrict__ p,
+                                                     const T *__restrict__ q, double *partials,
+                                                     CgState *st)
+{
+    __shared__ double red[kVNT / kWave];
+    if (st->done) return;
+    const T a = (T)st->alpha;
+    double s = 0.0;
+    VEC_LOOP(i, n)
+    {
+        const T xi = x[i] + a * p[i];
+        const T ri = r[i] - a * q[i];
+        x[i] = xi;
+        r[i] = ri;
+        if (FUSED) s += (double)ri * (double)ri;
+    }
+    if (FUSED) {
+        const double bs = block_sum<kVNT>(s, red);
+        double tot;
+        if (last_block_total<kVNT>(bs, blockIdx.x, gridDim.x, partials, &st->ticket, red, &tot) &&
+            threadIdx.x == 0)
+            cg_finish_rho(st, tot);
+    }
+}
+
+// r.r on its own (the timed, unfused iteration).
+template <typename T>
+__global__ __launch_bounds__(kVNT) void cg_rr_kernel(int64_t n, const T *__restrict__ r,
+                                                     double *partials, CgState *st)
+{
+    __shared__ double red[kVNT / kWave];
+    if (st->done) return;
+    double s = 0.0;
+    VEC_LOOP(i, n) s += (double)r[i] * (double)r[i];
+    const double bs = block_sum<kVNT>(s, red);
+    double tot;
+    if (last_block_total<kVNT>(bs, blockIdx.x, gridDim.x, partials, &st->ticket, red, &tot) &&
+        threadIdx.x == 0)
+        cg_finish_rho(st, tot);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kVNT) void cg_p_kernel(int64_t n, const T *__restrict__ r,
+                                                    T *__restrict__ p, const CgState *st)
+{
+    if (st->done) return;
+    const T b = (T)st->beta;
+    VEC_LOOP(i, n) p[i] = r[i] + b * p[i];
+}
+
+// out = sum (a - c)^2 (c may be null); with w non-null also writes w = a - c.
+__global__ __launch_bounds__(kVNT) void diff_norm2_kernel(int64_t n, const double *__restrict__ a,
+                                                          const double *__restrict__ c,
+                                                          double *__restrict__ w, double *partials,
+                                                          unsigned *ticket, double *out)
+{
+    __shared__ double red[kVNT / kWave];
+    double s = 0.0;
+    VEC_LOOP(i, n)
+    {
+        const double v = c ? a[i] - c[i] : a[i];
+        if (w) w[i] = v;
+        s += v * v;
+    }
+    const double bs = block_sum<kVNT>(s, red);
+    double tot;
+    if (last_block_total<kVNT>(bs, blockIdx.x, gridDim.x, partials, ticket, red, &tot) &&
+        threadIdx.x == 0)
+        *out = tot;
+}
+
+__global__ __launch_bounds__(kVNT) void nonfinite_kernel(int64_t n, const double *__restrict__ a,
+                                                         const double *__restrict__ b, int *flag)
+{
+    int bad = 0;
+    VEC_LOOP(i, n)
+    {
+        if (!__builtin_isfinite(a[i]) || !__builtin_isfinite(b[i])) bad = 1;
+    }
+    if (bad) atomicOr(flag, 1);
+}
+
+// Inner solve start: r32 = fp32(r / s); d = 0; p32 = r32; rho0 = r32.r32.
+__global__ __launch_bounds__(kVNT) void ir_inner_start_kernel(int64_t n, const double *__restrict__ r,
+                                                              double s, float *__restrict__ r32,
+                                                              float *__restrict__ d32,
+                                                              float *__restrict__ p32,
+                                                              double *partials, CgState *st)
+{
+    __shared__ double red[kVNT / kWave];
+    double acc = 0.0;
+    VEC_LOOP(i, n)
+    {
+        const float v = (float)(r[i] / s);
+        r32[i] = v;
+        p32[i] = v;
+        d32[i] = 0.0f;
+        acc += (double)v * (double)v;
+    }
+    const double bs = block_sum<kVNT>(acc, red);
+    double tot;
+    if (last_block_total<kVNT>(bs, blockIdx.x, gridDim.x, partials, &st->ticket, red, &tot) &&
+        threadIdx.x == 0) {
+        st->rho0 = st->rho = st->rr = tot;
+        if (tot == 0.0) {
+            st->status = (int)MXS_OK;
+            st->done = 1;
+        }
+    }
+}
+
+// x += s * fp64(d)
+__global__ __launch_bounds__(kVNT) void ir_correct_kernel(int64_t n, double *__restrict__ x,
+                                                          const float *__restrict__ d32, double s)
+{
+    VEC_LOOP(i, n) x[i] += s * (double)d32[i];
+}
+
+// ---------------------------------------------------------------------------
+// Workspace layout
+// ---------------------------------------------------------------------------
+static size_t up256(size_t b) { return (b + 255) / 256 * 256; }
+
+struct Ws {
+    CgState *st, *st32;
+    Aux *aux;
+    double *parts;
+    double *r, *p, *q;
+    float *d32, *r32, *p32, *q32;
+};
+
+static size_t layout(int64_t n, int32_t mixed, int64_t parts, char *base, Ws *w)
+{
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        char *p = base ? base + o : nullptr;
+        o += up256(bytes);
+        return p;
+    };
+    Ws t;
+    t.st = (CgState *)take(sizeof(CgState));
+    t.st32 = (CgState *)take(sizeof(CgState));
+    t.aux = (Aux *)take(sizeof(Aux));
+    t.parts = (double *)take(sizeof(double) * (size_t)parts);
+    t.r = (double *)take(sizeof(double) * (size_t)n);
+    t.p = (double *)take(sizeof(double) * (size_t)n);
+    t.q = (double *)take(sizeof(double) * (size_t)n);
+    t.d32 = t.r32 = t.p32 = t.q32 = nullptr;
+    if (mixed) {
+        t.d32 = (float *)take(sizeof(float) * (size_t)n);
+        t.r32 = (float *)take(sizeof(float) * (size_t)n);
+        t.p32 = (float *)take(sizeof(float) * (size_t)n);
+        t.q32 = (float *)take(sizeof(float) * (size_t)n);
+    }
+    if (w) *w = t;
+    return o;
+}
+
+size_t cg_workspace_bytes(int64_t n, int32_t mixed, int64_t parts64, int64_t parts32)
+{
+    const int64_t parts = std::max<int64_t>({parts64, parts32, kVecGridMax, 1});
+    return layout(n, mixed, parts, nullptr, nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// Host driver
+// ---------------------------------------------------------------------------
+namespace {
+
+// Pinned host copy of a CgState, one per host thread (kept for the process).
+CgState *pinned_state()
+{
+    thread_local CgState *p = nullptr;
+    if (!p) {
+        if (hipHostMalloc((void **)&p, sizeof(CgState) * 2, hipHostMallocPortable) != hipSuccess)
+            p = nullptr;
+    }
+    return p;
+}
+
+struct Timer {
+    bool on = false;
+    std::vector<hipEvent_t> ev; // 4 marks per iteration
+    size_t used = 0;
+    double ms[3] = {0, 0, 0}; // spmv, dot, axpy
+    hipStream_t s = nullptr;
+
+    mxs_status mark()
+    {
+        if (!on) return MXS_OK;
+        if (used == ev.size()) {
+            hipEvent_t e;
+            MXS_HIP(hipEventCreate(&e));
+            ev.push_back(e);
+        }
+        MXS_HIP(hipEventRecord(ev[used++], s));
+        return MXS_OK;
+    }
+    // After a synchronisation: fold the recorded intervals into the totals.
+    mxs_status collect()
+    {
+        if (!on) return MXS_OK;
+        for (size_t i = 0; i + 3 < used; i += 4) {
+            float a, b, c;
+            MXS_HIP(hipEventElapsedTime(&a, ev[i], ev[i + 1]));
+            MXS_HIP(hipEventElapsedTime(&b, ev[i + 1], ev[i + 2]));
+            MXS_HIP(hipEventElapsedTime(&c, ev[i + 2], ev[i + 3]));
+            ms[0] += a;
+            ms[1] += b;
+            ms[2] += c;
+        }
+        used = 0;
+        return MXS_OK;
+    }
+    ~Timer()
+    {
+        for (auto e : ev) (void)hipEventDestroy(e);
+    }
+};
+
+template <typename T>
+mxs_status enqueue_iteration(const mxs_mat_s *A, int64_t n, T *x, T *r, T *p, T *q, double *parts,
+                             CgState *st, Timer &tm, hipStream_t s)
+{
+    mxs_status e;
+    const DotSink ds{parts, st};
+    const mxs_dtype dt = sizeof(T) == 8 ? MXS_F64 : MXS_F32;
+    const uint32_t g = vec_grid(n);
+    if (!tm.on) {
+        if ((e = spmv_launch(A, p, q, &st->done, &ds, s)) != MXS_OK) return e;
+        cg_xr_kernel<T, true><<<g, kVNT, 0, s>>>(n, x, r, p, q, parts, st);
+        cg_p_kernel<T><<<g, kVNT, 0, s>>>(n, r, p, st);
+        return launch_status();
+    }
+    // Timed iteration: the same steps unfused, one kernel class at a time.
+    if ((e = tm.mark()) != MXS_OK) return e;
+    if ((e = spmv_launch(A, p, q, &st->done, nullptr, s)) != MXS_OK) return e;
+    if ((e = tm.mark()) != MXS_OK) return e;
+    if ((e = dot_sigma_launch(n, dt, p, q, &st->done, &ds, s)) != MXS_OK) return e;
+    if ((e = tm.mark()) != MXS_OK) return e;
+    cg_xr_kernel<T, false><<<g, kVNT, 0, s>>>(n, x, r, p, q, parts, st);
+    cg_rr_kernel<T><<<g, kVNT, 0, s>>>(n, r, parts, st);
+    cg_p_kernel<T><<<g, kVNT, 0, s>>>(n, r, p, st);
+    if ((e = launch_status()) != MXS_OK) return e;
+    return tm.mark();
+}
+
+// Runs iterations until the device flag is set; returns the final state.
+template <typename T>
+mxs_status run_loop(const mxs_mat_s *A, int64_t n, T *x, T *r, T *p, T *q, double *parts,
+                    CgState *st, int64_t maxit, int32_t every, Timer &tm, CgState *host,
+                    hipStream_t s)
+{
+    const int64_t C = std::max<int32_t>(every, 1);
+    MXS_HIP(hipMemcpyAsync(host, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+    MXS_HIP(hipStreamSynchronize(s));
+    int64_t launched = 0;
+    while (!host->done && launched < maxit + C) {
+        for (int64_t c = 0; c < C; ++c) {
+            mxs_status e = enqueue_iteration<T>(A, n, x, r, p, q, parts, st, tm, s);
+            if (e != MXS_OK) return e;
+        }
+        launched += C;
+        MXS_HIP(hipMemcpyAsync(host, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+        MXS_HIP(hipStreamSynchronize(s));
+        mxs_status e = tm.collect();
+        if (e != MXS_OK) return e;
+    }
+    return MXS_OK;
+}
+
+}  // namespace
+
+mxs_status cg_solve(const mxs_mat_s *A, const mxs_mat_s *A32, const double *b, double *x,
+                    const mxs_cg_opts *o, mxs_cg_result *res, void *wsp, size_t bytes,
+                    hipStream_t s)
+{
+    const int64_t n = A->nrows;
+    *res = mxs_cg_result{0, 0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const int64_t parts = std::max<int64_t>(
+        {spmv_dot_parts(A), A32 ? spmv_dot_parts(A32) : 0, kVecGridMax, 1});
+    if (layout(n, o->mixed, parts, nullptr, nullptr) > bytes) return MXS_ERR_INVALID_ARG;
+    Ws w;
+    layout(n, o->mixed, parts, (char *)wsp, &w);
+    CgState *host = pinned_state();
+    if (!host) return MXS_ERR_OUT_OF_MEMORY;
+    Timer tm;
+    tm.on = o->timing != 0;
+    tm.s = s;
+    const uint32_t g = vec_grid(n);
+    mxs_status e;
+
+    if (!o->mixed) {
+        cg_state_init<<<1, 1, 0, s>>>(w.st, o->rtol, (long long)o->maxit);
+        if ((e = spmv_launch(A, x, w.q, nullptr, nullptr, s)) != MXS_OK) return e;
+        cg_start_kernel<<<g, kVNT, 0, s>>>(n, b, x, w.q, w.r, w.p, w.parts, w.st);
+        MXS_HIP(hipGetLastError());
+        if (o->maxit > 0) {
+            if ((e = run_loop<double>(A, n, x, w.r, w.p, w.q, w.parts, w.st, o->maxit,
+                                      o->check_every, tm, host, s)) != MXS_OK)
+                return e;
+        } else {
+            MXS_HIP(hipMemcpyAsync(host, w.st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+            MXS_HIP(hipStreamSynchronize(s));
+        }
+        const CgState f = *host;
+        if (f.status == (int)MXS_ERR_NONFINITE) return MXS_ERR_NONFINITE;
+        res->iters = f.iters;
+        res->rel_resid = f.rho0 > 0.0 ? std::sqrt(f.rr) / std::sqrt(f.rho0) : 0.0;
+        res->t_spmv_ms = tm.ms[0];
+        res->t_dot_ms = tm.ms[1];
+        res->t_axpy_ms = tm.ms[2];
+        // true residual ||b - A x|| / ||b||
+        if ((e = spmv_launch(A, x, w.q, nullptr, nullptr, s)) != MXS_OK) return e;
+        if ((e = fill_bytes0(w.aux, sizeof(Aux), s)) != MXS_OK) return e;
+        diff_norm2_kernel<<<g, kVNT, 0, s>>>(n, b, w.q, nullptr, w.parts, &w.aux->ticket,
+                                             &w.aux->norm2[0]);
+        diff_norm2_kernel<<<g, kVNT, 0, s>>>(n, b, nullptr, nullptr, w.parts, &w.aux->ticket,
+                                             &w.aux->norm2[1]);
+        MXS_HIP(hipGetLastError());
+        double nn[2];
+        MXS_HIP(hipMemcpyAsync(nn, w.aux->norm2, sizeof(nn), hipMemcpyDeviceToHost, s));
+        MXS_HIP(hipStreamSynchronize(s));
+        res->true_rel_resid = nn[1] > 0.0 ? std::sqrt(nn[0]) / std::sqrt(nn[1]) : std::sqrt(nn[0]);
+        if (f.status == (int)MXS_ERR_BREAKDOWN) return MXS_ERR_BREAKDOWN;
+        return f.status == (int)MXS_OK ? MXS_OK : MXS_NOT_CONVERGED;
+    }
+
+    // ---- mixed precision: FP64 residual and update, FP32 inner CG ----
+    if ((e = fill_bytes0(w.aux, sizeof(Aux), s)) != MXS_OK) return e;
+    nonfinite_kernel<<<g, kVNT, 0, s>>>(n, b, x, &w.aux->nonfinite);
+    diff_norm2_kernel<<<g, kVNT, 0, s>>>(n, b, nullptr, nullptr, w.parts, &w.aux->ticket,
+                                         &w.aux->norm2[1]);
+    MXS_HIP(hipGetLastError());
+    Aux ha;
+    MXS_HIP(hipMemcpyAsync(&ha, w.aux, sizeof(Aux), hipMemcpyDeviceToHost, s));
+    MXS_HIP(hipStreamSynchronize(s));
+    if (ha.nonfinite) return MXS_ERR_NONFINITE;
+    const double bn = std::sqrt(ha.norm2[1]);
+    mxs_status status = MXS_NOT_CONVERGED;
+    for (int32_t outer = 0;; ++outer) {
+        if ((e = spmv_launch(A, x, w.q, nullptr, nullptr, s)) != MXS_OK) return e;
+        diff_norm2_kernel<<<g, kVNT, 0, s>>>(n, b, w.q, w.r, w.parts, &w.aux->ticket,
+                                             &w.aux->norm2[0]);
+        MXS_HIP(hipGetLastError());
+        double r2;
+        MXS_HIP(hipMemcpyAsync(&r2, &w.aux->norm2[0], sizeof(double), hipMemcpyDeviceToHost, s));
+        MXS_HIP(hipStreamSynchronize(s));
+        const double rn = std::sqrt(r2);
+        res->rel_resid = res->true_rel_resid = bn > 0.0 ? rn / bn : rn;
+        if (rn <= o->rtol * bn) {
+            status = MXS_OK;
+            break;
+        }
+        if (outer >= o->max_outer) break;
+        cg_state_init<<<1, 1, 0, s>>>(w.st32, o->inner_rtol, (long long)o->maxit);
+        ir_inner_start_kernel<<<g, kVNT, 0, s>>>(n, w.r, rn, w.r32, w.d32, w.p32, w.parts, w.st32);
+        MXS_HIP(hipGetLastError());
+        if (o->maxit > 0) {
+            if ((e = run_loop<float>(A32, n, w.d32, w.r32, w.p32, w.q32, w.parts, w.st32,
+                                     o->maxit, o->check_every, tm, host, s)) != MXS_OK)
+                return e;
+            res->iters += host->iters;
+        }
+        ir_correct_kernel<<<g, kVNT, 0, s>>>(n, x, w.d32, rn);
+        MXS_HIP(hipGetLastError());
+        res->outer_iters += 1;
+    }
+    res->t_spmv_ms = tm.ms[0];
+    res->t_dot_ms = tm.ms[1];
+    res->t_axpy_ms = tm.ms[2];
+    return status;
+}
+
+}  // namespace mxs

@@ -1,0 +1,269 @@
+// Internal declarations of libmxs: the handle, device helpers and the
+// launchers each translation unit provides.  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+#include <vector>
+
+#include "mxs.h"
+
+namespace mxs {
+
+constexpr int kWave = 64;  // CDNA wavefront width
+constexpr int kNumXcd = 8; // MI355X: 8 accelerator complex dies, 32 CUs each
+
+// ---------------------------------------------------------------------------
+// Error plumbing
+// ---------------------------------------------------------------------------
+#define MXS_HIP(call)                                     \
+    do {                                                  \
+        hipError_t e_ = (call);                           \
+        if (e_ != hipSuccess) return ::mxs::from_hip(e_); \
+    } while (0)
+
+inline mxs_status from_hip(hipError_t e)
+{
+    if (e == hipSuccess) return MXS_OK;
+    if (e == hipErrorOutOfMemory) return MXS_ERR_OUT_OF_MEMORY;
+    return MXS_ERR_HIP;
+}
+
+// Checks the launch that was just enqueued.
+inline mxs_status launch_status() { return from_hip(hipGetLastError()); }
+
+// ---------------------------------------------------------------------------
+// CG state kept in device memory (one per solve level)
+// ---------------------------------------------------------------------------
+struct CgState {
+    double rho0;     // r0.r0
+    double rho;      // r.r of the current iterate
+    double sigma;    // p.Ap
+    double alpha;    // rho / sigma
+    double beta;     // rho_new / rho
+    double rtol;     // stopping tolerance (relative to sqrt(rho0))
+    double rr;       // last reduced value of an auxiliary dot (residual norms)
+    long long iters; // loop SpMVs done
+    long long maxit;
+    int done;        // 1: every later CG kernel returns at entry
+    int status;      // mxs_status of the solve
+    unsigned ticket; // last-block-done counter, reset by the last block
+    int nonfinite;   // set when an input vector holds NaN or Inf
+};
+
+// Where a fused dot product of an SpMV epilogue goes.
+struct DotSink {
+    double *partials; // one per workgroup
+    CgState *st;      // finisher state (alpha = rho / (p.Ap))
+};
+
+// ---------------------------------------------------------------------------
+// The matrix handle
+// ---------------------------------------------------------------------------
+struct CsrPlan {
+    int32_t *blk_row = nullptr; // [nblk+1] first row of each row block
+    int64_t nblk = 0;
+};
+
+struct CooPlan {
+    void *carry = nullptr; // [2*ntiles] values: head partial, tail partial
+    int64_t ntiles = 0;
+};
+
+}  // namespace mxs
+
+struct mxs_mat_s {
+    mxs_format fmt = MXS_CSR;
+    mxs_dtype dtype = MXS_F64;
+    int32_t nrows = 0, ncols = 0;
+    int64_t nnz = 0;     // COO/CSR: stored entries; DIA: in-range slots
+    int32_t ndiag = 0;   // DIA only
+    const int32_t *idx0 = nullptr; // COO ai | CSR irp | DIA doff
+    const int32_t *idx1 = nullptr; // COO aj | CSR aj  | DIA unused
+    const void *vals = nullptr;    // values
+    std::vector<void *> owned;     // device allocations freed by mxs_destroy
+    int device = 0;
+    std::mutex mu;
+    bool optimized = false;
+    mxs::CsrPlan csr;
+    mxs::CooPlan coo;
+};
+
+namespace mxs {
+
+inline size_t dsize(mxs_dtype t) { return t == MXS_F64 ? 8 : 4; }
+
+// ---------------------------------------------------------------------------
+// Device helpers
+// ---------------------------------------------------------------------------
+
+// Workgroups are dispatched round-robin over the XCDs (workgroup b runs on
+// XCD b % 8).  The remap gives each XCD a contiguous range of logical
+// blocks, so rows that share x entries meet in the same L2.  The grid must
+// be padded to a multiple of 8; logical ids >= the real count must exit.
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t bid, uint32_t grid)
+{
+    const uint32_t per = grid / kNumXcd;
+    return (bid % kNumXcd) * per + bid / kNumXcd;
+}
+
+inline uint32_t pad_grid(int64_t nblocks)
+{
+    return (uint32_t)(((nblocks + kNumXcd - 1) / kNumXcd) * kNumXcd);
+}
+
+// Butterfly sum over the 64 lanes: every lane ends with the same value,
+// independent of scheduling.
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+__device__ __forceinline__ float wave_sum(float v)
+{
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// Sum over the workgroup (NT threads); the result is valid in thread 0.
+// smem must hold NT/64 doubles.  Fixed combination order.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double *smem)
+{
+    v = wave_sum(v);
+    const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+    if (NT > kWave) {
+        if (l == 0) smem[w] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double s = 0.0;
+#pragma unroll
+            for (int i = 0; i < NT / kWave; ++i) s += smem[i];
+            v = s;
+        }
+        __syncthreads();
+    }
+    return v;
+}
+
+// Last-workgroup-done reduction.  Thread 0 of each of `nparts` workgroups
+// publishes its partial at partials[part]; the workgroup that arrives last
+// sums all partials in index order (so the result does not depend on
+// arrival order), resets the ticket and returns true with the total in
+// *total (valid in thread 0).
+template <int NT>
+__device__ bool last_block_total(double part, int64_t part_idx, int64_t nparts, double *partials,
+                                 unsigned *ticket, double *smem, double *total)
+{
+    __shared__ int am_last;
+    if (threadIdx.x == 0) {
+        partials[part_idx] = part;
+        __threadfence();
+        unsigned t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL,
+                                            __HIP_MEMORY_SCOPE_AGENT);
+        am_last = (t == (unsigned)(nparts - 1));
+    }
+    __syncthreads();
+    if (!am_last) return false;
+    __threadfence();
+    double v = 0.0;
+    for (int64_t i = threadIdx.x; i < nparts; i += NT)
+        v += partials[i];
+    v = block_sum<NT>(v, smem);
+    if (threadIdx.x == 0) {
+        *total = v;
+        __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return true;
+}
+
+// Finisher of the fused p.Ap: one loop SpMV done; alpha = rho / sigma, or a
+// breakdown when sigma <= 0 or not finite.
+__device__ __forceinline__ void cg_finish_sigma(CgState *st, double sigma)
+{
+    st->sigma = sigma;
+    st->iters += 1;
+    if (!(sigma > 0.0) || !__builtin_isfinite(sigma)) {
+        st->status = (int)MXS_ERR_BREAKDOWN;
+        st->alpha = 0.0;
+        st->done = 1;
+    } else {
+        st->alpha = st->rho / sigma;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers provided by the translation units
+// ---------------------------------------------------------------------------
+
+// spmv.hip.  `done` (nullable) makes every workgroup return at entry when
+// *done != 0; `dot` (nullable, square A only) fuses sum_i y_i*x_i into the
+// epilogue and calls cg_finish_sigma on its total.
+mxs_status spmv_launch(const mxs_mat_s *A, const void *x, void *y, const int *done,
+                       const DotSink *dot, hipStream_t s);
+// p.Ap (n = nrows) reduced into `dot` as the COO path and the timed CG path do.
+mxs_status dot_sigma_launch(int64_t n, mxs_dtype t, const void *a, const void *b, const int *done,
+                            const DotSink *dot, hipStream_t s);
+// Number of per-workgroup partials the fused dot of spmv_launch writes.
+int64_t spmv_dot_parts(const mxs_mat_s *A);
+mxs_status build_plan(mxs_mat_s *A, hipStream_t s);
+
+// scan.hip
+// out[i] = sum_{k<i} in[k] for i in [0, n]; out has n+1 entries (the total
+// last).  Fails with MXS_ERR_INDEX_RANGE if the total exceeds INT32_MAX.
+mxs_status scan_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t s);
+mxs_status fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+mxs_status fill_bytes0(void *p, size_t bytes, hipStream_t s);
+
+// convert.hip
+mxs_status check_coo(const mxs_mat_s *A, hipStream_t s);  // syncs
+mxs_status check_csr(const mxs_mat_s *A, hipStream_t s);  // syncs
+mxs_status check_dia(const mxs_mat_s *A, hipStream_t s);  // syncs
+mxs_status sort_coo(int32_t nrows, int32_t ncols, int64_t nnz, int32_t *ai, int32_t *aj,
+                    void *av, mxs_dtype t, hipStream_t s);
+mxs_status dia_slot_count(const mxs_mat_s *A, int64_t *slots, hipStream_t s); // syncs
+mxs_status convert_size(const mxs_mat_s *A, mxs_format dst, int64_t *count, int32_t *ndiag,
+                        hipStream_t s);
+mxs_status convert(const mxs_mat_s *A, mxs_format dst, int32_t *idx0, int32_t *idx1,
+                   void *vals, int64_t count, int32_t ndiag, hipStream_t s);
+mxs_status cast_values(const void *src, mxs_dtype from, void *dst, mxs_dtype to, int64_t n,
+                       hipStream_t s);
+mxs_status csr_row_index(const int32_t *irp, int32_t nrows, int64_t nnz, int32_t *ai,
+                         hipStream_t s);
+
+// cg.hip
+mxs_status dot_launch(int64_t n, mxs_dtype t, const void *a, const void *b, double *result,
+                      hipStream_t s);
+mxs_status axpby_launch(int64_t n, mxs_dtype t, double alpha, const void *x, double beta,
+                        void *y, hipStream_t s);
+size_t cg_workspace_bytes(int64_t n, int32_t mixed, int64_t parts64, int64_t parts32);
+mxs_status cg_solve(const mxs_mat_s *A, const mxs_mat_s *A32, const double *b, double *x,
+                    const mxs_cg_opts *o, mxs_cg_result *r, void *ws, size_t bytes,
+                    hipStream_t s);
+
+// features.hip
+mxs_status features(const mxs_mat_s *A, double out[8], hipStream_t s);
+
+// gen.hip
+mxs_status stencil_coo(int32_t n, int32_t points, double diag, double offdiag, int32_t *ai,
+                       int32_t *aj, void *av, mxs_dtype t, hipStream_t s);
+
+// mlp.hip
+mxs_status mlp_inputs(const double *raw, int32_t n, const float *mu, const float *sd,
+                      float *X, hipStream_t s);
+mxs_status mlp_norm_stats(const double *raw, int32_t n, float *mu, float *sd, hipStream_t s);
+mxs_status mlp_forward(const float *w, const float *X, int32_t n, float *logits, hipStream_t s);
+mxs_status mlp_predict(const float *w, const float *X, int32_t n, const uint8_t *feasible,
+                       int32_t *fmt, hipStream_t s);
+size_t mlp_ws_bytes(int32_t n);
+mxs_status mlp_grad(const float *w, const float *X, const int32_t *labels, int32_t n,
+                    float *grad, float *loss, void *ws, hipStream_t s);
+mxs_status mlp_adam(float *w, float *m, float *v, const float *g, float lr, int32_t t,
+                    float b1, float b2, float eps, hipStream_t s);
+
+}  // namespace mxs
