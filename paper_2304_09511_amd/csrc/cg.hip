@@ -2,15 +2,15 @@
 // preconditioner disabled (Section VII-D), plus FP32-inner / FP64-outer
 // iterative refinement built on the same kernels.
 //
-// Scalars live on the device (CgState).  One CG iteration is three kernels:
-//   1. q = A p with p.q fused into the SpMV epilogue; its last workgroup
-//      computes alpha = rho / p.q (CSR, DIA; COO adds one dot kernel)
-//   2. x += alpha p, r -= alpha q with r.r fused; its last workgroup tests
-//      convergence and computes beta
-//   3. p = r + beta p
+// Scalars live on the device (CgState).  One CG iteration is five launches:
+//   1. q = A p with p.q partials fused into the SpMV epilogue (CSR, DIA;
+//      COO adds one dot kernel)    2. alpha = rho / p.q (one workgroup)
+//   3. x += alpha p, r -= alpha q with r.r partials fused
+//   4. convergence test, beta (one workgroup)    5. p = r + beta p
 // Every kernel returns at entry once the device flag `done` is set, so the
 // host enqueues iterations in batches and reads the flag once per batch.
-// Reductions are two-level in fixed order: results are deterministic.
+// Reductions are per-workgroup partials summed in index order by a
+// single-workgroup kernel: deterministic, and no device-scope fences.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,47 +34,48 @@ static uint32_t vec_grid(int64_t n)
          i += (int64_t)gridDim.x * kVNT)
 
 struct Aux {
-    double norm2[2]; // scratch results of norm kernels
-    unsigned ticket;
+    double norm2[2]; // results of norm kernels
     int nonfinite;
+    int pad;
 };
 
 // ---------------------------------------------------------------------------
-// Dot and axpby
+// Reductions
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kVNT) void dot_kernel(int64_t n, const T *__restrict__ a,
-                                                   const T *__restrict__ b, double *partials,
-                                                   unsigned *ticket, double *result)
+                                                   const T *__restrict__ b, double *partials)
 {
     __shared__ double red[kVNT / kWave];
     double s = 0.0;
     VEC_LOOP(i, n) s += (double)a[i] * (double)b[i];
     const double bs = block_sum<kVNT>(s, red);
-    double tot;
-    if (last_block_total<kVNT>(bs, blockIdx.x, gridDim.x, partials, ticket, red, &tot) &&
-        threadIdx.x == 0)
-        *result = tot;
+    if (threadIdx.x == 0) partials[blockIdx.x] = bs;
+}
+
+// *out = sum of the partials (single workgroup)
+__global__ __launch_bounds__(kVNT) void total_kernel(const double *__restrict__ partials,
+                                                     int64_t nparts, double *out)
+{
+    __shared__ double red[kVNT / kWave];
+    const double t = reduce_partials<kVNT>(partials, nparts, red);
+    if (threadIdx.x == 0) *out = t;
 }
 
 mxs_status dot_launch(int64_t n, mxs_dtype t, const void *a, const void *b, double *result,
                       hipStream_t s)
 {
     const uint32_t g = vec_grid(n);
-    char *tmp = nullptr;
-    MXS_HIP(hipMallocAsync((void **)&tmp, 256 + sizeof(double) * g, s));
-    unsigned *ticket = (unsigned *)tmp;
-    double *parts = (double *)(tmp + 256);
-    mxs_status st = fill_bytes0(ticket, 4, s);
-    if (st != MXS_OK) return st;
+    double *parts = nullptr;
+    MXS_HIP(hipMallocAsync((void **)&parts, sizeof(double) * g, s));
     if (t == MXS_F64)
-        dot_kernel<double><<<g, kVNT, 0, s>>>(n, (const double *)a, (const double *)b, parts, ticket,
-                                              result);
+        dot_kernel<double><<<g, kVNT, 0, s>>>(n, (const double *)a, (const double *)b, parts);
     else
-        dot_kernel<float><<<g, kVNT, 0, s>>>(n, (const float *)a, (const float *)b, parts, ticket,
-                                             result);
+        dot_kernel<float><<<g, kVNT, 0, s>>>(n, (const float *)a, (const float *)b, parts);
     MXS_HIP(hipGetLastError());
-    MXS_HIP(hipFreeAsync(tmp, s));
+    total_kernel<<<1, kVNT, 0, s>>>(parts, g, result);
+    MXS_HIP(hipGetLastError());
+    MXS_HIP(hipFreeAsync(parts, s));
     return MXS_OK;
 }
 
@@ -113,11 +114,11 @@ __global__ void cg_state_init(CgState *st, double rtol, long long maxit)
     st->maxit = maxit;
     st->done = 0;
     st->status = (int)MXS_NOT_CONVERGED;
-    st->ticket = 0u;
     st->nonfinite = 0;
+    st->pad = 0;
 }
 
-// r = b - q (q = A x0), p = r, rho0 = r.r; NaN/Inf in b or x0 stops the solve.
+// r = b - q (q = A x0), p = r, partials of r.r; flags NaN/Inf in b or x0.
 __global__ __launch_bounds__(kVNT) void cg_start_kernel(int64_t n, const double *__restrict__ b,
                                                         const double *__restrict__ x,
                                                         const double *__restrict__ q,
@@ -139,10 +140,17 @@ __global__ __launch_bounds__(kVNT) void cg_start_kernel(int64_t n, const double 
     }
     if (bad) atomicOr(&st->nonfinite, 1);
     const double bs = block_sum<kVNT>(s, red);
-    double tot;
-    if (last_block_total<kVNT>(bs, blockIdx.x, gridDim.x, partials, &st->ticket, red, &tot) &&
-        threadIdx.x == 0) {
-        if (__hip_atomic_load(&st->nonfinite, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) {
+    if (threadIdx.x == 0) partials[blockIdx.x] = bs;
+}
+
+// rho0 = r0.r0; stops at once for NaN/Inf input or a zero residual.
+__global__ __launch_bounds__(kVNT) void start_finish_kernel(const double *__restrict__ partials,
+                                                            int64_t nparts, CgState *st)
+{
+    __shared__ double red[kVNT / kWave];
+    const double tot = reduce_partials<kVNT>(partials, nparts, red);
+    if (threadIdx.x == 0) {
+        if (st->nonfinite) {
             st->status = (int)MXS_ERR_NONFINITE;
             st->done = 1;
         } else {
@@ -155,28 +163,12 @@ __global__ __launch_bounds__(kVNT) void cg_start_kernel(int64_t n, const double 
     }
 }
 
-// After r.r of the new residual: converged, capped, or beta for the next p.
-__device__ __forceinline__ void cg_finish_rho(CgState *st, double rr)
-{
-    st->rr = rr;
-    if (sqrt(rr) <= st->rtol * sqrt(st->rho0)) {
-        st->status = (int)MXS_OK;
-        st->done = 1;
-    } else if (st->iters >= st->maxit) {
-        st->status = (int)MXS_NOT_CONVERGED;
-        st->done = 1;
-    } else {
-        st->beta = rr / st->rho;
-    }
-    st->rho = rr;
-}
-
-// x += alpha p; r -= alpha q; with FUSED, r.r and the convergence test.
+// x += alpha p; r -= alpha q; with FUSED, partials of r.r.
 template <typename T, bool FUSED>
 __global__ __launch_bounds__(kVNT) void cg_xr_kernel(int64_t n, T *__restrict__ x,
                                                      T *__restrict__ r, const T *__restrict__ p,
                                                      const T *__restrict__ q, double *partials,
-                                                     CgState *st)
+                                                     const CgState *st)
 {
     __shared__ double red[kVNT / kWave];
     if (st->done) return;
@@ -192,27 +184,43 @@ __global__ __launch_bounds__(kVNT) void cg_xr_kernel(int64_t n, T *__restrict__ 
     }
     if (FUSED) {
         const double bs = block_sum<kVNT>(s, red);
-        double tot;
-        if (last_block_total<kVNT>(bs, blockIdx.x, gridDim.x, partials, &st->ticket, red, &tot) &&
-            threadIdx.x == 0)
-            cg_finish_rho(st, tot);
+        if (threadIdx.x == 0) partials[blockIdx.x] = bs;
     }
 }
 
-// r.r on its own (the timed, unfused iteration).
+// partials of r.r on their own (the timed, unfused iteration).
 template <typename T>
 __global__ __launch_bounds__(kVNT) void cg_rr_kernel(int64_t n, const T *__restrict__ r,
-                                                     double *partials, CgState *st)
+                                                     double *partials, const CgState *st)
 {
     __shared__ double red[kVNT / kWave];
     if (st->done) return;
     double s = 0.0;
     VEC_LOOP(i, n) s += (double)r[i] * (double)r[i];
     const double bs = block_sum<kVNT>(s, red);
-    double tot;
-    if (last_block_total<kVNT>(bs, blockIdx.x, gridDim.x, partials, &st->ticket, red, &tot) &&
-        threadIdx.x == 0)
-        cg_finish_rho(st, tot);
+    if (threadIdx.x == 0) partials[blockIdx.x] = bs;
+}
+
+// After r.r of the new residual: converged, capped, or beta for the next p.
+__global__ __launch_bounds__(kVNT) void rho_finish_kernel(const double *__restrict__ partials,
+                                                          int64_t nparts, CgState *st)
+{
+    __shared__ double red[kVNT / kWave];
+    if (st->done) return;
+    const double rr = reduce_partials<kVNT>(partials, nparts, red);
+    if (threadIdx.x == 0) {
+        st->rr = rr;
+        if (sqrt(rr) <= st->rtol * sqrt(st->rho0)) {
+            st->status = (int)MXS_OK;
+            st->done = 1;
+        } else if (st->iters >= st->maxit) {
+            st->status = (int)MXS_NOT_CONVERGED;
+            st->done = 1;
+        } else {
+            st->beta = rr / st->rho;
+        }
+        st->rho = rr;
+    }
 }
 
 template <typename T>
@@ -224,11 +232,10 @@ __global__ __launch_bounds__(kVNT) void cg_p_kernel(int64_t n, const T *__restri
     VEC_LOOP(i, n) p[i] = r[i] + b * p[i];
 }
 
-// out = sum (a - c)^2 (c may be null); with w non-null also writes w = a - c.
+// partials of sum (a - c)^2 (c may be null); with w non-null also w = a - c.
 __global__ __launch_bounds__(kVNT) void diff_norm2_kernel(int64_t n, const double *__restrict__ a,
                                                           const double *__restrict__ c,
-                                                          double *__restrict__ w, double *partials,
-                                                          unsigned *ticket, double *out)
+                                                          double *__restrict__ w, double *partials)
 {
     __shared__ double red[kVNT / kWave];
     double s = 0.0;
@@ -239,10 +246,7 @@ __global__ __launch_bounds__(kVNT) void diff_norm2_kernel(int64_t n, const doubl
         s += v * v;
     }
     const double bs = block_sum<kVNT>(s, red);
-    double tot;
-    if (last_block_total<kVNT>(bs, blockIdx.x, gridDim.x, partials, ticket, red, &tot) &&
-        threadIdx.x == 0)
-        *out = tot;
+    if (threadIdx.x == 0) partials[blockIdx.x] = bs;
 }
 
 __global__ __launch_bounds__(kVNT) void nonfinite_kernel(int64_t n, const double *__restrict__ a,
@@ -256,12 +260,12 @@ __global__ __launch_bounds__(kVNT) void nonfinite_kernel(int64_t n, const double
     if (bad) atomicOr(flag, 1);
 }
 
-// Inner solve start: r32 = fp32(r / s); d = 0; p32 = r32; rho0 = r32.r32.
+// Inner solve start: r32 = fp32(r / s); d = 0; p32 = r32; partials of r32.r32.
 __global__ __launch_bounds__(kVNT) void ir_inner_start_kernel(int64_t n, const double *__restrict__ r,
                                                               double s, float *__restrict__ r32,
                                                               float *__restrict__ d32,
                                                               float *__restrict__ p32,
-                                                              double *partials, CgState *st)
+                                                              double *partials)
 {
     __shared__ double red[kVNT / kWave];
     double acc = 0.0;
@@ -274,15 +278,7 @@ __global__ __launch_bounds__(kVNT) void ir_inner_start_kernel(int64_t n, const d
         acc += (double)v * (double)v;
     }
     const double bs = block_sum<kVNT>(acc, red);
-    double tot;
-    if (last_block_total<kVNT>(bs, blockIdx.x, gridDim.x, partials, &st->ticket, red, &tot) &&
-        threadIdx.x == 0) {
-        st->rho0 = st->rho = st->rr = tot;
-        if (tot == 0.0) {
-            st->status = (int)MXS_OK;
-            st->done = 1;
-        }
-    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = bs;
 }
 
 // x += s * fp64(d)
@@ -305,7 +301,7 @@ struct Ws {
     float *d32, *r32, *p32, *q32;
 };
 
-static size_t layout(int64_t n, int32_t mixed, int64_t parts, char *base, Ws *w)
+static size_t layout(int64_t n, int32_t mixed, char *base, Ws *w)
 {
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -317,7 +313,7 @@ static size_t layout(int64_t n, int32_t mixed, int64_t parts, char *base, Ws *w)
     t.st = (CgState *)take(sizeof(CgState));
     t.st32 = (CgState *)take(sizeof(CgState));
     t.aux = (Aux *)take(sizeof(Aux));
-    t.parts = (double *)take(sizeof(double) * (size_t)parts);
+    t.parts = (double *)take(sizeof(double) * (size_t)kMaxParts);
     t.r = (double *)take(sizeof(double) * (size_t)n);
     t.p = (double *)take(sizeof(double) * (size_t)n);
     t.q = (double *)take(sizeof(double) * (size_t)n);
@@ -332,10 +328,9 @@ static size_t layout(int64_t n, int32_t mixed, int64_t parts, char *base, Ws *w)
     return o;
 }
 
-size_t cg_workspace_bytes(int64_t n, int32_t mixed, int64_t parts64, int64_t parts32)
+size_t cg_workspace_bytes(int64_t n, int32_t mixed, int64_t, int64_t)
 {
-    const int64_t parts = std::max<int64_t>({parts64, parts32, kVecGridMax, 1});
-    return layout(n, mixed, parts, nullptr, nullptr);
+    return layout(n, mixed, nullptr, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -358,7 +353,7 @@ struct Timer {
     bool on = false;
     std::vector<hipEvent_t> ev; // 4 marks per iteration
     size_t used = 0;
-    double ms[3] = {0, 0, 0}; // spmv, dot, axpy
+    double ms[3] = {0, 0, 0}; // spmv, dot, vector updates
     hipStream_t s = nullptr;
 
     mxs_status mark()
@@ -405,6 +400,7 @@ mxs_status enqueue_iteration(const mxs_mat_s *A, int64_t n, T *x, T *r, T *p, T 
     if (!tm.on) {
         if ((e = spmv_launch(A, p, q, &st->done, &ds, s)) != MXS_OK) return e;
         cg_xr_kernel<T, true><<<g, kVNT, 0, s>>>(n, x, r, p, q, parts, st);
+        rho_finish_kernel<<<1, kVNT, 0, s>>>(parts, g, st);
         cg_p_kernel<T><<<g, kVNT, 0, s>>>(n, r, p, st);
         return launch_status();
     }
@@ -416,6 +412,7 @@ mxs_status enqueue_iteration(const mxs_mat_s *A, int64_t n, T *x, T *r, T *p, T 
     if ((e = tm.mark()) != MXS_OK) return e;
     cg_xr_kernel<T, false><<<g, kVNT, 0, s>>>(n, x, r, p, q, parts, st);
     cg_rr_kernel<T><<<g, kVNT, 0, s>>>(n, r, parts, st);
+    rho_finish_kernel<<<1, kVNT, 0, s>>>(parts, g, st);
     cg_p_kernel<T><<<g, kVNT, 0, s>>>(n, r, p, st);
     if ((e = launch_status()) != MXS_OK) return e;
     return tm.mark();
@@ -445,6 +442,16 @@ mxs_status run_loop(const mxs_mat_s *A, int64_t n, T *x, T *r, T *p, T *q, doubl
     return MXS_OK;
 }
 
+// ||a - c||^2 (c may be null; w = a - c when non-null) into *out.
+mxs_status norm2(int64_t n, const double *a, const double *c, double *w, double *parts,
+                 double *out, hipStream_t s)
+{
+    const uint32_t g = vec_grid(n);
+    diff_norm2_kernel<<<g, kVNT, 0, s>>>(n, a, c, w, parts);
+    total_kernel<<<1, kVNT, 0, s>>>(parts, g, out);
+    return launch_status();
+}
+
 }  // namespace
 
 mxs_status cg_solve(const mxs_mat_s *A, const mxs_mat_s *A32, const double *b, double *x,
@@ -453,11 +460,11 @@ mxs_status cg_solve(const mxs_mat_s *A, const mxs_mat_s *A32, const double *b, d
 {
     const int64_t n = A->nrows;
     *res = mxs_cg_result{0, 0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    const int64_t parts = std::max<int64_t>(
-        {spmv_dot_parts(A), A32 ? spmv_dot_parts(A32) : 0, kVecGridMax, 1});
-    if (layout(n, o->mixed, parts, nullptr, nullptr) > bytes) return MXS_ERR_INVALID_ARG;
+    if (spmv_dot_parts(A) > kMaxParts || (A32 && spmv_dot_parts(A32) > kMaxParts))
+        return MXS_ERR_UNSUPPORTED;
+    if (layout(n, o->mixed, nullptr, nullptr) > bytes) return MXS_ERR_INVALID_ARG;
     Ws w;
-    layout(n, o->mixed, parts, (char *)wsp, &w);
+    layout(n, o->mixed, (char *)wsp, &w);
     CgState *host = pinned_state();
     if (!host) return MXS_ERR_OUT_OF_MEMORY;
     Timer tm;
@@ -470,6 +477,7 @@ mxs_status cg_solve(const mxs_mat_s *A, const mxs_mat_s *A32, const double *b, d
         cg_state_init<<<1, 1, 0, s>>>(w.st, o->rtol, (long long)o->maxit);
         if ((e = spmv_launch(A, x, w.q, nullptr, nullptr, s)) != MXS_OK) return e;
         cg_start_kernel<<<g, kVNT, 0, s>>>(n, b, x, w.q, w.r, w.p, w.parts, w.st);
+        start_finish_kernel<<<1, kVNT, 0, s>>>(w.parts, g, w.st);
         MXS_HIP(hipGetLastError());
         if (o->maxit > 0) {
             if ((e = run_loop<double>(A, n, x, w.r, w.p, w.q, w.parts, w.st, o->maxit,
@@ -488,12 +496,8 @@ mxs_status cg_solve(const mxs_mat_s *A, const mxs_mat_s *A32, const double *b, d
         res->t_axpy_ms = tm.ms[2];
         // true residual ||b - A x|| / ||b||
         if ((e = spmv_launch(A, x, w.q, nullptr, nullptr, s)) != MXS_OK) return e;
-        if ((e = fill_bytes0(w.aux, sizeof(Aux), s)) != MXS_OK) return e;
-        diff_norm2_kernel<<<g, kVNT, 0, s>>>(n, b, w.q, nullptr, w.parts, &w.aux->ticket,
-                                             &w.aux->norm2[0]);
-        diff_norm2_kernel<<<g, kVNT, 0, s>>>(n, b, nullptr, nullptr, w.parts, &w.aux->ticket,
-                                             &w.aux->norm2[1]);
-        MXS_HIP(hipGetLastError());
+        if ((e = norm2(n, b, w.q, nullptr, w.parts, &w.aux->norm2[0], s)) != MXS_OK) return e;
+        if ((e = norm2(n, b, nullptr, nullptr, w.parts, &w.aux->norm2[1], s)) != MXS_OK) return e;
         double nn[2];
         MXS_HIP(hipMemcpyAsync(nn, w.aux->norm2, sizeof(nn), hipMemcpyDeviceToHost, s));
         MXS_HIP(hipStreamSynchronize(s));
@@ -505,9 +509,8 @@ mxs_status cg_solve(const mxs_mat_s *A, const mxs_mat_s *A32, const double *b, d
     // ---- mixed precision: FP64 residual and update, FP32 inner CG ----
     if ((e = fill_bytes0(w.aux, sizeof(Aux), s)) != MXS_OK) return e;
     nonfinite_kernel<<<g, kVNT, 0, s>>>(n, b, x, &w.aux->nonfinite);
-    diff_norm2_kernel<<<g, kVNT, 0, s>>>(n, b, nullptr, nullptr, w.parts, &w.aux->ticket,
-                                         &w.aux->norm2[1]);
     MXS_HIP(hipGetLastError());
+    if ((e = norm2(n, b, nullptr, nullptr, w.parts, &w.aux->norm2[1], s)) != MXS_OK) return e;
     Aux ha;
     MXS_HIP(hipMemcpyAsync(&ha, w.aux, sizeof(Aux), hipMemcpyDeviceToHost, s));
     MXS_HIP(hipStreamSynchronize(s));
@@ -516,9 +519,7 @@ mxs_status cg_solve(const mxs_mat_s *A, const mxs_mat_s *A32, const double *b, d
     mxs_status status = MXS_NOT_CONVERGED;
     for (int32_t outer = 0;; ++outer) {
         if ((e = spmv_launch(A, x, w.q, nullptr, nullptr, s)) != MXS_OK) return e;
-        diff_norm2_kernel<<<g, kVNT, 0, s>>>(n, b, w.q, w.r, w.parts, &w.aux->ticket,
-                                             &w.aux->norm2[0]);
-        MXS_HIP(hipGetLastError());
+        if ((e = norm2(n, b, w.q, w.r, w.parts, &w.aux->norm2[0], s)) != MXS_OK) return e;
         double r2;
         MXS_HIP(hipMemcpyAsync(&r2, &w.aux->norm2[0], sizeof(double), hipMemcpyDeviceToHost, s));
         MXS_HIP(hipStreamSynchronize(s));
@@ -530,7 +531,8 @@ mxs_status cg_solve(const mxs_mat_s *A, const mxs_mat_s *A32, const double *b, d
         }
         if (outer >= o->max_outer) break;
         cg_state_init<<<1, 1, 0, s>>>(w.st32, o->inner_rtol, (long long)o->maxit);
-        ir_inner_start_kernel<<<g, kVNT, 0, s>>>(n, w.r, rn, w.r32, w.d32, w.p32, w.parts, w.st32);
+        ir_inner_start_kernel<<<g, kVNT, 0, s>>>(n, w.r, rn, w.r32, w.d32, w.p32, w.parts);
+        start_finish_kernel<<<1, kVNT, 0, s>>>(w.parts, g, w.st32);
         MXS_HIP(hipGetLastError());
         if (o->maxit > 0) {
             if ((e = run_loop<float>(A32, n, w.d32, w.r32, w.p32, w.q32, w.parts, w.st32,

@@ -49,22 +49,35 @@ struct CgState {
     long long maxit;
     int done;        // 1: every later CG kernel returns at entry
     int status;      // mxs_status of the solve
-    unsigned ticket; // last-block-done counter, reset by the last block
     int nonfinite;   // set when an input vector holds NaN or Inf
+    int pad;
 };
 
-// Where a fused dot product of an SpMV epilogue goes.
+// Where a fused dot product of an SpMV epilogue goes: one partial per
+// workgroup, then a finish kernel computes alpha = rho / (p.Ap) into st.
 struct DotSink {
-    double *partials; // one per workgroup
-    CgState *st;      // finisher state (alpha = rho / (p.Ap))
+    double *partials;
+    CgState *st;
 };
 
 // ---------------------------------------------------------------------------
 // The matrix handle
 // ---------------------------------------------------------------------------
 struct CsrPlan {
-    int32_t *blk_row = nullptr; // [nblk+1] first row of each row block
-    int64_t nblk = 0;
+    int32_t *tile_row = nullptr; // [ntiles+1] first row owned by each tile (sentinel nrows)
+    int32_t *tile_info = nullptr; // [ntiles] overflow length and carry flags
+    void *carry = nullptr;       // [2*ntiles] head / tail pieces of rows too long to finish
+    int64_t ntiles = 0;
+    bool fixup = false;          // some row reaches past its owner's overflow window
+};
+
+struct DiaPlan {
+    void *blk = nullptr;     // values re-laid out by row block: [block][diagonal][row in block]
+    int32_t *pos = nullptr;  // [ndiag] LDS position of each diagonal's x window start
+    int32_t *runs = nullptr; // [3*nruns] first offset, length, LDS base of each x window
+    int32_t nruns = 0;
+    int32_t lds_elems = 0;   // x-window LDS per block in elements (0: windows off)
+    int32_t first_off = 0, last_off = 0;
 };
 
 struct CooPlan {
@@ -89,6 +102,7 @@ struct mxs_mat_s {
     bool optimized = false;
     mxs::CsrPlan csr;
     mxs::CooPlan coo;
+    mxs::DiaPlan dia;
 };
 
 namespace mxs {
@@ -151,35 +165,17 @@ __device__ __forceinline__ double block_sum(double v, double *smem)
     return v;
 }
 
-// Last-workgroup-done reduction.  Thread 0 of each of `nparts` workgroups
-// publishes its partial at partials[part]; the workgroup that arrives last
-// sums all partials in index order (so the result does not depend on
-// arrival order), resets the ticket and returns true with the total in
-// *total (valid in thread 0).
+// Sum of n partials (one per workgroup of the producing kernel) in index
+// order, run by a single workgroup of NT threads; valid in thread 0.  The
+// producing kernel has finished (kernel boundary), so plain loads see every
+// partial: no device-scope fences are needed.
 template <int NT>
-__device__ bool last_block_total(double part, int64_t part_idx, int64_t nparts, double *partials,
-                                 unsigned *ticket, double *smem, double *total)
+__device__ __forceinline__ double reduce_partials(const double *__restrict__ partials, int64_t n,
+                                                  double *smem)
 {
-    __shared__ int am_last;
-    if (threadIdx.x == 0) {
-        partials[part_idx] = part;
-        __threadfence();
-        unsigned t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL,
-                                            __HIP_MEMORY_SCOPE_AGENT);
-        am_last = (t == (unsigned)(nparts - 1));
-    }
-    __syncthreads();
-    if (!am_last) return false;
-    __threadfence();
     double v = 0.0;
-    for (int64_t i = threadIdx.x; i < nparts; i += NT)
-        v += partials[i];
-    v = block_sum<NT>(v, smem);
-    if (threadIdx.x == 0) {
-        *total = v;
-        __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    return true;
+    for (int64_t i = threadIdx.x; i < n; i += NT) v += partials[i];
+    return block_sum<NT>(v, smem);
 }
 
 // Finisher of the fused p.Ap: one loop SpMV done; alpha = rho / sigma, or a
@@ -203,7 +199,7 @@ __device__ __forceinline__ void cg_finish_sigma(CgState *st, double sigma)
 
 // spmv.hip.  `done` (nullable) makes every workgroup return at entry when
 // *done != 0; `dot` (nullable, square A only) fuses sum_i y_i*x_i into the
-// epilogue and calls cg_finish_sigma on its total.
+// epilogue and launches the finish kernel that applies cg_finish_sigma.
 mxs_status spmv_launch(const mxs_mat_s *A, const void *x, void *y, const int *done,
                        const DotSink *dot, hipStream_t s);
 // p.Ap (n = nrows) reduced into `dot` as the COO path and the timed CG path do.
@@ -211,6 +207,8 @@ mxs_status dot_sigma_launch(int64_t n, mxs_dtype t, const void *a, const void *b
                             const DotSink *dot, hipStream_t s);
 // Number of per-workgroup partials the fused dot of spmv_launch writes.
 int64_t spmv_dot_parts(const mxs_mat_s *A);
+// Capacity of every partials array (workgroups of any reducing launch).
+constexpr int64_t kMaxParts = 16384;
 mxs_status build_plan(mxs_mat_s *A, hipStream_t s);
 
 // scan.hip

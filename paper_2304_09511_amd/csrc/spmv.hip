@@ -5,139 +5,308 @@
 // design goals are wide coalesced loads of the matrix arrays, x gathers that
 // hit in L2, deterministic reductions without floating-point atomics, and
 // enough bytes in flight per CU.  No MFMA: SpMV is not a dense contraction.
+//
+// Each workgroup issues all of its block's matrix loads back to back
+// (branch-free: lanes past a block's end re-read its last entry and are
+// masked), then the dependent x gathers, so every wave keeps many loads in
+// flight; concurrency across workgroups hides the LDS phases.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <utility>
+#include <vector>
 
 #include "common.h"
 
+// Tunables (compile-time).
+#ifndef MXS_CSR_IPT64
+#define MXS_CSR_IPT64 8
+#endif
+#ifndef MXS_CSR_IPT32
+#define MXS_CSR_IPT32 8
+#endif
+#ifndef MXS_DIA_WIN
+#define MXS_DIA_WIN 0 // 1: stage the x windows of interior DIA blocks in LDS
+#endif
+#ifndef MXS_DIA_BLOCKED
+#define MXS_DIA_BLOCKED 1 // keep a row-blocked copy of the DIA values in the plan
+#endif
+#ifndef MXS_DIA_RPT64
+#define MXS_DIA_RPT64 1
+#endif
+#ifndef MXS_DIA_RPT32
+#define MXS_DIA_RPT32 4
+#endif
+#ifndef MXS_DIA_DU
+#define MXS_DIA_DU 4
+#endif
+#ifndef MXS_STREAM_NT
+#define MXS_STREAM_NT 1 // non-temporal loads for matrix values read once per SpMV
+#endif
+#ifndef MXS_COO_IPT
+#define MXS_COO_IPT 4
+#endif
+#ifndef MXS_PERSIST
+#define MXS_PERSIST 0 // 1: at most one resident wave of workgroups, each over a run of blocks
+#endif
+
 namespace mxs {
 
+// Matrix values and indices are read once per SpMV; loading them with the
+// non-temporal hint keeps x (reused across rows) resident in L2.
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T *p)
+{
+#if MXS_STREAM_NT
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
+
+// Persistent grid: at most as many workgroups as are resident at once.
+template <typename K>
+static int64_t resident_workgroups(K kernel, int nt)
+{
+    static std::mutex mu;
+    static std::map<std::pair<const void *, int>, int64_t> cache;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(mu);
+    auto key = std::make_pair((const void *)kernel, dev);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, nt, 0) != hipSuccess)
+        per_cu = 4;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 256;
+    const int64_t r = std::max<int64_t>(1, (int64_t)std::max(per_cu, 1) * cus);
+    cache[key] = r;
+    return r;
+}
+
+// Workgroup count and blocks per workgroup for a persistent launch over
+// `nblk` blocks: the grid is a multiple of 8 (for the XCD remap) and at most
+// the resident capacity; workgroup g takes blocks [g*per, (g+1)*per).
+static void persistent_grid(int64_t nblk, int64_t resident, uint32_t *grid, int64_t *per)
+{
+    const int64_t cap = std::max<int64_t>(kNumXcd, resident / kNumXcd * kNumXcd);
+    int64_t g = std::min<int64_t>(pad_grid(std::max<int64_t>(nblk, 1)), cap);
+    *per = (std::max<int64_t>(nblk, 1) + g - 1) / g;
+    g = (std::max<int64_t>(nblk, 1) + *per - 1) / *per;
+    *grid = pad_grid(g);
+}
+
 // ===========================================================================
-// CSR (Algorithm 2): row blocks of bounded non-zero count, products staged in
-// LDS, rows reduced by lane groups sized to the block's row count.
+// CSR (Algorithm 2), split by non-zeros: tile t covers entries
+// [t*TILE, (t+1)*TILE) and owns the rows that start in it.  A workgroup
+// loads its tile's columns and values at once (no dependent descriptor
+// load in front of them), gathers x, stages the products in LDS and reduces
+// each owned row with a lane group sized to the tile's row count.  The last
+// owned row usually ends a few entries past the tile: the owner reads up to
+// EXT more entries and finishes it.  Rows reaching further (long rows) leave
+// a head / tail piece in a carry array that an ordered fix-up kernel adds.
 // ===========================================================================
 template <typename T>
 struct CsrCfg;
 template <>
 struct CsrCfg<double> {
-    static constexpr int NT = 256;     // threads per workgroup
-    static constexpr int BUCKET = 1024; // target non-zeros per row block
-    static constexpr int TMAX = 2048;  // LDS capacity (a block holds < 2*BUCKET)
-    static constexpr int RMAX = 256;   // rows per block at most
+    static constexpr int NT = 256;
+    static constexpr int IPT = MXS_CSR_IPT64;
+    static constexpr int TILE = NT * IPT;
+    static constexpr int EXT = NT;  // entries past the tile an owner may read
+    static constexpr int RMAX = 256; // owned rows whose pointers are staged in LDS
 };
 template <>
 struct CsrCfg<float> {
     static constexpr int NT = 256;
-    static constexpr int BUCKET = 2048;
-    static constexpr int TMAX = 4096;
+    static constexpr int IPT = MXS_CSR_IPT32;
+    static constexpr int TILE = NT * IPT;
+    static constexpr int EXT = NT;
     static constexpr int RMAX = 256;
 };
 
-// Row-block boundaries.  Row r starts a block when its first entry falls in
-// another BUCKET-sized slice of the entry range than row r-1's, when either
-// row is longer than BUCKET, or every RMAX rows.  Rows of one block then
-// start within one slice and none is long, so a block holds fewer than
-// 2*BUCKET entries; a long row is a block of its own.
-template <int BUCKET, int RMAX>
-__global__ void csr_block_flags(const int32_t *__restrict__ irp, int32_t nrows,
-                                int32_t *__restrict__ flag)
+// Per-tile flags of the plan.
+constexpr int kCsrHeadCarry = 1 << 16; // head piece goes to the carry array
+constexpr int kCsrLastCarry = 1 << 17; // last owned row reaches past EXT: tail piece carried
+
+// tile_row[t] = first row whose first entry is at position >= t*TILE
+// (lower bound over irp); tile_row[ntiles] = nrows.
+__global__ void csr_tile_rows_kernel(const int32_t *__restrict__ irp, int32_t nrows, int64_t ntiles,
+                                     int tile, int32_t *__restrict__ tile_row)
 {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nrows) return;
-    int f = 1;
-    if (r > 0) {
-        const int32_t a = irp[r - 1], b = irp[r], c = irp[r + 1];
-        f = (a / BUCKET != b / BUCKET) || (b - a > BUCKET) || (c - b > BUCKET) ||
-            (r % RMAX == 0);
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t > ntiles) return;
+    if (t == ntiles) {
+        tile_row[t] = nrows;
+        return;
     }
-    flag[r] = f;
+    const int64_t key = t * (int64_t)tile;
+    int64_t lo = 0, hi = (int64_t)nrows + 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) / 2;
+        if (irp[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    tile_row[t] = (int32_t)min(lo, (int64_t)nrows);
 }
 
-__global__ void csr_block_scatter(const int32_t *__restrict__ flag, const int32_t *__restrict__ pos,
-                                  int32_t nrows, int32_t *__restrict__ blk_row)
+// tile_info[t]: entries the owner reads past its tile (low 16 bits) and the
+// two carry flags; *any_carry is set when a fix-up pass is needed.
+__global__ void csr_tile_info_kernel(const int32_t *__restrict__ irp, const int32_t *__restrict__ tile_row,
+                                     int64_t nnz, int64_t ntiles, int tile, int ext,
+                                     int32_t *__restrict__ info, int *__restrict__ any_carry)
 {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < nrows && flag[r]) blk_row[pos[r]] = (int32_t)r;
-    if (r == 0) blk_row[pos[nrows]] = nrows;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles) return;
+    const int32_t r_lo = tile_row[t], r_hi = tile_row[t + 1];
+    const int64_t k0 = t * (int64_t)tile;
+    const int64_t tile_end = min(nnz, k0 + tile);
+    int32_t v = 0;
+    if (r_hi > r_lo) {
+        const int64_t over = (int64_t)irp[r_hi] - tile_end;
+        if (over > ext) v |= kCsrLastCarry;
+        else if (over > 0) v |= (int32_t)over;
+    }
+    if (r_lo > 0 && irp[r_lo] > k0) {
+        // head piece: the row that started before k0; its owner finished it
+        // unless it reaches more than ext entries past the owner's tile
+        const int64_t h_start = irp[r_lo - 1];
+        const int64_t owner_end = (h_start / tile + 1) * (int64_t)tile;
+        if ((int64_t)irp[r_lo] - owner_end > ext) v |= kCsrHeadCarry;
+    }
+    info[t] = v;
+    if (v & kCsrLastCarry) atomicOr(any_carry, 1);
 }
 
 template <typename T, bool DOT>
 __global__ __launch_bounds__(256) void csr_spmv_kernel(
     const int32_t *__restrict__ irp, const int32_t *__restrict__ aj, const T *__restrict__ av,
-    const T *__restrict__ x, T *__restrict__ y, const int32_t *__restrict__ blk_row,
-    int64_t nblk, int64_t per, const int *__restrict__ done, DotSink dot)
+    const T *__restrict__ x, T *__restrict__ y, const int32_t *__restrict__ tile_row,
+    const int32_t *__restrict__ tile_info, int64_t nnz, int64_t ntiles, int64_t per,
+    T *__restrict__ carry, const int *__restrict__ done, double *__restrict__ partials)
 {
     using C = CsrCfg<T>;
-    constexpr int NT = C::NT;
-    constexpr int U = C::TMAX / NT; // entries per thread when a block is full
-    __shared__ T prod[C::TMAX];
-    __shared__ int32_t lrp[C::RMAX + 1];
+    constexpr int NT = C::NT, IPT = C::IPT, TILE = C::TILE, EXT = C::EXT, RMAX = C::RMAX;
+    static_assert(EXT == NT, "one overflow entry per thread");
+    __shared__ T prod[TILE + EXT];
+    __shared__ int32_t lrp[RMAX + 1];
     __shared__ double red[NT / kWave];
     if (done && *done) return;
     const int tid = threadIdx.x;
     const int64_t g = xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t b_lo = g * per, b_hi = min(nblk, b_lo + per);
+    const int64_t t_lo = g * per, t_hi = min(ntiles, t_lo + per);
     double dpart = 0.0;
-    for (int64_t b = b_lo; b < b_hi; ++b) {
-        const int32_t r0 = blk_row[b], r1 = blk_row[b + 1];
-        const int32_t nr = r1 - r0;
-        const int32_t k0 = irp[r0], k1 = irp[r1];
-        const int32_t nk = k1 - k0;
-        if (nk > C::TMAX) {
-            // One long row: the whole workgroup strides over it.
-            T s = T(0);
-            for (int32_t k = k0 + tid; k < k1; k += NT) s += av[k] * x[aj[k]];
-            const double tot = block_sum<NT>((double)s, red);
-            if (tid == 0) {
-                const T v = (T)tot;
-                y[r0] = v;
-                if (DOT) dpart += (double)v * (double)x[r0];
-            }
-            __syncthreads();
-            continue;
-        }
-        for (int i = tid; i <= nr; i += NT) lrp[i] = irp[r0 + i] - k0;
+    for (int64_t tile = t_lo; tile < t_hi; ++tile) {
+        const int64_t k0 = tile * TILE;
+        const int32_t n = (int32_t)min((int64_t)TILE, nnz - k0);
+        const int32_t r_lo = tile_row[tile], r_hi = tile_row[tile + 1];
+        const int32_t info = tile_info[tile];
+        const int32_t nr = r_hi - r_lo;
+        const int32_t n_ext = info & 0xffff;
+        const bool head_carry = info & kCsrHeadCarry;
+        const bool last_carry = info & kCsrLastCarry;
+        // row pointers of the owned rows (clamped indices, always in range)
+        const int32_t lr = irp[r_lo + min(tid, nr)];
+        const int32_t lr_hi = irp[r_lo + min(tid + NT, nr)];
         {
-            int32_t col[U];
-            T val[U];
+            // all matrix loads unconditional (lanes past the end re-read the
+            // last entry, masked later) so they issue back to back
+            const int32_t *__restrict__ ajb = aj + k0;
+            const T *__restrict__ avb = av + k0;
+            int32_t col[IPT + 1];
+            T val[IPT + 1], xv[IPT + 1];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int32_t k = u * NT + tid;
-                col[u] = k < nk ? aj[k0 + k] : 0;
-                val[u] = k < nk ? av[k0 + k] : T(0);
-            }
+            for (int e = 0; e < IPT; ++e) col[e] = ld_stream(&ajb[(uint32_t)min(e * NT + tid, n - 1)]);
+            const uint32_t ke = (uint32_t)(n + min(tid, max(n_ext - 1, 0)));
+            col[IPT] = n_ext > 0 ? ld_stream(&ajb[ke]) : 0;
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int32_t k = u * NT + tid;
-                if (k < nk) prod[k] = val[u] * x[col[u]];
+            for (int e = 0; e < IPT; ++e) val[e] = ld_stream(&avb[(uint32_t)min(e * NT + tid, n - 1)]);
+            val[IPT] = n_ext > 0 ? ld_stream(&avb[ke]) : T(0);
+#pragma unroll
+            for (int e = 0; e <= IPT; ++e) xv[e] = x[(uint32_t)col[e]];
+#pragma unroll
+            for (int e = 0; e < IPT; ++e) {
+                const int j = e * NT + tid;
+                if (j < n) prod[j] = val[e] * xv[e];
             }
+            if (tid < n_ext) prod[n + tid] = val[IPT] * xv[IPT];
+        }
+        const bool staged = nr <= RMAX;
+        if (staged) {
+            if (tid <= nr) lrp[tid] = lr - (int32_t)k0;
+            if (tid + NT <= nr) lrp[tid + NT] = lr_hi - (int32_t)k0;
         }
         __syncthreads();
+        auto rp = [&](int r) -> int32_t { return staged ? lrp[r] : irp[r_lo + r] - (int32_t)k0; };
+        if (head_carry) {
+            // piece of a long row that began in an earlier tile
+            const int32_t hl = min(rp(0), n);
+            T hs = T(0);
+            for (int j = tid; j < hl; j += NT) hs += prod[j];
+            const double tot = block_sum<NT>((double)hs, red);
+            if (tid == 0) carry[2 * tile] = (T)tot;
+        }
         // Lane-group size: the largest power of two G <= 64 with G*nr <= NT.
         int G = 64;
         while (G > 1 && G * nr > NT) G >>= 1;
         const int lane = tid & (G - 1);
         const int ngrp = NT / G;
+        const int32_t lim = n + n_ext; // local end of the entries loaded
         for (int r = tid / G; r < nr; r += ngrp) {
-            T s = T(0);
-            const int e = lrp[r + 1];
-            for (int k = lrp[r] + lane; k < e; k += G) s += prod[k];
-            for (int off = G >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
+            T sum = T(0);
+            const int e = min(rp(r + 1), lim);
+            for (int k = rp(r) + lane; k < e; k += G) sum += prod[k];
+            for (int off = G >> 1; off > 0; off >>= 1) sum += __shfl_xor(sum, off, kWave);
             if (lane == 0) {
-                y[r0 + r] = s;
-                if (DOT) dpart += (double)s * (double)x[r0 + r];
+                if (last_carry && r == nr - 1) {
+                    carry[2 * tile + 1] = sum;
+                } else {
+                    y[r_lo + r] = sum;
+                    if (DOT) dpart += (double)sum * (double)x[r_lo + r];
+                }
             }
         }
         __syncthreads();
     }
     if (DOT) {
         const double bs = block_sum<NT>(dpart, red);
-        double tot;
-        if (last_block_total<NT>(bs, blockIdx.x, gridDim.x, dot.partials, &dot.st->ticket, red,
-                                 &tot) &&
-            tid == 0)
-            cg_finish_sigma(dot.st, tot);
+        if (tid == 0) partials[blockIdx.x] = bs;
+    }
+}
+
+// Rows too long for their owner's overflow window: owner's tail piece plus
+// the head pieces of the following tiles, in tile order.
+template <typename T, bool DOT>
+__global__ __launch_bounds__(256) void csr_fixup_kernel(
+    const int32_t *__restrict__ irp, const int32_t *__restrict__ tile_row,
+    const int32_t *__restrict__ tile_info, const T *__restrict__ carry, const T *__restrict__ x,
+    T *__restrict__ y, int64_t nnz, int64_t ntiles, int tile, const int *__restrict__ done,
+    double *__restrict__ partials)
+{
+    __shared__ double red[256 / kWave];
+    if (done && *done) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double d = 0.0;
+    if (t < ntiles && (tile_info[t] & kCsrLastCarry)) {
+        const int32_t r = tile_row[t + 1] - 1;
+        const int64_t end = irp[r + 1];
+        T v = carry[2 * t + 1];
+        for (int64_t u = t + 1; u < ntiles; ++u) {
+            v += carry[2 * u];
+            if (end <= min(nnz, (u + 1) * (int64_t)tile)) break;
+        }
+        y[r] = v;
+        if (DOT) d = (double)v * (double)x[r];
+    }
+    if (DOT) {
+        const double bs = block_sum<256>(d, red);
+        if (threadIdx.x == 0) partials[blockIdx.x] = bs;
     }
 }
 
@@ -151,53 +320,133 @@ template <typename T>
 struct DiaCfg;
 template <>
 struct DiaCfg<double> {
-    static constexpr int RPT = 4;
+    static constexpr int RPT = MXS_DIA_RPT64;
 };
 template <>
 struct DiaCfg<float> {
-    static constexpr int RPT = 8;
+    static constexpr int RPT = MXS_DIA_RPT32;
 };
 
+constexpr int kDiaStage = 256;  // diagonals whose offsets / window positions fit in LDS
+constexpr int kDiaMaxRuns = 64;  // x windows per block
+constexpr int kDiaWinMax = 6144; // x-window elements per block (48 KiB in FP64)
+constexpr int kDiaDU = MXS_DIA_DU; // diagonals whose loads are issued together
+
+// Interior blocks (every diagonal inside [0, ncols) for all of the block's
+// rows) stage x in LDS: sorted offsets that lie within a block height of
+// each other form one run, and run j needs x[row0 + f_j, row0 + f_j + len_j)
+// once per block, instead of one shifted load per diagonal.  Each diagonal
+// then reads its x values from LDS at its run position.  Other blocks load
+// x from global memory with per-row range checks.
+// Values come either diagonal-major (av[d*nrows + i], the container's
+// layout; `blocked` false) or row-blocked (av[(b*ndiag + d)*ROWS + i - row0],
+// the plan's copy; `blocked` true), where each block's diagonals are one
+// contiguous stream.
 template <typename T, bool DOT>
 __global__ __launch_bounds__(256) void dia_spmv_kernel(
     int32_t nrows, int32_t ncols, int32_t ndiag, const int32_t *__restrict__ doff,
-    const T *__restrict__ av, const T *__restrict__ x, T *__restrict__ y, int64_t nblk,
-    int64_t per, const int *__restrict__ done, DotSink dot)
+    const T *__restrict__ av, int blocked, const T *__restrict__ x, T *__restrict__ y, int64_t nblk,
+    int64_t per, const int *__restrict__ done, double *__restrict__ partials,
+    const int32_t *__restrict__ wpos, const int32_t *__restrict__ wruns, int32_t nruns,
+    int32_t wlen, int32_t first_off, int32_t last_off)
 {
     constexpr int NT = kDiaNT;
     constexpr int RPT = DiaCfg<T>::RPT;
     constexpr int ROWS = NT * RPT;
+    constexpr int DU = kDiaDU;
+    extern __shared__ __align__(16) unsigned char dia_dyn[];
+    T *xw = reinterpret_cast<T *>(dia_dyn);
+    __shared__ int32_t spos[kDiaStage]; // window position (or offset) of each diagonal
+    __shared__ int32_t srun[3 * kDiaMaxRuns];
     __shared__ double red[NT / kWave];
     if (done && *done) return;
     const int tid = threadIdx.x;
+    const bool win = wlen > 0; // implies ndiag <= kDiaStage and nruns <= kDiaMaxRuns
+    const bool staged = ndiag <= kDiaStage;
+    if (staged)
+        for (int i = tid; i < ndiag; i += NT) spos[i] = win ? wpos[i] : doff[i];
+    if (win)
+        for (int i = tid; i < 3 * nruns; i += NT) srun[i] = wruns[i];
+    __syncthreads();
     const int64_t g = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t b_lo = g * per, b_hi = min(nblk, b_lo + per);
     double dpart = 0.0;
     for (int64_t b = b_lo; b < b_hi; ++b) {
         const int64_t row0 = b * ROWS;
-        const bool rows_full = row0 + ROWS <= nrows;
         T sum[RPT];
 #pragma unroll
         for (int r = 0; r < RPT; ++r) sum[r] = T(0);
-        for (int d = 0; d < ndiag; ++d) {
-            const int64_t off = doff[d];
-            const T *__restrict__ a = av + (int64_t)d * nrows;
-            if (rows_full && row0 + off >= 0 && row0 + ROWS - 1 + off < ncols) {
+        // Offsets ascend, so all diagonals stay in range for the block's rows
+        // iff the first and the last one do.
+        const bool interior = staged && ndiag > 0 && row0 + ROWS <= nrows &&
+                              row0 + first_off >= 0 && row0 + ROWS - 1 + last_off < ncols;
+        // value of diagonal d for the block's local row li is a_blk[d*dstride + li]
+        const T *__restrict__ a_blk = blocked ? av + b * (int64_t)ndiag * ROWS : av + row0;
+        const int64_t dstride = blocked ? (int64_t)ROWS : (int64_t)nrows;
+        if (interior) {
+            if (win) {
+                // stage the x windows (loads unconditional: indices clamped)
+                for (int i0 = 0; i0 < wlen; i0 += 8 * NT) {
+                    T wv[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        const int e = min(i0 + q * NT + tid, wlen - 1);
+                        int j = 0;
+                        for (int k = 1; k < nruns; ++k) j = e >= srun[3 * k + 2] ? k : j;
+                        wv[q] = x[row0 + srun[3 * j] + (e - srun[3 * j + 2])];
+                    }
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        const int e = i0 + q * NT + tid;
+                        if (e < wlen) xw[e] = wv[q];
+                    }
+                }
+                __syncthreads();
+            }
+            const T *__restrict__ x_blk = x + row0;
+            int d = 0;
+            for (; d + DU <= ndiag; d += DU) {
+                T va[DU][RPT], vx[DU][RPT];
+#pragma unroll
+                for (int q = 0; q < DU; ++q) {
+                    const int32_t p = __builtin_amdgcn_readfirstlane(spos[d + q]);
+                    const T *__restrict__ a = a_blk + (int64_t)(d + q) * dstride;
+#pragma unroll
+                    for (int r = 0; r < RPT; ++r) {
+                        const uint32_t li = (uint32_t)(r * NT + tid);
+                        va[q][r] = ld_stream(&a[li]);
+                        vx[q][r] = win ? xw[p + li] : x_blk[(int64_t)p + li];
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < DU; ++q)
+#pragma unroll
+                    for (int r = 0; r < RPT; ++r) sum[r] += va[q][r] * vx[q][r];
+            }
+            for (; d < ndiag; ++d) {
+                const int32_t p = __builtin_amdgcn_readfirstlane(spos[d]);
+                const T *__restrict__ a = a_blk + (int64_t)d * dstride;
                 T va[RPT], vx[RPT];
 #pragma unroll
                 for (int r = 0; r < RPT; ++r) {
-                    const int64_t i = row0 + r * NT + tid;
-                    va[r] = a[i];
-                    vx[r] = x[i + off];
+                    const uint32_t li = (uint32_t)(r * NT + tid);
+                    va[r] = ld_stream(&a[li]);
+                    vx[r] = win ? xw[p + li] : x_blk[(int64_t)p + li];
                 }
 #pragma unroll
                 for (int r = 0; r < RPT; ++r) sum[r] += va[r] * vx[r];
-            } else {
+            }
+            if (win) __syncthreads(); // the next block overwrites the windows
+        } else {
+            // boundary blocks: per-row range checks, one diagonal at a time
+            for (int d = 0; d < ndiag; ++d) {
+                const int64_t off = doff[d];
+                const T *__restrict__ a = a_blk + (int64_t)d * dstride;
 #pragma unroll
                 for (int r = 0; r < RPT; ++r) {
-                    const int64_t i = row0 + r * NT + tid;
-                    const int64_t k = i + off;
-                    if (i < nrows && k >= 0 && k < ncols) sum[r] += a[i] * x[k];
+                    const int64_t li = r * NT + tid;
+                    const int64_t k = row0 + li + off;
+                    if (row0 + li < nrows && k >= 0 && k < ncols) sum[r] += ld_stream(&a[li]) * x[k];
                 }
             }
         }
@@ -212,11 +461,7 @@ __global__ __launch_bounds__(256) void dia_spmv_kernel(
     }
     if (DOT) {
         const double bs = block_sum<NT>(dpart, red);
-        double tot;
-        if (last_block_total<NT>(bs, blockIdx.x, gridDim.x, dot.partials, &dot.st->ticket, red,
-                                 &tot) &&
-            tid == 0)
-            cg_finish_sigma(dot.st, tot);
+        if (tid == 0) partials[blockIdx.x] = bs;
     }
 }
 
@@ -230,10 +475,10 @@ __global__ __launch_bounds__(256) void dia_spmv_kernel(
 // as 0 by the tile that sees the gap, so y needs no separate clearing.
 // ===========================================================================
 constexpr int kCooNT = 256;
-constexpr int kCooIPT = 8;
+constexpr int kCooIPT = MXS_COO_IPT;
 constexpr int kCooTile = kCooNT * kCooIPT;
 
-__device__ __forceinline__ int coo_pad(int j) { return j + (j >> 3); }
+__device__ __forceinline__ int coo_pad(int j) { return j + j / kCooIPT; }
 
 template <typename T>
 struct SegPair {
@@ -279,7 +524,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void coo_spmv_kernel(
     int64_t nnz, int32_t nrows, const int32_t *__restrict__ ai, const int32_t *__restrict__ aj,
     const T *__restrict__ av, const T *__restrict__ x, T *__restrict__ y, T *__restrict__ carry,
-    int64_t ntiles, const int *__restrict__ done)
+    int64_t ntiles, int64_t per, const int *__restrict__ done)
 {
     constexpr int NT = kCooNT, IPT = kCooIPT, TILE = kCooTile;
     constexpr int PADDED = TILE + TILE / IPT;
@@ -288,74 +533,84 @@ __global__ __launch_bounds__(256) void coo_spmv_kernel(
     __shared__ int sh[NT / kWave];
     __shared__ T sv[NT / kWave];
     if (done && *done) return;
-    const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
-    if (tile >= ntiles) return;
     const int tid = threadIdx.x;
-    const int64_t k0 = tile * TILE;
-    const int n = (int)min((int64_t)TILE, nnz - k0);
-    {
-        int32_t row[IPT], col[IPT];
-        T val[IPT];
+    const int64_t g = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t t_lo = g * per, t_hi = min(ntiles, t_lo + per);
+
+    for (int64_t tile = t_lo; tile < t_hi; ++tile) {
+        const int64_t k0 = tile * TILE;
+        const int n = (int)min((int64_t)TILE, nnz - k0);
+        {
+            // Unconditional loads (the last tile clamps to its final entry) so
+            // they issue back to back: rows, columns, values, then x gathers.
+            const int32_t *__restrict__ aib = ai + k0;
+            const int32_t *__restrict__ ajb = aj + k0;
+            const T *__restrict__ avb = av + k0;
+            int32_t row[IPT], col[IPT];
+            T val[IPT], xv[IPT];
 #pragma unroll
-        for (int e = 0; e < IPT; ++e) {
-            const int j = e * NT + tid;
-            row[e] = j < n ? ai[k0 + j] : 0;
-            col[e] = j < n ? aj[k0 + j] : 0;
-            val[e] = j < n ? av[k0 + j] : T(0);
-        }
+            for (int e = 0; e < IPT; ++e) col[e] = ld_stream(&ajb[(uint32_t)min(e * NT + tid, n - 1)]);
 #pragma unroll
-        for (int e = 0; e < IPT; ++e) {
-            const int j = e * NT + tid;
-            if (j < n) {
-                srow[coo_pad(j)] = row[e];
-                sval[coo_pad(j)] = val[e] * x[col[e]];
+            for (int e = 0; e < IPT; ++e) val[e] = ld_stream(&avb[(uint32_t)min(e * NT + tid, n - 1)]);
+#pragma unroll
+            for (int e = 0; e < IPT; ++e) row[e] = ld_stream(&aib[(uint32_t)min(e * NT + tid, n - 1)]);
+#pragma unroll
+            for (int e = 0; e < IPT; ++e) xv[e] = x[(uint32_t)col[e]];
+#pragma unroll
+            for (int e = 0; e < IPT; ++e) {
+                const int j = e * NT + tid;
+                if (j < n) {
+                    srow[coo_pad(j)] = row[e];
+                    sval[coo_pad(j)] = val[e] * xv[e];
+                }
             }
         }
-    }
-    const int32_t prev_row = k0 > 0 ? ai[k0 - 1] : -1;
-    const int32_t next_row = k0 + n < nnz ? ai[k0 + n] : -1;
-    __syncthreads();
-    const int32_t first_row = srow[0];
-    const bool tile_cont = prev_row == first_row; // first segment began in an earlier tile
-    const int b0 = tid * IPT, b1 = min(b0 + IPT, n);
-    // pass 1: this thread's run as a (head seen, tail sum) pair
-    SegPair<T> mine = {0, T(0)};
-    for (int j = b0; j < b1; ++j) {
-        const int32_t pr = j == 0 ? prev_row : srow[coo_pad(j - 1)];
-        if (srow[coo_pad(j)] != pr) {
-            mine.h = 1;
-            mine.v = T(0);
-        }
-        mine.v += sval[coo_pad(j)];
-    }
-    const SegPair<T> cin = block_seg_excl_scan<T, NT>(mine, sh, sv);
-    // pass 2: emit every segment that closes inside this run
-    T s = cin.v;
-    for (int j = b0; j < b1; ++j) {
-        const int32_t row = srow[coo_pad(j)];
-        const int32_t pr = j == 0 ? prev_row : srow[coo_pad(j - 1)];
-        if (row != pr) {
-            if (j > 0) {
-                if (tile_cont && pr == first_row) carry[2 * tile] = s;
-                else y[pr] = s;
+        const int32_t prev_row = k0 > 0 ? ai[k0 - 1] : -1;
+        const int32_t next_row = k0 + n < nnz ? ai[k0 + n] : -1;
+        __syncthreads();
+        const int32_t first_row = srow[0];
+        const bool tile_cont = prev_row == first_row; // first segment began in an earlier tile
+        const int b0 = tid * IPT, b1 = min(b0 + IPT, n);
+        // pass 1: this thread's run as a (head seen, tail sum) pair
+        SegPair<T> mine = {0, T(0)};
+        for (int j = b0; j < b1; ++j) {
+            const int32_t pr = j == 0 ? prev_row : srow[coo_pad(j - 1)];
+            if (srow[coo_pad(j)] != pr) {
+                mine.h = 1;
+                mine.v = T(0);
             }
-            for (int32_t z = pr + 1; z < row; ++z) y[z] = T(0); // rows without entries
-            s = T(0);
+            mine.v += sval[coo_pad(j)];
         }
-        s += sval[coo_pad(j)];
-    }
-    if (b0 < n && b1 == n) {
-        // the thread holding the tile's last entry closes or hands over its segment
-        const int32_t last = srow[coo_pad(n - 1)];
-        const bool is_cont = tile_cont && last == first_row;
-        if (next_row == last) {
-            carry[2 * tile + (is_cont ? 0 : 1)] = s;
-        } else {
-            if (is_cont) carry[2 * tile] = s;
-            else y[last] = s;
-            if (k0 + n == nnz)
-                for (int32_t z = last + 1; z < nrows; ++z) y[z] = T(0);
+        const SegPair<T> cin = block_seg_excl_scan<T, NT>(mine, sh, sv);
+        // pass 2: emit every segment that closes inside this run
+        T s = cin.v;
+        for (int j = b0; j < b1; ++j) {
+            const int32_t rw = srow[coo_pad(j)];
+            const int32_t pr = j == 0 ? prev_row : srow[coo_pad(j - 1)];
+            if (rw != pr) {
+                if (j > 0) {
+                    if (tile_cont && pr == first_row) carry[2 * tile] = s;
+                    else y[pr] = s;
+                }
+                for (int32_t z = pr + 1; z < rw; ++z) y[z] = T(0); // rows without entries
+                s = T(0);
+            }
+            s += sval[coo_pad(j)];
         }
+        if (b0 < n && b1 == n) {
+            // the thread holding the tile's last entry closes or hands over its segment
+            const int32_t last = srow[coo_pad(n - 1)];
+            const bool is_cont = tile_cont && last == first_row;
+            if (next_row == last) {
+                carry[2 * tile + (is_cont ? 0 : 1)] = s;
+            } else {
+                if (is_cont) carry[2 * tile] = s;
+                else y[last] = s;
+                if (k0 + n == nnz)
+                    for (int32_t z = last + 1; z < nrows; ++z) y[z] = T(0);
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -394,11 +649,12 @@ __global__ void fill_kernel(T *__restrict__ p, T v, int64_t n, const int *__rest
         p[i] = v;
 }
 
-// Fused p.Ap for COO (the COO kernel has no per-row epilogue of its own).
+// p.Ap for COO (whose kernel has no per-row epilogue) and for the timed CG.
 template <typename T>
-__global__ __launch_bounds__(256) void dot_sigma_kernel(int64_t n, const T *__restrict__ a,
-                                                        const T *__restrict__ b,
-                                                        const int *__restrict__ done, DotSink dot)
+__global__ __launch_bounds__(256) void dot_partials_kernel(int64_t n, const T *__restrict__ a,
+                                                           const T *__restrict__ b,
+                                                           const int *__restrict__ done,
+                                                           double *__restrict__ partials)
 {
     constexpr int NT = 256;
     __shared__ double red[NT / kWave];
@@ -407,17 +663,23 @@ __global__ __launch_bounds__(256) void dot_sigma_kernel(int64_t n, const T *__re
     for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
         s += (double)a[i] * (double)b[i];
     const double bs = block_sum<NT>(s, red);
-    double tot;
-    if (last_block_total<NT>(bs, blockIdx.x, gridDim.x, dot.partials, &dot.st->ticket, red,
-                             &tot) &&
-        threadIdx.x == 0)
-        cg_finish_sigma(dot.st, tot);
+    if (threadIdx.x == 0) partials[blockIdx.x] = bs;
+}
+
+// alpha = rho / (p.Ap) from the partials of the kernel that ran before.
+__global__ __launch_bounds__(256) void sigma_finish_kernel(const double *__restrict__ partials,
+                                                           int64_t nparts, CgState *st)
+{
+    __shared__ double red[256 / kWave];
+    if (st->done) return;
+    const double tot = reduce_partials<256>(partials, nparts, red);
+    if (threadIdx.x == 0) cg_finish_sigma(st, tot);
 }
 
 // ===========================================================================
-// Launch configuration
+// Launch configuration and plans
 // ===========================================================================
-constexpr int64_t kDotGrid = 2048; // workgroups (= partials) of a fused dot
+constexpr int64_t kDotGridMax = 2048; // workgroups of the plain p.Ap kernel
 
 static int64_t dia_blocks(const mxs_mat_s *A)
 {
@@ -426,64 +688,161 @@ static int64_t dia_blocks(const mxs_mat_s *A)
     return (A->nrows + rows - 1) / rows;
 }
 
-// Workgroup count and row blocks per workgroup for CSR/DIA.  Without a fused
-// dot every row block gets its own workgroup; with one the grid is capped so
-// the final reduction reads at most kDotGrid partials.
-static void grid_for(int64_t nblk, bool dot, uint32_t *grid, int64_t *per)
+static int csr_tile(mxs_dtype t) { return t == MXS_F64 ? CsrCfg<double>::TILE : CsrCfg<float>::TILE; }
+
+// One workgroup per block/tile.  A fused dot writes one partial per
+// workgroup, so its grid is capped (each workgroup then takes a contiguous
+// run of blocks) to leave room for the fix-up partials.
+template <typename T>
+static void spmv_grid(const mxs_mat_s *A, bool dot, uint32_t *grid, int64_t *per)
 {
-    int64_t g = nblk;
-    if (dot) g = std::min<int64_t>(nblk, kDotGrid);
-    g = std::max<int64_t>(g, 1);
-    *per = (nblk + g - 1) / g;
-    g = (nblk + *per - 1) / *per;
-    *grid = pad_grid(std::max<int64_t>(g, 1));
+    const int64_t nblk = A->fmt == MXS_CSR ? A->csr.ntiles
+                         : A->fmt == MXS_DIA ? dia_blocks(A) : A->coo.ntiles;
+#if MXS_PERSIST
+    int64_t cap = A->fmt == MXS_CSR ? resident_workgroups(csr_spmv_kernel<T, false>, 256)
+                  : A->fmt == MXS_DIA ? resident_workgroups(dia_spmv_kernel<T, false>, kDiaNT)
+                                      : resident_workgroups(coo_spmv_kernel<T>, kCooNT);
+#else
+    int64_t cap = INT64_MAX / 2;
+#endif
+    if (dot) cap = std::min<int64_t>(cap, kMaxParts / 2);
+    persistent_grid(nblk, cap, grid, per);
 }
+
+static uint32_t fixup_grid(int64_t ntiles) { return (uint32_t)std::max<int64_t>(1, (ntiles + 255) / 256); }
 
 int64_t spmv_dot_parts(const mxs_mat_s *A)
 {
-    if (A->fmt == MXS_COO) return kDotGrid;
-    const int64_t nblk = A->fmt == MXS_CSR ? A->csr.nblk : dia_blocks(A);
+    if (A->fmt == MXS_COO) return kDotGridMax;
     uint32_t grid;
     int64_t per;
-    grid_for(nblk, true, &grid, &per);
-    return grid;
+    if (A->dtype == MXS_F64) spmv_grid<double>(A, true, &grid, &per);
+    else spmv_grid<float>(A, true, &grid, &per);
+    int64_t n = grid;
+    if (A->fmt == MXS_CSR && A->csr.fixup) n += fixup_grid(A->csr.ntiles);
+    return n;
+}
+
+static mxs_status build_csr_plan(mxs_mat_s *A, hipStream_t s)
+{
+    const int tile = csr_tile(A->dtype);
+    const int64_t nt = (A->nnz + tile - 1) / tile;
+    A->csr.ntiles = nt;
+    if (nt == 0) return MXS_OK;
+    int32_t *buf = nullptr;
+    // tile_row [nt+1], tile_info [nt], then one flag
+    MXS_HIP(hipMalloc((void **)&buf, sizeof(int32_t) * (2 * (size_t)nt + 2)));
+    A->owned.push_back(buf);
+    int32_t *tile_row = buf, *info = buf + nt + 1;
+    int *flag = nullptr;
+    MXS_HIP(hipMallocAsync((void **)&flag, sizeof(int), s));
+    mxs_status st = fill_i32(flag, 0, 1, s);
+    if (st != MXS_OK) return st;
+    const uint32_t g = (uint32_t)((nt + 1 + 255) / 256);
+    const int ext = A->dtype == MXS_F64 ? CsrCfg<double>::EXT : CsrCfg<float>::EXT;
+    csr_tile_rows_kernel<<<g, 256, 0, s>>>(A->idx0, A->nrows, nt, tile, tile_row);
+    csr_tile_info_kernel<<<g, 256, 0, s>>>(A->idx0, tile_row, A->nnz, nt, tile, ext, info, flag);
+    MXS_HIP(hipGetLastError());
+    int any = 0;
+    MXS_HIP(hipMemcpyAsync(&any, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    MXS_HIP(hipFreeAsync(flag, s));
+    MXS_HIP(hipStreamSynchronize(s));
+    A->csr.tile_row = tile_row;
+    A->csr.tile_info = info;
+    A->csr.fixup = any != 0;
+    void *carry = nullptr;
+    MXS_HIP(hipMalloc(&carry, 2 * (size_t)nt * dsize(A->dtype)));
+    A->owned.push_back(carry);
+    A->csr.carry = carry;
+    return MXS_OK;
+}
+
+// Row-blocked copy: out[(b*nd + d)*R + r] = av[d*nrows + b*R + r] (0 past the last row).
+template <typename T>
+__global__ void dia_block_copy_kernel(const T *__restrict__ av, int32_t nrows, int32_t nd, int R,
+                                      int64_t elems, T *__restrict__ out)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < elems;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = e / ((int64_t)nd * R);
+        const int64_t rem = e - b * (int64_t)nd * R;
+        const int64_t d = rem / R, r = rem - d * R;
+        const int64_t row = b * R + r;
+        out[e] = row < nrows ? av[d * nrows + row] : T(0);
+    }
+}
+
+// x windows of interior DIA blocks (see dia_spmv_kernel).
+static mxs_status build_dia_plan(mxs_mat_s *A, hipStream_t s)
+{
+    const int nd = A->ndiag;
+    if (nd == 0) return MXS_OK;
+    std::vector<int32_t> off(nd);
+    MXS_HIP(hipMemcpyAsync(off.data(), A->idx0, sizeof(int32_t) * nd, hipMemcpyDeviceToHost, s));
+    MXS_HIP(hipStreamSynchronize(s));
+    A->dia.first_off = off[0];
+    A->dia.last_off = off[nd - 1];
+    const int R = kDiaNT * (A->dtype == MXS_F64 ? DiaCfg<double>::RPT : DiaCfg<float>::RPT);
+    std::vector<int32_t> runs, pos(nd);
+    int64_t total = 0;
+    int d0 = 0;
+    for (int d = 1; d <= nd; ++d) {
+        if (d == nd || (int64_t)off[d] - off[d - 1] > R) {
+            const int64_t len = (int64_t)off[d - 1] - off[d0] + R;
+            for (int q = d0; q < d; ++q) pos[q] = (int32_t)(total + off[q] - off[d0]);
+            runs.push_back(off[d0]);
+            runs.push_back((int32_t)len);
+            runs.push_back((int32_t)total);
+            total += len;
+            d0 = d;
+        }
+    }
+#if MXS_DIA_BLOCKED
+    if (dia_blocks(A) * R <= (int64_t)A->nrows + A->nrows / 8) { // padding stays small
+        const int64_t nb = dia_blocks(A);
+        const size_t elems = (size_t)nb * nd * R;
+        void *blk = nullptr;
+        MXS_HIP(hipMalloc(&blk, elems * dsize(A->dtype)));
+        A->owned.push_back(blk);
+        const uint32_t g = (uint32_t)std::min<int64_t>(((int64_t)elems + 255) / 256, 65536);
+        if (A->dtype == MXS_F64)
+            dia_block_copy_kernel<double><<<g, 256, 0, s>>>((const double *)A->vals, A->nrows, nd, R,
+                                                            (int64_t)elems, (double *)blk);
+        else
+            dia_block_copy_kernel<float><<<g, 256, 0, s>>>((const float *)A->vals, A->nrows, nd, R,
+                                                           (int64_t)elems, (float *)blk);
+        MXS_HIP(hipGetLastError());
+        A->dia.blk = blk;
+    }
+#endif
+    const int64_t nruns = (int64_t)runs.size() / 3;
+    // windows only when they fit and save at least a quarter of the x loads
+    const bool use = MXS_DIA_WIN && nd <= kDiaStage && nruns <= kDiaMaxRuns &&
+                     total <= kDiaWinMax && 4 * total <= 3 * (int64_t)nd * R;
+    if (!use) return MXS_OK;
+    int32_t *dev = nullptr;
+    MXS_HIP(hipMalloc((void **)&dev, sizeof(int32_t) * ((size_t)nd + runs.size())));
+    A->owned.push_back(dev);
+    MXS_HIP(hipMemcpyAsync(dev, pos.data(), sizeof(int32_t) * nd, hipMemcpyHostToDevice, s));
+    MXS_HIP(hipMemcpyAsync(dev + nd, runs.data(), sizeof(int32_t) * runs.size(),
+                           hipMemcpyHostToDevice, s));
+    MXS_HIP(hipStreamSynchronize(s));
+    A->dia.pos = dev;
+    A->dia.runs = dev + nd;
+    A->dia.nruns = (int32_t)nruns;
+    A->dia.lds_elems = (int32_t)total;
+    return MXS_OK;
 }
 
 mxs_status build_plan(mxs_mat_s *A, hipStream_t s)
 {
     if (A->optimized) return MXS_OK;
+    mxs_status st = MXS_OK;
     if (A->fmt == MXS_CSR) {
-        const int32_t n = A->nrows;
-        const bool f64 = A->dtype == MXS_F64;
-        int32_t *flag = nullptr, *pos = nullptr;
-        MXS_HIP(hipMallocAsync((void **)&flag, sizeof(int32_t) * (size_t)std::max(n, 1), s));
-        MXS_HIP(hipMallocAsync((void **)&pos, sizeof(int32_t) * ((size_t)n + 1), s));
-        const int nb = (int)((n + 255) / 256);
-        if (n > 0) {
-            if (f64)
-                csr_block_flags<CsrCfg<double>::BUCKET, CsrCfg<double>::RMAX>
-                    <<<nb, 256, 0, s>>>(A->idx0, n, flag);
-            else
-                csr_block_flags<CsrCfg<float>::BUCKET, CsrCfg<float>::RMAX>
-                    <<<nb, 256, 0, s>>>(A->idx0, n, flag);
-            MXS_HIP(hipGetLastError());
-        }
-        mxs_status st = scan_i32(flag, pos, n, s);
-        if (st != MXS_OK) return st;
-        int32_t nblk = 0;
-        MXS_HIP(hipMemcpyAsync(&nblk, pos + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        MXS_HIP(hipStreamSynchronize(s));
-        int32_t *blk = nullptr;
-        MXS_HIP(hipMalloc((void **)&blk, sizeof(int32_t) * ((size_t)nblk + 1)));
-        csr_block_scatter<<<std::max(nb, 1), 256, 0, s>>>(flag, pos, n, blk);
-        MXS_HIP(hipGetLastError());
-        MXS_HIP(hipFreeAsync(flag, s));
-        MXS_HIP(hipFreeAsync(pos, s));
-        MXS_HIP(hipStreamSynchronize(s));
-        A->csr.blk_row = blk;
-        A->csr.nblk = nblk;
-        A->owned.push_back(blk);
-    } else if (A->fmt == MXS_COO) {
+        st = build_csr_plan(A, s);
+    } else if (A->fmt == MXS_DIA) {
+        st = build_dia_plan(A, s);
+    } else {
         const int64_t nt = (A->nnz + kCooTile - 1) / kCooTile;
         void *carry = nullptr;
         if (nt > 0) {
@@ -493,79 +852,118 @@ mxs_status build_plan(mxs_mat_s *A, hipStream_t s)
         A->coo.carry = carry;
         A->coo.ntiles = nt;
     }
-    A->optimized = true;
-    return MXS_OK;
+    if (st == MXS_OK) A->optimized = true;
+    return st;
 }
 
-mxs_status dot_sigma_launch(int64_t n, mxs_dtype t, const void *a, const void *b, const int *done,
-                            const DotSink *dot, hipStream_t s);
-
 template <typename T>
-static mxs_status spmv_typed(const mxs_mat_s *A, const T *x, T *y, const int *done,
-                             const DotSink *dot, hipStream_t s)
+static mxs_status dot_sigma_typed(int64_t n, const T *a, const T *b, const int *done,
+                                  const DotSink *dot, hipStream_t s)
 {
-    const DotSink ds = dot ? *dot : DotSink{nullptr, nullptr};
-    if (A->nrows == 0) return MXS_OK;
-    switch (A->fmt) {
-    case MXS_CSR: {
-        const int64_t nblk = A->csr.nblk;
-        uint32_t grid;
-        int64_t per;
-        grid_for(nblk, dot != nullptr, &grid, &per);
-        if (dot)
-            csr_spmv_kernel<T, true><<<grid, 256, 0, s>>>(
-                A->idx0, A->idx1, (const T *)A->vals, x, y, A->csr.blk_row, nblk, per, done, ds);
-        else
-            csr_spmv_kernel<T, false><<<grid, 256, 0, s>>>(
-                A->idx0, A->idx1, (const T *)A->vals, x, y, A->csr.blk_row, nblk, per, done, ds);
-        return launch_status();
-    }
-    case MXS_DIA: {
-        const int64_t nblk = dia_blocks(A);
-        uint32_t grid;
-        int64_t per;
-        grid_for(nblk, dot != nullptr, &grid, &per);
-        if (dot)
-            dia_spmv_kernel<T, true><<<grid, kDiaNT, 0, s>>>(A->nrows, A->ncols, A->ndiag, A->idx0,
-                                                             (const T *)A->vals, x, y, nblk, per,
-                                                             done, ds);
-        else
-            dia_spmv_kernel<T, false><<<grid, kDiaNT, 0, s>>>(A->nrows, A->ncols, A->ndiag,
-                                                              A->idx0, (const T *)A->vals, x, y,
-                                                              nblk, per, done, ds);
-        return launch_status();
-    }
-    case MXS_COO: {
-        const int64_t nt = A->coo.ntiles;
-        if (nt == 0) {
-            fill_kernel<T><<<(uint32_t)std::min<int64_t>((A->nrows + 255) / 256, 4096), 256, 0, s>>>(
-                y, T(0), A->nrows, done);
-        } else {
-            coo_spmv_kernel<T><<<pad_grid(nt), kCooNT, 0, s>>>(
-                A->nnz, A->nrows, A->idx0, A->idx1, (const T *)A->vals, x, y, (T *)A->coo.carry,
-                nt, done);
-            MXS_HIP(hipGetLastError());
-            coo_fixup_kernel<T><<<(uint32_t)((nt + 255) / 256), 256, 0, s>>>(
-                A->nnz, A->idx0, (const T *)A->coo.carry, y, nt, done);
-        }
-        MXS_HIP(hipGetLastError());
-        if (dot) return dot_sigma_launch(A->nrows, A->dtype, x, y, done, dot, s);
-        return MXS_OK;
-    }
-    }
-    return MXS_ERR_UNSUPPORTED;
+    const uint32_t g = (uint32_t)std::clamp<int64_t>((n + 1023) / 1024, 1, kDotGridMax);
+    dot_partials_kernel<T><<<g, 256, 0, s>>>(n, a, b, done, dot->partials);
+    MXS_HIP(hipGetLastError());
+    sigma_finish_kernel<<<1, 256, 0, s>>>(dot->partials, g, dot->st);
+    return launch_status();
 }
 
 mxs_status dot_sigma_launch(int64_t n, mxs_dtype t, const void *a, const void *b, const int *done,
                             const DotSink *dot, hipStream_t s)
 {
     if (t == MXS_F64)
-        dot_sigma_kernel<double><<<(uint32_t)kDotGrid, 256, 0, s>>>(n, (const double *)a,
-                                                                    (const double *)b, done, *dot);
-    else
-        dot_sigma_kernel<float><<<(uint32_t)kDotGrid, 256, 0, s>>>(n, (const float *)a,
-                                                                  (const float *)b, done, *dot);
-    return launch_status();
+        return dot_sigma_typed<double>(n, (const double *)a, (const double *)b, done, dot, s);
+    return dot_sigma_typed<float>(n, (const float *)a, (const float *)b, done, dot, s);
+}
+
+template <typename T>
+static mxs_status spmv_typed(const mxs_mat_s *A, const T *x, T *y, const int *done,
+                             const DotSink *dot, hipStream_t s)
+{
+    if (A->nrows == 0) return MXS_OK;
+    uint32_t grid = 0;
+    int64_t per = 1;
+    double *parts = dot ? dot->partials : nullptr;
+    int64_t nparts = 0;
+    const uint32_t fill_g = (uint32_t)std::min<int64_t>((A->nrows + 255) / 256, 4096);
+    switch (A->fmt) {
+    case MXS_CSR: {
+        const int64_t nt = A->csr.ntiles;
+        if (nt == 0) {
+            fill_kernel<T><<<fill_g, 256, 0, s>>>(y, T(0), A->nrows, done);
+            MXS_HIP(hipGetLastError());
+            if (dot) return dot_sigma_typed<T>(A->nrows, x, y, done, dot, s);
+            return MXS_OK;
+        }
+        spmv_grid<T>(A, dot != nullptr, &grid, &per);
+        const int32_t *tr = A->csr.tile_row, *ti = A->csr.tile_info;
+        if (dot)
+            csr_spmv_kernel<T, true><<<grid, 256, 0, s>>>(A->idx0, A->idx1, (const T *)A->vals, x, y,
+                                                          tr, ti, A->nnz, nt, per,
+                                                          (T *)A->csr.carry, done, parts);
+        else
+            csr_spmv_kernel<T, false><<<grid, 256, 0, s>>>(A->idx0, A->idx1, (const T *)A->vals, x,
+                                                           y, tr, ti, A->nnz, nt, per,
+                                                           (T *)A->csr.carry, done, parts);
+        MXS_HIP(hipGetLastError());
+        nparts = grid;
+        if (A->csr.fixup) {
+            const uint32_t fg = fixup_grid(nt);
+            if (dot)
+                csr_fixup_kernel<T, true><<<fg, 256, 0, s>>>(A->idx0, tr, ti, (const T *)A->csr.carry,
+                                                             x, y, A->nnz, nt, csr_tile(A->dtype),
+                                                             done, parts + grid);
+            else
+                csr_fixup_kernel<T, false><<<fg, 256, 0, s>>>(A->idx0, tr, ti, (const T *)A->csr.carry,
+                                                              x, y, A->nnz, nt, csr_tile(A->dtype),
+                                                              done, nullptr);
+            MXS_HIP(hipGetLastError());
+            nparts += fg;
+        }
+        break;
+    }
+    case MXS_DIA: {
+        spmv_grid<T>(A, dot != nullptr, &grid, &per);
+        const DiaPlan &P = A->dia;
+        const size_t lds = sizeof(T) * (size_t)P.lds_elems;
+        const T *vals = P.blk ? (const T *)P.blk : (const T *)A->vals;
+        const int blocked = P.blk != nullptr;
+        if (dot)
+            dia_spmv_kernel<T, true><<<grid, kDiaNT, lds, s>>>(
+                A->nrows, A->ncols, A->ndiag, A->idx0, vals, blocked, x, y, dia_blocks(A), per,
+                done, parts, P.pos, P.runs, P.nruns, P.lds_elems, P.first_off, P.last_off);
+        else
+            dia_spmv_kernel<T, false><<<grid, kDiaNT, lds, s>>>(
+                A->nrows, A->ncols, A->ndiag, A->idx0, vals, blocked, x, y, dia_blocks(A), per,
+                done, parts, P.pos, P.runs, P.nruns, P.lds_elems, P.first_off, P.last_off);
+        MXS_HIP(hipGetLastError());
+        nparts = grid;
+        break;
+    }
+    case MXS_COO: {
+        const int64_t nt = A->coo.ntiles;
+        if (nt == 0) {
+            fill_kernel<T><<<fill_g, 256, 0, s>>>(y, T(0), A->nrows, done);
+        } else {
+            spmv_grid<T>(A, false, &grid, &per);
+            coo_spmv_kernel<T><<<grid, kCooNT, 0, s>>>(A->nnz, A->nrows, A->idx0, A->idx1,
+                                                       (const T *)A->vals, x, y, (T *)A->coo.carry,
+                                                       nt, per, done);
+            MXS_HIP(hipGetLastError());
+            coo_fixup_kernel<T><<<(uint32_t)((nt + 255) / 256), 256, 0, s>>>(
+                A->nnz, A->idx0, (const T *)A->coo.carry, y, nt, done);
+        }
+        MXS_HIP(hipGetLastError());
+        if (dot) return dot_sigma_typed<T>(A->nrows, x, y, done, dot, s);
+        return MXS_OK;
+    }
+    default:
+        return MXS_ERR_UNSUPPORTED;
+    }
+    if (dot) {
+        sigma_finish_kernel<<<1, 256, 0, s>>>(dot->partials, nparts, dot->st);
+        return launch_status();
+    }
+    return MXS_OK;
 }
 
 mxs_status spmv_launch(const mxs_mat_s *A, const void *x, void *y, const int *done,
