@@ -27,7 +27,7 @@
 #define MXS_CSR_IPT64 8
 #endif
 #ifndef MXS_CSR_IPT32
-#define MXS_CSR_IPT32 8
+#define MXS_CSR_IPT32 16
 #endif
 #ifndef MXS_DIA_WIN
 #define MXS_DIA_WIN 0 // 1: stage the x windows of interior DIA blocks in LDS
@@ -338,6 +338,14 @@ constexpr int kDiaDU = MXS_DIA_DU; // diagonals whose loads are issued together
 // once per block, instead of one shifted load per diagonal.  Each diagonal
 // then reads its x values from LDS at its run position.  Other blocks load
 // x from global memory with per-row range checks.
+// Offset of diagonal d for the boundary path (spos holds window positions
+// when windows are on, offsets otherwise).
+__device__ __forceinline__ int64_t spos_off(const int32_t *spos, const int32_t *, bool win,
+                                            const int32_t *__restrict__ doff, int d)
+{
+    return win ? (int64_t)doff[d] : (int64_t)spos[d];
+}
+
 // Values come either diagonal-major (av[d*nrows + i], the container's
 // layout; `blocked` false) or row-blocked (av[(b*ndiag + d)*ROWS + i - row0],
 // the plan's copy; `blocked` true), where each block's diagonals are one
@@ -438,16 +446,32 @@ __global__ __launch_bounds__(256) void dia_spmv_kernel(
             }
             if (win) __syncthreads(); // the next block overwrites the windows
         } else {
-            // boundary blocks: per-row range checks, one diagonal at a time
-            for (int d = 0; d < ndiag; ++d) {
-                const int64_t off = doff[d];
-                const T *__restrict__ a = a_blk + (int64_t)d * dstride;
+            // boundary blocks: same chunks, loads at clamped indices (always
+            // in range) and products masked by the row's range test
+            const int64_t lmax = min((int64_t)ROWS, (int64_t)nrows - row0) - 1;
+            int d = 0;
+            for (; d < ndiag; d += DU) {
+                T va[DU][RPT], vx[DU][RPT];
+                bool ok[DU][RPT];
 #pragma unroll
-                for (int r = 0; r < RPT; ++r) {
-                    const int64_t li = r * NT + tid;
-                    const int64_t k = row0 + li + off;
-                    if (row0 + li < nrows && k >= 0 && k < ncols) sum[r] += ld_stream(&a[li]) * x[k];
+                for (int q = 0; q < DU; ++q) {
+                    const int dq = min(d + q, ndiag - 1);
+                    const int64_t off = staged ? spos_off(spos, wpos, win, doff, dq) : doff[dq];
+                    const T *__restrict__ a = a_blk + (int64_t)dq * dstride;
+#pragma unroll
+                    for (int r = 0; r < RPT; ++r) {
+                        const int64_t li = r * NT + tid;
+                        const int64_t k = row0 + li + off;
+                        ok[q][r] = d + q < ndiag && li <= lmax && k >= 0 && k < ncols;
+                        va[q][r] = ld_stream(&a[min(li, lmax)]);
+                        vx[q][r] = x[min(max(k, (int64_t)0), (int64_t)ncols - 1)];
+                    }
                 }
+#pragma unroll
+                for (int q = 0; q < DU; ++q)
+#pragma unroll
+                    for (int r = 0; r < RPT; ++r)
+                        if (ok[q][r]) sum[r] += va[q][r] * vx[q][r];
             }
         }
 #pragma unroll

@@ -1,0 +1,339 @@
+"""Storage-format selection for SpMV.
+
+The paper's HPCG runs pick each process's format with a run-first auto-tuner
+(time every format, keep the fastest; Section VII-D, Table III) and name a
+dynamic selection mechanism as further work (Section IX).  This module
+provides both:
+
+* ``exhaustive_select`` -- the run-first tuner: time one SpMV in every
+  feasible format (median of repeats) and keep the fastest;
+* ``Selector`` -- an MLP 8-64-64-3 over eight matrix features
+  (``mxs.features``), trained and evaluated on the GPU by the library's own
+  kernels (``mlp_train_step``, ``mlp_predict``), with DIA masked out where the
+  container refuses it.  Without a model, selection falls back to the tuner.
+
+The dataset builder labels synthetic matrices (5 families, rows log-uniform
+in [1e4, 1e7]) by the tuner's timings; labels are written as JSON lines and
+the builder resumes an interrupted file.
+
+    python -m paper_2304_09511_amd.selector label --n 2000 --out labels.jsonl
+    python -m paper_2304_09511_amd.selector train --data labels.jsonl --out model.json
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+import numpy as np
+
+import paper_2304_09511_amd as mxs
+
+FAMILIES = ("stencil7", "stencil27", "banded", "zipf", "block")
+FORMATS = ("coo", "csr", "dia")
+TIE_ORDER = ("csr", "dia", "coo")  # equal medians: the general-purpose format first
+
+
+# ---------------------------------------------------------------------------
+# Run-first tuner
+# ---------------------------------------------------------------------------
+def time_spmv(A, x, y, reps=10, warm=3):
+    """Median time (ms) of one SpMV over `reps` individually timed calls."""
+    import torch
+    for _ in range(warm):
+        mxs.spmv(A, x, y)
+    ts = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        mxs.spmv(A, x, y)
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    return statistics.median(ts)
+
+
+def time_formats(A_coo, reps=10, warm=3, seed=1):
+    """Median SpMV time per format (inf where DIA is refused)."""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    dt = torch.float64 if A_coo.dtype == mxs.F64 else torch.float32
+    x = torch.rand(A_coo.ncols, generator=g, device="cuda", dtype=dt) * 2 - 1
+    y = torch.empty(A_coo.nrows, device="cuda", dtype=dt)
+    out = {}
+    for f in FORMATS:
+        if f == "coo":
+            B = A_coo
+        else:
+            try:
+                B = A_coo.convert(f)
+            except mxs.MxsError as e:
+                if e.status == -5:
+                    out[f] = math.inf
+                    continue
+                raise
+        B.optimize()
+        out[f] = time_spmv(B, x, y, reps, warm)
+        if B is not A_coo:
+            B.close()
+    return out
+
+
+def best_format(times):
+    m = min(times.values())
+    for f in TIE_ORDER:
+        if times[f] == m:
+            return f
+    return "csr"
+
+
+def exhaustive_select(A_coo, reps=10, warm=3):
+    """The run-first tuner: (fastest format, per-format times)."""
+    t = time_formats(A_coo, reps, warm)
+    return best_format(t), t
+
+
+# ---------------------------------------------------------------------------
+# Dataset
+# ---------------------------------------------------------------------------
+def matrix_spec(i, seed=4):
+    """Family, row count and seed of dataset matrix i (400 per family)."""
+    g = np.random.Generator(np.random.PCG64([seed, i]))
+    fam = FAMILIES[i % len(FAMILIES)]
+    rows = int(round(10 ** g.uniform(4.0, 7.0)))
+    spec = {"i": i, "family": fam, "seed": int(g.integers(1, 2 ** 31 - 1))}
+    if fam.startswith("stencil"):
+        spec["n"] = max(2, int(round(rows ** (1.0 / 3.0))))
+    elif fam == "block":
+        spec["nblockrows"] = max(1, rows // 8)
+    else:
+        spec["rows"] = rows
+        if fam == "banded":
+            spec["ndiag"] = int(g.integers(3, 65))
+    return spec
+
+
+def generate(spec, dtype=None):
+    """The matrix of a spec as a COO Matrix on the device."""
+    import torch
+
+    import workloads as wl
+    fam = spec["family"]
+    if fam == "stencil7":
+        nr, nc, ai, aj, av = wl.device_stencil(spec["n"], 7)
+    elif fam == "stencil27":
+        nr, nc, ai, aj, av = wl.device_stencil(spec["n"], 27)
+    elif fam == "banded":
+        nr, nc, ai, aj, av = wl.device_banded(spec["rows"], spec["ndiag"], 2000, spec["seed"])
+    elif fam == "zipf":
+        nr, nc, ai, aj, av = wl.device_zipf_rows(spec["rows"], spec["seed"])
+    else:
+        nr, nc, ai, aj, av = wl.device_block_random(spec["nblockrows"], spec["seed"])
+    if dtype is not None:
+        av = av.to(dtype)
+    A = mxs.Matrix.coo(nr, nc, ai, aj, av, borrow=True)
+    del ai, aj, av
+    return A
+
+
+def label_dataset(n, out, seed=4, reps=10, warm=3, log=sys.stderr):
+    """Appends one JSON line per matrix to `out`, skipping indices already
+    there (so an interrupted run resumes)."""
+    import torch
+    done = set()
+    if os.path.exists(out):
+        for line in open(out):
+            try:
+                done.add(json.loads(line)["i"])
+            except (ValueError, KeyError):
+                pass
+    t_start = time.time()
+    with open(out, "a") as fh:
+        for i in range(n):
+            if i in done:
+                continue
+            spec = matrix_spec(i, seed)
+            t0 = time.time()
+            A = generate(spec)
+            feats = mxs.features(A)
+            times = time_formats(A, reps, warm)
+            rec = dict(spec, nrows=A.nrows, nnz=A.nnz, features=feats.tolist(),
+                       times_ms={f: (None if math.isinf(v) else v) for f, v in times.items()},
+                       label=best_format(times))
+            A.close()
+            del A
+            torch.cuda.empty_cache()
+            fh.write(json.dumps(rec) + "\n")
+            fh.flush()
+            print(f"[label] {i} {spec['family']} rows={rec['nrows']} nnz={rec['nnz']} "
+                  f"-> {rec['label']} {rec['times_ms']} ({time.time() - t0:.2f}s, "
+                  f"total {time.time() - t_start:.0f}s)", file=log, flush=True)
+
+
+def load_dataset(path):
+    recs = [json.loads(line) for line in open(path) if line.strip()]
+    recs.sort(key=lambda r: r["i"])
+    F = np.array([r["features"] for r in recs], dtype=np.float64)
+    T = np.array([[math.inf if r["times_ms"][f] is None else r["times_ms"][f] for f in FORMATS]
+                  for r in recs], dtype=np.float64)
+    y = np.array([FORMATS.index(r["label"]) for r in recs], dtype=np.int32)
+    return recs, F, T, y
+
+
+def split(n, n_train, seed=4):
+    perm = np.random.Generator(np.random.PCG64(seed)).permutation(n)
+    return np.sort(perm[:n_train]), np.sort(perm[n_train:])
+
+
+def regret(T, choice):
+    """Mean of t(chosen)/min_f t(f) - 1 over the rows of T."""
+    best = T.min(axis=1)
+    return float(np.mean(T[np.arange(T.shape[0]), choice] / best - 1.0))
+
+
+# ---------------------------------------------------------------------------
+# The network
+# ---------------------------------------------------------------------------
+NI, NH, NO = 8, 64, 3
+
+
+def he_init(seed=6):
+    """He-normal weights (std sqrt(2/fan_in)), zero biases, in the layout of
+    mxs_mlp_forward: W1[8][64], b1, W2[64][64], b2, W3[64][3], b3."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    parts = [g.standard_normal(NI * NH) * math.sqrt(2.0 / NI), np.zeros(NH),
+             g.standard_normal(NH * NH) * math.sqrt(2.0 / NH), np.zeros(NH),
+             g.standard_normal(NH * NO) * math.sqrt(2.0 / NH), np.zeros(NO)]
+    w = np.concatenate(parts).astype(np.float32)
+    assert w.size == mxs.NPARAM
+    return w
+
+
+class Selector:
+    """MLP 8-64-64-3 format selector; parameters and normalisation live on
+    the device while training and predicting."""
+
+    def __init__(self, w=None, mu=None, sd=None):
+        self.w = None if w is None else np.asarray(w, np.float32)
+        self.mu = None if mu is None else np.asarray(mu, np.float32)
+        self.sd = None if sd is None else np.asarray(sd, np.float32)
+        self.loss_curve = []
+
+    def _dev(self, a, dt=None):
+        import torch
+        return torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dt) if dt else \
+            torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+    def fit(self, F, y, epochs=300, lr=1e-3, batch=128, seed=6):
+        import torch
+        raw = self._dev(F.astype(np.float64))
+        mu, sd = mxs.mlp_norm_stats(raw)
+        X = mxs.mlp_inputs(raw, mu, sd)
+        Y = self._dev(y.astype(np.int32))
+        w = self._dev(he_init(seed))
+        m = torch.zeros_like(w)
+        v = torch.zeros_like(w)
+        n = X.shape[0]
+        ws = mxs.mlp_workspace(min(batch, n))
+        order = np.random.Generator(np.random.PCG64(seed))
+        step = 0
+        for ep in range(epochs):
+            perm = torch.from_numpy(order.permutation(n)).cuda()
+            tot = torch.zeros(1, dtype=torch.float64, device="cuda")
+            for s0 in range(0, n, batch):
+                idx = perm[s0:s0 + batch]
+                Xb = X.index_select(0, idx).contiguous()
+                Yb = Y.index_select(0, idx).contiguous()
+                step += 1
+                loss = mxs.mlp_train_step(w, m, v, Xb, Yb, lr, step, workspace=ws)
+                tot += loss.double() * Xb.shape[0]
+            self.loss_curve.append(float(tot) / n)
+        self.w = w.cpu().numpy()
+        self.mu = mu.cpu().numpy()
+        self.sd = sd.cpu().numpy()
+        return self
+
+    def predict(self, F, feasible=None):
+        """Format index per row of F (raw features); feasible: bool [n][3]."""
+        import torch
+        raw = self._dev(np.atleast_2d(F).astype(np.float64))
+        X = mxs.mlp_inputs(raw, self._dev(self.mu), self._dev(self.sd))
+        fz = None if feasible is None else self._dev(np.asarray(feasible, np.uint8))
+        out = mxs.mlp_predict(self._dev(self.w), X, fz)
+        torch.cuda.synchronize()
+        return out.cpu().numpy()
+
+    def select(self, A):
+        """Format name for a Matrix (DIA masked when the container refuses it)."""
+        f = mxs.features(A)
+        feas = [True, True, dia_feasible(f)]
+        return FORMATS[int(self.predict(f[None, :], [feas])[0])]
+
+    def save(self, path):
+        json.dump({"layout": "W1[8][64] b1 W2[64][64] b2 W3[64][3] b3", "w": self.w.tolist(),
+                   "mu": self.mu.tolist(), "sd": self.sd.tolist(),
+                   "loss_curve": self.loss_curve}, open(path, "w"))
+
+    @classmethod
+    def load(cls, path):
+        d = json.load(open(path))
+        s = cls(d["w"], d["mu"], d["sd"])
+        s.loss_curve = d.get("loss_curve", [])
+        return s
+
+
+def dia_feasible(features):
+    """The container's refusal rule: ndiag * rows <= 8 * nnz."""
+    return features[5] * features[0] <= 8 * features[1]
+
+
+def select_format(A, model=None):
+    """The learned choice when a model is given, else the run-first tuner."""
+    if model is not None:
+        return model.select(A)
+    return exhaustive_select(A)[0]
+
+
+def evaluate(model, F, T):
+    """Accuracy, mean regret of the model and of always-CSR, on rows of F/T."""
+    feas = np.isfinite(T)
+    choice = model.predict(F, feas)
+    best = np.array([FORMATS.index(best_format(dict(zip(FORMATS, t)))) for t in T])
+    return {"n": int(F.shape[0]), "accuracy": float(np.mean(choice == best)),
+            "mean_regret": regret(T, choice), "always_csr_regret": regret(T, np.ones(len(T), int)),
+            "exhaustive_cost_x_one_spmv": 3.0}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    a = sub.add_parser("label")
+    a.add_argument("--n", type=int, default=2000)
+    a.add_argument("--out", required=True)
+    a.add_argument("--seed", type=int, default=4)
+    b = sub.add_parser("train")
+    b.add_argument("--data", required=True)
+    b.add_argument("--out", required=True)
+    b.add_argument("--epochs", type=int, default=300)
+    b.add_argument("--train", type=int, default=1500)
+    args = ap.parse_args(argv)
+    mxs.load()
+    if args.cmd == "label":
+        label_dataset(args.n, args.out, args.seed)
+    else:
+        recs, F, T, y = load_dataset(args.data)
+        tr, te = split(len(recs), min(args.train, len(recs) - 1))
+        model = Selector().fit(F[tr], y[tr], epochs=args.epochs)
+        model.save(args.out)
+        print(json.dumps({"train": evaluate(model, F[tr], T[tr]),
+                          "held_out": evaluate(model, F[te], T[te])}))
+
+
+if __name__ == "__main__":
+    main()

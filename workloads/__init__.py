@@ -271,3 +271,119 @@ def integer_vector(n: int, seed: int, lo: int = -8, hi: int = 8, dtype=np.float6
     """Integer-valued x in [lo, hi]: with integer matrices every partial sum is
     an exactly representable integer, so any summation order is exact."""
     return rng(seed).integers(lo, hi + 1, n).astype(dtype)
+
+
+# ---------------------------------------------------------------------------
+# Device-side generators (torch on the GPU) for the selector's large
+# synthetic dataset.  Same families and canonical order as above; values are
+# N(0,1) except the stencils.  Reproducible for a given seed and device.
+# ---------------------------------------------------------------------------
+def _tgen(seed, device):
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    return g
+
+
+def _sorted_unique_cols(torch, g, rows, ncols, device):
+    """Uniform columns, distinct within a row (duplicates redrawn), sorted by
+    (row, col).  rows: int64 row id per entry (non-decreasing)."""
+    n = rows.numel()
+    cols = torch.randint(0, ncols, (n,), generator=g, device=device, dtype=torch.int64)
+    while True:
+        key = rows * ncols + cols
+        key, order = torch.sort(key)
+        rows = key // ncols
+        cols = key % ncols
+        dup = torch.zeros(n, dtype=torch.bool, device=device)
+        if n > 1:
+            dup[1:] = key[1:] == key[:-1]
+        nd = int(dup.sum())
+        if nd == 0:
+            return rows, cols
+        cols[dup] = torch.randint(0, ncols, (nd,), generator=g, device=device, dtype=torch.int64)
+
+
+def device_stencil(n: int, points: int = 27, device="cuda", dtype=None):
+    """(nrows, ncols, ai, aj, av) of the n^3 stencil as device tensors."""
+    import torch
+    dtype = dtype or torch.float64
+    N = n ** 3
+    idx = torch.arange(N, device=device, dtype=torch.int64)
+    gx, gy, gz = idx % n, (idx // n) % n, idx // (n * n)
+    cols, valid, vals = [], [], []
+    diag = 26.0 if points == 27 else 6.0
+    for (dx, dy, dz) in _stencil_offsets(points):
+        ok = torch.ones(N, dtype=torch.bool, device=device)
+        for gcoord, d in ((gx, dx), (gy, dy), (gz, dz)):
+            if d < 0:
+                ok &= gcoord >= 1
+            elif d > 0:
+                ok &= gcoord <= n - 2
+        valid.append(ok)
+        cols.append(idx + dx + n * dy + n * n * dz)
+        vals.append(diag if (dx, dy, dz) == (0, 0, 0) else -1.0)
+    valid = torch.stack(valid, 1)
+    cols = torch.stack(cols, 1)
+    vals = torch.tensor(vals, dtype=dtype, device=device).expand(N, -1)
+    ai = idx[:, None].expand(-1, len(_stencil_offsets(points)))[valid]
+    return N, N, ai.to(torch.int32), cols[valid].to(torch.int32), vals[valid].contiguous()
+
+
+def device_banded(N: int, ndiag: int, max_offset: int, seed: int, device="cuda", dtype=None):
+    import torch
+    dtype = dtype or torch.float64
+    g0 = rng(seed)
+    m = min(max_offset, N - 1)
+    ndiag = min(ndiag, 2 * m + 1)
+    offs = np.sort(g0.choice(np.arange(-m, m + 1), size=ndiag, replace=False))
+    o = torch.from_numpy(offs.astype(np.int64)).to(device)
+    rows = torch.arange(N, device=device, dtype=torch.int64)[:, None]
+    cols = rows + o[None, :]
+    valid = (cols >= 0) & (cols < N)
+    ai = rows.expand(-1, ndiag)[valid]
+    aj = cols[valid]
+    g = _tgen(seed, device)
+    av = torch.randn(ai.numel(), generator=g, device=device, dtype=dtype)
+    return N, N, ai.to(torch.int32), aj.to(torch.int32), av
+
+
+def device_zipf_rows(N: int, seed: int, s: float = 2.0, mean: float = 16.0, cap: int = 5000,
+                     device="cuda", dtype=None):
+    import torch
+    dtype = dtype or torch.float64
+    cap = min(cap, N)
+    k, p = _zipf_pmf(s, cap)
+    c = zipf_scale(s, mean, cap)
+    cdf = torch.from_numpy(np.cumsum(p)).to(device)
+    cdf[-1] = 1.0
+    g = _tgen(seed, device)
+    u = torch.rand(N, generator=g, device=device, dtype=torch.float64)
+    kk = torch.searchsorted(cdf, u, right=True).clamp(0, cap - 1).to(torch.float64) + 1.0
+    L = torch.clamp(torch.floor(c * kk + torch.rand(N, generator=g, device=device,
+                                                      dtype=torch.float64)), max=cap)
+    L = L.to(torch.int64)
+    rows = torch.repeat_interleave(torch.arange(N, device=device, dtype=torch.int64), L)
+    rows, cols = _sorted_unique_cols(torch, g, rows, N, device)
+    av = torch.randn(rows.numel(), generator=g, device=device, dtype=dtype)
+    return N, N, rows.to(torch.int32), cols.to(torch.int32), av
+
+
+def device_block_random(nblockrows: int, seed: int, max_blocks: int = 8, bs: int = 8,
+                        device="cuda", dtype=None):
+    import torch
+    dtype = dtype or torch.float64
+    g = _tgen(seed, device)
+    nb = torch.randint(1, max_blocks + 1, (nblockrows,), generator=g, device=device)
+    nb = torch.clamp(nb, max=nblockrows)
+    br = torch.repeat_interleave(torch.arange(nblockrows, device=device, dtype=torch.int64), nb)
+    br, bc = _sorted_unique_cols(torch, g, br, nblockrows, device)
+    ii = torch.arange(bs, device=device, dtype=torch.int64)
+    rows = (br[:, None, None] * bs + ii[None, :, None]).expand(-1, bs, bs)
+    cols = (bc[:, None, None] * bs + ii[None, None, :]).expand(-1, bs, bs)
+    ncols = nblockrows * bs
+    key, _ = torch.sort((rows * ncols + cols).reshape(-1))
+    ai = (key // ncols).to(torch.int32)
+    aj = (key % ncols).to(torch.int32)
+    av = torch.randn(ai.numel(), generator=g, device=device, dtype=dtype)
+    return nblockrows * bs, ncols, ai, aj, av
