@@ -92,6 +92,7 @@ def _bind(lib):
         "orc_dot": (D, [I64, P, P]),
         "orc_cg": (C.c_int, [I64, I64, P, P, P, P, P, D, I64, P, P]),
         "orc_mixed_ir": (C.c_int, [I64, I64, P, P, P, P, P, D, D, I64, I64, P, P]),
+        "orc_mixed_ru": (C.c_int, [I64, I64, P, P, P, P, P, D, D, I64, P, P]),
         "orc_features": (None, [I64, I64, I64, P, P, P]),
         "orc_mlp_nparam": (I64, []),
         "orc_mlp_forward": (None, [P, P, I64, P]),
@@ -249,6 +250,18 @@ def mixed_ir(n, ai, aj, av, b, x0=None, tol=1e-10, inner_rtol=1e-4, inner_maxit=
     out = np.zeros(1, np.float64)
     st = _load().orc_mixed_ir(n, ai.shape[0], _p(ai), _p(aj), _p(av), _p(b), _p(x), tol,
                               inner_rtol, inner_maxit, max_outer, _p(counts), _p(out))
+    return int(st), x, int(counts[0]), int(counts[1]), float(out[0])
+
+
+def mixed_ru(n, ai, aj, av, b, x0=None, tol=1e-10, delta=0.1, maxit=10000):
+    """FP32 CG with FP64 reliable updates (residual replacement).
+    Returns (status, x, updates, iters, true_rel_resid)."""
+    ai, aj, av, b = _i32(ai), _i32(aj), _f64(av), _f64(b)
+    x = np.zeros(n, np.float64) if x0 is None else _f64(x0).copy()
+    counts = np.zeros(2, np.int64)
+    out = np.zeros(1, np.float64)
+    st = _load().orc_mixed_ru(n, ai.shape[0], _p(ai), _p(aj), _p(av), _p(b), _p(x), tol, delta,
+                              maxit, _p(counts), _p(out))
     return int(st), x, int(counts[0]), int(counts[1]), float(out[0])
 
 

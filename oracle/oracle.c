@@ -484,6 +484,114 @@ int orc_mixed_ir(int64_t n, int64_t nnz, const int32_t *ai, const int32_t *aj,
     return status;
 }
 
+/* Mixed-precision CG with reliable updates (van der Vorst and Ye's residual
+ * replacement, used for mixed precision by Clark et al.): one CG recurrence
+ * runs in FP32 (SpMV with fp32(A), FP32 vectors, dot products accumulated
+ * in FP64) and accumulates its correction in an FP32 vector d.  After each
+ * iteration, when the recursive residual norm has dropped to delta times the
+ * largest residual norm since the last update, or to the stopping threshold
+ * tol*||b||, the update is made: x += fp64(d), d = 0, the residual is
+ * recomputed as b - A x in FP64 and replaces the FP32 one, and the largest
+ * norm restarts from it.  The search direction is kept.  The solve stops when
+ * the recomputed residual meets ||b - A x|| <= tol*||b||.
+ * counts[0] = updates, counts[1] = iterations; out[0] = ||b - A x||/||b||
+ * of the returned x. */
+int orc_mixed_ru(int64_t n, int64_t nnz, const int32_t *ai, const int32_t *aj,
+                 const double *av, const double *b, double *x, double tol, double delta,
+                 int64_t maxit, int64_t *counts, double *out)
+{
+    counts[0] = counts[1] = 0;
+    out[0] = 0.0;
+    if (!all_finite(n, b) || !all_finite(n, x))
+        return ORC_NONFINITE;
+    size_t nb = (size_t)(n ? n : 1);
+    float *av32 = (float *)malloc((size_t)(nnz ? nnz : 1) * sizeof(float));
+    for (int64_t k = 0; k < nnz; ++k)
+        av32[k] = (float)av[k];
+    double *r = (double *)malloc(nb * sizeof(double));
+    float *r32 = (float *)malloc(nb * sizeof(float));
+    float *d = (float *)malloc(nb * sizeof(float));
+    float *p = (float *)malloc(nb * sizeof(float));
+    float *q = (float *)malloc(nb * sizeof(float));
+    double bn = sqrt(dot(n, b, b));
+    double thresh = tol * bn;
+    int status = ORC_NOT_CONVERGED;
+
+    /* true residual, and the FP32 recurrence started from it */
+    orc_coo_spmv(n, nnz, ai, aj, av, x, r);
+    for (int64_t i = 0; i < n; ++i)
+        r[i] = b[i] - r[i];
+    double rn = sqrt(dot(n, r, r));
+    out[0] = bn > 0.0 ? rn / bn : rn;
+    if (rn <= thresh) {
+        status = ORC_OK;
+        goto done;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        r32[i] = (float)r[i];
+        p[i] = r32[i];
+        d[i] = 0.0f;
+    }
+    double rho = dot_f32(n, r32, r32);
+    double rmax = sqrt(rho);
+    for (int64_t k = 1; k <= maxit; ++k) {
+        orc_coo_spmv_f32(n, nnz, ai, aj, av32, p, q);
+        double sigma = dot_f32(n, p, q);
+        counts[1] = k;
+        if (!(sigma > 0.0) || !isfinite(sigma)) {
+            status = ORC_BREAKDOWN;
+            break;
+        }
+        float alpha = (float)(rho / sigma);
+        for (int64_t i = 0; i < n; ++i)
+            d[i] += alpha * p[i];
+        for (int64_t i = 0; i < n; ++i)
+            r32[i] -= alpha * q[i];
+        double rho_new = dot_f32(n, r32, r32);
+        double rn32 = sqrt(rho_new);
+        if (rn32 <= delta * rmax || rn32 <= thresh) {
+            /* reliable update */
+            for (int64_t i = 0; i < n; ++i) {
+                x[i] += (double)d[i];
+                d[i] = 0.0f;
+            }
+            counts[0]++;
+            orc_coo_spmv(n, nnz, ai, aj, av, x, r);
+            for (int64_t i = 0; i < n; ++i)
+                r[i] = b[i] - r[i];
+            rn = sqrt(dot(n, r, r));
+            out[0] = bn > 0.0 ? rn / bn : rn;
+            if (rn <= thresh) {
+                status = ORC_OK;
+                break;
+            }
+            for (int64_t i = 0; i < n; ++i)
+                r32[i] = (float)r[i];
+            rho_new = dot_f32(n, r32, r32);
+            rmax = sqrt(rho_new);
+        } else if (rn32 > rmax) {
+            rmax = rn32;
+        }
+        float beta = (float)(rho_new / rho);
+        for (int64_t i = 0; i < n; ++i)
+            p[i] = r32[i] + beta * p[i];
+        rho = rho_new;
+    }
+    if (status != ORC_OK) {
+        /* fold in the correction not yet applied and report its residual */
+        for (int64_t i = 0; i < n; ++i)
+            x[i] += (double)d[i];
+        orc_coo_spmv(n, nnz, ai, aj, av, x, r);
+        for (int64_t i = 0; i < n; ++i)
+            r[i] = b[i] - r[i];
+        rn = sqrt(dot(n, r, r));
+        out[0] = bn > 0.0 ? rn / bn : rn;
+    }
+done:
+    free(av32); free(r); free(r32); free(d); free(p); free(q);
+    return status;
+}
+
 /* ======================================================================
  * Format-selector features (an addition to the paper: its auto-tuners pick
  * a format per matrix, Sections VII-D and IX)

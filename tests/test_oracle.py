@@ -336,6 +336,65 @@ def test_mixed_refinement_on_spd_matches_solve():
 
 
 # --------------------------------------------------------------------------
+# Mixed CG with reliable updates
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n,delta", [(5, 0.1), (16, 0.1), (16, 1e-3), (24, 0.5)])
+def test_reliable_update_reaches_fp64_residual(n, delta):
+    """FP32 recurrences with FP64 residual replacement reach a residual FP32
+    alone cannot, within a small multiple of the FP64 CG iteration bound."""
+    a = wl.stencil(n)
+    N = a.nrows
+    b = 27.0 - stencil_rowcount(n).astype(np.float64)
+    tol = 1e-10
+    st, x, upd, it, true_rel = orc.mixed_ru(N, a.ai, a.aj, a.av, b, tol=tol, delta=delta)
+    lam = stencil_spectrum(n)
+    kappa = lam.max() / lam.min()
+    bound = math.ceil(0.5 * math.sqrt(kappa) * math.log(2 * math.sqrt(kappa) / tol))
+    assert st == orc.OK and upd >= 1 and 1 <= it <= 1.5 * bound
+    import scipy.sparse as sp
+    A = sp.csr_matrix((a.av, (a.ai, a.aj)), shape=(N, N))
+    r = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
+    assert r <= tol and abs(r - true_rel) <= 1e-3 * tol
+    assert np.max(np.abs(x - 1.0)) <= kappa * tol * 10
+
+
+def test_reliable_update_on_spd_matches_solve():
+    a, A = spd(20, 8)
+    b = wl.uniform_vector(20, seed=4)
+    st, x, upd, it, true_rel = orc.mixed_ru(20, a.ai, a.aj, a.av, b, tol=1e-12, delta=0.1)
+    assert st == orc.OK and upd >= 2  # FP32 alone cannot reach 1e-12
+    xs = np.linalg.solve(A, b)
+    assert np.max(np.abs(x - xs)) <= 1e-10 * np.max(np.abs(xs))
+
+
+def test_reliable_update_first_iterate():
+    """One iteration without an update: x1 = (r.r / r.Ar) r in FP32."""
+    a, A = spd(12, 5)
+    b = wl.uniform_vector(12, seed=7)
+    st, x, upd, it, _ = orc.mixed_ru(12, a.ai, a.aj, a.av, b, tol=1e-30, delta=1e-30, maxit=1)
+    assert st == orc.NOT_CONVERGED and upd == 0 and it == 1
+    x1 = (b @ b) / (b @ A @ b) * b
+    assert np.max(np.abs(x - x1)) <= 1e-6 * np.max(np.abs(x1))
+
+
+def test_reliable_update_statuses():
+    a, A = spd(6, 1)
+    z = np.zeros(6)
+    st, x, upd, it, _ = orc.mixed_ru(6, a.ai, a.aj, a.av, z)
+    assert st == orc.OK and it == 0 and upd == 0 and not x.any()
+    bad = z.copy()
+    bad[2] = np.inf
+    assert orc.mixed_ru(6, a.ai, a.aj, a.av, bad)[0] == orc.NONFINITE
+    ind = wl.Coo(2, 2, np.array([0, 1], np.int32), np.array([0, 1], np.int32), np.array([1.0, -1.0]))
+    assert orc.mixed_ru(2, ind.ai, ind.aj, ind.av, np.ones(2))[0] == orc.BREAKDOWN
+    b = wl.uniform_vector(6, 1)
+    st, x, upd, it, true_rel = orc.mixed_ru(6, a.ai, a.aj, a.av, b, tol=1e-30, maxit=3)
+    assert st == orc.NOT_CONVERGED and it == 3
+    # the reported residual is that of the returned x (pending correction folded in)
+    assert true_rel == pytest.approx(np.linalg.norm(b - A @ x) / np.linalg.norm(b), rel=1e-6)
+
+
+# --------------------------------------------------------------------------
 # Features
 # --------------------------------------------------------------------------
 @pytest.mark.parametrize("n", [3, 5, 16])

@@ -58,6 +58,18 @@ MUTANTS = [
      "x[i] += rn * (double)d[i];",
      "x[i] += (double)d[i];",
      [lambda: pins.test_mixed_refinement_reaches_fp64_residual(8)]),
+    ("ru_update_drops_correction",
+     "                x[i] += (double)d[i];\n                d[i] = 0.0f;",
+     "                x[i] += 0.0 * (double)d[i];\n                d[i] = 0.0f;",
+     [lambda: pins.test_reliable_update_reaches_fp64_residual(5, 0.1)]),
+    ("ru_keeps_fp32_residual",
+     "            for (int64_t i = 0; i < n; ++i)\n                r32[i] = (float)r[i];\n            rho_new",
+     "            for (int64_t i = 0; i < n; ++i)\n                r32[i] = r32[i];\n            rho_new",
+     [pins.test_reliable_update_on_spd_matches_solve]),
+    ("ru_alpha_inverted",
+     "            break;\n        }\n        float alpha = (float)(rho / sigma);",
+     "            break;\n        }\n        float alpha = (float)(sigma / rho);",
+     [pins.test_reliable_update_first_iterate]),
     ("features_variance_not_normalised",
      "var = nrows ? var / (double)nrows : 0.0;",
      "var = var;",
