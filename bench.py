@@ -130,12 +130,25 @@ def cg_runs(torch, mxs, mats, rtol, label):
     return res, bn
 
 
+MIXED_VARIANTS = (("fp64", {}),
+                  ("ir_inner1e-4", dict(mixed="ir", inner_rtol=1e-4, max_outer=20)),
+                  ("ir_inner1e-5", dict(mixed="ir", inner_rtol=1e-5, max_outer=20)),
+                  ("ir_inner1e-6", dict(mixed="ir", inner_rtol=1e-6, max_outer=20)),
+                  ("ru_delta0.1", dict(mixed="ru", delta=0.1)),
+                  ("ru_delta0.01", dict(mixed="ru", delta=0.01)))
+
+
 def mixed_vs_fp64(torch, mxs, n, fmts=("dia", "csr")):
+    """FP64 CG against the two mixed-precision solvers (iterative refinement
+    with an FP32 inner CG; FP32 CG with FP64 reliable updates) to 1e-10, each
+    timed to tolerance after one warm-up solve, with the solution's error
+    against the oracle's stored FP64 solution at sampled rows."""
     mats = build_matrices(mxs, n)
     out = {"workload": f"27-point stencil {n}^3 ({mats['csr'].nrows} rows, {mats['csr'].nnz} nnz), "
-                       f"b = A*1, x0 = 0, tol 1e-10 on ||b - A x|| / ||b||"}
+                       f"b = A*1, x0 = 0, tol 1e-10 on ||b - A x|| / ||b|| (FP64 CG: recursive)"}
     ones = torch.ones(mats["csr"].nrows, dtype=torch.float64, device="cuda")
     b = mxs.spmv(mats["csr"], ones)
+    gold = {"fp64": load_golden(f"cg_stencil{n}_tol1e-10"), "ir": load_golden(f"mixed_stencil{n}_tol1e-10")}
     for fmt in fmts:
         A = mats[fmt]
         A32 = A.cast(mxs.F32)
@@ -143,10 +156,10 @@ def mixed_vs_fp64(torch, mxs, n, fmts=("dia", "csr")):
         ws64 = mxs.cg_workspace(A)
         wsm = mxs.cg_workspace(A, mixed=True)
         rows = {}
-        for mode in ("fp64", "mixed"):
-            kw = dict(rtol=1e-10, maxit=20000)
-            if mode == "mixed":
-                kw.update(mixed=True, A32=A32, inner_rtol=1e-4, max_outer=20, workspace=wsm)
+        for name, kw in MIXED_VARIANTS:
+            kw = dict(kw, rtol=1e-10, maxit=20000)
+            if kw.get("mixed"):
+                kw.update(A32=A32, workspace=wsm)
             else:
                 kw.update(workspace=ws64)
             mxs.cg_solve(A, b, **kw)  # warm-up
@@ -155,17 +168,29 @@ def mixed_vs_fp64(torch, mxs, n, fmts=("dia", "csr")):
             st, x, r = mxs.cg_solve(A, b, **kw)
             torch.cuda.synchronize()
             t = (time.perf_counter() - t0) * 1e3
-            rows[mode] = {"status": st, "time_to_tol_ms": round(t, 3), "iters": r["iters"],
-                          "outer_iters": r["outer_iters"], "true_rel_resid": r["true_rel_resid"],
-                          "max_abs_err_vs_ones": float((x - 1.0).abs().max())}
-            rows[mode + "_x"] = x
-        rows["max_abs_diff_mixed_vs_fp64"] = float((rows.pop("mixed_x") - rows.pop("fp64_x")).abs().max())
-        rows["speedup_mixed_over_fp64"] = round(rows["fp64"]["time_to_tol_ms"] / rows["mixed"]["time_to_tol_ms"], 3)
+            rec = {"status": st, "time_to_tol_ms": round(t, 3), "iters": r["iters"],
+                   "outer_iters": r["outer_iters"], "true_rel_resid": r["true_rel_resid"],
+                   "max_abs_err_vs_ones": float((x - 1.0).abs().max())}
+            g = gold["fp64"]
+            if g is not None:
+                idx = torch.tensor(g["sample_idx"], dtype=torch.int64, device="cuda")
+                xo = torch.tensor(g["x_sample"], dtype=torch.float64, device="cuda")
+                rec["max_rel_err_vs_oracle_fp64_x_sampled"] = float((x[idx] - xo).abs().max() / xo.abs().max())
+            rows[name] = rec
+        fp = rows["fp64"]["time_to_tol_ms"]
+        for name in rows:
+            rows[name]["speedup_over_fp64"] = round(fp / rows[name]["time_to_tol_ms"], 3)
+        best = max((k for k in rows if k != "fp64" and rows[k]["status"] == 0),
+                   key=lambda k: rows[k]["speedup_over_fp64"], default=None)
+        rows["best_mixed"] = best
         out[fmt] = rows
-        log(f"[bench] {n}^3 {fmt}: fp64 {rows['fp64']['time_to_tol_ms']:.1f} ms ({rows['fp64']['iters']} it), "
-            f"mixed {rows['mixed']['time_to_tol_ms']:.1f} ms ({rows['mixed']['outer_iters']} outer, "
-            f"{rows['mixed']['iters']} inner), speedup {rows['speedup_mixed_over_fp64']}")
+        log(f"[bench] {n}^3 {fmt}: " + ", ".join(
+            f"{k} {v['time_to_tol_ms']:.1f} ms ({v['iters']} it)" for k, v in rows.items() if isinstance(v, dict)))
         A32.close()
+    out["oracle"] = {k: (None if g is None else {kk: g.get(kk) for kk in ("iters", "outer_iters", "inner_iters",
+                                                                          "true_rel_resid", "inner_rtol")})
+                     for k, g in gold.items()}
+    out["oracle"]["source"] = "tests/golden/*.json (tests/golden/make_golden.py, oracle only)"
     for A in mats.values():
         A.close()
     return out
@@ -201,6 +226,113 @@ def cpu_baseline(orc, coo_host, nbytes, budget_s=12.0):
             "host_cores_available": cores, "host_cpu": model}
 
 
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def load_golden(name):
+    path = os.path.join(GOLDEN, name + ".json")
+    return json.load(open(path)) if os.path.exists(path) else None
+
+
+def compare_golden(section, name, x_by_fmt=None):
+    """Adds the oracle's stored iteration count (written by
+    tests/golden/make_golden.py) beside the GPU's."""
+    g = load_golden(name)
+    if g is None:
+        section["oracle"] = None
+        return None
+    section["oracle"] = {"iters": g.get("iters"), "outer_iters": g.get("outer_iters"),
+                         "inner_iters": g.get("inner_iters"), "true_rel_resid": g["true_rel_resid"],
+                         "source": f"tests/golden/{name}.json"}
+    return g
+
+
+def irregular_runs(torch, mxs, checks):
+    """SpMV on the two irregular 4,000,000-row workloads in every format the
+    container accepts: protocol median of 10 x 100 calls, GB/s, GFLOP/s.  The
+    outputs of 2,000 seeded rows go to the oracle check of the CPU leg."""
+    import workloads as wl
+    gens = {
+        "zipf_4M": ("row lengths L = min(5000, floor(3.04109 k + u)), k ~ Zipf(2) on [1, 5000], "
+                    "distinct uniform columns, N(0,1) values, 4,000,000 rows, seed 2",
+                    lambda: wl.device_zipf_rows(4_000_000, seed=2)),
+        "banded_4M": ("11 distinct diagonal offsets uniform in [-2000, 2000], every in-range slot "
+                      "N(0,1), 4,000,000 rows, seed 3",
+                      lambda: wl.device_banded(4_000_000, 11, 2000, seed=3)),
+    }
+    out = {}
+    for name, (desc, gen) in gens.items():
+        t0 = time.time()
+        nr, nc, ai, aj, av = gen()
+        coo = mxs.Matrix.coo(nr, nc, ai, aj, av, borrow=True)
+        g = torch.Generator(device="cuda")
+        g.manual_seed(1)
+        x = torch.rand(nc, generator=g, device="cuda", dtype=torch.float64) * 2 - 1
+        y = torch.empty(nr, dtype=torch.float64, device="cuda")
+        rows = np.sort(np.random.Generator(np.random.PCG64(9)).choice(nr, 2000, replace=False))
+        irp = torch.zeros(nr + 1, dtype=torch.int64, device="cuda")
+        irp[1:] = torch.cumsum(torch.bincount(ai.long(), minlength=nr), 0)
+        irp_h = irp.cpu().numpy()
+        starts, ends = irp_h[rows], irp_h[rows + 1]
+        sel = torch.from_numpy(np.concatenate([np.arange(a, b) for a, b in zip(starts, ends)])).cuda()
+        sub = (len(rows), nc, np.concatenate([[0], np.cumsum(ends - starts)]).astype(np.int32),
+               aj[sel].cpu().numpy(), av[sel].cpu().numpy())
+        x_h = x.cpu().numpy()
+        rec = {"workload": desc, "rows": nr, "nnz": coo.nnz, "x": "U[-1,1) (torch generator, seed 1)"}
+        for fmt in FORMATS:
+            if fmt == "coo":
+                A = coo
+            else:
+                try:
+                    A = coo.convert(fmt)
+                except mxs.MxsError as e:
+                    if e.status == -5:
+                        rec[fmt] = {"refused": "MXS_ERR_DIA_TOO_SPARSE"}
+                        continue
+                    raise
+            A.optimize()
+            tc = time_calls(torch, lambda: mxs.spmv(A, x, y))
+            nb = algorithmic_bytes(A, fmt)
+            med = tc["median_ms"] * 1e-3
+            rec[fmt] = {"us_per_call": round(med * 1e6, 2), "mean_us": round(tc["mean_ms"] * 1e3, 2),
+                        "min_us": round(tc["min_ms"] * 1e3, 2), "algorithmic_bytes": nb,
+                        "GBps": round(nb / med / 1e9, 1), "frac_of_peak": round(nb / med / 1e9 / PEAK_HBM_GBS, 4),
+                        "GFLOPs": round(2 * coo.nnz / med / 1e9, 1)}
+            if fmt == "dia":
+                rec[fmt]["ndiag"] = A.ndiag
+            checks.append({"name": f"{name}/{fmt}", "csr_rows": sub, "x": x_h, "y": y.cpu().numpy()[rows]})
+            log(f"[bench] {name} {fmt}: {rec[fmt]['us_per_call']} us, {rec[fmt]['GBps']} GB/s, "
+                f"{rec[fmt]['GFLOPs']} GFLOP/s")
+            if A is not coo:
+                A.close()
+        coo.close()
+        del coo, ai, aj, av, x, y, irp, sel
+        torch.cuda.empty_cache()
+        rec["setup_s"] = round(time.time() - t0, 2)
+        out[name] = rec
+    return out
+
+
+def parity_checks(orc, checks):
+    """Relative max-norm of each GPU output against the oracle: the full
+    vector for the stencil, the sampled rows for the irregular matrices."""
+    res = {}
+    ref_cache = {}
+    for c in checks:
+        if "coo" in c:
+            key = id(c["coo"][1])
+            if key not in ref_cache:
+                nrows, ai, aj, av = c["coo"]
+                ref_cache[key] = orc.coo_spmv(nrows, ai, aj, av, c["x"])
+            ref = ref_cache[key]
+        else:
+            m, ncols, irp, aj, av = c["csr_rows"]
+            ref = orc.csr_spmv(irp, aj, av, c["x"])
+        den = float(np.max(np.abs(ref))) if ref.size else 1.0
+        res[c["name"]] = float(np.max(np.abs(c["y"] - ref)) / (den if den > 0 else 1.0)) if ref.size else 0.0
+    return res
+
+
 def pmc_mode(args):
     import torch
 
@@ -232,6 +364,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cg", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-irregular", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--pmc", choices=FORMATS, default=None)
     args = ap.parse_args()
@@ -254,17 +387,14 @@ def main():
     bytes_f = {f: algorithmic_bytes(mats[f], f) for f in FORMATS}
     step_bytes = sum(bytes_f.values())
 
-    # parity of this exact configuration against the oracle (full vector)
-    import oracle as orc
-    t = time.time()
+    # outputs of this exact configuration, checked against the oracle in the
+    # CPU leg below
+    checks = []
     ai, aj, av = mats["coo"].export()
-    ref = orc.coo_spmv(n, ai, aj, av, x.cpu().numpy())
-    parity = {}
+    x_host = x.cpu().numpy()
     for f in FORMATS:
         y = mxs.spmv(mats[f], x, ys[f]).cpu().numpy()
-        parity[f] = float(np.max(np.abs(y - ref)) / np.max(np.abs(ref)))
-    log(f"[bench] parity vs oracle (rel max-norm): {parity} ({time.time() - t:.1f}s)")
-    assert all(v <= 1e-12 for v in parity.values()), parity
+        checks.append({"name": f"stencil{args.n}/{f}", "coo": (n, ai, aj, av), "x": x_host, "y": y})
 
     # ---- timed region: K steps, one SpMV per format per step ----
     ev = {f: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -320,21 +450,29 @@ def main():
                                   f"FP64 values 26/-1, int32 indices), resident in HBM; one step = one "
                                   f"SpMV in each of COO, CSR, DIA",
                       "x": "U[-1,1) seed 1", "formats": list(FORMATS)},
-           "per_format": per, "parity_rel_maxnorm": parity, "roofline": roofline}
+           "per_format": per, "roofline": roofline}
 
     if not args.no_cg:
         out["cg"], _ = cg_runs(torch, mxs, mats, 1e-9, f"{args.n}^3")
         out["cg"]["config"] = f"b = A*1, x0 = 0, unpreconditioned CG to 1e-9 (||r_k|| / ||r_0||)"
-    coo_host = (ai, aj, av, n)
+        compare_golden(out["cg"], f"cg_stencil{args.n}_tol1e-9")
     for A in mats.values():
         A.close()
     del ys
     torch.cuda.empty_cache()
+    if not args.no_irregular:
+        out["irregular"] = irregular_runs(torch, mxs, checks)
     if not args.no_mixed:
         out["mixed_cg"] = mixed_vs_fp64(torch, mxs, args.mixed_n)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(orc, coo_host, bytes_f["coo"], args.cpu_seconds)
+        import oracle as orc
+        out["cpu_baseline"] = cpu_baseline(orc, (ai, aj, av, n), bytes_f["coo"], args.cpu_seconds)
         log(f"[bench] CPU oracle: {out['cpu_baseline']['value']} GB/s ({out['cpu_baseline']['sample']})")
+        out["parity_vs_oracle"] = parity_checks(orc, checks)
+        bad = {k: v for k, v in out["parity_vs_oracle"].items() if not v <= 1e-12}
+        assert not bad, bad
+    else:
+        out["parity_vs_oracle"] = "not run (--no-cpu): the oracle runs only in the CPU leg"
     print(json.dumps(out), flush=True)
 
 

@@ -67,6 +67,12 @@ const char *mxs_status_string(mxs_status s);
 /* Library version as major*10000 + minor*100 + patch. */
 int32_t mxs_version(void);
 
+/* Detail of the last HIP failure seen by this thread (HIP error name and
+ * message, the failing call and, if one was pending, the error another
+ * library left in HIP's per-thread error slot, which every entry point
+ * clears on entry).  Empty if none; valid until the thread's next failure. */
+const char *mxs_last_error(void);
+
 /* ------------------------------------------------------------------------
  * Containers (Section III-B: COO, CSR, DIA; typed for double and float as
  * in Section VI-A's containers).  All three validate their input on the
@@ -184,18 +190,31 @@ mxs_status mxs_axpby(int64_t n, mxs_dtype dtype, double alpha, const void *x, do
 typedef struct {
     double rtol;         /* FP64 CG: stop when ||r_k|| <= rtol*||r_0|| (recursive r).
                             Mixed: stop when ||b - A x|| <= rtol*||b|| (FP64). */
-    int64_t maxit;       /* FP64 CG: iteration cap.  Mixed: cap per inner solve. */
-    int32_t mixed;       /* 0: FP64 CG on A.  1: refinement with FP32 inner CG on A32. */
-    int32_t max_outer;   /* mixed: at most this many corrections */
-    double inner_rtol;   /* mixed: inner solves stop at ||r|| <= inner_rtol*||r_0|| */
+    int64_t maxit;       /* FP64 CG and mixed = 2: iteration cap.  mixed = 1: cap per
+                            inner solve. */
+    int32_t mixed;       /* 0: FP64 CG on A.
+                            1: iterative refinement: r = b - A x in FP64, an FP32 CG on
+                               A32 solves for the correction from zero, x += correction;
+                               repeated until converged or max_outer corrections.
+                            2: reliable updates: one FP32 CG on A32 whose accumulated
+                               correction is added to x in FP64, and whose residual is
+                               replaced by b - A x (FP64), whenever its recursive
+                               residual falls to ru_delta times its largest value since
+                               the last update, or to rtol*||b||; the search direction
+                               is kept (van der Vorst and Ye's residual replacement). */
+    int32_t max_outer;   /* mixed = 1: at most this many corrections */
+    double inner_rtol;   /* mixed = 1: inner solves stop at ||r|| <= inner_rtol*||r_0|| */
     int32_t check_every; /* host reads the device convergence flag every this many
                             iterations (>= 1); iterations past convergence are no-ops */
-    int32_t timing;      /* 1: time SpMV, dot and vector-update kernels with events */
+    int32_t timing;      /* 1: time SpMV, dot and vector-update kernels with events
+                            (mixed = 2 counts its FP64 updates as vector updates) */
+    double ru_delta;     /* mixed = 2: update factor in [0, 1] */
 } mxs_cg_opts;
 
 typedef struct {
-    int64_t iters;         /* FP64: CG iterations (loop SpMVs).  Mixed: total inner iterations */
-    int64_t outer_iters;   /* mixed: corrections applied; FP64: 0 */
+    int64_t iters;         /* FP64: CG iterations (loop SpMVs).  Mixed: FP32 iterations */
+    int64_t outer_iters;   /* mixed = 1: corrections applied; mixed = 2: reliable updates
+                              triggered; FP64: 0 */
     double rel_resid;      /* FP64: ||r_k||/||r_0|| (recursive).  Mixed: ||b-Ax||/||b|| */
     double true_rel_resid; /* ||b - A x||/||b|| from an FP64 SpMV at exit */
     double t_spmv_ms;      /* timing = 1: summed kernel times per class; else 0 */
@@ -208,8 +227,8 @@ mxs_status mxs_cg_workspace_size(mxs_mat A, int32_t mixed, size_t *bytes);
 
 /* Solves A x = b (A square, symmetric positive definite, FP64) [syncs].
  * x holds x0 on entry and the solution on exit; b and x are FP64 device
- * vectors of nrows entries.  With opts->mixed = 1, A32 must be an FP32
- * handle of the same matrix (e.g. from mxs_cast) used by the inner solves.
+ * vectors of nrows entries.  With opts->mixed = 1 or 2, A32 must be an FP32
+ * handle of the same matrix (e.g. from mxs_cast) used by the FP32 recurrences.
  * Returns MXS_OK on convergence, MXS_NOT_CONVERGED at the cap (x valid),
  * MXS_ERR_BREAKDOWN when p.Ap <= 0 (x holds the last iterate),
  * MXS_ERR_NONFINITE for NaN/Inf in b or x0, MXS_ERR_INVALID_ARG for a
@@ -258,7 +277,7 @@ mxs_status mxs_mlp_inputs(const double *raw, int32_t n, const float *mu, const f
 /* Normalisation statistics of a training set [async]: mu[f], sd[f] are the
  * mean and population standard deviation over the n samples of t(raw[s][f])
  * (t as in mxs_mlp_inputs), accumulated in FP64; sd is replaced by 1 where
- * it is 0. */
+ * it is 0 or below 1e-6 |mu| (a constant feature up to rounding). */
 mxs_status mxs_mlp_norm_stats(const double *raw, int32_t n, float *mu, float *sd,
                               void *stream);
 

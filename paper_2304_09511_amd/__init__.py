@@ -50,7 +50,7 @@ def lib_path() -> str:
 class CgOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("maxit", C.c_int64), ("mixed", C.c_int32),
                 ("max_outer", C.c_int32), ("inner_rtol", C.c_double),
-                ("check_every", C.c_int32), ("timing", C.c_int32)]
+                ("check_every", C.c_int32), ("timing", C.c_int32), ("ru_delta", C.c_double)]
 
 
 class CgResult(C.Structure):
@@ -66,6 +66,7 @@ P, I32, I64, U32, D, F, SZ = (C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_
 _SIGS = {
     "mxs_status_string": (C.c_char_p, [I32]),
     "mxs_version": (I32, []),
+    "mxs_last_error": (C.c_char_p, []),
     "mxs_coo_create": (I32, [P, I32, I32, I64, P, P, P, I32, U32, P]),
     "mxs_csr_create": (I32, [P, I32, I32, I64, P, P, P, I32, U32, P]),
     "mxs_dia_create": (I32, [P, I32, I32, I32, P, P, I32, U32, P]),
@@ -104,6 +105,11 @@ def load(path: str | None = None):
     if not os.path.exists(p):
         raise RuntimeError(f"{p} is missing: build it with `python -m paper_2304_09511_amd.build` "
                            "(or __graft_entry__.build()); there is no fallback path")
+    # torch first: its HIP runtime is required by the name libamdhip64.so and
+    # carries the soname libamdhip64.so.7, which libmxs requires.  Loaded in
+    # this order the process has one HIP runtime; the other order would load
+    # a second runtime (and HSA) beside torch's, which then sees no device.
+    _torch()
     lib = C.CDLL(p)
     for name, (res, args) in _SIGS.items():
         f = getattr(lib, name)
@@ -116,6 +122,10 @@ def load(path: str | None = None):
 
 def _check(st: int, where: str, ok=(0,)):
     if st not in ok:
+        if st in (-6, -7) and _lib is not None:
+            detail = _lib.mxs_last_error()
+            if detail:
+                where = f"{where} [{detail.decode(errors='replace')}]"
         raise MxsError(st, where)
     return st
 
@@ -334,14 +344,20 @@ def cg_workspace(A: Matrix, mixed=False):
     return torch.empty(max(n.value, 1), dtype=torch.uint8, device="cuda")
 
 
+MIXED_MODES = {False: 0, True: 1, 0: 0, 1: 1, 2: 2, "fp64": 0, "ir": 1, "ru": 2}
+
+
 def cg_solve(A: Matrix, b, x0=None, rtol=1e-9, maxit=10000, mixed=False, A32=None,
-             inner_rtol=1e-4, max_outer=20, check_every=16, timing=False, workspace=None):
-    """Solves A x = b.  Returns (status, x, CgResult as a dict)."""
+             inner_rtol=1e-4, max_outer=20, check_every=16, timing=False, workspace=None,
+             delta=0.1):
+    """Solves A x = b.  mixed: False (FP64 CG), True or "ir" (iterative
+    refinement with FP32 inner CG), "ru" (FP32 CG with FP64 reliable
+    updates).  Returns (status, x, CgResult as a dict)."""
     torch = _torch()
+    mode = MIXED_MODES[mixed]
     x = torch.zeros_like(b) if x0 is None else x0.clone()
-    ws = workspace if workspace is not None else cg_workspace(A, mixed)
-    o = CgOpts(rtol, maxit, 1 if mixed else 0, max_outer, inner_rtol, check_every,
-               1 if timing else 0)
+    ws = workspace if workspace is not None else cg_workspace(A, mode)
+    o = CgOpts(rtol, maxit, mode, max_outer, inner_rtol, check_every, 1 if timing else 0, delta)
     r = CgResult()
     st = load().mxs_cg_solve(A.handle, A32.handle if A32 is not None else None, _ptr(b), _ptr(x),
                              C.byref(o), C.byref(r), _ptr(ws), ws.numel(), _stream())

@@ -6,12 +6,28 @@
 
 #include <algorithm>
 #include <climits>
+#include <cstdio>
 #include <cstring>
 #include <new>
 
 #include "common.h"
 
 using namespace mxs;
+
+namespace mxs {
+
+// Detail of the last failed HIP call on this thread (see mxs_last_error).
+thread_local char g_last_error[512];
+thread_local char g_stale_error[160];
+
+mxs_status note_hip_error(hipError_t e, const char *where)
+{
+    snprintf(g_last_error, sizeof g_last_error, "%s: %s at %s%s", hipGetErrorName(e),
+             hipGetErrorString(e), where, g_stale_error);
+    return from_hip(e);
+}
+
+}  // namespace mxs
 
 namespace {
 
@@ -20,14 +36,25 @@ hipStream_t S(void *stream) { return (hipStream_t)stream; }
 bool valid_dtype(mxs_dtype t) { return t == MXS_F64 || t == MXS_F32; }
 bool valid_format(mxs_format f) { return f == MXS_COO || f == MXS_CSR || f == MXS_DIA; }
 
+// Every entry point that touches the GPU runs its body through guarded():
+// an error another library left pending in HIP's per-thread error slot is
+// cleared first (and named in the detail of a later failure), so launch
+// checks report only this call's own launches.
 template <typename F>
 mxs_status guarded(F &&f)
 {
+    const hipError_t stale = hipGetLastError();
+    if (stale != hipSuccess)
+        snprintf(g_stale_error, sizeof g_stale_error, " [an earlier %s pending before this call was cleared]",
+                 hipGetErrorName(stale));
+    else
+        g_stale_error[0] = 0;
     try {
         return f();
     } catch (const std::bad_alloc &) {
         return MXS_ERR_OUT_OF_MEMORY;
     } catch (...) {
+        snprintf(g_last_error, sizeof g_last_error, "C++ exception inside libmxs%s", g_stale_error);
         return MXS_ERR_HIP;
     }
 }
@@ -93,6 +120,8 @@ const char *mxs_status_string(mxs_status s)
 }
 
 int32_t mxs_version(void) { return 10000; }
+
+const char *mxs_last_error(void) { return g_last_error; }
 
 // ---------------------------------------------------------------------------
 // Containers
@@ -390,7 +419,10 @@ mxs_status mxs_cg_solve(mxs_mat A, mxs_mat A32, const double *b, double *x, cons
     if (opts->mixed && (!A32 || A32->dtype != MXS_F32 || A32->nrows != A->nrows ||
                         A32->ncols != A->ncols))
         return MXS_ERR_INVALID_ARG;
-    if (!(opts->rtol >= 0.0) || opts->maxit < 0 || (opts->mixed && opts->max_outer < 0))
+    if (opts->mixed < 0 || opts->mixed > 2) return MXS_ERR_INVALID_ARG;
+    if (!(opts->rtol >= 0.0) || opts->maxit < 0 || (opts->mixed == 1 && opts->max_outer < 0))
+        return MXS_ERR_INVALID_ARG;
+    if (opts->mixed == 2 && !(opts->ru_delta >= 0.0 && opts->ru_delta <= 1.0))
         return MXS_ERR_INVALID_ARG;
     if (workspace_bytes < cg_workspace_bytes(A->nrows, opts->mixed ? 1 : 0, 0, 0))
         return MXS_ERR_INVALID_ARG;

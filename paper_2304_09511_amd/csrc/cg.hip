@@ -116,6 +116,10 @@ __global__ void cg_state_init(CgState *st, double rtol, long long maxit)
     st->status = (int)MXS_NOT_CONVERGED;
     st->nonfinite = 0;
     st->pad = 0;
+    st->rmax = st->delta = st->thresh = st->rtrue2 = 0.0;
+    st->nupd = 0;
+    st->noupd = 1;
+    st->last = 0;
 }
 
 // r = b - q (q = A x0), p = r, partials of r.r; flags NaN/Inf in b or x0.
@@ -289,6 +293,128 @@ __global__ __launch_bounds__(kVNT) void ir_correct_kernel(int64_t n, double *__r
 }
 
 // ---------------------------------------------------------------------------
+// Mixed CG with reliable updates: FP32 recurrences (A32 SpMV, FP32 vectors,
+// FP64-accumulated dots) and a correction d accumulated in FP32; when the
+// recursive residual falls to delta * (largest since the last update) or to
+// rtol * ||b||, x += d in FP64 and the residual is recomputed as b - A x in
+// FP64 and replaces the FP32 one, keeping the search direction (residual
+// replacement, van der Vorst and Ye; the mixed precision named in Section I).
+// The update kernels run every iteration but return at entry unless the
+// finish kernel of that iteration asked for an update (st->noupd == 0).
+// ---------------------------------------------------------------------------
+
+// r = b - q (FP64); r32 = fp32(r); partials of r.r in [0, grid) and of
+// r32.r32 in [grid, 2 grid).  START also sets p32 = r32, d32 = 0 and flags
+// NaN/Inf in b or x.
+template <bool START>
+__global__ __launch_bounds__(kVNT) void ru_resid_kernel(int64_t n, const double *__restrict__ b,
+                                                        const double *__restrict__ x,
+                                                        const double *__restrict__ q,
+                                                        float *__restrict__ r32,
+                                                        float *__restrict__ p32,
+                                                        float *__restrict__ d32, double *partials,
+                                                        CgState *st)
+{
+    __shared__ double red[kVNT / kWave];
+    if (!START && st->noupd) return;
+    double s1 = 0.0, s2 = 0.0;
+    int bad = 0;
+    VEC_LOOP(i, n)
+    {
+        const double bi = b[i];
+        if (START && (!__builtin_isfinite(bi) || !__builtin_isfinite(x[i]))) bad = 1;
+        const double ri = bi - q[i];
+        const float v = (float)ri;
+        r32[i] = v;
+        if (START) {
+            p32[i] = v;
+            d32[i] = 0.0f;
+        }
+        s1 += ri * ri;
+        s2 += (double)v * (double)v;
+    }
+    if (START && bad) atomicOr(&st->nonfinite, 1);
+    const double b1 = block_sum<kVNT>(s1, red);
+    const double b2 = block_sum<kVNT>(s2, red);
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = b1;
+        partials[gridDim.x + blockIdx.x] = b2;
+    }
+}
+
+// After a residual replacement: converged, stopped at the cap, or the
+// recurrence continues from the new FP32 residual (beta, rho, rmax).
+template <bool START>
+__global__ __launch_bounds__(kVNT) void ru_resid_finish_kernel(const double *__restrict__ partials,
+                                                               int64_t nparts, CgState *st)
+{
+    __shared__ double red[kVNT / kWave];
+    if (!START && st->noupd) return;
+    const double rt2 = reduce_partials<kVNT>(partials, nparts, red);
+    const double r32sq = reduce_partials<kVNT>(partials + nparts, nparts, red);
+    if (threadIdx.x == 0) {
+        st->rtrue2 = rt2;
+        st->noupd = 1;
+        if (START && st->nonfinite) {
+            st->status = (int)MXS_ERR_NONFINITE;
+            st->done = 1;
+        } else if (sqrt(rt2) <= st->thresh) {
+            st->status = (int)MXS_OK;
+            st->done = 1;
+        } else if (st->last) {
+            st->status = (int)MXS_NOT_CONVERGED;
+            st->done = 1;
+        } else {
+            if (START) st->rho0 = r32sq;
+            else st->beta = r32sq / st->rho;
+            st->rho = r32sq;
+            st->rmax = sqrt(r32sq);
+        }
+    }
+}
+
+// After r32.r32 of the new FP32 residual: ask for an update, stop at the
+// cap, or take beta for the next direction.
+__global__ __launch_bounds__(kVNT) void ru_rho_finish_kernel(const double *__restrict__ partials,
+                                                             int64_t nparts, CgState *st)
+{
+    __shared__ double red[kVNT / kWave];
+    if (st->done) return;
+    const double rr = reduce_partials<kVNT>(partials, nparts, red);
+    if (threadIdx.x == 0) {
+        const double rn = sqrt(rr);
+        st->rr = rr;
+        const bool cap = st->iters >= st->maxit;
+        if (rn <= st->delta * st->rmax || rn <= st->thresh) {
+            st->noupd = 0;
+            st->last = cap ? 1 : 0;
+            st->nupd += 1;
+        } else if (cap) {
+            st->status = (int)MXS_NOT_CONVERGED;
+            st->done = 1;
+        } else {
+            if (rn > st->rmax) st->rmax = rn;
+            st->beta = rr / st->rho;
+            st->rho = rr;
+        }
+    }
+}
+
+// x += fp64(d); d = 0 -- when an update is pending, or always with FORCE
+// (the final fold after the loop).
+template <bool FORCE>
+__global__ __launch_bounds__(kVNT) void ru_apply_kernel(int64_t n, double *__restrict__ x,
+                                                        float *__restrict__ d32, const CgState *st)
+{
+    if (!FORCE && st->noupd) return;
+    VEC_LOOP(i, n)
+    {
+        x[i] += (double)d32[i];
+        d32[i] = 0.0f;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Workspace layout
 // ---------------------------------------------------------------------------
 static size_t up256(size_t b) { return (b + 255) / 256 * 256; }
@@ -418,11 +544,12 @@ mxs_status enqueue_iteration(const mxs_mat_s *A, int64_t n, T *x, T *r, T *p, T 
     return tm.mark();
 }
 
-// Runs iterations until the device flag is set; returns the final state.
-template <typename T>
-mxs_status run_loop(const mxs_mat_s *A, int64_t n, T *x, T *r, T *p, T *q, double *parts,
-                    CgState *st, int64_t maxit, int32_t every, Timer &tm, CgState *host,
-                    hipStream_t s)
+// Runs iterations (each enqueued by `iter`) until the device flag is set,
+// reading the flag every `every` iterations; returns with the final state in
+// *host.
+template <typename Iter>
+mxs_status run_loop(const CgState *st, int64_t maxit, int32_t every, Timer &tm, CgState *host,
+                    hipStream_t s, Iter &&iter)
 {
     const int64_t C = std::max<int32_t>(every, 1);
     MXS_HIP(hipMemcpyAsync(host, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
@@ -430,7 +557,7 @@ mxs_status run_loop(const mxs_mat_s *A, int64_t n, T *x, T *r, T *p, T *q, doubl
     int64_t launched = 0;
     while (!host->done && launched < maxit + C) {
         for (int64_t c = 0; c < C; ++c) {
-            mxs_status e = enqueue_iteration<T>(A, n, x, r, p, q, parts, st, tm, s);
+            mxs_status e = iter();
             if (e != MXS_OK) return e;
         }
         launched += C;
@@ -440,6 +567,37 @@ mxs_status run_loop(const mxs_mat_s *A, int64_t n, T *x, T *r, T *p, T *q, doubl
         if (e != MXS_OK) return e;
     }
     return MXS_OK;
+}
+
+// One reliable-update iteration: the FP32 CG step, then the update kernels
+// (no-ops unless this step asked for an update), then the next direction.
+mxs_status enqueue_ru_iteration(const mxs_mat_s *A, const mxs_mat_s *A32, int64_t n,
+                                const double *b, double *x, double *q64, float *d32, float *r32,
+                                float *p32, float *q32, double *parts, CgState *st, Timer &tm,
+                                hipStream_t s)
+{
+    mxs_status e;
+    const DotSink ds{parts, st};
+    const uint32_t g = vec_grid(n);
+    if (tm.on) {
+        if ((e = tm.mark()) != MXS_OK) return e;
+        if ((e = spmv_launch(A32, p32, q32, &st->done, nullptr, s)) != MXS_OK) return e;
+        if ((e = tm.mark()) != MXS_OK) return e;
+        if ((e = dot_sigma_launch(n, MXS_F32, p32, q32, &st->done, &ds, s)) != MXS_OK) return e;
+        if ((e = tm.mark()) != MXS_OK) return e;
+    } else {
+        if ((e = spmv_launch(A32, p32, q32, &st->done, &ds, s)) != MXS_OK) return e;
+    }
+    cg_xr_kernel<float, true><<<g, kVNT, 0, s>>>(n, d32, r32, p32, q32, parts, st);
+    ru_rho_finish_kernel<<<1, kVNT, 0, s>>>(parts, g, st);
+    ru_apply_kernel<false><<<g, kVNT, 0, s>>>(n, x, d32, st);
+    if ((e = launch_status()) != MXS_OK) return e;
+    if ((e = spmv_launch(A, x, q64, &st->noupd, nullptr, s)) != MXS_OK) return e;
+    ru_resid_kernel<false><<<g, kVNT, 0, s>>>(n, b, x, q64, r32, nullptr, nullptr, parts, st);
+    ru_resid_finish_kernel<false><<<1, kVNT, 0, s>>>(parts, g, st);
+    cg_p_kernel<float><<<g, kVNT, 0, s>>>(n, r32, p32, st);
+    if ((e = launch_status()) != MXS_OK) return e;
+    return tm.mark();
 }
 
 // ||a - c||^2 (c may be null; w = a - c when non-null) into *out.
@@ -480,8 +638,9 @@ mxs_status cg_solve(const mxs_mat_s *A, const mxs_mat_s *A32, const double *b, d
         start_finish_kernel<<<1, kVNT, 0, s>>>(w.parts, g, w.st);
         MXS_HIP(hipGetLastError());
         if (o->maxit > 0) {
-            if ((e = run_loop<double>(A, n, x, w.r, w.p, w.q, w.parts, w.st, o->maxit,
-                                      o->check_every, tm, host, s)) != MXS_OK)
+            if ((e = run_loop(w.st, o->maxit, o->check_every, tm, host, s, [&] {
+                     return enqueue_iteration<double>(A, n, x, w.r, w.p, w.q, w.parts, w.st, tm, s);
+                 })) != MXS_OK)
                 return e;
         } else {
             MXS_HIP(hipMemcpyAsync(host, w.st, sizeof(CgState), hipMemcpyDeviceToHost, s));
@@ -502,6 +661,57 @@ mxs_status cg_solve(const mxs_mat_s *A, const mxs_mat_s *A32, const double *b, d
         MXS_HIP(hipMemcpyAsync(nn, w.aux->norm2, sizeof(nn), hipMemcpyDeviceToHost, s));
         MXS_HIP(hipStreamSynchronize(s));
         res->true_rel_resid = nn[1] > 0.0 ? std::sqrt(nn[0]) / std::sqrt(nn[1]) : std::sqrt(nn[0]);
+        if (f.status == (int)MXS_ERR_BREAKDOWN) return MXS_ERR_BREAKDOWN;
+        return f.status == (int)MXS_OK ? MXS_OK : MXS_NOT_CONVERGED;
+    }
+
+    if (o->mixed == 2) {
+        // ---- mixed precision with reliable updates ----
+        if ((e = fill_bytes0(w.aux, sizeof(Aux), s)) != MXS_OK) return e;
+        if ((e = norm2(n, b, nullptr, nullptr, w.parts, &w.aux->norm2[1], s)) != MXS_OK) return e;
+        double b2;
+        MXS_HIP(hipMemcpyAsync(&b2, &w.aux->norm2[1], sizeof(double), hipMemcpyDeviceToHost, s));
+        MXS_HIP(hipStreamSynchronize(s));
+        const double bn = std::sqrt(b2);
+        CgState init{};
+        init.rtol = o->rtol;
+        init.maxit = (long long)o->maxit;
+        init.status = (int)MXS_NOT_CONVERGED;
+        init.delta = o->ru_delta;
+        init.thresh = o->rtol * bn;
+        init.noupd = 1;
+        *host = init;
+        MXS_HIP(hipMemcpyAsync(w.st32, host, sizeof(CgState), hipMemcpyHostToDevice, s));
+        if ((e = spmv_launch(A, x, w.q, nullptr, nullptr, s)) != MXS_OK) return e;
+        ru_resid_kernel<true><<<g, kVNT, 0, s>>>(n, b, x, w.q, w.r32, w.p32, w.d32, w.parts, w.st32);
+        ru_resid_finish_kernel<true><<<1, kVNT, 0, s>>>(w.parts, g, w.st32);
+        MXS_HIP(hipGetLastError());
+        if (o->maxit > 0) {
+            if ((e = run_loop(w.st32, o->maxit, o->check_every, tm, host, s, [&] {
+                     return enqueue_ru_iteration(A, A32, n, b, x, w.q, w.d32, w.r32, w.p32, w.q32,
+                                                 w.parts, w.st32, tm, s);
+                 })) != MXS_OK)
+                return e;
+        } else {
+            MXS_HIP(hipMemcpyAsync(host, w.st32, sizeof(CgState), hipMemcpyDeviceToHost, s));
+            MXS_HIP(hipStreamSynchronize(s));
+        }
+        const CgState f = *host;
+        if (f.status == (int)MXS_ERR_NONFINITE) return MXS_ERR_NONFINITE;
+        // fold in a correction not yet applied (cap or breakdown; zero otherwise)
+        ru_apply_kernel<true><<<g, kVNT, 0, s>>>(n, x, w.d32, w.st32);
+        MXS_HIP(hipGetLastError());
+        if ((e = spmv_launch(A, x, w.q, nullptr, nullptr, s)) != MXS_OK) return e;
+        if ((e = norm2(n, b, w.q, nullptr, w.parts, &w.aux->norm2[0], s)) != MXS_OK) return e;
+        double r2;
+        MXS_HIP(hipMemcpyAsync(&r2, &w.aux->norm2[0], sizeof(double), hipMemcpyDeviceToHost, s));
+        MXS_HIP(hipStreamSynchronize(s));
+        res->iters = f.iters;
+        res->outer_iters = f.nupd;
+        res->rel_resid = res->true_rel_resid = bn > 0.0 ? std::sqrt(r2) / bn : std::sqrt(r2);
+        res->t_spmv_ms = tm.ms[0];
+        res->t_dot_ms = tm.ms[1];
+        res->t_axpy_ms = tm.ms[2];
         if (f.status == (int)MXS_ERR_BREAKDOWN) return MXS_ERR_BREAKDOWN;
         return f.status == (int)MXS_OK ? MXS_OK : MXS_NOT_CONVERGED;
     }
@@ -535,8 +745,10 @@ mxs_status cg_solve(const mxs_mat_s *A, const mxs_mat_s *A32, const double *b, d
         start_finish_kernel<<<1, kVNT, 0, s>>>(w.parts, g, w.st32);
         MXS_HIP(hipGetLastError());
         if (o->maxit > 0) {
-            if ((e = run_loop<float>(A32, n, w.d32, w.r32, w.p32, w.q32, w.parts, w.st32,
-                                     o->maxit, o->check_every, tm, host, s)) != MXS_OK)
+            if ((e = run_loop(w.st32, o->maxit, o->check_every, tm, host, s, [&] {
+                     return enqueue_iteration<float>(A32, n, w.d32, w.r32, w.p32, w.q32, w.parts,
+                                                     w.st32, tm, s);
+                 })) != MXS_OK)
                 return e;
             res->iters += host->iters;
         }

@@ -18,10 +18,17 @@ constexpr int kNumXcd = 8; // MI355X: 8 accelerator complex dies, 32 CUs each
 // ---------------------------------------------------------------------------
 // Error plumbing
 // ---------------------------------------------------------------------------
-#define MXS_HIP(call)                                     \
-    do {                                                  \
-        hipError_t e_ = (call);                           \
-        if (e_ != hipSuccess) return ::mxs::from_hip(e_); \
+// Records a failed HIP call (error name, message and source position) for
+// mxs_last_error(); returns the status it maps to.
+mxs_status note_hip_error(hipError_t e, const char *where);
+
+#define MXS_STR2(x) #x
+#define MXS_STR(x) MXS_STR2(x)
+#define MXS_HIP(call)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return ::mxs::note_hip_error(e_, #call " (" __FILE__ ":" MXS_STR(__LINE__) ")"); \
     } while (0)
 
 inline mxs_status from_hip(hipError_t e)
@@ -32,7 +39,11 @@ inline mxs_status from_hip(hipError_t e)
 }
 
 // Checks the launch that was just enqueued.
-inline mxs_status launch_status() { return from_hip(hipGetLastError()); }
+inline mxs_status launch_status()
+{
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? MXS_OK : note_hip_error(e, "kernel launch");
+}
 
 // ---------------------------------------------------------------------------
 // CG state kept in device memory (one per solve level)
@@ -51,6 +62,14 @@ struct CgState {
     int status;      // mxs_status of the solve
     int nonfinite;   // set when an input vector holds NaN or Inf
     int pad;
+    // mixed CG with reliable updates
+    double rmax;     // largest recursive residual norm since the last update
+    double delta;    // update when the residual norm drops to delta * rmax
+    double thresh;   // rtol * ||b||: stop on ||b - A x|| <= thresh
+    double rtrue2;   // ||b - A x||^2 at the last update
+    long long nupd;  // updates made
+    int noupd;       // 0 only while an update is pending (update kernels run)
+    int last;        // the pending update is the last allowed (iteration cap)
 };
 
 // Where a fused dot product of an SpMV epilogue goes: one partial per

@@ -510,12 +510,4 @@ mxs_status cast_values(const void *src, mxs_dtype from, void *dst, mxs_dtype to,
     return launch_status();
 }
 
-// ---------------------------------------------------------------------------
-// Sorting unsorted COO input into canonical (row, col) order
-// ---------------------------------------------------------------------------
-mxs_status sort_coo(int32_t, int32_t, int64_t, int32_t *, int32_t *, void *, mxs_dtype, hipStream_t)
-{
-    return MXS_ERR_UNSORTED;
-}
-
 }  // namespace mxs

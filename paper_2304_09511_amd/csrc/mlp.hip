@@ -54,7 +54,9 @@ __global__ void mlp_norm_kernel(const double *__restrict__ raw, int32_t n, float
     }
     const double sdev = n ? sqrt(q / n) : 0.0;
     mu[f] = (float)m;
-    sd[f] = sdev > 0.0 ? (float)sdev : 1.0f;
+    // a spread below 1e-6 of the mean is a constant feature up to rounding
+    // (the two-pass sum need not return the constant exactly): scale 1
+    sd[f] = sdev > 1e-6 * fabs(m) && sdev > 0.0 ? (float)sdev : 1.0f;
 }
 
 // ---------------------------------------------------------------------------

@@ -25,6 +25,7 @@ import argparse
 import json
 import math
 import os
+import pathlib
 import statistics
 import sys
 import time
@@ -33,6 +34,9 @@ import numpy as np
 
 import paper_2304_09511_amd as mxs
 
+DATA_DIR = pathlib.Path(__file__).resolve().parent / "selector_data"
+DATA_PATH = DATA_DIR / "labels.jsonl"
+MODEL_PATH = DATA_DIR / "model.json"
 FAMILIES = ("stencil7", "stencil27", "banded", "zipf", "block")
 FORMATS = ("coo", "csr", "dia")
 TIE_ORDER = ("csr", "dia", "coo")  # equal medians: the general-purpose format first
@@ -119,27 +123,27 @@ def matrix_spec(i, seed=4):
     return spec
 
 
-def generate(spec, dtype=None):
-    """The matrix of a spec as a COO Matrix on the device."""
-    import torch
-
+def generate_arrays(spec, device="cuda"):
+    """(nrows, ncols, ai, aj, av) of a spec's matrix as tensors on `device`."""
     import workloads as wl
     fam = spec["family"]
     if fam == "stencil7":
-        nr, nc, ai, aj, av = wl.device_stencil(spec["n"], 7)
-    elif fam == "stencil27":
-        nr, nc, ai, aj, av = wl.device_stencil(spec["n"], 27)
-    elif fam == "banded":
-        nr, nc, ai, aj, av = wl.device_banded(spec["rows"], spec["ndiag"], 2000, spec["seed"])
-    elif fam == "zipf":
-        nr, nc, ai, aj, av = wl.device_zipf_rows(spec["rows"], spec["seed"])
-    else:
-        nr, nc, ai, aj, av = wl.device_block_random(spec["nblockrows"], spec["seed"])
+        return wl.device_stencil(spec["n"], 7, device=device)
+    if fam == "stencil27":
+        return wl.device_stencil(spec["n"], 27, device=device)
+    if fam == "banded":
+        return wl.device_banded(spec["rows"], spec["ndiag"], 2000, spec["seed"], device=device)
+    if fam == "zipf":
+        return wl.device_zipf_rows(spec["rows"], spec["seed"], device=device)
+    return wl.device_block_random(spec["nblockrows"], spec["seed"], device=device)
+
+
+def generate(spec, dtype=None):
+    """The matrix of a spec as a borrowing COO Matrix on the device."""
+    nr, nc, ai, aj, av = generate_arrays(spec)
     if dtype is not None:
         av = av.to(dtype)
-    A = mxs.Matrix.coo(nr, nc, ai, aj, av, borrow=True)
-    del ai, aj, av
-    return A
+    return mxs.Matrix.coo(nr, nc, ai, aj, av, borrow=True)
 
 
 def label_dataset(n, out, seed=4, reps=10, warm=3, log=sys.stderr):

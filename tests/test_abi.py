@@ -121,3 +121,17 @@ def test_mlp_calls_reject_bad_arguments(lib):
 def test_load_fails_loudly_without_library(tmp_path):
     with pytest.raises(RuntimeError, match="no fallback"):
         mxs.load(str(tmp_path / "missing.so"))
+
+
+def test_one_hip_runtime_whatever_the_import_order():
+    """Loading libmxs before torch must not put a second HIP/HSA runtime in
+    the process (the second one would see no device)."""
+    import subprocess
+    import sys
+    code = ("import re, sys; sys.path.insert(0, %r); import paper_2304_09511_amd as mxs; mxs.load(); "
+            "import torch; m = open('/proc/self/maps').read(); "
+            "print(len(set(re.findall(r'\\S*libamdhip64\\S*', m))), "
+            "len(set(re.findall(r'\\S*libhsa-runtime64\\S*', m))))" % ROOT)
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.split() == ["1", "1"], out.stdout

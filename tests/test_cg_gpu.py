@@ -161,3 +161,64 @@ def test_mixed_statuses(gpu):
     with pytest.raises(gpu.MxsError) as e:
         gpu.cg_solve(A, b, mixed=True, A32=None)
     assert e.value.status == -1
+
+
+@pytest.mark.parametrize("fmt", ["coo", "csr", "dia"])
+@pytest.mark.parametrize("n,delta", [(8, 0.1), (24, 0.1), (24, 1e-3)])
+def test_reliable_update_reaches_fp64_tolerance(gpu, n, delta, fmt):
+    """FP32 CG with FP64 reliable updates against the oracle's run of the same
+    method: both reach the FP64 tolerance (residual recomputed by the oracle's
+    FP64 SpMV), solutions within the conditioning bound of each other;
+    iteration and update counts are reported and bounded, not pinned."""
+    a = wl.stencil(n)
+    b = orc.coo_spmv(a.nrows, a.ai, a.aj, a.av, np.ones(a.ncols))
+    A = build(gpu, a, fmt)
+    A32 = A.cast(gpu.F32)
+    st, x, res = gpu.cg_solve(A, to_dev(b), rtol=1e-10, mixed="ru", A32=A32, delta=delta)
+    x = x.cpu().numpy()
+    st_o, x_o, upd_o, it_o, true_o = orc.mixed_ru(a.nrows, a.ai, a.aj, a.av, b, tol=1e-10, delta=delta)
+    print(f"[ru] n={n} delta={delta} {fmt} iters={res['iters']} updates={res['outer_iters']} "
+          f"oracle iters={it_o} updates={upd_o}", flush=True)
+    assert st == 0 and st_o == 0
+    r = b - orc.coo_spmv(a.nrows, a.ai, a.aj, a.av, x)
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= 1e-10
+    assert res["true_rel_resid"] == pytest.approx(np.linalg.norm(r) / np.linalg.norm(b), rel=1e-6)
+    kappa = stencil_kappa(n)
+    assert np.max(np.abs(x - x_o)) <= 20 * kappa * 1e-10
+    assert abs(res["iters"] - it_o) <= max(3, 0.1 * it_o)
+    assert res["outer_iters"] >= 1
+
+
+def test_reliable_update_statuses_and_polling(gpu):
+    a = wl.stencil(6)
+    A = build(gpu, a, "csr")
+    A32 = A.cast(gpu.F32)
+    torch = __import__("torch")
+    z = torch.zeros(a.nrows, dtype=torch.float64, device="cuda")
+    st, x, res = gpu.cg_solve(A, z, mixed="ru", A32=A32)
+    assert st == 0 and res["iters"] == 0 and not bool(x.any())
+    bad = z.clone()
+    bad[3] = float("nan")
+    with pytest.raises(gpu.MxsError) as e:
+        gpu.cg_solve(A, bad, mixed="ru", A32=A32)
+    assert e.value.status == -9
+    bh = wl.uniform_vector(a.nrows, seed=2)
+    b = to_dev(bh)
+    st, x, res = gpu.cg_solve(A, b, rtol=1e-30, mixed="ru", A32=A32, maxit=5)
+    assert st == 1 and res["iters"] == 5
+    # the reported residual is that of the returned x
+    r = bh - orc.coo_spmv(a.nrows, a.ai, a.aj, a.av, x.cpu().numpy())
+    assert res["true_rel_resid"] == pytest.approx(np.linalg.norm(r) / np.linalg.norm(bh), rel=1e-6)
+    # the flag-polling interval changes nothing
+    outs = [gpu.cg_solve(A, b, rtol=1e-11, mixed="ru", A32=A32, check_every=c) for c in (1, 7, 64)]
+    for st_c, x_c, r_c in outs[1:]:
+        assert st_c == outs[0][0] and r_c["iters"] == outs[0][2]["iters"]
+        assert torch.equal(x_c, outs[0][1])
+    with pytest.raises(gpu.MxsError) as e:
+        gpu.cg_solve(A, b, mixed="ru", A32=A32, delta=1.5)
+    assert e.value.status == -1
+    # indefinite: p.Ap = 0 at the first step
+    ind = wl.Coo(2, 2, np.array([0, 1], np.int32), np.array([0, 1], np.int32), np.array([1.0, -1.0]))
+    I = build(gpu, ind, "csr")
+    st, x, res = gpu.cg_solve(I, to_dev(np.ones(2)), mixed="ru", A32=I.cast(gpu.F32))
+    assert st == -8

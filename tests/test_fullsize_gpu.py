@@ -1,0 +1,164 @@
+"""Parity at the benchmark's full sizes, in the configuration it times.
+
+* 128^3 stencil (2,097,152 rows, 55,742,968 entries): the device-built
+  matrix equals the host generator's bit for bit; SpMV in every format
+  within 1e-12 of the oracle over the whole vector; CG to 1e-9 in every
+  format against the oracle's stored run (iterations within 2, sampled x).
+* Zipf and banded, 4,000,000 rows: SpMV in every accepted format against the
+  oracle on 2,000 seeded rows.
+* 192^3 stencil (7,077,888 rows): FP64 CG and mixed refinement to 1e-10
+  against the oracle's stored solutions at 4,098 sampled rows.
+
+Stored oracle results come from tests/golden/make_golden.py.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle as orc
+import workloads as wl
+from _cases import rel_maxnorm
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def golden(name):
+    return json.load(open(os.path.join(GOLDEN, name + ".json")))
+
+
+def to_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def formats_of(mxs, A):
+    out = {"coo": A}
+    for f in ("csr", "dia"):
+        try:
+            out[f] = A.convert(f)
+        except mxs.MxsError as e:
+            if e.status != -5:
+                raise
+    for B in out.values():
+        B.optimize()
+    return out
+
+
+@pytest.fixture(scope="module")
+def stencil128(gpu):
+    a = wl.stencil(128)
+    A = gpu.stencil(128, fmt="coo")
+    mats = formats_of(gpu, A)
+    yield a, mats
+    for B in mats.values():
+        B.close()
+
+
+def test_stencil128_device_matrix_is_the_generator(gpu, stencil128):
+    a, mats = stencil128
+    ai, aj, av = mats["coo"].export()
+    assert np.array_equal(ai, a.ai) and np.array_equal(aj, a.aj) and np.array_equal(av, a.av)
+    assert mats["dia"].ndiag == 27
+
+
+def test_stencil128_spmv_full_vector(gpu, stencil128):
+    a, mats = stencil128
+    x = wl.uniform_vector(a.ncols, seed=1)
+    ref = orc.coo_spmv(a.nrows, a.ai, a.aj, a.av, x)
+    xd = to_dev(x)
+    for fmt, B in mats.items():
+        y = gpu.spmv(B, xd).cpu().numpy()
+        assert rel_maxnorm(y, ref) <= 1e-12, fmt
+
+
+def test_stencil128_spmv_integer_data_bit_exact(gpu, stencil128):
+    a, mats = stencil128
+    x = wl.integer_vector(a.ncols, seed=4)
+    ref = orc.coo_spmv(a.nrows, a.ai, a.aj, a.av, x)
+    xd = to_dev(x)
+    for fmt, B in mats.items():
+        assert np.array_equal(gpu.spmv(B, xd).cpu().numpy(), ref), fmt
+
+
+def test_stencil128_cg_matches_oracle_run(gpu, stencil128):
+    import torch
+    g = golden("cg_stencil128_tol1e-9")
+    a, mats = stencil128
+    b = gpu.spmv(mats["csr"], torch.ones(a.nrows, dtype=torch.float64, device="cuda"))
+    idx = torch.tensor(g["sample_idx"], device="cuda")
+    xo = np.array(g["x_sample"])
+    for fmt, B in mats.items():
+        st, x, r = gpu.cg_solve(B, b, rtol=1e-9, maxit=20000)
+        assert st == 0 and r["rel_resid"] <= 1e-9, fmt
+        assert abs(r["iters"] - g["iters"]) <= 2, (fmt, r["iters"], g["iters"])
+        assert r["true_rel_resid"] <= 2e-9, fmt
+        err = np.max(np.abs(x[idx].cpu().numpy() - xo)) / np.max(np.abs(xo))
+        assert err <= 1e-5, (fmt, err)
+
+
+@pytest.mark.parametrize("family", ["zipf", "banded"])
+def test_irregular_4M_spmv_sampled_rows(gpu, family):
+    if family == "zipf":
+        a = wl.zipf_rows(4_000_000, seed=2)
+    else:
+        a = wl.banded(4_000_000, ndiag=11, max_offset=2000, seed=3)
+    x = wl.uniform_vector(a.ncols, seed=1)
+    rows = np.sort(wl.rng(9).choice(a.nrows, 2000, replace=False))
+    irp = np.concatenate([[0], np.cumsum(np.bincount(a.ai, minlength=a.nrows))])
+    sel = np.concatenate([np.arange(irp[r], irp[r + 1]) for r in rows])
+    sub_irp = np.concatenate([[0], np.cumsum(irp[rows + 1] - irp[rows])]).astype(np.int32)
+    ref = orc.csr_spmv(sub_irp, a.aj[sel], a.av[sel], x)
+    A = gpu.Matrix.coo(a.nrows, a.ncols, a.ai, a.aj, a.av)
+    mats = formats_of(gpu, A)
+    assert ("dia" in mats) == (family == "banded")
+    xd = to_dev(x)
+    for fmt, B in mats.items():
+        y = gpu.spmv(B, xd).cpu().numpy()
+        assert rel_maxnorm(y[rows], ref) <= 1e-12, fmt
+        assert np.all(np.isfinite(y)), fmt
+    for B in mats.values():
+        B.close()
+
+
+@pytest.fixture(scope="module")
+def stencil192(gpu):
+    A = gpu.stencil(192, fmt="coo")
+    D = A.convert("dia").optimize()
+    A.close()
+    yield D
+    D.close()
+
+
+def test_stencil192_fp64_cg_matches_oracle(gpu, stencil192):
+    import torch
+    g = golden("cg_stencil192_tol1e-10")
+    D = stencil192
+    b = gpu.spmv(D, torch.ones(D.nrows, dtype=torch.float64, device="cuda"))
+    st, x, r = gpu.cg_solve(D, b, rtol=1e-10, maxit=20000)
+    assert st == 0 and abs(r["iters"] - g["iters"]) <= 2, (r["iters"], g["iters"])
+    idx = torch.tensor(g["sample_idx"], device="cuda")
+    xo = np.array(g["x_sample"])
+    assert np.max(np.abs(x[idx].cpu().numpy() - xo)) / np.max(np.abs(xo)) <= 1e-5
+
+
+def test_stencil192_mixed_refinement_matches_oracle(gpu, stencil192):
+    """FP32 inner CG with FP64 outer residual: true residual at most 1e-10 and
+    the solution within the conditioning bound of the oracle's.  Iteration
+    counts are reported against the oracle's but not pinned."""
+    import torch
+    g = golden("mixed_stencil192_tol1e-10")
+    D = stencil192
+    D32 = D.cast(gpu.F32).optimize()
+    b = gpu.spmv(D, torch.ones(D.nrows, dtype=torch.float64, device="cuda"))
+    st, x, r = gpu.cg_solve(D, b, rtol=1e-10, maxit=20000, mixed=True, A32=D32,
+                            inner_rtol=g["inner_rtol"], max_outer=g["max_outer"])
+    assert st == 0 and r["true_rel_resid"] <= 1e-10, r
+    assert r["outer_iters"] <= g["max_outer"]
+    idx = torch.tensor(g["sample_idx"], device="cuda")
+    xo = np.array(g["x_sample"])
+    assert np.max(np.abs(x[idx].cpu().numpy() - xo)) / np.max(np.abs(xo)) <= 1e-5
+    D32.close()

@@ -214,3 +214,31 @@ def test_csr_and_dia_validation_statuses(gpu):
     with pytest.raises(gpu.MxsError) as e:
         gpu.Matrix.dia(3, 3, np.array([0, 3], np.int32), np.zeros(6))
     assert e.value.status == -2
+
+
+@pytest.mark.parametrize("name", ["stencil16", "zipf20k", "random37x53", "block3000", "one_column"])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_unsorted_coo_is_sorted_on_create(gpu, name, dtype):
+    """An owned COO built from shuffled entries holds the canonical (row, col)
+    order: its arrays equal the sorted input bit for bit."""
+    a = dict(CASES)[name]
+    s = wl.shuffled(a, seed=17)
+    A = gpu.Matrix.coo(s.nrows, s.ncols, s.ai, s.aj, s.av.astype(dtype))
+    ai, aj, av = A.export()
+    assert np.array_equal(ai, a.ai) and np.array_equal(aj, a.aj)
+    assert np.array_equal(av, a.av.astype(dtype))
+    x = wl.uniform_vector(a.ncols, seed=3).astype(dtype)
+    y = gpu.spmv(A, to_dev(x)).cpu().numpy()
+    ref = orc.coo_spmv(a.nrows, a.ai, a.aj, a.av, x.astype(np.float64))
+    assert rel_maxnorm(y, ref) <= (1e-12 if dtype == np.float64 else 1e-5)
+
+
+def test_unsorted_coo_with_duplicate_is_refused(gpu):
+    a = wl.stencil(5)
+    s = wl.shuffled(a, seed=4)
+    aj = s.aj.copy()
+    k = int(np.flatnonzero(s.ai == s.ai[0])[1])
+    aj[k] = aj[0]                                   # two entries at one (row, col)
+    with pytest.raises(gpu.MxsError) as e:
+        gpu.Matrix.coo(s.nrows, s.ncols, s.ai, aj, s.av)
+    assert e.value.status == -4
