@@ -111,8 +111,12 @@ def test_committed_labels_are_consistent():
         assert r["label"] == S.best_format(t)
         assert (r["times_ms"]["dia"] is None) == (not S.dia_feasible(r["features"]))
         assert dict((k, v) for k, v in r.items() if k in S.matrix_spec(r["i"])) == S.matrix_spec(r["i"])
+    # stencils are deterministic and banded features depend only on the
+    # offsets (numpy-seeded), so these regenerate identically on the CPU;
+    # the other families draw from torch's device generator
     checked = 0
-    for r in sorted(recs, key=lambda r: r["nnz"])[:10]:
+    det = [r for r in recs if r["family"] in ("stencil7", "stencil27", "banded")]
+    for r in sorted(det, key=lambda r: r["nnz"])[:10]:
         spec = S.matrix_spec(r["i"])
         nr, nc, ai, aj, _ = S.generate_arrays(spec, device="cpu")
         f = orc.features(nr, nc, ai.numpy(), aj.numpy())
