@@ -54,11 +54,11 @@ __global__ __launch_bounds__(kVNT) void dot_kernel(int64_t n, const T *__restric
 }
 
 // *out = sum of the partials (single workgroup)
-__global__ __launch_bounds__(kVNT) void total_kernel(const double *__restrict__ partials,
+__global__ __launch_bounds__(kFinNT) void total_kernel(const double *__restrict__ partials,
                                                      int64_t nparts, double *out)
 {
-    __shared__ double red[kVNT / kWave];
-    const double t = reduce_partials<kVNT>(partials, nparts, red);
+    __shared__ double red[kFinNT / kWave];
+    const double t = reduce_partials<kFinNT>(partials, nparts, red);
     if (threadIdx.x == 0) *out = t;
 }
 
@@ -73,7 +73,7 @@ mxs_status dot_launch(int64_t n, mxs_dtype t, const void *a, const void *b, doub
     else
         dot_kernel<float><<<g, kVNT, 0, s>>>(n, (const float *)a, (const float *)b, parts);
     MXS_HIP(hipGetLastError());
-    total_kernel<<<1, kVNT, 0, s>>>(parts, g, result);
+    total_kernel<<<1, kFinNT, 0, s>>>(parts, g, result);
     MXS_HIP(hipGetLastError());
     MXS_HIP(hipFreeAsync(parts, s));
     return MXS_OK;
@@ -148,11 +148,11 @@ __global__ __launch_bounds__(kVNT) void cg_start_kernel(int64_t n, const double 
 }
 
 // rho0 = r0.r0; stops at once for NaN/Inf input or a zero residual.
-__global__ __launch_bounds__(kVNT) void start_finish_kernel(const double *__restrict__ partials,
+__global__ __launch_bounds__(kFinNT) void start_finish_kernel(const double *__restrict__ partials,
                                                             int64_t nparts, CgState *st)
 {
-    __shared__ double red[kVNT / kWave];
-    const double tot = reduce_partials<kVNT>(partials, nparts, red);
+    __shared__ double red[kFinNT / kWave];
+    const double tot = reduce_partials<kFinNT>(partials, nparts, red);
     if (threadIdx.x == 0) {
         if (st->nonfinite) {
             st->status = (int)MXS_ERR_NONFINITE;
@@ -206,12 +206,12 @@ __global__ __launch_bounds__(kVNT) void cg_rr_kernel(int64_t n, const T *__restr
 }
 
 // After r.r of the new residual: converged, capped, or beta for the next p.
-__global__ __launch_bounds__(kVNT) void rho_finish_kernel(const double *__restrict__ partials,
+__global__ __launch_bounds__(kFinNT) void rho_finish_kernel(const double *__restrict__ partials,
                                                           int64_t nparts, CgState *st)
 {
-    __shared__ double red[kVNT / kWave];
+    __shared__ double red[kFinNT / kWave];
     if (st->done) return;
-    const double rr = reduce_partials<kVNT>(partials, nparts, red);
+    const double rr = reduce_partials<kFinNT>(partials, nparts, red);
     if (threadIdx.x == 0) {
         st->rr = rr;
         if (sqrt(rr) <= st->rtol * sqrt(st->rho0)) {
@@ -345,13 +345,13 @@ __global__ __launch_bounds__(kVNT) void ru_resid_kernel(int64_t n, const double 
 // After a residual replacement: converged, stopped at the cap, or the
 // recurrence continues from the new FP32 residual (beta, rho, rmax).
 template <bool START>
-__global__ __launch_bounds__(kVNT) void ru_resid_finish_kernel(const double *__restrict__ partials,
+__global__ __launch_bounds__(kFinNT) void ru_resid_finish_kernel(const double *__restrict__ partials,
                                                                int64_t nparts, CgState *st)
 {
-    __shared__ double red[kVNT / kWave];
+    __shared__ double red[kFinNT / kWave];
     if (!START && st->noupd) return;
-    const double rt2 = reduce_partials<kVNT>(partials, nparts, red);
-    const double r32sq = reduce_partials<kVNT>(partials + nparts, nparts, red);
+    const double rt2 = reduce_partials<kFinNT>(partials, nparts, red);
+    const double r32sq = reduce_partials<kFinNT>(partials + nparts, nparts, red);
     if (threadIdx.x == 0) {
         st->rtrue2 = rt2;
         st->noupd = 1;
@@ -375,12 +375,12 @@ __global__ __launch_bounds__(kVNT) void ru_resid_finish_kernel(const double *__r
 
 // After r32.r32 of the new FP32 residual: ask for an update, stop at the
 // cap, or take beta for the next direction.
-__global__ __launch_bounds__(kVNT) void ru_rho_finish_kernel(const double *__restrict__ partials,
+__global__ __launch_bounds__(kFinNT) void ru_rho_finish_kernel(const double *__restrict__ partials,
                                                              int64_t nparts, CgState *st)
 {
-    __shared__ double red[kVNT / kWave];
+    __shared__ double red[kFinNT / kWave];
     if (st->done) return;
-    const double rr = reduce_partials<kVNT>(partials, nparts, red);
+    const double rr = reduce_partials<kFinNT>(partials, nparts, red);
     if (threadIdx.x == 0) {
         const double rn = sqrt(rr);
         st->rr = rr;
@@ -526,7 +526,7 @@ mxs_status enqueue_iteration(const mxs_mat_s *A, int64_t n, T *x, T *r, T *p, T 
     if (!tm.on) {
         if ((e = spmv_launch(A, p, q, &st->done, &ds, s)) != MXS_OK) return e;
         cg_xr_kernel<T, true><<<g, kVNT, 0, s>>>(n, x, r, p, q, parts, st);
-        rho_finish_kernel<<<1, kVNT, 0, s>>>(parts, g, st);
+        rho_finish_kernel<<<1, kFinNT, 0, s>>>(parts, g, st);
         cg_p_kernel<T><<<g, kVNT, 0, s>>>(n, r, p, st);
         return launch_status();
     }
@@ -538,7 +538,7 @@ mxs_status enqueue_iteration(const mxs_mat_s *A, int64_t n, T *x, T *r, T *p, T 
     if ((e = tm.mark()) != MXS_OK) return e;
     cg_xr_kernel<T, false><<<g, kVNT, 0, s>>>(n, x, r, p, q, parts, st);
     cg_rr_kernel<T><<<g, kVNT, 0, s>>>(n, r, parts, st);
-    rho_finish_kernel<<<1, kVNT, 0, s>>>(parts, g, st);
+    rho_finish_kernel<<<1, kFinNT, 0, s>>>(parts, g, st);
     cg_p_kernel<T><<<g, kVNT, 0, s>>>(n, r, p, st);
     if ((e = launch_status()) != MXS_OK) return e;
     return tm.mark();
@@ -589,12 +589,12 @@ mxs_status enqueue_ru_iteration(const mxs_mat_s *A, const mxs_mat_s *A32, int64_
         if ((e = spmv_launch(A32, p32, q32, &st->done, &ds, s)) != MXS_OK) return e;
     }
     cg_xr_kernel<float, true><<<g, kVNT, 0, s>>>(n, d32, r32, p32, q32, parts, st);
-    ru_rho_finish_kernel<<<1, kVNT, 0, s>>>(parts, g, st);
+    ru_rho_finish_kernel<<<1, kFinNT, 0, s>>>(parts, g, st);
     ru_apply_kernel<false><<<g, kVNT, 0, s>>>(n, x, d32, st);
     if ((e = launch_status()) != MXS_OK) return e;
     if ((e = spmv_launch(A, x, q64, &st->noupd, nullptr, s)) != MXS_OK) return e;
     ru_resid_kernel<false><<<g, kVNT, 0, s>>>(n, b, x, q64, r32, nullptr, nullptr, parts, st);
-    ru_resid_finish_kernel<false><<<1, kVNT, 0, s>>>(parts, g, st);
+    ru_resid_finish_kernel<false><<<1, kFinNT, 0, s>>>(parts, g, st);
     cg_p_kernel<float><<<g, kVNT, 0, s>>>(n, r32, p32, st);
     if ((e = launch_status()) != MXS_OK) return e;
     return tm.mark();
@@ -606,7 +606,7 @@ mxs_status norm2(int64_t n, const double *a, const double *c, double *w, double 
 {
     const uint32_t g = vec_grid(n);
     diff_norm2_kernel<<<g, kVNT, 0, s>>>(n, a, c, w, parts);
-    total_kernel<<<1, kVNT, 0, s>>>(parts, g, out);
+    total_kernel<<<1, kFinNT, 0, s>>>(parts, g, out);
     return launch_status();
 }
 
@@ -635,7 +635,7 @@ mxs_status cg_solve(const mxs_mat_s *A, const mxs_mat_s *A32, const double *b, d
         cg_state_init<<<1, 1, 0, s>>>(w.st, o->rtol, (long long)o->maxit);
         if ((e = spmv_launch(A, x, w.q, nullptr, nullptr, s)) != MXS_OK) return e;
         cg_start_kernel<<<g, kVNT, 0, s>>>(n, b, x, w.q, w.r, w.p, w.parts, w.st);
-        start_finish_kernel<<<1, kVNT, 0, s>>>(w.parts, g, w.st);
+        start_finish_kernel<<<1, kFinNT, 0, s>>>(w.parts, g, w.st);
         MXS_HIP(hipGetLastError());
         if (o->maxit > 0) {
             if ((e = run_loop(w.st, o->maxit, o->check_every, tm, host, s, [&] {
@@ -684,7 +684,7 @@ mxs_status cg_solve(const mxs_mat_s *A, const mxs_mat_s *A32, const double *b, d
         MXS_HIP(hipMemcpyAsync(w.st32, host, sizeof(CgState), hipMemcpyHostToDevice, s));
         if ((e = spmv_launch(A, x, w.q, nullptr, nullptr, s)) != MXS_OK) return e;
         ru_resid_kernel<true><<<g, kVNT, 0, s>>>(n, b, x, w.q, w.r32, w.p32, w.d32, w.parts, w.st32);
-        ru_resid_finish_kernel<true><<<1, kVNT, 0, s>>>(w.parts, g, w.st32);
+        ru_resid_finish_kernel<true><<<1, kFinNT, 0, s>>>(w.parts, g, w.st32);
         MXS_HIP(hipGetLastError());
         if (o->maxit > 0) {
             if ((e = run_loop(w.st32, o->maxit, o->check_every, tm, host, s, [&] {
@@ -742,7 +742,7 @@ mxs_status cg_solve(const mxs_mat_s *A, const mxs_mat_s *A32, const double *b, d
         if (outer >= o->max_outer) break;
         cg_state_init<<<1, 1, 0, s>>>(w.st32, o->inner_rtol, (long long)o->maxit);
         ir_inner_start_kernel<<<g, kVNT, 0, s>>>(n, w.r, rn, w.r32, w.d32, w.p32, w.parts);
-        start_finish_kernel<<<1, kVNT, 0, s>>>(w.parts, g, w.st32);
+        start_finish_kernel<<<1, kFinNT, 0, s>>>(w.parts, g, w.st32);
         MXS_HIP(hipGetLastError());
         if (o->maxit > 0) {
             if ((e = run_loop(w.st32, o->maxit, o->check_every, tm, host, s, [&] {

@@ -97,6 +97,7 @@ struct DiaPlan {
     int32_t nruns = 0;
     int32_t lds_elems = 0;   // x-window LDS per block in elements (0: windows off)
     int32_t first_off = 0, last_off = 0;
+    int32_t triples = 0;     // 1: offsets form runs o, o+1, o+2 (ndiag a multiple of 3)
 };
 
 struct CooPlan {
@@ -192,10 +193,27 @@ template <int NT>
 __device__ __forceinline__ double reduce_partials(const double *__restrict__ partials, int64_t n,
                                                   double *smem)
 {
-    double v = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += NT) v += partials[i];
+    // thread t sums partials t, t + NT, ... in eight interleaved accumulators
+    // (eight independent loads in flight), then the fixed combination below
+    constexpr int U = 8;
+    double acc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc[u] = 0.0;
+    int64_t i = threadIdx.x;
+    for (; i + (int64_t)(U - 1) * NT < n; i += (int64_t)U * NT) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = partials[i + (int64_t)u * NT];
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc[u] += v[u];
+    }
+    for (; i < n; i += NT) acc[0] += partials[i];
+    const double v = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     return block_sum<NT>(v, smem);
 }
+
+// Threads of the single-workgroup kernels that reduce partials.
+constexpr int kFinNT = 1024;
 
 // Finisher of the fused p.Ap: one loop SpMV done; alpha = rho / sigma, or a
 // breakdown when sigma <= 0 or not finite.
@@ -227,7 +245,7 @@ mxs_status dot_sigma_launch(int64_t n, mxs_dtype t, const void *a, const void *b
 // Number of per-workgroup partials the fused dot of spmv_launch writes.
 int64_t spmv_dot_parts(const mxs_mat_s *A);
 // Capacity of every partials array (workgroups of any reducing launch).
-constexpr int64_t kMaxParts = 16384;
+constexpr int64_t kMaxParts = 1 << 18;
 mxs_status build_plan(mxs_mat_s *A, hipStream_t s);
 
 // scan.hip

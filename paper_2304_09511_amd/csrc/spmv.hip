@@ -39,11 +39,19 @@
 #define MXS_DIA_RPT64 1
 #endif
 #ifndef MXS_DIA_RPT32
-#define MXS_DIA_RPT32 4
+#define MXS_DIA_RPT32 2
 #endif
 #ifndef MXS_DIA_DU
 #define MXS_DIA_DU 4
 #endif
+#ifndef MXS_DIA_SHARE
+#define MXS_DIA_SHARE 1 // 1: one x load per run of three consecutive offsets, neighbours by lane shifts
+#endif
+
+#ifndef MXS_DIA_TU
+#define MXS_DIA_TU 2 // runs of three offsets whose loads are issued together
+#endif
+
 #ifndef MXS_STREAM_NT
 #define MXS_STREAM_NT 1 // non-temporal loads for matrix values read once per SpMV
 #endif
@@ -346,6 +354,28 @@ __device__ __forceinline__ int64_t spos_off(const int32_t *spos, const int32_t *
     return win ? (int64_t)doff[d] : (int64_t)spos[d];
 }
 
+// Lane shifts across the 64-lane wave (DPP wave_shr:1 / wave_shl:1): lane l
+// receives lane l-1 (resp. l+1) of v; the lane without a source (0, resp.
+// 63) receives `edge`.
+__device__ __forceinline__ int dpp_shift(int edge, int v, bool right)
+{
+    return right ? __builtin_amdgcn_update_dpp(edge, v, 0x138, 0xf, 0xf, false)
+                 : __builtin_amdgcn_update_dpp(edge, v, 0x130, 0xf, 0xf, false);
+}
+__device__ __forceinline__ float lane_shift(float edge, float v, bool right)
+{
+    return __builtin_bit_cast(float, dpp_shift(__builtin_bit_cast(int, edge),
+                                               __builtin_bit_cast(int, v), right));
+}
+__device__ __forceinline__ double lane_shift(double edge, double v, bool right)
+{
+    const int2 e = __builtin_bit_cast(int2, edge), w = __builtin_bit_cast(int2, v);
+    int2 o;
+    o.x = dpp_shift(e.x, w.x, right);
+    o.y = dpp_shift(e.y, w.y, right);
+    return __builtin_bit_cast(double, o);
+}
+
 // Values come either diagonal-major (av[d*nrows + i], the container's
 // layout; `blocked` false) or row-blocked (av[(b*ndiag + d)*ROWS + i - row0],
 // the plan's copy; `blocked` true), where each block's diagonals are one
@@ -356,7 +386,7 @@ __global__ __launch_bounds__(256) void dia_spmv_kernel(
     const T *__restrict__ av, int blocked, const T *__restrict__ x, T *__restrict__ y, int64_t nblk,
     int64_t per, const int *__restrict__ done, double *__restrict__ partials,
     const int32_t *__restrict__ wpos, const int32_t *__restrict__ wruns, int32_t nruns,
-    int32_t wlen, int32_t first_off, int32_t last_off)
+    int32_t wlen, int32_t first_off, int32_t last_off, int32_t triples)
 {
     constexpr int NT = kDiaNT;
     constexpr int RPT = DiaCfg<T>::RPT;
@@ -413,6 +443,71 @@ __global__ __launch_bounds__(256) void dia_spmv_kernel(
             }
             const T *__restrict__ x_blk = x + row0;
             int d = 0;
+#if MXS_DIA_SHARE
+            if (triples && !win) {
+                // offsets o, o+1, o+2: one x load at o+1 per row; its
+                // neighbours come from the adjacent lanes, and the two values
+                // past the wave's ends from wave-uniform loads
+                const int wbase = __builtin_amdgcn_readfirstlane(tid & ~(kWave - 1));
+                constexpr int TU = MXS_DIA_TU;
+                for (; d + 3 * TU <= ndiag; d += 3 * TU) {
+                    T va[TU][3][RPT], xc[TU][RPT], el[TU][RPT], er[TU][RPT];
+#pragma unroll
+                    for (int t = 0; t < TU; ++t) {
+                        const int32_t o0 = __builtin_amdgcn_readfirstlane(spos[d + 3 * t]);
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) {
+                            const T *__restrict__ a = a_blk + (int64_t)(d + 3 * t + k) * dstride;
+#pragma unroll
+                            for (int r = 0; r < RPT; ++r)
+                                va[t][k][r] = ld_stream(&a[(uint32_t)(r * NT + tid)]);
+                        }
+#pragma unroll
+                        for (int r = 0; r < RPT; ++r) {
+                            const int64_t w0 = (int64_t)r * NT + wbase + o0; // wave's first row + o0
+                            xc[t][r] = x_blk[(int64_t)o0 + 1 + r * NT + tid];
+                            el[t][r] = x_blk[w0];
+                            er[t][r] = x_blk[w0 + kWave + 1];
+                        }
+                    }
+#pragma unroll
+                    for (int t = 0; t < TU; ++t)
+#pragma unroll
+                        for (int r = 0; r < RPT; ++r) {
+                            const T xl = lane_shift(el[t][r], xc[t][r], true);
+                            const T xr = lane_shift(er[t][r], xc[t][r], false);
+                            sum[r] += va[t][0][r] * xl;
+                            sum[r] += va[t][1][r] * xc[t][r];
+                            sum[r] += va[t][2][r] * xr;
+                        }
+                }
+                for (; d + 3 <= ndiag; d += 3) {
+                    const int32_t o0 = __builtin_amdgcn_readfirstlane(spos[d]);
+                    T va[3][RPT], xc[RPT], el[RPT], er[RPT];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        const T *__restrict__ a = a_blk + (int64_t)(d + k) * dstride;
+#pragma unroll
+                        for (int r = 0; r < RPT; ++r) va[k][r] = ld_stream(&a[(uint32_t)(r * NT + tid)]);
+                    }
+#pragma unroll
+                    for (int r = 0; r < RPT; ++r) {
+                        const int64_t w0 = (int64_t)r * NT + wbase + o0;
+                        xc[r] = x_blk[(int64_t)o0 + 1 + r * NT + tid];
+                        el[r] = x_blk[w0];
+                        er[r] = x_blk[w0 + kWave + 1];
+                    }
+#pragma unroll
+                    for (int r = 0; r < RPT; ++r) {
+                        const T xl = lane_shift(el[r], xc[r], true);
+                        const T xr = lane_shift(er[r], xc[r], false);
+                        sum[r] += va[0][r] * xl;
+                        sum[r] += va[1][r] * xc[r];
+                        sum[r] += va[2][r] * xr;
+                    }
+                }
+            }
+#endif
             for (; d + DU <= ndiag; d += DU) {
                 T va[DU][RPT], vx[DU][RPT];
 #pragma unroll
@@ -691,12 +786,12 @@ __global__ __launch_bounds__(256) void dot_partials_kernel(int64_t n, const T *_
 }
 
 // alpha = rho / (p.Ap) from the partials of the kernel that ran before.
-__global__ __launch_bounds__(256) void sigma_finish_kernel(const double *__restrict__ partials,
-                                                           int64_t nparts, CgState *st)
+__global__ __launch_bounds__(kFinNT) void sigma_finish_kernel(const double *__restrict__ partials,
+                                                              int64_t nparts, CgState *st)
 {
-    __shared__ double red[256 / kWave];
+    __shared__ double red[kFinNT / kWave];
     if (st->done) return;
-    const double tot = reduce_partials<256>(partials, nparts, red);
+    const double tot = reduce_partials<kFinNT>(partials, nparts, red);
     if (threadIdx.x == 0) cg_finish_sigma(st, tot);
 }
 
@@ -806,6 +901,10 @@ static mxs_status build_dia_plan(mxs_mat_s *A, hipStream_t s)
     MXS_HIP(hipStreamSynchronize(s));
     A->dia.first_off = off[0];
     A->dia.last_off = off[nd - 1];
+    bool tri = nd % 3 == 0;
+    for (int t = 0; tri && t < nd / 3; ++t)
+        tri = off[3 * t + 1] == off[3 * t] + 1 && off[3 * t + 2] == off[3 * t] + 2;
+    A->dia.triples = tri ? 1 : 0;
     const int R = kDiaNT * (A->dtype == MXS_F64 ? DiaCfg<double>::RPT : DiaCfg<float>::RPT);
     std::vector<int32_t> runs, pos(nd);
     int64_t total = 0;
@@ -887,7 +986,7 @@ static mxs_status dot_sigma_typed(int64_t n, const T *a, const T *b, const int *
     const uint32_t g = (uint32_t)std::clamp<int64_t>((n + 1023) / 1024, 1, kDotGridMax);
     dot_partials_kernel<T><<<g, 256, 0, s>>>(n, a, b, done, dot->partials);
     MXS_HIP(hipGetLastError());
-    sigma_finish_kernel<<<1, 256, 0, s>>>(dot->partials, g, dot->st);
+    sigma_finish_kernel<<<1, kFinNT, 0, s>>>(dot->partials, g, dot->st);
     return launch_status();
 }
 
@@ -954,11 +1053,11 @@ static mxs_status spmv_typed(const mxs_mat_s *A, const T *x, T *y, const int *do
         if (dot)
             dia_spmv_kernel<T, true><<<grid, kDiaNT, lds, s>>>(
                 A->nrows, A->ncols, A->ndiag, A->idx0, vals, blocked, x, y, dia_blocks(A), per,
-                done, parts, P.pos, P.runs, P.nruns, P.lds_elems, P.first_off, P.last_off);
+                done, parts, P.pos, P.runs, P.nruns, P.lds_elems, P.first_off, P.last_off, P.triples);
         else
             dia_spmv_kernel<T, false><<<grid, kDiaNT, lds, s>>>(
                 A->nrows, A->ncols, A->ndiag, A->idx0, vals, blocked, x, y, dia_blocks(A), per,
-                done, parts, P.pos, P.runs, P.nruns, P.lds_elems, P.first_off, P.last_off);
+                done, parts, P.pos, P.runs, P.nruns, P.lds_elems, P.first_off, P.last_off, P.triples);
         MXS_HIP(hipGetLastError());
         nparts = grid;
         break;
@@ -984,7 +1083,7 @@ static mxs_status spmv_typed(const mxs_mat_s *A, const T *x, T *y, const int *do
         return MXS_ERR_UNSUPPORTED;
     }
     if (dot) {
-        sigma_finish_kernel<<<1, 256, 0, s>>>(dot->partials, nparts, dot->st);
+        sigma_finish_kernel<<<1, kFinNT, 0, s>>>(dot->partials, nparts, dot->st);
         return launch_status();
     }
     return MXS_OK;
