@@ -313,6 +313,43 @@ def irregular_runs(torch, mxs, checks):
     return out
 
 
+def selector_eval(torch, mxs, n_live=40):
+    """The committed selector on its 500 held-out matrices (stored timings),
+    and live on a seeded sample of them re-timed on this GPU: accuracy, mean
+    regret against the run-first tuner, the always-CSR baseline, and the
+    selection cost of each."""
+    from paper_2304_09511_amd import selector as S
+    model = S.Selector.load(str(S.MODEL_PATH))
+    recs, F, T, y = S.load_dataset(str(S.DATA_PATH))
+    tr, te = S.split(len(recs), 1500)
+    out = {"stored_held_out": S.evaluate(model, F[te], T[te])}
+    pick = np.sort(np.random.Generator(np.random.PCG64(12)).choice(te, n_live, replace=False))
+    Tl, choice, t_model, t_tuner = [], [], [], []
+    for i in pick:
+        A = S.generate(recs[i])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f = model.select(A)
+        t_model.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        best, times = S.exhaustive_select(A)
+        t_tuner.append(time.perf_counter() - t0)
+        Tl.append([times[k] for k in S.FORMATS])
+        choice.append(S.FORMATS.index(f))
+        A.close()
+        torch.cuda.empty_cache()
+    Tl = np.array(Tl)
+    choice = np.array(choice)
+    best = Tl.argmin(axis=1)
+    out["live"] = {"matrices": int(n_live), "accuracy": float(np.mean(choice == best)),
+                   "mean_regret": S.regret(Tl, choice),
+                   "always_csr_regret": S.regret(Tl, np.ones(len(Tl), int)),
+                   "model_select_ms_median": round(1e3 * statistics.median(t_model), 3),
+                   "tuner_select_ms_median": round(1e3 * statistics.median(t_tuner), 3)}
+    log(f"[bench] selector held out: {out['stored_held_out']}; live: {out['live']}")
+    return out
+
+
 def parity_checks(orc, checks):
     """Relative max-norm of each GPU output against the oracle: the full
     vector for the stencil, the sampled rows for the irregular matrices."""
@@ -365,6 +402,7 @@ def main():
     ap.add_argument("--no-cg", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-irregular", action="store_true")
+    ap.add_argument("--no-selector", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--pmc", choices=FORMATS, default=None)
     args = ap.parse_args()
@@ -464,6 +502,8 @@ def main():
         out["irregular"] = irregular_runs(torch, mxs, checks)
     if not args.no_mixed:
         out["mixed_cg"] = mixed_vs_fp64(torch, mxs, args.mixed_n)
+    if not args.no_selector:
+        out["selector"] = selector_eval(torch, mxs)
     if not args.no_cpu:
         import oracle as orc
         out["cpu_baseline"] = cpu_baseline(orc, (ai, aj, av, n), bytes_f["coo"], args.cpu_seconds)
