@@ -192,20 +192,12 @@ __global__ void csr_tile_info_kernel(const int32_t *__restrict__ irp, const int3
     if (v & kCsrLastCarry) atomicOr(any_carry, 1);
 }
 
-#ifndef MXS_COO_UNROLL
-#define MXS_COO_UNROLL 0 // 1: each thread reads its run from LDS at once and reduces it unrolled
-#endif
-
 #ifndef MXS_CSR_TRIM
 #define MXS_CSR_TRIM 1 // 1: waves skip the second row-pointer load and extension loads they do not need
 #endif
 
 #ifndef MXS_DIA_YNT
 #define MXS_DIA_YNT 1 // 1: DIA writes y with non-temporal stores
-#endif
-
-#ifndef MXS_CSR_YNT
-#define MXS_CSR_YNT 0 // 1: CSR writes y with non-temporal stores
 #endif
 
 #ifndef MXS_CSR_WPE
@@ -308,11 +300,7 @@ __global__ __launch_bounds__(256) MXS_CSR_ATTR void csr_spmv_kernel(
                 if (last_carry && r == nr - 1) {
                     carry[2 * tile + 1] = sum;
                 } else {
-#if MXS_CSR_YNT
-                    __builtin_nontemporal_store(sum, &y[r_lo + r]);
-#else
                     y[r_lo + r] = sum;
-#endif
                     if (DOT) dpart += (double)sum * (double)x[r_lo + r];
                 }
             }
@@ -730,55 +718,6 @@ __global__ __launch_bounds__(256) void coo_spmv_kernel(
         __syncthreads();
         const int32_t first_row = srow[0];
         const bool tile_cont = prev_row == first_row; // first segment began in an earlier tile
-#if MXS_COO_UNROLL
-        // this thread's run [b0, b0 + cnt): rows and products read at once
-        const int b0 = tid * IPT;
-        const int cnt = max(0, min(IPT, n - b0));
-        int32_t rr[IPT];
-        T vv[IPT];
-#pragma unroll
-        for (int e = 0; e < IPT; ++e) {
-            const int j = coo_pad(min(b0 + e, n - 1)); // clamped: a written slot
-            rr[e] = srow[j];
-            vv[e] = sval[j];
-        }
-        const int32_t before = b0 == 0 ? prev_row : srow[coo_pad(min(b0, n) - 1)];
-        // pass 1: this thread's run as a (head seen, tail sum) pair
-        SegPair<T> mine = {0, T(0)};
-        int32_t pr = before;
-#pragma unroll
-        for (int e = 0; e < IPT; ++e) {
-            if (e < cnt) {
-                if (rr[e] != pr) {
-                    mine.h = 1;
-                    mine.v = T(0);
-                }
-                mine.v += vv[e];
-                pr = rr[e];
-            }
-        }
-        const SegPair<T> cin = block_seg_excl_scan<T, NT>(mine, sh, sv);
-        // pass 2: emit every segment that closes inside this run
-        T s = cin.v;
-        pr = before;
-#pragma unroll
-        for (int e = 0; e < IPT; ++e) {
-            if (e < cnt) {
-                const int32_t rw = rr[e];
-                if (rw != pr) {
-                    if (b0 + e > 0) {
-                        if (tile_cont && pr == first_row) carry[2 * tile] = s;
-                        else y[pr] = s;
-                    }
-                    for (int32_t z = pr + 1; z < rw; ++z) y[z] = T(0); // rows without entries
-                    s = T(0);
-                }
-                s += vv[e];
-                pr = rw;
-            }
-        }
-        const int b1 = b0 + cnt;
-#else
         const int b0 = tid * IPT, b1 = min(b0 + IPT, n);
         // pass 1: this thread's run as a (head seen, tail sum) pair
         SegPair<T> mine = {0, T(0)};
@@ -806,7 +745,6 @@ __global__ __launch_bounds__(256) void coo_spmv_kernel(
             }
             s += sval[coo_pad(j)];
         }
-#endif
         if (b0 < n && b1 == n) {
             // the thread holding the tile's last entry closes or hands over its segment
             const int32_t last = srow[coo_pad(n - 1)];

@@ -242,3 +242,51 @@ def test_unsorted_coo_with_duplicate_is_refused(gpu):
     with pytest.raises(gpu.MxsError) as e:
         gpu.Matrix.coo(s.nrows, s.ncols, s.ai, aj, s.av)
     assert e.value.status == -4
+
+
+def _diagonals(n, offsets, seed, integer=False):
+    """Square matrix whose entries are every in-range slot of the given
+    diagonals (values N(0,1), or small integers)."""
+    g = wl.rng(seed)
+    ai, aj = [], []
+    for o in sorted(offsets):
+        i = np.arange(max(0, -o), min(n, n - o))
+        ai.append(i)
+        aj.append(i + o)
+    ai = np.concatenate(ai).astype(np.int32)
+    aj = np.concatenate(aj).astype(np.int32)
+    order = np.lexsort((aj, ai))
+    ai, aj = ai[order], aj[order]
+    av = g.integers(-4, 5, ai.size).astype(np.float64) if integer else g.standard_normal(ai.size)
+    if integer:
+        av[av == 0] = 1.0
+    return wl.Coo(n, n, ai, aj, av)
+
+
+@pytest.mark.parametrize("offsets", [
+    [-700, -699, -698, -3, -2, -1, 40, 41, 42],            # runs of three (shared x loads)
+    [-5, -4, -3, 0, 1, 2, 3, 4, 5, 9, 10, 11],              # adjacent runs
+    [-2, -1, 0, 7, 8],                                      # not all runs of three
+    list(range(-150, 150)),                                 # 300 diagonals (offsets not staged)
+], ids=["triples", "adjacent_triples", "mixed", "ndiag300"])
+@pytest.mark.parametrize("n", [1000, 70000])
+def test_dia_offset_structures(gpu, offsets, n):
+    """DIA paths chosen by the offset structure against the oracle: FP64 within
+    1e-12, integer data bit-exact, FP32 within its rounding bound."""
+    a = _diagonals(n, offsets, seed=n + len(offsets))
+    A = build(gpu, a, "dia")
+    assert A is not None and A.ndiag == len(offsets)
+    x = wl.uniform_vector(n, seed=3)
+    ref = orc.coo_spmv(n, a.ai, a.aj, a.av, x)
+    y = gpu.spmv(A, to_dev(x)).cpu().numpy()
+    assert rel_maxnorm(y, ref) <= 1e-12
+    ai_ = _diagonals(n, offsets, seed=5, integer=True)
+    B = build(gpu, ai_, "dia")
+    xi = wl.integer_vector(n, seed=6)
+    assert np.array_equal(gpu.spmv(B, to_dev(xi)).cpu().numpy(),
+                          orc.coo_spmv(n, ai_.ai, ai_.aj, ai_.av, xi))
+    A32 = A.cast(gpu.F32)
+    y32 = gpu.spmv(A32, to_dev(x.astype(np.float32))).cpu().numpy().astype(np.float64)
+    ref32 = orc.coo_spmv(n, a.ai, a.aj, a.av.astype(np.float32).astype(np.float64),
+                         x.astype(np.float32).astype(np.float64))
+    assert np.all(np.abs(y32 - ref32) <= row_bound(a, x, U32) + 1e-30)
