@@ -92,6 +92,7 @@ def _bind(lib):
         "orc_dot": (D, [I64, P, P]),
         "orc_cg": (C.c_int, [I64, I64, P, P, P, P, P, D, I64, P, P]),
         "orc_mixed_ir": (C.c_int, [I64, I64, P, P, P, P, P, D, D, I64, I64, P, P]),
+        "orc_split_offsets": (I64, [I64, I64, I64, P, P, D, P]),
         "orc_mixed_ru": (C.c_int, [I64, I64, P, P, P, P, P, D, D, I64, P, P]),
         "orc_features": (None, [I64, I64, I64, P, P, P]),
         "orc_mlp_nparam": (I64, []),
@@ -263,6 +264,14 @@ def mixed_ru(n, ai, aj, av, b, x0=None, tol=1e-10, delta=0.1, maxit=10000):
     st = _load().orc_mixed_ru(n, ai.shape[0], _p(ai), _p(aj), _p(av), _p(b), _p(x), tol, delta,
                               maxit, _p(counts), _p(out))
     return int(st), x, int(counts[0]), int(counts[1]), float(out[0])
+
+
+def split_offsets(nrows, ncols, ai, aj, min_fill=0.5):
+    """Offsets of the band of a split (ascending)."""
+    ai, aj = _i32(ai), _i32(aj)
+    out = np.empty(max(nrows + ncols - 1, 1), np.int32)
+    nd = _load().orc_split_offsets(nrows, ncols, ai.shape[0], _p(ai), _p(aj), min_fill, _p(out))
+    return out[:nd].copy()
 
 
 # ------------------------------------------------------------ selector

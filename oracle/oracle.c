@@ -228,6 +228,37 @@ int64_t orc_dia_offsets(int64_t nrows, int64_t ncols, int64_t nnz, const int32_t
     return nd;
 }
 
+/* Band of a split matrix (a DIA band plus a remainder: the hybrid DIA/CSR
+ * format among the further formats of Section IX, and the local/remote split
+ * of the distributed HPCG runs, Section VII-D and Table III).  The band is
+ * the diagonals, in ascending offset order, that hold at least one stored
+ * entry and at least min_fill times as many stored entries as the diagonal
+ * has slots inside the matrix (compared in FP64); entries on them form the
+ * band and all others the remainder.  Returns the number of band offsets
+ * written to doff. */
+int64_t orc_split_offsets(int64_t nrows, int64_t ncols, int64_t nnz, const int32_t *ai,
+                          const int32_t *aj, double min_fill, int32_t *doff)
+{
+    int64_t span = nrows + ncols - 1;
+    if (span <= 0)
+        return 0;
+    int64_t *count = (int64_t *)calloc((size_t)span, sizeof(int64_t));
+    for (int64_t k = 0; k < nnz; ++k)
+        count[(int64_t)aj[k] - (int64_t)ai[k] + (nrows - 1)]++;
+    int64_t nd = 0;
+    for (int64_t s = 0; s < span; ++s) {
+        int64_t d = s - (nrows - 1);
+        /* rows i with 0 <= i < nrows and 0 <= i + d < ncols */
+        int64_t lo = d < 0 ? -d : 0;
+        int64_t hi = ncols - d < nrows ? ncols - d : nrows;
+        int64_t slots = hi - lo;
+        if (count[s] > 0 && (double)count[s] >= min_fill * (double)slots)
+            doff[nd++] = (int32_t)d;
+    }
+    free(count);
+    return nd;
+}
+
 /* DIA values from sorted COO: av_dia[d*nrows + i] = A(i, i + doff[d]), and
  * +0.0 in every slot that holds no stored entry. */
 void orc_coo_to_dia(int64_t nrows, int64_t nnz, const int32_t *ai, const int32_t *aj,

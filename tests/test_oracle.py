@@ -395,6 +395,52 @@ def test_reliable_update_statuses():
 
 
 # --------------------------------------------------------------------------
+# Split matrices: the band of diagonals
+# --------------------------------------------------------------------------
+def _coo_from_dense(M):
+    ai, aj = np.nonzero(M)
+    return wl.Coo(M.shape[0], M.shape[1], ai.astype(np.int32), aj.astype(np.int32), M[ai, aj])
+
+
+def test_split_band_hand_built():
+    """6x6: main diagonal full (6 of 6 slots), offset +1 with 2 of 5, offset
+    -2 with 3 of 4.  The thresholds select exactly the diagonals whose fill
+    reaches them (equality included)."""
+    M = np.zeros((6, 6))
+    M[np.arange(6), np.arange(6)] = 1.0
+    M[0, 1] = M[3, 4] = 2.0
+    M[2, 0] = M[3, 1] = M[5, 3] = 3.0
+    a = _coo_from_dense(M)
+    band = lambda f: orc.split_offsets(6, 6, a.ai, a.aj, f).tolist()
+    assert band(0.5) == [-2, 0]
+    assert band(0.4) == [-2, 0, 1]
+    assert band(0.8) == [0]
+    assert band(1.0) == [0]
+    assert band(0.0) == [-2, 0, 1]
+
+
+def test_split_band_full_rectangular_and_stencil():
+    """A full 3x5 matrix: every one of its 7 diagonals is full, so all are
+    kept even at min_fill = 1 (this fixes the slot count of each diagonal of a
+    rectangular matrix); the 27-point stencil's diagonals are all at least
+    half full."""
+    a = _coo_from_dense(np.arange(1.0, 16.0).reshape(3, 5))
+    assert orc.split_offsets(3, 5, a.ai, a.aj, 1.0).tolist() == list(range(-2, 5))
+    a = _coo_from_dense(np.arange(1.0, 16.0).reshape(5, 3))
+    assert orc.split_offsets(5, 3, a.ai, a.aj, 1.0).tolist() == list(range(-4, 3))
+    s = wl.stencil(16)
+    assert np.array_equal(orc.split_offsets(s.nrows, s.ncols, s.ai, s.aj, 0.5),
+                          orc.dia_offsets(s.nrows, s.ncols, s.ai, s.aj))
+
+
+def test_split_band_random_matrix_is_empty():
+    a = wl.random_coo(200, 300, 0.01, seed=4)
+    assert orc.split_offsets(200, 300, a.ai, a.aj, 0.5).size == 0
+    assert orc.split_offsets(200, 300, a.ai, a.aj, 0.0).size == \
+        np.unique(a.aj.astype(np.int64) - a.ai).size
+
+
+# --------------------------------------------------------------------------
 # Features
 # --------------------------------------------------------------------------
 @pytest.mark.parametrize("n", [3, 5, 16])

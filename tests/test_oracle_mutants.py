@@ -70,6 +70,14 @@ MUTANTS = [
      "            break;\n        }\n        float alpha = (float)(rho / sigma);",
      "            break;\n        }\n        float alpha = (float)(sigma / rho);",
      [pins.test_reliable_update_first_iterate]),
+    ("split_strict_threshold",
+     "if (count[s] > 0 && (double)count[s] >= min_fill * (double)slots)",
+     "if (count[s] > 0 && (double)count[s] > min_fill * (double)slots)",
+     [pins.test_split_band_hand_built]),
+    ("split_slots_square_only",
+     "int64_t hi = ncols - d < nrows ? ncols - d : nrows;",
+     "int64_t hi = nrows - d < nrows ? nrows - d : nrows;",
+     [pins.test_split_band_full_rectangular_and_stencil]),
     ("features_variance_not_normalised",
      "var = nrows ? var / (double)nrows : 0.0;",
      "var = var;",
