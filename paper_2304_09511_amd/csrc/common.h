@@ -103,6 +103,12 @@ struct DiaPlan {
 struct CooPlan {
     void *carry = nullptr; // [2*ntiles] values: head partial, tail partial
     int64_t ntiles = 0;
+    // Row-pointer tiles (the CSR tiling; used when no tile owns more rows
+    // than fit in LDS): first owned row and extension/carry word per tile.
+    bool rows = false;
+    int32_t *tile_row = nullptr; // [ntiles + 1]
+    int32_t *tile_info = nullptr; // [ntiles]
+    bool fixup = false;           // some row is longer than its owner's window
 };
 
 }  // namespace mxs
@@ -123,6 +129,8 @@ struct mxs_mat_s {
     mxs::CsrPlan csr;
     mxs::CooPlan coo;
     mxs::DiaPlan dia;
+    mxs_mat_s *band = nullptr; // HDC: the DIA band (owned by this handle)
+    mxs_mat_s *rest = nullptr; // HDC: the COO or CSR remainder (owned)
 };
 
 namespace mxs {
@@ -247,6 +255,16 @@ int64_t spmv_dot_parts(const mxs_mat_s *A);
 // Capacity of every partials array (workgroups of any reducing launch).
 constexpr int64_t kMaxParts = 1 << 18;
 mxs_status build_plan(mxs_mat_s *A, hipStream_t s);
+// spmv.hip: y += A x for a COO or CSR handle (the remainder of a split).
+mxs_status spmv_acc_launch(const mxs_mat_s *A, const void *x, void *y, const int *done,
+                           hipStream_t s);
+
+// split.hip
+mxs_status split_size(const mxs_mat_s *A, double min_fill, int32_t *band_ndiag, int64_t *rest_nnz,
+                      hipStream_t s); // syncs
+mxs_status split(const mxs_mat_s *A, double min_fill, mxs_format rest_fmt, int32_t *band_doff,
+                 void *band_vals, int32_t *rest_idx0, int32_t *rest_idx1, void *rest_vals,
+                 mxs_mat_s **out, hipStream_t s); // syncs
 
 // scan.hip
 // out[i] = sum_{k<i} in[k] for i in [0, n]; out has n+1 entries (the total

@@ -192,6 +192,10 @@ __global__ void csr_tile_info_kernel(const int32_t *__restrict__ irp, const int3
     if (v & kCsrLastCarry) atomicOr(any_carry, 1);
 }
 
+#ifndef MXS_COO_ROWS
+#define MXS_COO_ROWS 1 // 1: COO on the CSR tiling when every tile's rows fit in LDS
+#endif
+
 #ifndef MXS_CSR_TRIM
 #define MXS_CSR_TRIM 1 // 1: waves skip the second row-pointer load and extension loads they do not need
 #endif
@@ -214,7 +218,7 @@ __global__ __launch_bounds__(256) MXS_CSR_ATTR void csr_spmv_kernel(
     const int32_t *__restrict__ irp, const int32_t *__restrict__ aj, const T *__restrict__ av,
     const T *__restrict__ x, T *__restrict__ y, const int32_t *__restrict__ tile_row,
     const int32_t *__restrict__ tile_info, int64_t nnz, int64_t ntiles, int64_t per,
-    T *__restrict__ carry, const int *__restrict__ done, double *__restrict__ partials)
+    T *__restrict__ carry, const int *__restrict__ done, double *__restrict__ partials, int acc)
 {
     using C = CsrCfg<T>;
     constexpr int NT = C::NT, IPT = C::IPT, TILE = C::TILE, EXT = C::EXT, RMAX = C::RMAX;
@@ -300,8 +304,9 @@ __global__ __launch_bounds__(256) MXS_CSR_ATTR void csr_spmv_kernel(
                 if (last_carry && r == nr - 1) {
                     carry[2 * tile + 1] = sum;
                 } else {
-                    y[r_lo + r] = sum;
-                    if (DOT) dpart += (double)sum * (double)x[r_lo + r];
+                    const T yv = acc ? y[r_lo + r] + sum : sum;
+                    y[r_lo + r] = yv;
+                    if (DOT) dpart += (double)yv * (double)x[r_lo + r];
                 }
             }
         }
@@ -320,7 +325,7 @@ __global__ __launch_bounds__(256) void csr_fixup_kernel(
     const int32_t *__restrict__ irp, const int32_t *__restrict__ tile_row,
     const int32_t *__restrict__ tile_info, const T *__restrict__ carry, const T *__restrict__ x,
     T *__restrict__ y, int64_t nnz, int64_t ntiles, int tile, const int *__restrict__ done,
-    double *__restrict__ partials)
+    double *__restrict__ partials, int acc)
 {
     __shared__ double red[256 / kWave];
     if (done && *done) return;
@@ -334,6 +339,7 @@ __global__ __launch_bounds__(256) void csr_fixup_kernel(
             v += carry[2 * u];
             if (end <= min(nnz, (u + 1) * (int64_t)tile)) break;
         }
+        if (acc) v += y[r];
         y[r] = v;
         if (DOT) d = (double)v * (double)x[r];
     }
@@ -672,7 +678,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void coo_spmv_kernel(
     int64_t nnz, int32_t nrows, const int32_t *__restrict__ ai, const int32_t *__restrict__ aj,
     const T *__restrict__ av, const T *__restrict__ x, T *__restrict__ y, T *__restrict__ carry,
-    int64_t ntiles, int64_t per, const int *__restrict__ done)
+    int64_t ntiles, int64_t per, const int *__restrict__ done, int acc)
 {
     constexpr int NT = kCooNT, IPT = kCooIPT, TILE = kCooTile;
     constexpr int PADDED = TILE + TILE / IPT;
@@ -738,9 +744,10 @@ __global__ __launch_bounds__(256) void coo_spmv_kernel(
             if (rw != pr) {
                 if (j > 0) {
                     if (tile_cont && pr == first_row) carry[2 * tile] = s;
-                    else y[pr] = s;
+                    else y[pr] = acc ? y[pr] + s : s;
                 }
-                for (int32_t z = pr + 1; z < rw; ++z) y[z] = T(0); // rows without entries
+                if (!acc)
+                    for (int32_t z = pr + 1; z < rw; ++z) y[z] = T(0); // rows without entries
                 s = T(0);
             }
             s += sval[coo_pad(j)];
@@ -753,8 +760,8 @@ __global__ __launch_bounds__(256) void coo_spmv_kernel(
                 carry[2 * tile + (is_cont ? 0 : 1)] = s;
             } else {
                 if (is_cont) carry[2 * tile] = s;
-                else y[last] = s;
-                if (k0 + n == nnz)
+                else y[last] = acc ? y[last] + s : s;
+                if (k0 + n == nnz && !acc)
                     for (int32_t z = last + 1; z < nrows; ++z) y[z] = T(0);
             }
         }
@@ -762,12 +769,142 @@ __global__ __launch_bounds__(256) void coo_spmv_kernel(
     }
 }
 
+// COO on the CSR tiling.  The plan (computed once from the row ids) gives
+// each tile of TILE entries its first owned row -- the rows whose first entry
+// lies in the tile -- and how far its last row reaches past the tile.  The
+// kernel loads row ids with the columns and values, stages products and row
+// ids in LDS, and rebuilds the owned rows' local start positions: an entry
+// whose row differs from the previous entry's opens that row, and the empty
+// rows before it start at the same position.  Rows are then reduced by lane
+// groups as in CSR; rows longer than the owner's window leave carries.
+constexpr int kCooRowsMax = 512; // owned rows per tile whose starts fit in LDS
+
+template <typename T>
+__global__ __launch_bounds__(256) void coo_rows_kernel(
+    const int32_t *__restrict__ ai, const int32_t *__restrict__ aj, const T *__restrict__ av,
+    const T *__restrict__ x, T *__restrict__ y, const int32_t *__restrict__ tile_row,
+    const int32_t *__restrict__ tile_info, int64_t nnz, int64_t ntiles, int64_t per,
+    T *__restrict__ carry, const int *__restrict__ done, int acc)
+{
+    using C = CsrCfg<T>;
+    constexpr int NT = C::NT, IPT = C::IPT, TILE = C::TILE, EXT = C::EXT, RM = kCooRowsMax;
+    static_assert(EXT == NT, "one overflow entry per thread");
+    __shared__ T prod[TILE + EXT];
+    __shared__ int32_t srow[TILE];
+    __shared__ int32_t lrp[RM + 1];
+    __shared__ double red[NT / kWave];
+    if (done && *done) return;
+    const int tid = threadIdx.x;
+    const int64_t g = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t t_lo = g * per, t_hi = min(ntiles, t_lo + per);
+    for (int64_t tile = t_lo; tile < t_hi; ++tile) {
+        const int64_t k0 = tile * TILE;
+        const int32_t n = (int32_t)min((int64_t)TILE, nnz - k0);
+        const int32_t r_lo = tile_row[tile], r_hi = tile_row[tile + 1];
+        const int32_t info = tile_info[tile];
+        const int32_t nr = r_hi - r_lo; // at most RM (checked by the plan)
+        const int32_t n_ext = info & 0xffff;
+        const bool head_carry = info & kCsrHeadCarry;
+        const bool last_carry = info & kCsrLastCarry;
+        const int32_t lim = n + n_ext; // local end of the entries loaded
+        const int32_t prev_row = k0 > 0 ? ai[k0 - 1] : -1;
+        const bool ext_wave = (tid & ~(kWave - 1)) < n_ext; // uniform per wave
+        {
+            // matrix loads unconditional (clamped indices) so they issue back to back
+            const int32_t *__restrict__ aib = ai + k0;
+            const int32_t *__restrict__ ajb = aj + k0;
+            const T *__restrict__ avb = av + k0;
+            int32_t row[IPT], col[IPT + 1];
+            T val[IPT + 1], xv[IPT + 1];
+#pragma unroll
+            for (int e = 0; e < IPT; ++e) col[e] = ld_stream(&ajb[(uint32_t)min(e * NT + tid, n - 1)]);
+            const uint32_t ke = (uint32_t)(n + min(tid, max(n_ext - 1, 0)));
+            col[IPT] = ext_wave ? ld_stream(&ajb[ke]) : 0;
+#pragma unroll
+            for (int e = 0; e < IPT; ++e) val[e] = ld_stream(&avb[(uint32_t)min(e * NT + tid, n - 1)]);
+            val[IPT] = ext_wave ? ld_stream(&avb[ke]) : T(0);
+#pragma unroll
+            for (int e = 0; e < IPT; ++e) row[e] = ld_stream(&aib[(uint32_t)min(e * NT + tid, n - 1)]);
+#pragma unroll
+            for (int e = 0; e < IPT; ++e) xv[e] = x[(uint32_t)col[e]];
+            xv[IPT] = ext_wave ? x[(uint32_t)col[IPT]] : T(0);
+#pragma unroll
+            for (int e = 0; e < IPT; ++e) {
+                const int j = e * NT + tid;
+                if (j < n) {
+                    prod[j] = val[e] * xv[e];
+                    srow[j] = row[e];
+                }
+            }
+            if (tid < n_ext) prod[n + tid] = val[IPT] * xv[IPT];
+        }
+        // owned rows without a start in the tile are the empty rows at the end
+        for (int q = tid; q <= nr; q += NT) lrp[q] = lim;
+        __syncthreads();
+        for (int j = tid; j < n; j += NT) {
+            const int32_t R = srow[j];
+            const int32_t P = j == 0 ? prev_row : srow[j - 1];
+            if (R != P) {
+                const int32_t q_hi = min(R, r_hi - 1);
+                for (int32_t q = max(P + 1, r_lo); q <= q_hi; ++q) lrp[q - r_lo] = j;
+            }
+        }
+        __syncthreads();
+        if (head_carry) {
+            // piece of a long row that began in an earlier tile
+            const int32_t hl = min(lrp[0], n);
+            T hs = T(0);
+            for (int j = tid; j < hl; j += NT) hs += prod[j];
+            const double tot = block_sum<NT>((double)hs, red);
+            if (tid == 0) carry[2 * tile] = (T)tot;
+        }
+        // lane-group size: the largest power of two G <= 64 with G*nr <= NT
+        int G = 64;
+        while (G > 1 && G * nr > NT) G >>= 1;
+        const int lane = tid & (G - 1);
+        const int ngrp = NT / G;
+        for (int r = tid / G; r < nr; r += ngrp) {
+            T sum = T(0);
+            const int e = min(lrp[r + 1], lim);
+            for (int k = lrp[r] + lane; k < e; k += G) sum += prod[k];
+            for (int off = G >> 1; off > 0; off >>= 1) sum += __shfl_xor(sum, off, kWave);
+            if (lane == 0) {
+                if (last_carry && r == nr - 1) carry[2 * tile + 1] = sum;
+                else y[r_lo + r] = acc ? y[r_lo + r] + sum : sum;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Rows longer than their owner's window: the owner's tail piece plus the head
+// pieces of the following tiles, in tile order, while the row continues.
+template <typename T>
+__global__ void coo_rows_fixup_kernel(const int32_t *__restrict__ ai,
+                                      const int32_t *__restrict__ tile_row,
+                                      const int32_t *__restrict__ tile_info,
+                                      const T *__restrict__ carry, T *__restrict__ y, int64_t nnz,
+                                      int64_t ntiles, int tile, const int *__restrict__ done, int acc)
+{
+    if (done && *done) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles || !(tile_info[t] & kCsrLastCarry)) return;
+    const int32_t r = tile_row[t + 1] - 1;
+    T v = carry[2 * t + 1];
+    for (int64_t u = t + 1; u < ntiles; ++u) {
+        v += carry[2 * u];
+        const int64_t ue = (u + 1) * (int64_t)tile; // first entry after tile u
+        if (ue >= nnz || ai[ue] != r) break;
+    }
+    y[r] = acc ? y[r] + v : v;
+}
+
 // Adds the pieces of rows that span tiles, in tile order.  The owner of such
 // a row is the tile holding its first entry.
 template <typename T>
 __global__ void coo_fixup_kernel(int64_t nnz, const int32_t *__restrict__ ai,
                                  const T *__restrict__ carry, T *__restrict__ y, int64_t ntiles,
-                                 const int *__restrict__ done)
+                                 const int *__restrict__ done, int acc)
 {
     constexpr int TILE = kCooTile;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -785,7 +922,7 @@ __global__ void coo_fixup_kernel(int64_t nnz, const int32_t *__restrict__ ai,
         const int64_t ue = min(nnz, (u + 1) * TILE);
         if (ai[ue - 1] != last || ue >= nnz || ai[ue] != last) break;
     }
-    y[last] = v;
+    y[last] = acc ? y[last] + v : v;
 }
 
 template <typename T>
@@ -861,7 +998,7 @@ static uint32_t fixup_grid(int64_t ntiles) { return (uint32_t)std::max<int64_t>(
 
 int64_t spmv_dot_parts(const mxs_mat_s *A)
 {
-    if (A->fmt == MXS_COO) return kDotGridMax;
+    if (A->fmt == MXS_COO || A->fmt == MXS_HDC) return kDotGridMax;
     uint32_t grid;
     int64_t per;
     if (A->dtype == MXS_F64) spmv_grid<double>(A, true, &grid, &per);
@@ -986,23 +1123,86 @@ static mxs_status build_dia_plan(mxs_mat_s *A, hipStream_t s)
     return MXS_OK;
 }
 
+// Largest number of rows any tile owns.
+__global__ void tile_rows_max_kernel(const int32_t *__restrict__ tile_row, int64_t ntiles,
+                                     int *__restrict__ out)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < ntiles) atomicMax(out, tile_row[t + 1] - tile_row[t]);
+}
+
+mxs_status coo_irp_launch(int64_t nnz, int32_t nrows, const int32_t *ai, int32_t *irp,
+                          hipStream_t s);
+
+// COO plan: the CSR tiling derived from the row ids through a temporary row
+// pointer array (freed here), kept when every tile owns at most kCooRowsMax
+// rows; otherwise the segmented-scan tiles.
+static mxs_status build_coo_plan(mxs_mat_s *A, hipStream_t s)
+{
+    A->coo = CooPlan{};
+    if (A->nnz == 0) return MXS_OK;
+    const int tile = csr_tile(A->dtype);
+    const int64_t nt = (A->nnz + tile - 1) / tile;
+    int32_t *irp = nullptr;
+    int *flags = nullptr; // [0] any carry, [1] most rows in a tile
+    MXS_HIP(hipMallocAsync((void **)&irp, sizeof(int32_t) * ((size_t)A->nrows + 1), s));
+    MXS_HIP(hipMallocAsync((void **)&flags, 2 * sizeof(int), s));
+    int32_t *buf = nullptr;
+    if (hipMalloc((void **)&buf, sizeof(int32_t) * (2 * (size_t)nt + 1)) != hipSuccess) {
+        (void)hipFreeAsync(irp, s);
+        (void)hipFreeAsync(flags, s);
+        (void)hipStreamSynchronize(s);
+        return MXS_ERR_OUT_OF_MEMORY;
+    }
+    A->owned.push_back(buf);
+    int32_t *tile_row = buf, *info = buf + nt + 1;
+    mxs_status st = coo_irp_launch(A->nnz, A->nrows, A->idx0, irp, s);
+    if (st == MXS_OK) st = fill_i32(flags, 0, 2, s);
+    int h[2] = {0, 0};
+    if (st == MXS_OK) {
+        const uint32_t g = (uint32_t)((nt + 1 + 255) / 256);
+        const int ext = A->dtype == MXS_F64 ? CsrCfg<double>::EXT : CsrCfg<float>::EXT;
+        csr_tile_rows_kernel<<<g, 256, 0, s>>>(irp, A->nrows, nt, tile, tile_row);
+        csr_tile_info_kernel<<<g, 256, 0, s>>>(irp, tile_row, A->nnz, nt, tile, ext, info, flags);
+        tile_rows_max_kernel<<<g, 256, 0, s>>>(tile_row, nt, flags + 1);
+        st = launch_status();
+        if (st == MXS_OK &&
+            hipMemcpyAsync(h, flags, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess)
+            st = MXS_ERR_HIP;
+    }
+    (void)hipFreeAsync(irp, s);
+    (void)hipFreeAsync(flags, s);
+    MXS_HIP(hipStreamSynchronize(s));
+    if (st != MXS_OK) return st;
+    if (MXS_COO_ROWS && h[1] <= kCooRowsMax) {
+        A->coo.rows = true;
+        A->coo.tile_row = tile_row;
+        A->coo.tile_info = info;
+        A->coo.fixup = h[0] != 0;
+        A->coo.ntiles = nt;
+    } else {
+        A->coo.ntiles = (A->nnz + kCooTile - 1) / kCooTile;
+    }
+    void *carry = nullptr;
+    MXS_HIP(hipMalloc(&carry, 2 * (size_t)A->coo.ntiles * dsize(A->dtype)));
+    A->owned.push_back(carry);
+    A->coo.carry = carry;
+    return MXS_OK;
+}
+
 mxs_status build_plan(mxs_mat_s *A, hipStream_t s)
 {
     if (A->optimized) return MXS_OK;
     mxs_status st = MXS_OK;
-    if (A->fmt == MXS_CSR) {
+    if (A->fmt == MXS_HDC) {
+        st = build_plan(A->band, s);
+        if (st == MXS_OK) st = build_plan(A->rest, s);
+    } else if (A->fmt == MXS_CSR) {
         st = build_csr_plan(A, s);
     } else if (A->fmt == MXS_DIA) {
         st = build_dia_plan(A, s);
     } else {
-        const int64_t nt = (A->nnz + kCooTile - 1) / kCooTile;
-        void *carry = nullptr;
-        if (nt > 0) {
-            MXS_HIP(hipMalloc(&carry, 2 * (size_t)nt * dsize(A->dtype)));
-            A->owned.push_back(carry);
-        }
-        A->coo.carry = carry;
-        A->coo.ntiles = nt;
+        st = build_coo_plan(A, s);
     }
     if (st == MXS_OK) A->optimized = true;
     return st;
@@ -1029,7 +1229,7 @@ mxs_status dot_sigma_launch(int64_t n, mxs_dtype t, const void *a, const void *b
 
 template <typename T>
 static mxs_status spmv_typed(const mxs_mat_s *A, const T *x, T *y, const int *done,
-                             const DotSink *dot, hipStream_t s)
+                             const DotSink *dot, hipStream_t s, int acc)
 {
     if (A->nrows == 0) return MXS_OK;
     uint32_t grid = 0;
@@ -1041,7 +1241,7 @@ static mxs_status spmv_typed(const mxs_mat_s *A, const T *x, T *y, const int *do
     case MXS_CSR: {
         const int64_t nt = A->csr.ntiles;
         if (nt == 0) {
-            fill_kernel<T><<<fill_g, 256, 0, s>>>(y, T(0), A->nrows, done);
+            if (!acc) fill_kernel<T><<<fill_g, 256, 0, s>>>(y, T(0), A->nrows, done);
             MXS_HIP(hipGetLastError());
             if (dot) return dot_sigma_typed<T>(A->nrows, x, y, done, dot, s);
             return MXS_OK;
@@ -1051,11 +1251,11 @@ static mxs_status spmv_typed(const mxs_mat_s *A, const T *x, T *y, const int *do
         if (dot)
             csr_spmv_kernel<T, true><<<grid, 256, 0, s>>>(A->idx0, A->idx1, (const T *)A->vals, x, y,
                                                           tr, ti, A->nnz, nt, per,
-                                                          (T *)A->csr.carry, done, parts);
+                                                          (T *)A->csr.carry, done, parts, acc);
         else
             csr_spmv_kernel<T, false><<<grid, 256, 0, s>>>(A->idx0, A->idx1, (const T *)A->vals, x,
                                                            y, tr, ti, A->nnz, nt, per,
-                                                           (T *)A->csr.carry, done, parts);
+                                                           (T *)A->csr.carry, done, parts, acc);
         MXS_HIP(hipGetLastError());
         nparts = grid;
         if (A->csr.fixup) {
@@ -1063,11 +1263,11 @@ static mxs_status spmv_typed(const mxs_mat_s *A, const T *x, T *y, const int *do
             if (dot)
                 csr_fixup_kernel<T, true><<<fg, 256, 0, s>>>(A->idx0, tr, ti, (const T *)A->csr.carry,
                                                              x, y, A->nnz, nt, csr_tile(A->dtype),
-                                                             done, parts + grid);
+                                                             done, parts + grid, acc);
             else
                 csr_fixup_kernel<T, false><<<fg, 256, 0, s>>>(A->idx0, tr, ti, (const T *)A->csr.carry,
                                                               x, y, A->nnz, nt, csr_tile(A->dtype),
-                                                              done, nullptr);
+                                                              done, nullptr, acc);
             MXS_HIP(hipGetLastError());
             nparts += fg;
         }
@@ -1094,15 +1294,26 @@ static mxs_status spmv_typed(const mxs_mat_s *A, const T *x, T *y, const int *do
     case MXS_COO: {
         const int64_t nt = A->coo.ntiles;
         if (nt == 0) {
-            fill_kernel<T><<<fill_g, 256, 0, s>>>(y, T(0), A->nrows, done);
+            if (!acc) fill_kernel<T><<<fill_g, 256, 0, s>>>(y, T(0), A->nrows, done);
         } else {
             spmv_grid<T>(A, false, &grid, &per);
-            coo_spmv_kernel<T><<<grid, kCooNT, 0, s>>>(A->nnz, A->nrows, A->idx0, A->idx1,
-                                                       (const T *)A->vals, x, y, (T *)A->coo.carry,
-                                                       nt, per, done);
-            MXS_HIP(hipGetLastError());
-            coo_fixup_kernel<T><<<(uint32_t)((nt + 255) / 256), 256, 0, s>>>(
-                A->nnz, A->idx0, (const T *)A->coo.carry, y, nt, done);
+            if (A->coo.rows) {
+                coo_rows_kernel<T><<<grid, 256, 0, s>>>(A->idx0, A->idx1, (const T *)A->vals, x, y,
+                                                        A->coo.tile_row, A->coo.tile_info, A->nnz,
+                                                        nt, per, (T *)A->coo.carry, done, acc);
+                MXS_HIP(hipGetLastError());
+                if (A->coo.fixup)
+                    coo_rows_fixup_kernel<T><<<(uint32_t)((nt + 255) / 256), 256, 0, s>>>(
+                        A->idx0, A->coo.tile_row, A->coo.tile_info, (const T *)A->coo.carry, y,
+                        A->nnz, nt, csr_tile(A->dtype), done, acc);
+            } else {
+                coo_spmv_kernel<T><<<grid, kCooNT, 0, s>>>(A->nnz, A->nrows, A->idx0, A->idx1,
+                                                           (const T *)A->vals, x, y,
+                                                           (T *)A->coo.carry, nt, per, done, acc);
+                MXS_HIP(hipGetLastError());
+                coo_fixup_kernel<T><<<(uint32_t)((nt + 255) / 256), 256, 0, s>>>(
+                    A->nnz, A->idx0, (const T *)A->coo.carry, y, nt, done, acc);
+            }
         }
         MXS_HIP(hipGetLastError());
         if (dot) return dot_sigma_typed<T>(A->nrows, x, y, done, dot, s);
@@ -1118,12 +1329,28 @@ static mxs_status spmv_typed(const mxs_mat_s *A, const T *x, T *y, const int *do
     return MXS_OK;
 }
 
+mxs_status spmv_acc_launch(const mxs_mat_s *A, const void *x, void *y, const int *done,
+                           hipStream_t s)
+{
+    if (A->fmt != MXS_COO && A->fmt != MXS_CSR) return MXS_ERR_UNSUPPORTED;
+    if (A->dtype == MXS_F64)
+        return spmv_typed<double>(A, (const double *)x, (double *)y, done, nullptr, s, 1);
+    return spmv_typed<float>(A, (const float *)x, (float *)y, done, nullptr, s, 1);
+}
+
 mxs_status spmv_launch(const mxs_mat_s *A, const void *x, void *y, const int *done,
                        const DotSink *dot, hipStream_t s)
 {
+    if (A->fmt == MXS_HDC) {
+        // the band writes every row; the remainder adds onto it
+        mxs_status st = spmv_launch(A->band, x, y, done, nullptr, s);
+        if (st == MXS_OK && A->rest->nnz > 0) st = spmv_acc_launch(A->rest, x, y, done, s);
+        if (st == MXS_OK && dot) st = dot_sigma_launch(A->nrows, A->dtype, y, x, done, dot, s);
+        return st;
+    }
     if (A->dtype == MXS_F64)
-        return spmv_typed<double>(A, (const double *)x, (double *)y, done, dot, s);
-    return spmv_typed<float>(A, (const float *)x, (float *)y, done, dot, s);
+        return spmv_typed<double>(A, (const double *)x, (double *)y, done, dot, s, 0);
+    return spmv_typed<float>(A, (const float *)x, (float *)y, done, dot, s, 0);
 }
 
 }  // namespace mxs

@@ -290,3 +290,36 @@ def test_dia_offset_structures(gpu, offsets, n):
     ref32 = orc.coo_spmv(n, a.ai, a.aj, a.av.astype(np.float32).astype(np.float64),
                          x.astype(np.float32).astype(np.float64))
     assert np.all(np.abs(y32 - ref32) <= row_bound(a, x, U32) + 1e-30)
+
+
+def _gappy(nrows, seed, lead=37, trail=53, p_empty=0.3, max_len=40, long_rows=()):
+    """Rows with 1..max_len entries, about p_empty of them empty, `lead` empty
+    rows first and `trail` empty rows last; rows listed in long_rows get 3,000
+    entries (they span tiles)."""
+    g = wl.rng(seed)
+    ncols = 5000
+    ai, aj = [], []
+    for r in range(lead, nrows - trail):
+        k = 3000 if r in long_rows else (0 if g.random() < p_empty else int(g.integers(1, max_len + 1)))
+        if k:
+            ai.append(np.full(k, r))
+            aj.append(np.sort(g.choice(ncols, k, replace=False)))
+    ai = np.concatenate(ai).astype(np.int32)
+    aj = np.concatenate(aj).astype(np.int32)
+    av = g.integers(-3, 4, ai.size).astype(np.float64)
+    av[av == 0] = 2.0
+    return wl.Coo(nrows, ncols, ai, aj, av)
+
+
+@pytest.mark.parametrize("long_rows", [(), (500, 501, 2200)], ids=["short", "long"])
+def test_coo_empty_rows_inside_and_around_tiles(gpu, long_rows):
+    """COO and CSR on rows with gaps (leading, trailing, inside tiles) and rows
+    that span several tiles: integer data bit-exact, every empty row zero."""
+    a = _gappy(4000, seed=len(long_rows) + 1, long_rows=set(long_rows))
+    x = wl.integer_vector(a.ncols, seed=2)
+    ref = orc.coo_spmv(a.nrows, a.ai, a.aj, a.av, x)
+    for fmt in ("coo", "csr"):
+        A = build(gpu, a, fmt)
+        y = to_dev(np.full(a.nrows, np.nan))
+        gpu.spmv(A, to_dev(x), y)
+        assert np.array_equal(y.cpu().numpy(), ref), fmt
