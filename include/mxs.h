@@ -51,7 +51,7 @@ typedef enum {
     MXS_ERR_UNSUPPORTED = -10    /* operation not defined for this format/dtype/shape */
 } mxs_status;
 
-typedef enum { MXS_COO = 0, MXS_CSR = 1, MXS_DIA = 2 } mxs_format;
+typedef enum { MXS_COO = 0, MXS_CSR = 1, MXS_DIA = 2, MXS_HDC = 3 } mxs_format;
 typedef enum { MXS_F64 = 0, MXS_F32 = 1 } mxs_dtype;
 
 /* Opaque host-side handle of a sparse matrix in one storage format. */
@@ -236,6 +236,35 @@ mxs_status mxs_cg_workspace_size(mxs_mat A, int32_t mixed, size_t *bytes);
 mxs_status mxs_cg_solve(mxs_mat A, mxs_mat A32, const double *b, double *x,
                         const mxs_cg_opts *opts, mxs_cg_result *res, void *workspace,
                         size_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Split matrices (MXS_HDC): a DIA band plus a remainder.  The hybrid
+ * DIA/CSR format is among the further formats of Section IX; the
+ * distributed HPCG runs of Section VII-D split each process's matrix into a
+ * local part and a remote part with separate formats (Table III).
+ * --------------------------------------------------------------------- */
+
+/* Sizes of the split of A (COO or CSR) [syncs]: the band is the diagonals
+ * that hold at least one entry and at least min_fill times as many entries
+ * as they have slots inside the matrix (compared in FP64); *band_ndiag gets
+ * their number and *rest_nnz the number of entries off them. */
+mxs_status mxs_split_size(mxs_mat A, double min_fill, int32_t *band_ndiag, int64_t *rest_nnz,
+                          void *stream);
+
+/* Splits A (COO or CSR) [syncs] into caller-allocated arrays: the band as
+ * DIA (band_doff[band_ndiag] ascending, band_vals[band_ndiag*nrows]
+ * diagonal-major with +0.0 in empty slots) and the remaining entries in
+ * rest_format, MXS_COO (rest_idx0 = row ids [rest_nnz]) or MXS_CSR
+ * (rest_idx0 = row pointers [nrows+1]), with rest_idx1 = columns and
+ * rest_vals = values [rest_nnz], in canonical order.  *out is an MXS_HDC
+ * handle that borrows all of these arrays (nnz = band in-range slots plus
+ * remainder entries; ndiag = band diagonals); mxs_spmv on it computes y = A x
+ * as the band's product plus the remainder's, and mxs_cg_solve accepts it
+ * (FP64, mixed = 0).  Conversion, cast and features of an MXS_HDC handle
+ * return MXS_ERR_UNSUPPORTED. */
+mxs_status mxs_split(mxs_mat A, double min_fill, mxs_format rest_format, int32_t *band_doff,
+                     void *band_vals, int32_t *rest_idx0, int32_t *rest_idx1, void *rest_vals,
+                     mxs_mat *out, void *stream);
 
 /* ------------------------------------------------------------------------
  * HPCG problem setup (Section VII-D: Poisson on a regular 3-D grid)

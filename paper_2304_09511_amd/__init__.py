@@ -22,12 +22,12 @@ __all__ = [
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = os.path.join(_HERE, "libmxs.so")
 
-COO, CSR, DIA = 0, 1, 2
+COO, CSR, DIA, HDC = 0, 1, 2, 3
 F64, F32 = 0, 1
 BORROW = 1
 NPARAM = 4931
 FORMATS = {"coo": COO, "csr": CSR, "dia": DIA}
-FORMAT_NAMES = {COO: "coo", CSR: "csr", DIA: "dia"}
+FORMAT_NAMES = {COO: "coo", CSR: "csr", DIA: "dia", HDC: "hdc"}
 
 STATUS = {
     0: "MXS_OK", 1: "MXS_NOT_CONVERGED", -1: "MXS_ERR_INVALID_ARG", -2: "MXS_ERR_INDEX_RANGE",
@@ -75,6 +75,8 @@ _SIGS = {
     "mxs_arrays": (I32, [P, P, P, P]),
     "mxs_convert_size": (I32, [P, I32, P, P, P]),
     "mxs_convert": (I32, [P, I32, P, P, P, P, P]),
+    "mxs_split_size": (I32, [P, D, P, P, P]),
+    "mxs_split": (I32, [P, D, I32, P, P, P, P, P, P, P]),
     "mxs_cast": (I32, [P, I32, P, P, P]),
     "mxs_optimize": (I32, [P, P]),
     "mxs_spmv": (I32, [P, P, P, P]),
@@ -271,6 +273,30 @@ class Matrix:
                                   _ptr(vals) if vals.numel() else None, C.byref(h), _stream()),
                "mxs_convert")
         return Matrix(h, [t for t in (i0, i1, vals) if t is not None])
+
+    def split_size(self, min_fill=0.5):
+        nd, rn = C.c_int32(), C.c_int64()
+        _check(load().mxs_split_size(self._h, min_fill, C.byref(nd), C.byref(rn), _stream()),
+               "mxs_split_size")
+        return nd.value, rn.value
+
+    def split(self, min_fill=0.5, rest="csr"):
+        """A DIA band (diagonals at least min_fill full) plus the remaining
+        entries in `rest` ("coo" or "csr"), as an HDC Matrix on fresh tensors."""
+        torch = _torch()
+        f = FORMATS.get(rest, rest)
+        nd, rn = self.split_size(min_fill)
+        dt = _torch_dtype(self.dtype)
+        doff = torch.empty(nd, dtype=torch.int32, device="cuda")
+        band = torch.empty(nd * self.nrows, dtype=dt, device="cuda")
+        i0 = torch.empty(self.nrows + 1 if f == CSR else rn, dtype=torch.int32, device="cuda")
+        i1 = torch.empty(rn, dtype=torch.int32, device="cuda")
+        vals = torch.empty(rn, dtype=dt, device="cuda")
+        h = C.c_void_p()
+        nz = lambda t: _ptr(t) if t.numel() else None
+        _check(load().mxs_split(self._h, min_fill, f, nz(doff), nz(band), nz(i0), nz(i1), nz(vals),
+                                C.byref(h), _stream()), "mxs_split")
+        return Matrix(h, [doff, band, i0, i1, vals])
 
     def cast(self, dtype):
         torch = _torch()

@@ -62,6 +62,8 @@ mxs_status guarded(F &&f)
 void release(mxs_mat_s *A)
 {
     if (!A) return;
+    release(A->band);
+    release(A->rest);
     for (void *p : A->owned)
         if (p) (void)hipFree(p);
     delete A;
@@ -277,6 +279,7 @@ mxs_status mxs_info(mxs_mat A, mxs_format *fmt, mxs_dtype *dtype, int32_t *nrows
 mxs_status mxs_arrays(mxs_mat A, const int32_t **idx0, const int32_t **idx1, const void **vals)
 {
     if (!A) return MXS_ERR_INVALID_ARG;
+    if (A->fmt == MXS_HDC) return MXS_ERR_UNSUPPORTED;
     if (idx0) *idx0 = A->idx0;
     if (idx1) *idx1 = A->idx1;
     if (vals) *vals = A->vals;
@@ -290,6 +293,7 @@ mxs_status mxs_convert_size(mxs_mat src, mxs_format dst, int64_t *count, int32_t
                             void *stream)
 {
     if (!src || !valid_format(dst)) return MXS_ERR_INVALID_ARG;
+    if (src->fmt == MXS_HDC) return MXS_ERR_UNSUPPORTED;
     return guarded([&] {
         int64_t c = 0;
         int32_t nd = 0;
@@ -305,6 +309,7 @@ mxs_status mxs_convert(mxs_mat src, mxs_format dst, int32_t *idx0, int32_t *idx1
                        mxs_mat *out, void *stream)
 {
     if (!src || !valid_format(dst) || !out) return MXS_ERR_INVALID_ARG;
+    if (src->fmt == MXS_HDC) return MXS_ERR_UNSUPPORTED;
     return guarded([&] {
         hipStream_t s = S(stream);
         int64_t count = 0;
@@ -340,6 +345,7 @@ mxs_status mxs_convert(mxs_mat src, mxs_format dst, int32_t *idx0, int32_t *idx1
 mxs_status mxs_cast(mxs_mat src, mxs_dtype dtype, void *vals, mxs_mat *out, void *stream)
 {
     if (!src || !valid_dtype(dtype) || !out) return MXS_ERR_INVALID_ARG;
+    if (src->fmt == MXS_HDC) return MXS_ERR_UNSUPPORTED;
     const int64_t n = value_count(src);
     if (n > 0 && !vals) return MXS_ERR_INVALID_ARG;
     return guarded([&] {
@@ -420,6 +426,7 @@ mxs_status mxs_cg_solve(mxs_mat A, mxs_mat A32, const double *b, double *x, cons
                         A32->ncols != A->ncols))
         return MXS_ERR_INVALID_ARG;
     if (opts->mixed < 0 || opts->mixed > 2) return MXS_ERR_INVALID_ARG;
+    if (opts->mixed && A->fmt == MXS_HDC) return MXS_ERR_UNSUPPORTED;
     if (!(opts->rtol >= 0.0) || opts->maxit < 0 || (opts->mixed == 1 && opts->max_outer < 0))
         return MXS_ERR_INVALID_ARG;
     if (opts->mixed == 2 && !(opts->ru_delta >= 0.0 && opts->ru_delta <= 1.0))
@@ -437,6 +444,42 @@ mxs_status mxs_cg_solve(mxs_mat A, mxs_mat A32, const double *b, double *x, cons
         }
         return cg_solve(A, opts->mixed ? A32 : nullptr, b, x, opts, res, workspace,
                         workspace_bytes, s);
+    });
+}
+
+// ---------------------------------------------------------------------------
+// Split matrices
+// ---------------------------------------------------------------------------
+mxs_status mxs_split_size(mxs_mat A, double min_fill, int32_t *band_ndiag, int64_t *rest_nnz,
+                          void *stream)
+{
+    if (!A || !band_ndiag || !rest_nnz || !(min_fill >= 0.0)) return MXS_ERR_INVALID_ARG;
+    if (A->fmt != MXS_COO && A->fmt != MXS_CSR) return MXS_ERR_UNSUPPORTED;
+    return guarded([&] { return split_size(A, min_fill, band_ndiag, rest_nnz, S(stream)); });
+}
+
+mxs_status mxs_split(mxs_mat A, double min_fill, mxs_format rest_format, int32_t *band_doff,
+                     void *band_vals, int32_t *rest_idx0, int32_t *rest_idx1, void *rest_vals,
+                     mxs_mat *out, void *stream)
+{
+    if (!A || !out || !(min_fill >= 0.0) || (rest_format != MXS_COO && rest_format != MXS_CSR))
+        return MXS_ERR_INVALID_ARG;
+    if (A->fmt != MXS_COO && A->fmt != MXS_CSR) return MXS_ERR_UNSUPPORTED;
+    if (rest_format == MXS_CSR && A->nrows > 0 && !rest_idx0) return MXS_ERR_INVALID_ARG;
+    return guarded([&] {
+        hipStream_t s = S(stream);
+        int32_t nd = 0;
+        int64_t rn = 0;
+        mxs_status st = split_size(A, min_fill, &nd, &rn, s);
+        if (st != MXS_OK) return st;
+        if ((nd > 0 && (!band_doff || !band_vals)) ||
+            (rn > 0 && (!rest_idx0 || !rest_idx1 || !rest_vals)))
+            return MXS_ERR_INVALID_ARG;
+        mxs_mat_s *h = nullptr;
+        st = split(A, min_fill, rest_format, band_doff, band_vals, rest_idx0, rest_idx1, rest_vals,
+                   &h, s);
+        if (st == MXS_OK) *out = h;
+        return st;
     });
 }
 
@@ -468,6 +511,7 @@ mxs_status mxs_stencil_coo(int32_t n, int32_t points, double diag, double offdia
 mxs_status mxs_features(mxs_mat A, double out[8], void *stream)
 {
     if (!A || !out) return MXS_ERR_INVALID_ARG;
+    if (A->fmt == MXS_HDC) return MXS_ERR_UNSUPPORTED;
     return guarded([&] { return features(A, out, S(stream)); });
 }
 
