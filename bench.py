@@ -56,6 +56,16 @@ def algorithmic_bytes(A, fmt, s=8):
     return s * A.nnz + 4 * A.ndiag + s * (A.ncols + A.nrows)  # DIA: nnz = in-range slots
 
 
+def split_bytes(H, rest):
+    """Algorithmic bytes of a split SpMV: the band as DIA, the remainder as
+    COO or CSR, x read once and y written once (the accumulate pass's read
+    of y is the method's own traffic and is not counted)."""
+    band_slots = H.nnz - H._keep[3].numel()
+    rn = H._keep[3].numel()
+    rest_bytes = rn * 16 if rest == "coo" else rn * 12 + 4 * (H.nrows + 1)
+    return 8 * band_slots + 4 * H.ndiag + rest_bytes + 8 * (H.ncols + H.nrows)
+
+
 def source_sha():
     return hashlib.sha256(open(SPMV_SRC, "rb").read()).hexdigest()[:16]
 
@@ -259,6 +269,9 @@ def irregular_runs(torch, mxs, checks):
         "banded_4M": ("11 distinct diagonal offsets uniform in [-2000, 2000], every in-range slot "
                       "N(0,1), 4,000,000 rows, seed 3",
                       lambda: wl.device_banded(4_000_000, 11, 2000, seed=3)),
+        "banded_noise_4M": ("the banded 4M matrix plus 1,600,000 entries at uniform random "
+                            "positions (long-range couplings), N(0,1), seed 3",
+                            lambda: wl.device_banded_noise(4_000_000, 11, 2000, 1_600_000, seed=3)),
     }
     out = {}
     for name, (desc, gen) in gens.items():
@@ -279,9 +292,12 @@ def irregular_runs(torch, mxs, checks):
                aj[sel].cpu().numpy(), av[sel].cpu().numpy())
         x_h = x.cpu().numpy()
         rec = {"workload": desc, "rows": nr, "nnz": coo.nnz, "x": "U[-1,1) (torch generator, seed 1)"}
-        for fmt in FORMATS:
+        fmts = FORMATS + (("hdc_csr", "hdc_coo") if "noise" in name else ())
+        for fmt in fmts:
             if fmt == "coo":
                 A = coo
+            elif fmt.startswith("hdc"):
+                A = coo.split(0.5, fmt[4:])
             else:
                 try:
                     A = coo.convert(fmt)
@@ -292,14 +308,17 @@ def irregular_runs(torch, mxs, checks):
                     raise
             A.optimize()
             tc = time_calls(torch, lambda: mxs.spmv(A, x, y))
-            nb = algorithmic_bytes(A, fmt)
+            nb = algorithmic_bytes(A, fmt) if not fmt.startswith("hdc") else split_bytes(A, fmt[4:])
             med = tc["median_ms"] * 1e-3
             rec[fmt] = {"us_per_call": round(med * 1e6, 2), "mean_us": round(tc["mean_ms"] * 1e3, 2),
                         "min_us": round(tc["min_ms"] * 1e3, 2), "algorithmic_bytes": nb,
                         "GBps": round(nb / med / 1e9, 1), "frac_of_peak": round(nb / med / 1e9 / PEAK_HBM_GBS, 4),
                         "GFLOPs": round(2 * coo.nnz / med / 1e9, 1)}
-            if fmt == "dia":
+            if fmt == "dia" or fmt.startswith("hdc"):
                 rec[fmt]["ndiag"] = A.ndiag
+            if fmt.startswith("hdc"):
+                rec[fmt]["band_diagonals_min_fill"] = 0.5
+                rec[fmt]["remainder_entries"] = int(A._keep[3].numel())
             checks.append({"name": f"{name}/{fmt}", "csr_rows": sub, "x": x_h, "y": y.cpu().numpy()[rows]})
             log(f"[bench] {name} {fmt}: {rec[fmt]['us_per_call']} us, {rec[fmt]['GBps']} GB/s, "
                 f"{rec[fmt]['GFLOPs']} GFLOP/s")

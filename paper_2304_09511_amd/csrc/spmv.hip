@@ -204,10 +204,6 @@ __global__ void csr_tile_info_kernel(const int32_t *__restrict__ irp, const int3
 #define MXS_DIA_YNT 1 // 1: DIA writes y with non-temporal stores
 #endif
 
-#ifndef MXS_CSR_LATE_RP
-#define MXS_CSR_LATE_RP 0 // 1: CSR issues its row-pointer loads after the matrix loads
-#endif
-
 #ifndef MXS_CSR_WPE
 #define MXS_CSR_WPE 0 // >0: ask the compiler for this many waves per SIMD
 #endif
@@ -244,25 +240,18 @@ __global__ __launch_bounds__(256) MXS_CSR_ATTR void csr_spmv_kernel(
         const int32_t n_ext = info & 0xffff;
         const bool head_carry = info & kCsrHeadCarry;
         const bool last_carry = info & kCsrLastCarry;
-#if !MXS_CSR_LATE_RP
         // row pointers of the owned rows (clamped indices, always in range)
         const int32_t lr = irp[r_lo + min(tid, nr)];
-#endif
 #if MXS_CSR_TRIM
         // the extension entries are read by the waves whose lanes reach them
         const bool ext_wave = (tid & ~(kWave - 1)) < n_ext; // uniform per wave
 #else
         const bool ext_wave = n_ext > 0;
 #endif
-#if !MXS_CSR_LATE_RP
 #if MXS_CSR_TRIM
         const int32_t lr_hi = nr >= NT ? irp[r_lo + min(tid + NT, nr)] : 0; // uniform test
 #else
         const int32_t lr_hi = irp[r_lo + min(tid + NT, nr)];
-#endif
-#endif
-#if MXS_CSR_LATE_RP
-        int32_t lr, lr_hi;
 #endif
         {
             // all matrix loads unconditional (lanes past the end re-read the
@@ -278,12 +267,6 @@ __global__ __launch_bounds__(256) MXS_CSR_ATTR void csr_spmv_kernel(
 #pragma unroll
             for (int e = 0; e < IPT; ++e) val[e] = ld_stream(&avb[(uint32_t)min(e * NT + tid, n - 1)]);
             val[IPT] = ext_wave ? ld_stream(&avb[ke]) : T(0);
-#if MXS_CSR_LATE_RP
-            // row pointers of the owned rows (clamped indices, always in
-            // range), issued behind the matrix loads
-            lr = irp[r_lo + min(tid, nr)];
-            lr_hi = nr >= NT ? irp[r_lo + min(tid + NT, nr)] : 0;
-#endif
 #pragma unroll
             for (int e = 0; e < IPT; ++e) xv[e] = x[(uint32_t)col[e]];
             xv[IPT] = ext_wave ? x[(uint32_t)col[IPT]] : T(0);

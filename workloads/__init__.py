@@ -387,3 +387,25 @@ def device_block_random(nblockrows: int, seed: int, max_blocks: int = 8, bs: int
     aj = (key % ncols).to(torch.int32)
     av = torch.randn(ai.numel(), generator=g, device=device, dtype=dtype)
     return nblockrows * bs, ncols, ai, aj, av
+
+
+def device_banded_noise(N: int, ndiag: int, max_offset: int, noise: int, seed: int, device="cuda",
+                        dtype=None):
+    """The banded matrix of device_banded plus `noise` entries at uniform
+    random positions (N(0,1) values; a position already on the band keeps the
+    band's value), sorted by (row, column)."""
+    import torch
+    dtype = dtype or torch.float64
+    nr, nc, ai, aj, av = device_banded(N, ndiag, max_offset, seed, device=device, dtype=dtype)
+    g = _tgen(seed + 1, device)
+    ni = torch.randint(0, N, (noise,), generator=g, device=device, dtype=torch.int64)
+    nj = torch.randint(0, N, (noise,), generator=g, device=device, dtype=torch.int64)
+    nv = torch.randn(noise, generator=g, device=device, dtype=dtype)
+    key = torch.cat([ai.long() * N + aj.long(), ni * N + nj])
+    val = torch.cat([av, nv])
+    key, order = torch.sort(key, stable=True)
+    val = val[order]
+    first = torch.ones_like(key, dtype=torch.bool)
+    first[1:] = key[1:] != key[:-1]
+    key, val = key[first], val[first]
+    return N, N, (key // N).to(torch.int32), (key % N).to(torch.int32), val.contiguous()
