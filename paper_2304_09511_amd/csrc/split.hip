@@ -29,12 +29,47 @@ uint32_t grid_of(int64_t n)
     return (uint32_t)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65536));
 }
 
-// count[j - i + nrows - 1] = entries on each diagonal
-__global__ void split_count_kernel(int64_t nnz, int32_t nrows, const int32_t *__restrict__ ai,
-                                   const int32_t *__restrict__ aj, int32_t *__restrict__ count)
+// count[j - i + nrows - 1] = entries on each diagonal.  A banded matrix has
+// few distinct diagonals, so each workgroup first counts its chunk of
+// entries in an LDS hash table keyed by diagonal (open addressing, a few
+// probes) and then adds one total per diagonal to the global counts; entries
+// that find no free slot are counted in global memory directly.
+constexpr int kHashSlots = 1024;
+constexpr int kHashProbes = 8;
+constexpr int64_t kCountChunk = 16384; // entries per workgroup
+constexpr uint32_t kHashEmpty = 0xffffffffu; // diagonal indices are below 2^32 - 1
+
+__global__ __launch_bounds__(256) void split_count_kernel(int64_t nnz, int32_t nrows,
+                                                          const int32_t *__restrict__ ai,
+                                                          const int32_t *__restrict__ aj,
+                                                          int32_t *__restrict__ count)
 {
-    SPLIT_LOOP(k, nnz)
-    atomicAdd(&count[(int64_t)aj[k] - ai[k] + nrows - 1], 1);
+    __shared__ uint32_t hkey[kHashSlots];
+    __shared__ int32_t hcnt[kHashSlots];
+    for (int i = threadIdx.x; i < kHashSlots; i += blockDim.x) {
+        hkey[i] = kHashEmpty;
+        hcnt[i] = 0;
+    }
+    __syncthreads();
+    const int64_t k0 = (int64_t)blockIdx.x * kCountChunk;
+    const int64_t k1 = min(nnz, k0 + kCountChunk);
+    for (int64_t k = k0 + threadIdx.x; k < k1; k += blockDim.x) {
+        const uint32_t key = (uint32_t)((int64_t)aj[k] - ai[k] + nrows - 1);
+        uint32_t slot = (key * 2654435761u) >> 22; // Fibonacci hashing to 10 bits
+        bool done = false;
+        for (int p = 0; p < kHashProbes && !done; ++p) {
+            const uint32_t old = atomicCAS(&hkey[slot], kHashEmpty, key);
+            if (old == kHashEmpty || old == key) {
+                atomicAdd(&hcnt[slot], 1);
+                done = true;
+            }
+            slot = (slot + 1) & (kHashSlots - 1);
+        }
+        if (!done) atomicAdd(&count[key], 1);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kHashSlots; i += blockDim.x)
+        if (hkey[i] != kHashEmpty) atomicAdd(&count[hkey[i]], hcnt[i]);
 }
 
 // keep[s] = 1 for band diagonals; *rest_nnz gets the entries of the others
@@ -151,7 +186,8 @@ mxs_status build_map(const mxs_mat_s *A, const int32_t *ai, double min_fill, Spl
     mxs_status st = fill_i32(m->count, 0, m->span, s);
     if (st == MXS_OK) st = fill_bytes0(m->rest, sizeof(unsigned long long), s);
     if (st != MXS_OK) return st;
-    split_count_kernel<<<grid_of(A->nnz), 256, 0, s>>>(A->nnz, A->nrows, ai, A->idx1, m->count);
+    split_count_kernel<<<(uint32_t)((A->nnz + kCountChunk - 1) / kCountChunk), 256, 0, s>>>(
+        A->nnz, A->nrows, ai, A->idx1, m->count);
     split_select_kernel<<<grid_of(m->span), 256, 0, s>>>(m->span, A->nrows, A->ncols, m->count,
                                                          min_fill, m->keep, m->rest);
     if ((st = launch_status()) != MXS_OK) return st;

@@ -162,3 +162,41 @@ def test_stencil192_mixed_refinement_matches_oracle(gpu, stencil192):
     xo = np.array(g["x_sample"])
     assert np.max(np.abs(x[idx].cpu().numpy() - xo)) / np.max(np.abs(xo)) <= 1e-5
     D32.close()
+
+
+def test_near_int32_entry_limit_all_formats(gpu):
+    """A ragged tridiagonal matrix (2, -1, -1) with 2^29 + 7 rows: 1.61e9
+    entries, close to the int32 entry limit, built on the device.  Integer x,
+    so every format must match the oracle exactly on 4,096 sampled rows (and
+    the two end rows)."""
+    import torch
+    mxs = gpu
+    N = (1 << 29) + 7
+    i = torch.arange(N, device="cuda", dtype=torch.int32)
+    # canonical order: row by row, columns i-1, i, i+1 where they exist
+    ai = torch.stack([i, i, i], 1).reshape(-1)
+    aj = torch.stack([i - 1, i, i + 1], 1).reshape(-1)
+    av = torch.tensor([-1.0, 2.0, -1.0], device="cuda", dtype=torch.float64).repeat(N)
+    keep = (aj >= 0) & (aj < N)
+    ai, aj, av = ai[keep], aj[keep], av[keep]
+    nnz = ai.numel()
+    assert nnz == 3 * N - 2 and nnz < 2 ** 31 - 1
+    A = mxs.Matrix.coo(N, N, ai, aj, av, borrow=True)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(3)
+    x = torch.randint(-8, 9, (N,), generator=g, device="cuda").double()
+    rows = np.unique(np.concatenate([wl.rng(4).choice(N, 4096, replace=False), [0, N - 1]]))
+    xr = x.cpu().numpy()
+    sub = [(r, c) for r in rows for c in (r - 1, r, r + 1) if 0 <= c < N]
+    si = np.array([np.searchsorted(rows, r) for r, _ in sub], np.int32)
+    sj = np.array([c for _, c in sub], np.int32)
+    sv = np.array([2.0 if r == c else -1.0 for r, c in sub])
+    ref = orc.coo_spmv(rows.size, si, sj, sv, xr)
+    for fmt in ("coo", "csr", "dia"):
+        B = A if fmt == "coo" else A.convert(fmt)
+        y = mxs.spmv(B, x)
+        assert np.array_equal(y[torch.from_numpy(rows).cuda()].cpu().numpy(), ref), fmt
+        if B is not A:
+            B.close()
+        del y
+        torch.cuda.empty_cache()
