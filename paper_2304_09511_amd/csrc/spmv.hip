@@ -262,10 +262,10 @@ __global__ __launch_bounds__(256) MXS_CSR_ATTR void csr_spmv_kernel(
             T val[IPT + 1], xv[IPT + 1];
 #pragma unroll
             for (int e = 0; e < IPT; ++e) col[e] = ld_stream(&ajb[(uint32_t)min(e * NT + tid, n - 1)]);
-            const uint32_t ke = (uint32_t)(n + min(tid, max(n_ext - 1, 0)));
-            col[IPT] = ext_wave ? ld_stream(&ajb[ke]) : 0;
 #pragma unroll
             for (int e = 0; e < IPT; ++e) val[e] = ld_stream(&avb[(uint32_t)min(e * NT + tid, n - 1)]);
+            const uint32_t ke = (uint32_t)(n + min(tid, max(n_ext - 1, 0)));
+            col[IPT] = ext_wave ? ld_stream(&ajb[ke]) : 0;
             val[IPT] = ext_wave ? ld_stream(&avb[ke]) : T(0);
 #pragma unroll
             for (int e = 0; e < IPT; ++e) xv[e] = x[(uint32_t)col[e]];
@@ -319,6 +319,41 @@ __global__ __launch_bounds__(256) MXS_CSR_ATTR void csr_spmv_kernel(
         const double bs = block_sum<NT>(dpart, red);
         if (tid == 0) partials[blockIdx.x] = bs;
     }
+}
+
+// Matrices with far more rows than entries (e.g. the remainder of a split):
+// fixed-size entry tiles would each own very many rows, so a thread takes a
+// row instead.  Rows are short here by construction (the average is below
+// one half), so the sequential inner loop is short.
+constexpr int64_t kRowwiseGridMax = 8192;
+
+template <typename T, bool DOT>
+__global__ __launch_bounds__(256) void csr_rowwise_kernel(
+    const int32_t *__restrict__ irp, const int32_t *__restrict__ aj, const T *__restrict__ av,
+    const T *__restrict__ x, T *__restrict__ y, int32_t nrows, const int *__restrict__ done,
+    double *__restrict__ partials, int acc)
+{
+    __shared__ double red[256 / kWave];
+    if (done && *done) return;
+    double dpart = 0.0;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nrows;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t k1 = irp[r + 1];
+        T s = T(0);
+        for (int32_t k = irp[r]; k < k1; ++k) s += av[k] * x[aj[k]];
+        const T yv = acc ? y[r] + s : s;
+        y[r] = yv;
+        if (DOT) dpart += (double)yv * (double)x[r];
+    }
+    if (DOT) {
+        const double bs = block_sum<256>(dpart, red);
+        if (threadIdx.x == 0) partials[blockIdx.x] = bs;
+    }
+}
+
+static uint32_t rowwise_grid(int32_t nrows)
+{
+    return (uint32_t)std::clamp<int64_t>(((int64_t)nrows + 255) / 256, 1, kRowwiseGridMax);
 }
 
 // Rows too long for their owner's overflow window: owner's tail piece plus
@@ -1002,6 +1037,7 @@ static uint32_t fixup_grid(int64_t ntiles) { return (uint32_t)std::max<int64_t>(
 int64_t spmv_dot_parts(const mxs_mat_s *A)
 {
     if (A->fmt == MXS_COO || A->fmt == MXS_HDC) return kDotGridMax;
+    if (A->fmt == MXS_CSR && A->csr.rowwise) return rowwise_grid(A->nrows);
     uint32_t grid;
     int64_t per;
     if (A->dtype == MXS_F64) spmv_grid<double>(A, true, &grid, &per);
@@ -1017,6 +1053,10 @@ static mxs_status build_csr_plan(mxs_mat_s *A, hipStream_t s)
     const int64_t nt = (A->nnz + tile - 1) / tile;
     A->csr.ntiles = nt;
     if (nt == 0) return MXS_OK;
+    if ((int64_t)A->nrows > 2 * A->nnz) {
+        A->csr.rowwise = true;
+        return MXS_OK;
+    }
     int32_t *buf = nullptr;
     // tile_row [nt+1], tile_info [nt], then one flag
     MXS_HIP(hipMalloc((void **)&buf, sizeof(int32_t) * (2 * (size_t)nt + 2)));
@@ -1248,6 +1288,19 @@ static mxs_status spmv_typed(const mxs_mat_s *A, const T *x, T *y, const int *do
             MXS_HIP(hipGetLastError());
             if (dot) return dot_sigma_typed<T>(A->nrows, x, y, done, dot, s);
             return MXS_OK;
+        }
+        if (A->csr.rowwise) {
+            grid = rowwise_grid(A->nrows);
+            if (dot)
+                csr_rowwise_kernel<T, true><<<grid, 256, 0, s>>>(A->idx0, A->idx1, (const T *)A->vals,
+                                                                 x, y, A->nrows, done, parts, acc);
+            else
+                csr_rowwise_kernel<T, false><<<grid, 256, 0, s>>>(A->idx0, A->idx1,
+                                                                  (const T *)A->vals, x, y, A->nrows,
+                                                                  done, nullptr, acc);
+            MXS_HIP(hipGetLastError());
+            nparts = grid;
+            break;
         }
         spmv_grid<T>(A, dot != nullptr, &grid, &per);
         const int32_t *tr = A->csr.tile_row, *ti = A->csr.tile_info;
