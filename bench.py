@@ -257,6 +257,19 @@ def compare_golden(section, name, x_by_fmt=None):
     return g
 
 
+def impl_report(mxs, A, x, y, reps=20):
+    """Every applicable implementation of A's format timed by mxs_tune (median
+    of `reps` calls after 3 warm-ups); the default implementation is restored
+    afterwards, so the other figures stay those of the default plan."""
+    names = mxs.Matrix.IMPL_NAMES[A.format]
+    default = A.impl
+    best, ms = A.tune(x, y, reps=reps)
+    A.impl = default
+    return {"default": names[default], "fastest": names[best],
+            "median_us": {names[i]: (None if m is None else round(m * 1e3, 2))
+                          for i, m in enumerate(ms)}}
+
+
 def irregular_runs(torch, mxs, checks):
     """SpMV on the two irregular 4,000,000-row workloads in every format the
     container accepts: protocol median of 10 x 100 calls, GB/s, GFLOP/s.  The
@@ -325,6 +338,9 @@ def irregular_runs(torch, mxs, checks):
             checks.append({"name": f"{name}/{fmt}", "csr_rows": sub, "x": x_h, "y": y.cpu().numpy()[rows]})
             log(f"[bench] {name} {fmt}: {rec[fmt]['us_per_call']} us, {rec[fmt]['GBps']} GB/s, "
                 f"{rec[fmt]['GFLOPs']} GFLOP/s")
+            if not fmt.startswith("hdc"):
+                rec[fmt]["implementations"] = impl_report(mxs, A, x, y)
+                log(f"[bench]   implementations: {rec[fmt]['implementations']['median_us']}")
             if A is not coo:
                 A.close()
         coo.close()
@@ -496,6 +512,10 @@ def main():
         per[f]["protocol_10x100"]["frac_of_peak"] = round(gbps / PEAK_HBM_GBS, 4)
         log(f"[bench]   {f} protocol (median of 10 x 100 back-to-back): "
             f"{tc['median_ms'] * 1e3:.2f} us, {gbps:.1f} GB/s ({100 * gbps / PEAK_HBM_GBS:.1f}%)")
+
+    for f in FORMATS:
+        per[f]["implementations"] = impl_report(mxs, mats[f], x, ys[f])
+        log(f"[bench]   {f} implementations (median us): {per[f]['implementations']['median_us']}")
 
     # dominant kernel of the step and its roofline
     dom = max(FORMATS, key=lambda f: per[f]["us_per_call"])

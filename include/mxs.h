@@ -160,10 +160,41 @@ mxs_status mxs_cast(mxs_mat src, mxs_dtype dtype, void *vals, mxs_mat *out, void
  * SpMV (Algorithms 1-3)
  * --------------------------------------------------------------------- */
 
-/* Builds the format's execution plan [syncs]: CSR row blocks of bounded
- * non-zero count (a single long row gets a block of its own), COO tile
- * carries.  Idempotent.  mxs_spmv runs it on first use if not called. */
+/* Builds the format's execution plan [syncs]: CSR and COO tiles of a fixed
+ * number of entries with their row starts and carries, a row-blocked copy of
+ * the DIA values (when its padding stays within nrows/8 rows), and what every
+ * implementation below needs.  Idempotent.  mxs_spmv runs it on first use if
+ * not called. */
 mxs_status mxs_optimize(mxs_mat A, void *stream);
+
+/* SpMV implementations (Section 3 keeps one kernel per format; no single
+ * kernel wins on every matrix, so each format here has several, all giving
+ * the same sums within rounding):
+ *   COO  0: row tiles (the CSR tiling rebuilt from the row ids; applicable
+ *           when no tile owns more than 512 rows)
+ *        1: segmented-scan tiles (always applicable)
+ *   CSR  0: tiles of a fixed number of entries   1: a thread per row
+ *   DIA  0: row-blocked values, one x load per run of three consecutive
+ *           offsets (needs the row-blocked copy and offsets in such runs)
+ *        1: row-blocked values (needs the copy)
+ *        2: diagonal-major values as stored (always applicable)
+ * After mxs_optimize the default is: COO 0 where applicable, else 1; CSR 1
+ * when nrows > 2*nnz, else 0; DIA the lowest applicable id.
+ * mxs_impl_count: number of ids of A's format (0 for split matrices).
+ * mxs_set_impl [syncs: builds the plan]: MXS_ERR_UNSUPPORTED for an id that
+ *   is not applicable to A or a split matrix.
+ * mxs_get_impl [syncs: builds the plan]: the active id.
+ * mxs_tune [syncs]: runs every applicable implementation (3 untimed calls,
+ *   then `reps` >= 1 timed calls y = A*x each), keeps the one with the
+ *   smallest median time and returns its id; ms[mxs_impl_count] (may be
+ *   NULL) receives each median in milliseconds, -1 where not applicable.
+ *   y is overwritten with A*x.  Split matrices: MXS_ERR_UNSUPPORTED.
+ * Changing the implementation must not overlap other calls on the handle. */
+int32_t mxs_impl_count(mxs_mat A);
+mxs_status mxs_set_impl(mxs_mat A, int32_t impl, void *stream);
+mxs_status mxs_get_impl(mxs_mat A, int32_t *impl, void *stream);
+mxs_status mxs_tune(mxs_mat A, const void *x, void *y, int32_t reps, int32_t *impl,
+                    double *ms, void *stream);
 
 /* y = A*x, overwriting y[nrows]; x has ncols entries [async].  Entry-wise
  * the result is sum over stored (i, j, v) of v*x[j] (Algorithm 1 with y

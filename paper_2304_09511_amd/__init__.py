@@ -79,6 +79,10 @@ _SIGS = {
     "mxs_split": (I32, [P, D, I32, P, P, P, P, P, P, P]),
     "mxs_cast": (I32, [P, I32, P, P, P]),
     "mxs_optimize": (I32, [P, P]),
+    "mxs_impl_count": (I32, [P]),
+    "mxs_set_impl": (I32, [P, I32, P]),
+    "mxs_get_impl": (I32, [P, P, P]),
+    "mxs_tune": (I32, [P, P, P, I32, P, P, P]),
     "mxs_spmv": (I32, [P, P, P, P]),
     "mxs_dot": (I32, [I64, I32, P, P, P, P]),
     "mxs_axpby": (I32, [I64, I32, D, P, D, P, P]),
@@ -319,6 +323,40 @@ class Matrix:
     def optimize(self):
         _check(load().mxs_optimize(self._h, _stream()), "mxs_optimize")
         return self
+
+    # SpMV implementations of the format (ids as in mxs_set_impl)
+    IMPL_NAMES = {COO: ("row_tiles", "segmented"), CSR: ("entry_tiles", "row_per_thread"),
+                  DIA: ("blocked_shared_x", "blocked", "diagonal_major")}
+
+    @property
+    def impl(self):
+        v = C.c_int32()
+        _check(load().mxs_get_impl(self._h, C.byref(v), _stream()), "mxs_get_impl")
+        return v.value
+
+    @impl.setter
+    def impl(self, i):
+        _check(load().mxs_set_impl(self._h, int(i), _stream()), "mxs_set_impl")
+
+    def impl_count(self):
+        return load().mxs_impl_count(self._h)
+
+    def tune(self, x, y=None, reps=10):
+        """Times every applicable implementation on y = A x, keeps the
+        fastest; returns (id, [median ms per id, None where not applicable])."""
+        torch = _torch()
+        if y is None:
+            y = torch.empty(self.nrows, dtype=x.dtype, device=x.device)
+        if _dtype_code(x) != self.dtype or _dtype_code(y) != self.dtype:
+            raise TypeError("x and y must have the matrix's dtype")
+        if x.numel() != self.ncols or y.numel() != self.nrows:
+            raise ValueError("vector lengths do not match the matrix")
+        n = max(self.impl_count(), 1)
+        ms = (C.c_double * n)()
+        best = C.c_int32()
+        _check(load().mxs_tune(self._h, _ptr(x), _ptr(y), int(reps), C.byref(best), ms,
+                               _stream()), "mxs_tune")
+        return best.value, [None if m < 0 else m for m in ms[:self.impl_count()]]
 
     def close(self):
         if self._h is not None and _lib is not None:

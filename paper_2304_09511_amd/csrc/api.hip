@@ -376,6 +376,53 @@ mxs_status mxs_optimize(mxs_mat A, void *stream)
     return guarded([&] { return ensure_plan(A, S(stream)); });
 }
 
+int32_t mxs_impl_count(mxs_mat A)
+{
+    return A ? impl_count(A) : 0;
+}
+
+mxs_status mxs_set_impl(mxs_mat A, int32_t impl, void *stream)
+{
+    if (!A) return MXS_ERR_INVALID_ARG;
+    if (A->fmt == MXS_HDC) return MXS_ERR_UNSUPPORTED;
+    return guarded([&] {
+        mxs_status st = ensure_plan(A, S(stream));
+        if (st != MXS_OK) return st;
+        std::lock_guard<std::mutex> lk(A->mu);
+        if (!impl_ok(A, impl)) return MXS_ERR_UNSUPPORTED;
+        set_impl(A, impl);
+        return MXS_OK;
+    });
+}
+
+mxs_status mxs_get_impl(mxs_mat A, int32_t *impl, void *stream)
+{
+    if (!A || !impl) return MXS_ERR_INVALID_ARG;
+    if (A->fmt == MXS_HDC) return MXS_ERR_UNSUPPORTED;
+    return guarded([&] {
+        mxs_status st = ensure_plan(A, S(stream));
+        if (st == MXS_OK) *impl = A->impl;
+        return st;
+    });
+}
+
+mxs_status mxs_tune(mxs_mat A, const void *x, void *y, int32_t reps, int32_t *impl, double *ms,
+                    void *stream)
+{
+    if (!A || reps < 1 || reps > 10000) return MXS_ERR_INVALID_ARG;
+    if (A->fmt == MXS_HDC) return MXS_ERR_UNSUPPORTED;
+    const size_t es = dsize(A->dtype);
+    if ((A->ncols > 0 && !x) || (A->nrows > 0 && !y)) return MXS_ERR_INVALID_ARG;
+    if (overlaps(x, es * A->ncols, y, es * A->nrows)) return MXS_ERR_INVALID_ARG;
+    return guarded([&] {
+        hipStream_t s = S(stream);
+        mxs_status st = ensure_plan(A, s);
+        if (st != MXS_OK) return st;
+        std::lock_guard<std::mutex> lk(A->mu);
+        return tune(A, x, y, reps, impl, ms, s);
+    });
+}
+
 mxs_status mxs_spmv(mxs_mat A, const void *x, void *y, void *stream)
 {
     if (!A) return MXS_ERR_INVALID_ARG;

@@ -99,17 +99,23 @@ struct DiaPlan {
     int32_t lds_elems = 0;   // x-window LDS per block in elements (0: windows off)
     int32_t first_off = 0, last_off = 0;
     int32_t triples = 0;     // 1: offsets form runs o, o+1, o+2 (ndiag a multiple of 3)
+    bool use_blk = false;    // the active implementation reads the row-blocked copy
+    bool use_share = false;  // ... and shares x loads over runs of three offsets
 };
 
 struct CooPlan {
+    // the active implementation's tiles and carries
+    bool rows = false;     // row tiles (else segmented-scan tiles)
     void *carry = nullptr; // [2*ntiles] values: head partial, tail partial
     int64_t ntiles = 0;
-    // Row-pointer tiles (the CSR tiling; used when no tile owns more rows
-    // than fit in LDS): first owned row and extension/carry word per tile.
-    bool rows = false;
-    int32_t *tile_row = nullptr; // [ntiles + 1]
-    int32_t *tile_info = nullptr; // [ntiles]
+    // Row tiles (the CSR tiling; possible when no tile owns more rows than
+    // fit in LDS): first owned row and extension/carry word per tile.
+    bool rows_ok = false;
+    int32_t *tile_row = nullptr; // [nt_rows + 1]
+    int32_t *tile_info = nullptr; // [nt_rows]
     bool fixup = false;           // some row is longer than its owner's window
+    int64_t nt_rows = 0, nt_seg = 0;
+    void *carry_rows = nullptr, *carry_seg = nullptr;
 };
 
 }  // namespace mxs
@@ -127,6 +133,7 @@ struct mxs_mat_s {
     int device = 0;
     std::mutex mu;
     bool optimized = false;
+    int32_t impl = -1; // active SpMV implementation (see mxs_set_impl)
     mxs::CsrPlan csr;
     mxs::CooPlan coo;
     mxs::DiaPlan dia;
@@ -256,6 +263,12 @@ int64_t spmv_dot_parts(const mxs_mat_s *A);
 // Capacity of every partials array (workgroups of any reducing launch).
 constexpr int64_t kMaxParts = 1 << 18;
 mxs_status build_plan(mxs_mat_s *A, hipStream_t s);
+// spmv.hip: the SpMV implementations of a format and the choice among them.
+int32_t impl_count(const mxs_mat_s *A);
+bool impl_ok(const mxs_mat_s *A, int32_t impl);
+void set_impl(mxs_mat_s *A, int32_t impl); // impl_ok(A, impl) holds
+mxs_status tune(mxs_mat_s *A, const void *x, void *y, int32_t reps, int32_t *impl_out,
+                double *ms, hipStream_t s); // syncs
 // spmv.hip: y += A x for a COO or CSR handle (the remainder of a split).
 mxs_status spmv_acc_launch(const mxs_mat_s *A, const void *x, void *y, const int *done,
                            hipStream_t s);

@@ -192,10 +192,6 @@ __global__ void csr_tile_info_kernel(const int32_t *__restrict__ irp, const int3
     if (v & kCsrLastCarry) atomicOr(any_carry, 1);
 }
 
-#ifndef MXS_COO_ROWS
-#define MXS_COO_ROWS 1 // 1: COO on the CSR tiling when every tile's rows fit in LDS
-#endif
-
 #ifndef MXS_CSR_TRIM
 #define MXS_CSR_TRIM 1 // 1: waves skip the second row-pointer load and extension loads they do not need
 #endif
@@ -1053,10 +1049,8 @@ static mxs_status build_csr_plan(mxs_mat_s *A, hipStream_t s)
     const int64_t nt = (A->nnz + tile - 1) / tile;
     A->csr.ntiles = nt;
     if (nt == 0) return MXS_OK;
-    if ((int64_t)A->nrows > 2 * A->nnz) {
-        A->csr.rowwise = true;
-        return MXS_OK;
-    }
+    // default: a thread per row when rows outnumber entries two to one
+    A->csr.rowwise = (int64_t)A->nrows > 2 * A->nnz;
     int32_t *buf = nullptr;
     // tile_row [nt+1], tile_info [nt], then one flag
     MXS_HIP(hipMalloc((void **)&buf, sizeof(int32_t) * (2 * (size_t)nt + 2)));
@@ -1217,19 +1211,118 @@ static mxs_status build_coo_plan(mxs_mat_s *A, hipStream_t s)
     (void)hipFreeAsync(flags, s);
     MXS_HIP(hipStreamSynchronize(s));
     if (st != MXS_OK) return st;
-    if (MXS_COO_ROWS && h[1] <= kCooRowsMax) {
-        A->coo.rows = true;
-        A->coo.tile_row = tile_row;
-        A->coo.tile_info = info;
-        A->coo.fixup = h[0] != 0;
-        A->coo.ntiles = nt;
-    } else {
-        A->coo.ntiles = (A->nnz + kCooTile - 1) / kCooTile;
-    }
+    A->coo.rows_ok = h[1] <= kCooRowsMax;
+    A->coo.tile_row = tile_row;
+    A->coo.tile_info = info;
+    A->coo.fixup = h[0] != 0;
+    A->coo.nt_rows = nt;
+    A->coo.nt_seg = (A->nnz + kCooTile - 1) / kCooTile;
+    // carries of either implementation (two values per tile)
+    const int64_t nc = std::max(A->coo.nt_rows, A->coo.nt_seg);
     void *carry = nullptr;
-    MXS_HIP(hipMalloc(&carry, 2 * (size_t)A->coo.ntiles * dsize(A->dtype)));
+    MXS_HIP(hipMalloc(&carry, 2 * (size_t)nc * dsize(A->dtype)));
     A->owned.push_back(carry);
-    A->coo.carry = carry;
+    A->coo.carry_rows = A->coo.carry_seg = carry;
+    return MXS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Implementations of each format's SpMV (no single one wins on every matrix):
+//   COO 0: row tiles (the CSR tiling rebuilt from the row ids)
+//       1: segmented-scan tiles
+//   CSR 0: entry tiles           1: a thread per row
+//   DIA 0: row-blocked values, x shared over runs of three offsets
+//       1: row-blocked values    2: diagonal-major values (no copy), x shared
+// ---------------------------------------------------------------------------
+int32_t impl_count(const mxs_mat_s *A)
+{
+    return A->fmt == MXS_DIA ? 3 : (A->fmt == MXS_COO || A->fmt == MXS_CSR) ? 2 : 0;
+}
+
+bool impl_ok(const mxs_mat_s *A, int32_t impl)
+{
+    if (impl < 0 || impl >= impl_count(A)) return false;
+    if (A->nnz == 0) return true;
+    switch (A->fmt) {
+    case MXS_COO: return impl == 1 || A->coo.rows_ok;
+    case MXS_CSR: return true;
+    case MXS_DIA:
+        if (impl == 0) return A->dia.blk != nullptr && A->dia.triples;
+        if (impl == 1) return A->dia.blk != nullptr;
+        return true;
+    default: return false;
+    }
+}
+
+static int32_t default_impl(const mxs_mat_s *A)
+{
+    switch (A->fmt) {
+    case MXS_COO: return impl_ok(A, 0) ? 0 : 1;
+    case MXS_CSR: return A->csr.rowwise ? 1 : 0;
+    case MXS_DIA: return impl_ok(A, 0) ? 0 : impl_ok(A, 1) ? 1 : 2;
+    default: return -1;
+    }
+}
+
+void set_impl(mxs_mat_s *A, int32_t impl)
+{
+    A->impl = impl;
+    switch (A->fmt) {
+    case MXS_COO:
+        A->coo.rows = impl == 0 && A->coo.rows_ok;
+        A->coo.ntiles = A->coo.rows ? A->coo.nt_rows : A->coo.nt_seg;
+        A->coo.carry = A->coo.rows ? A->coo.carry_rows : A->coo.carry_seg;
+        break;
+    case MXS_CSR: A->csr.rowwise = impl == 1; break;
+    case MXS_DIA:
+        A->dia.use_blk = impl != 2 && A->dia.blk != nullptr;
+        A->dia.use_share = impl != 1 && A->dia.triples;
+        break;
+    default: break;
+    }
+}
+
+mxs_status tune(mxs_mat_s *A, const void *x, void *y, int32_t reps, int32_t *impl_out,
+                double *ms, hipStream_t s)
+{
+    const int32_t n = impl_count(A);
+    std::vector<hipEvent_t> ev(2 * (size_t)reps);
+    for (auto &e : ev) MXS_HIP(hipEventCreate(&e));
+    auto destroy = [&] {
+        for (auto e : ev) (void)hipEventDestroy(e);
+    };
+    int32_t best = -1;
+    double best_ms = 0.0;
+    for (int32_t i = 0; i < n; ++i) {
+        if (ms) ms[i] = -1.0;
+        if (!impl_ok(A, i)) continue;
+        set_impl(A, i);
+        mxs_status st = MXS_OK;
+        for (int w = 0; w < 3 && st == MXS_OK; ++w) st = spmv_launch(A, x, y, nullptr, nullptr, s);
+        for (int r = 0; r < reps && st == MXS_OK; ++r) {
+            if (hipEventRecord(ev[2 * r], s) != hipSuccess) st = MXS_ERR_HIP;
+            if (st == MXS_OK) st = spmv_launch(A, x, y, nullptr, nullptr, s);
+            if (st == MXS_OK && hipEventRecord(ev[2 * r + 1], s) != hipSuccess) st = MXS_ERR_HIP;
+        }
+        if (st == MXS_OK && hipStreamSynchronize(s) != hipSuccess) st = MXS_ERR_HIP;
+        std::vector<float> t((size_t)reps);
+        for (int r = 0; r < reps && st == MXS_OK; ++r)
+            if (hipEventElapsedTime(&t[r], ev[2 * r], ev[2 * r + 1]) != hipSuccess) st = MXS_ERR_HIP;
+        if (st != MXS_OK) {
+            destroy();
+            return st;
+        }
+        std::nth_element(t.begin(), t.begin() + reps / 2, t.end());
+        const double med = t[reps / 2];
+        if (ms) ms[i] = med;
+        if (best < 0 || med < best_ms) {
+            best = i;
+            best_ms = med;
+        }
+    }
+    destroy();
+    set_impl(A, best);
+    if (impl_out) *impl_out = best;
     return MXS_OK;
 }
 
@@ -1247,7 +1340,10 @@ mxs_status build_plan(mxs_mat_s *A, hipStream_t s)
     } else {
         st = build_coo_plan(A, s);
     }
-    if (st == MXS_OK) A->optimized = true;
+    if (st == MXS_OK) {
+        if (A->fmt != MXS_HDC) set_impl(A, default_impl(A));
+        A->optimized = true;
+    }
     return st;
 }
 
@@ -1333,16 +1429,17 @@ static mxs_status spmv_typed(const mxs_mat_s *A, const T *x, T *y, const int *do
         spmv_grid<T>(A, dot != nullptr, &grid, &per);
         const DiaPlan &P = A->dia;
         const size_t lds = sizeof(T) * (size_t)P.lds_elems;
-        const T *vals = P.blk ? (const T *)P.blk : (const T *)A->vals;
-        const int blocked = P.blk != nullptr;
+        const T *vals = P.use_blk ? (const T *)P.blk : (const T *)A->vals;
+        const int blocked = P.use_blk ? 1 : 0;
+        const int32_t share = P.use_share ? 1 : 0;
         if (dot)
             dia_spmv_kernel<T, true><<<grid, kDiaNT, lds, s>>>(
                 A->nrows, A->ncols, A->ndiag, A->idx0, vals, blocked, x, y, dia_blocks(A), per,
-                done, parts, P.pos, P.runs, P.nruns, P.lds_elems, P.first_off, P.last_off, P.triples);
+                done, parts, P.pos, P.runs, P.nruns, P.lds_elems, P.first_off, P.last_off, share);
         else
             dia_spmv_kernel<T, false><<<grid, kDiaNT, lds, s>>>(
                 A->nrows, A->ncols, A->ndiag, A->idx0, vals, blocked, x, y, dia_blocks(A), per,
-                done, parts, P.pos, P.runs, P.nruns, P.lds_elems, P.first_off, P.last_off, P.triples);
+                done, parts, P.pos, P.runs, P.nruns, P.lds_elems, P.first_off, P.last_off, share);
         MXS_HIP(hipGetLastError());
         nparts = grid;
         break;

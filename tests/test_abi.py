@@ -91,6 +91,10 @@ def test_create_rejects_bad_arguments_on_host(lib):
 def test_calls_reject_null_handles_and_bad_enums(lib):
     assert lib.mxs_spmv(None, FAKE, FAKE, None) == -1
     assert lib.mxs_optimize(None, None) == -1
+    assert lib.mxs_impl_count(None) == 0
+    assert lib.mxs_set_impl(None, 0, None) == -1
+    assert lib.mxs_get_impl(None, FAKE, None) == -1
+    assert lib.mxs_tune(None, FAKE, FAKE, 5, None, None, None) == -1
     assert lib.mxs_info(None, None, None, None, None, None, None) == -1
     assert lib.mxs_arrays(None, None, None, None) == -1
     assert lib.mxs_convert_size(None, 0, None, None, None) == -1

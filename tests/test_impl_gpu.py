@@ -1,0 +1,176 @@
+"""Every SpMV implementation of every format against the CPU oracle, through
+the C ABI, and the run-first choice among them (mxs_tune).
+
+Bars as for SpMV: FP64 within 1e-12 relative max-norm of the oracle and within
+the per-row rounding bound; integer data bit-exact; bitwise reproducible per
+implementation.  CG with each implementation matches the oracle's CG.
+"""
+import numpy as np
+import pytest
+
+import oracle as orc
+import workloads as wl
+from _cases import U64, rel_maxnorm, row_bound, small_cases
+
+pytestmark = pytest.mark.gpu
+
+CASES = small_cases()
+IDS = [c[0] for c in CASES]
+UNSUPPORTED = -10
+
+
+def to_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def build(mxs, a, fmt):
+    A = mxs.Matrix.coo(a.nrows, a.ncols, a.ai, a.aj, a.av)
+    if fmt != "coo":
+        try:
+            A = A.convert(fmt)
+        except mxs.MxsError as e:
+            if e.status == -5:
+                return None
+            raise
+    return A.optimize()
+
+
+def applicable(mxs, A):
+    """Ids accepted by mxs_set_impl; the refusals must be MXS_ERR_UNSUPPORTED."""
+    ok = []
+    for i in range(A.impl_count()):
+        try:
+            A.impl = i
+            ok.append(i)
+        except mxs.MxsError as e:
+            assert e.status == UNSUPPORTED
+    return ok
+
+
+@pytest.mark.parametrize("fmt", ["coo", "csr", "dia"])
+@pytest.mark.parametrize("name,a", CASES, ids=IDS)
+def test_every_impl_matches_oracle(gpu, name, a, fmt):
+    mxs = gpu
+    print(f"[impl] {name} {fmt} {a.nrows}x{a.ncols} nnz={a.nnz}", flush=True)
+    A = build(mxs, a, fmt)
+    if A is None:
+        pytest.skip("DIA refused (more than 8 slots per non-zero)")
+    default = A.impl
+    ids = applicable(mxs, A)
+    assert default in ids
+    # the always-applicable fallback of each format
+    assert {"coo": 1, "csr": 1, "dia": 2}[fmt] in ids
+    x = wl.uniform_vector(a.ncols, seed=1)
+    xd = to_dev(x)
+    ref = orc.coo_spmv(a.nrows, a.ai, a.aj, a.av, x)
+    for i in ids:
+        A.impl = i
+        assert A.impl == i
+        y = to_dev(np.full(a.nrows, np.nan))
+        mxs.spmv(A, xd, y)
+        y1 = y.cpu().numpy()
+        assert rel_maxnorm(y1, ref) <= 1e-12, i
+        assert np.all(np.abs(y1 - ref) <= row_bound(a, x, U64) + 1e-300), i
+        assert np.array_equal(mxs.spmv(A, xd).cpu().numpy(), y1), i
+
+
+@pytest.mark.parametrize("fmt", ["coo", "csr", "dia"])
+@pytest.mark.parametrize("name", ["stencil16", "gappy_long", "empty_rows"])
+def test_every_impl_integer_data_bit_exact(gpu, name, fmt):
+    mxs = gpu
+    if name == "stencil16":
+        a = wl.stencil(16)
+    elif name == "empty_rows":
+        a = dict(CASES)["empty_rows"]
+        a = wl.Coo(a.nrows, a.ncols, a.ai, a.aj, np.round(a.av * 4) + 1.0)
+    else:
+        from test_spmv_gpu import _gappy
+        a = _gappy(4000, seed=2, long_rows={500, 501, 2200})
+    A = build(mxs, a, fmt)
+    if A is None:
+        pytest.skip("DIA refused (more than 8 slots per non-zero)")
+    x = wl.integer_vector(a.ncols, seed=3)
+    ref = orc.coo_spmv(a.nrows, a.ai, a.aj, a.av, x)
+    for i in applicable(mxs, A):
+        A.impl = i
+        assert np.array_equal(mxs.spmv(A, to_dev(x)).cpu().numpy(), ref), i
+
+
+def test_applicability_rules(gpu):
+    """COO row tiles need at most 512 rows per tile; DIA id 0 needs offsets in
+    runs of three, ids 0 and 1 the row-blocked copy."""
+    mxs = gpu
+    sparse = dict(CASES)["empty_rows"]   # 10,000 rows, 100 live: one tile owns them all
+    # (defaults read before applicable(), which leaves its last id active)
+    A = build(mxs, sparse, "coo")
+    assert A.impl == 1 and applicable(mxs, A) == [1]
+    S = build(mxs, wl.stencil(16), "dia")
+    assert S.impl == 0 and applicable(mxs, S) == [0, 1, 2]
+    from test_spmv_gpu import _diagonals
+    M = build(mxs, _diagonals(5000, [-2, -1, 0, 7, 8], seed=1), "dia")
+    assert M.impl == 1 and applicable(mxs, M) == [1, 2]
+    C = build(mxs, sparse, "csr")
+    assert C.impl == 1 and applicable(mxs, C) == [0, 1]     # rows > 2 nnz: a thread per row
+    assert build(mxs, wl.stencil(16), "csr").impl == 0
+    for B in (A, S):
+        with pytest.raises(mxs.MxsError) as e:
+            B.impl = B.impl_count()
+        assert e.value.status == UNSUPPORTED
+        with pytest.raises(mxs.MxsError) as e:
+            B.impl = -1
+        assert e.value.status == UNSUPPORTED
+
+
+@pytest.mark.parametrize("fmt", ["coo", "csr", "dia"])
+def test_tune_keeps_an_applicable_fastest_impl(gpu, fmt):
+    mxs = gpu
+    a = wl.stencil(24)
+    A = build(mxs, a, fmt)
+    x = wl.uniform_vector(a.ncols, seed=4)
+    y = to_dev(np.full(a.nrows, np.nan))
+    best, ms = A.tune(to_dev(x), y, reps=5)
+    ids = applicable(mxs, A)
+    assert len(ms) == A.impl_count()
+    assert [i for i, m in enumerate(ms) if m is not None] == ids
+    assert best in ids and ms[best] == min(m for m in ms if m is not None) and ms[best] > 0
+    # applicable() left the last id active; tune again and the choice is kept
+    best2, _ = A.tune(to_dev(x), y, reps=3)
+    assert A.impl == best2
+    ref = orc.coo_spmv(a.nrows, a.ai, a.aj, a.av, x)
+    assert rel_maxnorm(y.cpu().numpy(), ref) <= 1e-12   # tune leaves y = A x
+    assert rel_maxnorm(mxs.spmv(A, to_dev(x)).cpu().numpy(), ref) <= 1e-12
+
+
+def test_tune_argument_checks(gpu):
+    import ctypes as C
+    mxs = gpu
+    a = wl.stencil(6)
+    A = build(mxs, a, "csr")
+    x = to_dev(np.ones(a.ncols))
+    lib = mxs.load()
+    assert lib.mxs_tune(A.handle, mxs._ptr(x), mxs._ptr(to_dev(np.zeros(a.nrows))), 0,
+                        None, None, None) == -1
+    assert lib.mxs_tune(A.handle, mxs._ptr(x), mxs._ptr(x), 3, None, None, None) == -1  # aliasing
+    H = mxs.Matrix.coo(a.nrows, a.ncols, a.ai, a.aj, a.av).split(0.5, "csr")
+    assert H.impl_count() == 0
+    v = C.c_int32()
+    assert lib.mxs_get_impl(H.handle, C.byref(v), None) == UNSUPPORTED
+    assert lib.mxs_set_impl(H.handle, 0, None) == UNSUPPORTED
+    assert lib.mxs_tune(H.handle, mxs._ptr(x), mxs._ptr(to_dev(np.zeros(a.nrows))), 3,
+                        None, None, None) == UNSUPPORTED
+
+
+@pytest.mark.parametrize("fmt", ["coo", "csr", "dia"])
+def test_cg_with_every_impl_matches_oracle(gpu, fmt):
+    """The fused SpMV + p.Ap of each implementation inside CG."""
+    mxs = gpu
+    a = wl.stencil(12)
+    b = orc.coo_spmv(a.nrows, a.ai, a.aj, a.av, np.ones(a.ncols))
+    st_o, x_o, it_o, _, _ = orc.cg(a.nrows, a.ai, a.aj, a.av, b, tol=1e-10, maxit=2000)
+    A = build(mxs, a, fmt)
+    for i in applicable(mxs, A):
+        A.impl = i
+        st, x, res = mxs.cg_solve(A, to_dev(b), rtol=1e-10, maxit=2000)
+        assert st == 0 and abs(res["iters"] - it_o) <= 2, (i, res["iters"], it_o)
+        assert np.max(np.abs(x.cpu().numpy() - x_o)) <= 1e-8, i
