@@ -325,7 +325,8 @@ class Matrix:
         return self
 
     # SpMV implementations of the format (ids as in mxs_set_impl)
-    IMPL_NAMES = {COO: ("row_tiles", "segmented"), CSR: ("entry_tiles", "row_per_thread"),
+    IMPL_NAMES = {COO: ("row_tiles", "segmented"),
+                  CSR: ("entry_tiles", "row_per_thread", "staged_gather"),
                   DIA: ("blocked_shared_x", "blocked", "diagonal_major")}
 
     @property

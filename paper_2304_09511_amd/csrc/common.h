@@ -88,7 +88,8 @@ struct CsrPlan {
     void *carry = nullptr;       // [2*ntiles] head / tail pieces of rows too long to finish
     int64_t ntiles = 0;
     bool fixup = false;          // some row reaches past its owner's overflow window
-    bool rowwise = false;        // fewer than one entry per two rows: a thread per row
+    bool rowwise = false;        // a thread per row (default when rows outnumber entries 2:1)
+    bool gx = false;             // entry tiles, x gathered per row from LDS-staged columns
 };
 
 struct DiaPlan {

@@ -200,6 +200,14 @@ __global__ void csr_tile_info_kernel(const int32_t *__restrict__ irp, const int3
 #define MXS_DIA_YNT 1 // 1: DIA writes y with non-temporal stores
 #endif
 
+#ifndef MXS_CSR_GX_DEFAULT
+#define MXS_CSR_GX_DEFAULT 0 // 1: the staged-gather implementation is CSR's default
+#endif
+
+#ifndef MXS_CSR_GXU
+#define MXS_CSR_GXU 8 // staged-gather CSR: entries a lane gathers per step
+#endif
+
 #ifndef MXS_CSR_WPE
 #define MXS_CSR_WPE 0 // >0: ask the compiler for this many waves per SIMD
 #endif
@@ -209,7 +217,12 @@ __global__ void csr_tile_info_kernel(const int32_t *__restrict__ irp, const int3
 #define MXS_CSR_ATTR
 #endif
 
-template <typename T, bool DOT>
+// GX (the staged-gather implementation): the tile's columns and values are
+// staged in LDS and x is gathered in the reduction, by the lane group of each
+// row.  Lanes then gather x for neighbouring rows at the same position in
+// their rows, which for banded matrices are neighbouring addresses: fewer
+// cache lines per gather instruction than gathering in entry order.
+template <typename T, bool DOT, bool GX>
 __global__ __launch_bounds__(256) MXS_CSR_ATTR void csr_spmv_kernel(
     const int32_t *__restrict__ irp, const int32_t *__restrict__ aj, const T *__restrict__ av,
     const T *__restrict__ x, T *__restrict__ y, const int32_t *__restrict__ tile_row,
@@ -219,7 +232,8 @@ __global__ __launch_bounds__(256) MXS_CSR_ATTR void csr_spmv_kernel(
     using C = CsrCfg<T>;
     constexpr int NT = C::NT, IPT = C::IPT, TILE = C::TILE, EXT = C::EXT, RMAX = C::RMAX;
     static_assert(EXT == NT, "one overflow entry per thread");
-    __shared__ T prod[TILE + EXT];
+    __shared__ T prod[TILE + EXT]; // products, or the values when GX
+    __shared__ int32_t scol[GX ? TILE + EXT : 1];
     __shared__ int32_t lrp[RMAX + 1];
     __shared__ double red[NT / kWave];
     if (done && *done) return;
@@ -263,15 +277,30 @@ __global__ __launch_bounds__(256) MXS_CSR_ATTR void csr_spmv_kernel(
             const uint32_t ke = (uint32_t)(n + min(tid, max(n_ext - 1, 0)));
             col[IPT] = ext_wave ? ld_stream(&ajb[ke]) : 0;
             val[IPT] = ext_wave ? ld_stream(&avb[ke]) : T(0);
+            if constexpr (GX) {
 #pragma unroll
-            for (int e = 0; e < IPT; ++e) xv[e] = x[(uint32_t)col[e]];
-            xv[IPT] = ext_wave ? x[(uint32_t)col[IPT]] : T(0);
+                for (int e = 0; e < IPT; ++e) {
+                    const int j = e * NT + tid;
+                    if (j < n) {
+                        prod[j] = val[e];
+                        scol[j] = col[e];
+                    }
+                }
+                if (tid < n_ext) {
+                    prod[n + tid] = val[IPT];
+                    scol[n + tid] = col[IPT];
+                }
+            } else {
 #pragma unroll
-            for (int e = 0; e < IPT; ++e) {
-                const int j = e * NT + tid;
-                if (j < n) prod[j] = val[e] * xv[e];
+                for (int e = 0; e < IPT; ++e) xv[e] = x[(uint32_t)col[e]];
+                xv[IPT] = ext_wave ? x[(uint32_t)col[IPT]] : T(0);
+#pragma unroll
+                for (int e = 0; e < IPT; ++e) {
+                    const int j = e * NT + tid;
+                    if (j < n) prod[j] = val[e] * xv[e];
+                }
+                if (tid < n_ext) prod[n + tid] = val[IPT] * xv[IPT];
             }
-            if (tid < n_ext) prod[n + tid] = val[IPT] * xv[IPT];
         }
         const bool staged = nr <= RMAX;
         if (staged) {
@@ -284,7 +313,7 @@ __global__ __launch_bounds__(256) MXS_CSR_ATTR void csr_spmv_kernel(
             // piece of a long row that began in an earlier tile
             const int32_t hl = min(rp(0), n);
             T hs = T(0);
-            for (int j = tid; j < hl; j += NT) hs += prod[j];
+            for (int j = tid; j < hl; j += NT) hs += GX ? prod[j] * x[(uint32_t)scol[j]] : prod[j];
             const double tot = block_sum<NT>((double)hs, red);
             if (tid == 0) carry[2 * tile] = (T)tot;
         }
@@ -297,7 +326,28 @@ __global__ __launch_bounds__(256) MXS_CSR_ATTR void csr_spmv_kernel(
         for (int r = tid / G; r < nr; r += ngrp) {
             T sum = T(0);
             const int e = min(rp(r + 1), lim);
-            for (int k = rp(r) + lane; k < e; k += G) sum += prod[k];
+            if constexpr (GX) {
+                // U entries per lane per step; lanes past the row's end
+                // re-read its last entry with a zero value
+                constexpr int U = MXS_CSR_GXU;
+                for (int k0l = rp(r) + lane; k0l < e; k0l += U * G) {
+                    int32_t c[U];
+                    T v[U], xg[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int k = k0l + u * G;
+                        const int kk = min(k, e - 1);
+                        c[u] = scol[kk];
+                        v[u] = k < e ? prod[kk] : T(0);
+                    }
+#pragma unroll
+                    for (int u = 0; u < U; ++u) xg[u] = x[(uint32_t)c[u]];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) sum += v[u] * xg[u];
+                }
+            } else {
+                for (int k = rp(r) + lane; k < e; k += G) sum += prod[k];
+            }
             for (int off = G >> 1; off > 0; off >>= 1) sum += __shfl_xor(sum, off, kWave);
             if (lane == 0) {
                 if (last_carry && r == nr - 1) {
@@ -1018,7 +1068,7 @@ static void spmv_grid(const mxs_mat_s *A, bool dot, uint32_t *grid, int64_t *per
     const int64_t nblk = A->fmt == MXS_CSR ? A->csr.ntiles
                          : A->fmt == MXS_DIA ? dia_blocks(A) : A->coo.ntiles;
 #if MXS_PERSIST
-    int64_t cap = A->fmt == MXS_CSR ? resident_workgroups(csr_spmv_kernel<T, false>, 256)
+    int64_t cap = A->fmt == MXS_CSR ? resident_workgroups(csr_spmv_kernel<T, false, false>, 256)
                   : A->fmt == MXS_DIA ? resident_workgroups(dia_spmv_kernel<T, false>, kDiaNT)
                                       : resident_workgroups(coo_spmv_kernel<T>, kCooNT);
 #else
@@ -1231,12 +1281,13 @@ static mxs_status build_coo_plan(mxs_mat_s *A, hipStream_t s)
 //   COO 0: row tiles (the CSR tiling rebuilt from the row ids)
 //       1: segmented-scan tiles
 //   CSR 0: entry tiles           1: a thread per row
+//       2: entry tiles, x gathered per row from LDS-staged columns
 //   DIA 0: row-blocked values, x shared over runs of three offsets
 //       1: row-blocked values    2: diagonal-major values (no copy), x shared
 // ---------------------------------------------------------------------------
 int32_t impl_count(const mxs_mat_s *A)
 {
-    return A->fmt == MXS_DIA ? 3 : (A->fmt == MXS_COO || A->fmt == MXS_CSR) ? 2 : 0;
+    return A->fmt == MXS_DIA || A->fmt == MXS_CSR ? 3 : A->fmt == MXS_COO ? 2 : 0;
 }
 
 bool impl_ok(const mxs_mat_s *A, int32_t impl)
@@ -1258,7 +1309,7 @@ static int32_t default_impl(const mxs_mat_s *A)
 {
     switch (A->fmt) {
     case MXS_COO: return impl_ok(A, 0) ? 0 : 1;
-    case MXS_CSR: return A->csr.rowwise ? 1 : 0;
+    case MXS_CSR: return A->csr.rowwise ? 1 : MXS_CSR_GX_DEFAULT ? 2 : 0;
     case MXS_DIA: return impl_ok(A, 0) ? 0 : impl_ok(A, 1) ? 1 : 2;
     default: return -1;
     }
@@ -1273,7 +1324,10 @@ void set_impl(mxs_mat_s *A, int32_t impl)
         A->coo.ntiles = A->coo.rows ? A->coo.nt_rows : A->coo.nt_seg;
         A->coo.carry = A->coo.rows ? A->coo.carry_rows : A->coo.carry_seg;
         break;
-    case MXS_CSR: A->csr.rowwise = impl == 1; break;
+    case MXS_CSR:
+        A->csr.rowwise = impl == 1;
+        A->csr.gx = impl == 2;
+        break;
     case MXS_DIA:
         A->dia.use_blk = impl != 2 && A->dia.blk != nullptr;
         A->dia.use_share = impl != 1 && A->dia.triples;
@@ -1400,14 +1454,10 @@ static mxs_status spmv_typed(const mxs_mat_s *A, const T *x, T *y, const int *do
         }
         spmv_grid<T>(A, dot != nullptr, &grid, &per);
         const int32_t *tr = A->csr.tile_row, *ti = A->csr.tile_info;
-        if (dot)
-            csr_spmv_kernel<T, true><<<grid, 256, 0, s>>>(A->idx0, A->idx1, (const T *)A->vals, x, y,
-                                                          tr, ti, A->nnz, nt, per,
-                                                          (T *)A->csr.carry, done, parts, acc);
-        else
-            csr_spmv_kernel<T, false><<<grid, 256, 0, s>>>(A->idx0, A->idx1, (const T *)A->vals, x,
-                                                           y, tr, ti, A->nnz, nt, per,
-                                                           (T *)A->csr.carry, done, parts, acc);
+        auto kern = dot ? (A->csr.gx ? csr_spmv_kernel<T, true, true> : csr_spmv_kernel<T, true, false>)
+                        : (A->csr.gx ? csr_spmv_kernel<T, false, true> : csr_spmv_kernel<T, false, false>);
+        kern<<<grid, 256, 0, s>>>(A->idx0, A->idx1, (const T *)A->vals, x, y, tr, ti, A->nnz, nt, per,
+                                  (T *)A->csr.carry, done, dot ? parts : nullptr, acc);
         MXS_HIP(hipGetLastError());
         nparts = grid;
         if (A->csr.fixup) {
