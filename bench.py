@@ -341,6 +341,17 @@ def irregular_runs(torch, mxs, checks):
             if not fmt.startswith("hdc"):
                 rec[fmt]["implementations"] = impl_report(mxs, A, x, y)
                 log(f"[bench]   implementations: {rec[fmt]['implementations']['median_us']}")
+            else:
+                # each part's implementation chosen by mxs_tune
+                t = A.tune(x, y, reps=20)
+                names = mxs.Matrix.IMPL_NAMES
+                rest_fmt = mxs.FORMATS[fmt[4:]]
+                tc = time_calls(torch, lambda: mxs.spmv(A, x, y))
+                rec[fmt]["tuned"] = {"band": names[mxs.DIA][t["band"][0]],
+                                     "rest": names[rest_fmt][t["rest"][0]],
+                                     "us_per_call": round(tc["median_ms"] * 1e3, 2),
+                                     "timing": "protocol median of 10 x 100 calls after tuning"}
+                log(f"[bench]   tuned parts: {rec[fmt]['tuned']}")
             if A is not coo:
                 A.close()
         coo.close()

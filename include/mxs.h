@@ -297,6 +297,14 @@ mxs_status mxs_split(mxs_mat A, double min_fill, mxs_format rest_format, int32_t
                      void *band_vals, int32_t *rest_idx0, int32_t *rest_idx1, void *rest_vals,
                      mxs_mat *out, void *stream);
 
+/* The two parts of a split matrix H as handles of their own [host only]:
+ * *band (MXS_DIA) and *rest (MXS_COO or MXS_CSR), either pointer may be
+ * NULL.  They stay valid until H is destroyed and belong to H: mxs_destroy
+ * on a part returns MXS_ERR_INVALID_ARG.  Every other call accepts them, so
+ * each part's implementation can be chosen (mxs_set_impl, mxs_tune); the
+ * choice holds for H's product.  MXS_ERR_UNSUPPORTED if H is not MXS_HDC. */
+mxs_status mxs_split_parts(mxs_mat H, mxs_mat *band, mxs_mat *rest);
+
 /* ------------------------------------------------------------------------
  * HPCG problem setup (Section VII-D: Poisson on a regular 3-D grid)
  * --------------------------------------------------------------------- */

@@ -77,6 +77,7 @@ _SIGS = {
     "mxs_convert": (I32, [P, I32, P, P, P, P, P]),
     "mxs_split_size": (I32, [P, D, P, P, P]),
     "mxs_split": (I32, [P, D, I32, P, P, P, P, P, P, P]),
+    "mxs_split_parts": (I32, [P, P, P]),
     "mxs_cast": (I32, [P, I32, P, P, P]),
     "mxs_optimize": (I32, [P, P]),
     "mxs_impl_count": (I32, [P]),
@@ -185,9 +186,10 @@ def _dev(a, dtype=None, device="cuda"):
 class Matrix:
     """A libmxs handle plus the tensors whose memory it borrows."""
 
-    def __init__(self, handle, keep=()):
+    def __init__(self, handle, keep=(), owned=True):
         self._h = handle
         self._keep = list(keep)
+        self._owned = owned  # False for the parts of a split matrix
         lib = load()
         fmt, dt, nr, nc, nnz, nd = (C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(),
                                     C.c_int64(), C.c_int32())
@@ -284,10 +286,31 @@ class Matrix:
                "mxs_split_size")
         return nd.value, rn.value
 
-    def split(self, min_fill=0.5, rest="csr"):
+    def split(self, min_fill=0.5, rest="csr", x=None, reps=10):
         """A DIA band (diagonals at least min_fill full) plus the remaining
-        entries in `rest` ("coo" or "csr"), as an HDC Matrix on fresh tensors."""
+        entries in `rest` ("coo" or "csr"), as an HDC Matrix on fresh tensors.
+        rest="auto" splits both ways, tunes each (tune(), on x or a seeded
+        uniform vector) and keeps the faster split; its choice is in
+        .tuning."""
         torch = _torch()
+        if rest == "auto":
+            if x is None:
+                g = torch.Generator(device="cuda")
+                g.manual_seed(1)
+                x = (torch.rand(self.ncols, generator=g, device="cuda",
+                                dtype=torch.float64) * 2 - 1).to(_torch_dtype(self.dtype))
+            best = None
+            for r in ("coo", "csr"):
+                H = self.split(min_fill, r)
+                H.tuning = H.tune(x, reps=reps)
+                H.tuning["rest_format"] = r
+                if best is None or H.tuning["ms"] < best.tuning["ms"]:
+                    if best is not None:
+                        best.close()
+                    best = H
+                else:
+                    H.close()
+            return best
         f = FORMATS.get(rest, rest)
         nd, rn = self.split_size(min_fill)
         dt = _torch_dtype(self.dtype)
@@ -342,12 +365,25 @@ class Matrix:
     def impl_count(self):
         return load().mxs_impl_count(self._h)
 
+    def parts(self):
+        """(band, rest) of a split matrix: handles owned by this one."""
+        b, r = C.c_void_p(), C.c_void_p()
+        _check(load().mxs_split_parts(self._h, C.byref(b), C.byref(r)), "mxs_split_parts")
+        return Matrix(b, [self], owned=False), Matrix(r, [self], owned=False)
+
     def tune(self, x, y=None, reps=10):
         """Times every applicable implementation on y = A x, keeps the
-        fastest; returns (id, [median ms per id, None where not applicable])."""
+        fastest; returns (id, [median ms per id, None where not applicable]).
+        A split matrix tunes its two parts and returns a dict: each part's
+        choice and times, and the median time of the whole product ("ms")."""
         torch = _torch()
         if y is None:
             y = torch.empty(self.nrows, dtype=x.dtype, device=x.device)
+        if self.format == HDC:
+            band, rest = self.parts()
+            out = {"band": band.tune(x, y, reps), "rest": rest.tune(x, y, reps)}
+            out["ms"] = _median_ms(torch, lambda: spmv(self, x, y), reps)
+            return out
         if _dtype_code(x) != self.dtype or _dtype_code(y) != self.dtype:
             raise TypeError("x and y must have the matrix's dtype")
         if x.numel() != self.ncols or y.numel() != self.nrows:
@@ -360,7 +396,7 @@ class Matrix:
         return best.value, [None if m < 0 else m for m in ms[:self.impl_count()]]
 
     def close(self):
-        if self._h is not None and _lib is not None:
+        if self._h is not None and _lib is not None and self._owned:
             _check(_lib.mxs_destroy(self._h), "mxs_destroy")
         self._h = None
         self._keep = []
@@ -370,6 +406,21 @@ class Matrix:
             self.close()
         except Exception:
             pass
+
+
+def _median_ms(torch, fn, reps):
+    for _ in range(3):
+        fn()
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    ts.sort()
+    return ts[len(ts) // 2]
 
 
 # --------------------------------------------------------------- operations

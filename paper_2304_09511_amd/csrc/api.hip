@@ -252,6 +252,7 @@ mxs_status mxs_dia_create(mxs_mat *out, int32_t nrows, int32_t ncols, int32_t nd
 mxs_status mxs_destroy(mxs_mat A)
 {
     if (!A) return MXS_OK;
+    if (A->part) return MXS_ERR_INVALID_ARG; // released with its split matrix
     return guarded([&] {
         int dev = 0;
         (void)hipGetDevice(&dev);
@@ -374,6 +375,15 @@ mxs_status mxs_optimize(mxs_mat A, void *stream)
 {
     if (!A) return MXS_ERR_INVALID_ARG;
     return guarded([&] { return ensure_plan(A, S(stream)); });
+}
+
+mxs_status mxs_split_parts(mxs_mat H, mxs_mat *band, mxs_mat *rest)
+{
+    if (!H) return MXS_ERR_INVALID_ARG;
+    if (H->fmt != MXS_HDC) return MXS_ERR_UNSUPPORTED;
+    if (band) *band = H->band;
+    if (rest) *rest = H->rest;
+    return MXS_OK;
 }
 
 int32_t mxs_impl_count(mxs_mat A)

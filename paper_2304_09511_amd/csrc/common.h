@@ -140,6 +140,7 @@ struct mxs_mat_s {
     mxs::DiaPlan dia;
     mxs_mat_s *band = nullptr; // HDC: the DIA band (owned by this handle)
     mxs_mat_s *rest = nullptr; // HDC: the COO or CSR remainder (owned)
+    bool part = false;         // the band or remainder of a split (its parent owns it)
 };
 
 namespace mxs {

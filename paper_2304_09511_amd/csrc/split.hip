@@ -314,6 +314,7 @@ mxs_status split(const mxs_mat_s *A, double min_fill, mxs_format rest_fmt, int32
     h->nnz = band->nnz + rest_nnz;
     h->ndiag = m.ndiag;
     h->device = A->device;
+    band->part = rest->part = true;
     h->band = band;
     h->rest = rest;
     *out = h;

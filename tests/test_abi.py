@@ -92,6 +92,7 @@ def test_calls_reject_null_handles_and_bad_enums(lib):
     assert lib.mxs_spmv(None, FAKE, FAKE, None) == -1
     assert lib.mxs_optimize(None, None) == -1
     assert lib.mxs_impl_count(None) == 0
+    assert lib.mxs_split_parts(None, None, None) == -1
     assert lib.mxs_set_impl(None, 0, None) == -1
     assert lib.mxs_get_impl(None, FAKE, None) == -1
     assert lib.mxs_tune(None, FAKE, FAKE, 5, None, None, None) == -1

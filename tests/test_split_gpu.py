@@ -178,3 +178,58 @@ def test_split_unsupported_and_invalid(gpu):
 def _stencil_arrays():
     s = wl.stencil(5)
     return s.nrows, s.ncols, s.ai, s.aj, s.av
+
+
+@pytest.mark.parametrize("rest", ["coo", "csr"])
+def test_split_parts_every_impl_pair_matches_oracle(gpu, rest):
+    """The parts are handles of their own; every implementation of the band
+    with every implementation of the remainder gives the oracle's product."""
+    mxs = gpu
+    a = banded_noise(30000, seed=7)
+    H = mxs.Matrix.coo(a.nrows, a.ncols, a.ai, a.aj, a.av).split(0.5, rest)
+    band, part = H.parts()
+    assert band.format == mxs.DIA and band.ndiag == H.ndiag
+    assert part.format == mxs.FORMATS[rest] and part.nnz == H._keep[3].numel()
+    lib = mxs.load()
+    assert lib.mxs_destroy(band.handle) == -1 and lib.mxs_destroy(part.handle) == -1
+    x = wl.uniform_vector(a.ncols, seed=5)
+    xd = to_dev(x)
+    ref = orc.coo_spmv(a.nrows, a.ai, a.aj, a.av, x)
+    for bi in range(band.impl_count()):
+        try:
+            band.impl = bi
+        except mxs.MxsError as e:
+            assert e.status == -10
+            continue
+        for ri in range(part.impl_count()):
+            try:
+                part.impl = ri
+            except mxs.MxsError as e:
+                assert e.status == -10
+                continue
+            y = to_dev(np.full(a.nrows, np.nan))
+            mxs.spmv(H, xd, y)
+            assert rel_maxnorm(y.cpu().numpy(), ref) <= 1e-12, (bi, ri)
+    with pytest.raises(mxs.MxsError) as e:
+        mxs.Matrix.coo(a.nrows, a.ncols, a.ai, a.aj, a.av).parts()
+    assert e.value.status == -10
+
+
+def test_split_tune_and_auto_rest(gpu):
+    mxs = gpu
+    a = banded_noise(30000, seed=8)
+    A = mxs.Matrix.coo(a.nrows, a.ncols, a.ai, a.aj, a.av)
+    x = wl.uniform_vector(a.ncols, seed=6)
+    xd = to_dev(x)
+    ref = orc.coo_spmv(a.nrows, a.ai, a.aj, a.av, x)
+    H = A.split(0.5, "csr")
+    y = to_dev(np.full(a.nrows, np.nan))
+    t = H.tune(xd, y, reps=3)
+    assert rel_maxnorm(y.cpu().numpy(), ref) <= 1e-12     # tune leaves y = A x
+    band, part = H.parts()
+    assert band.impl == t["band"][0] and part.impl == t["rest"][0] and t["ms"] > 0
+    assert rel_maxnorm(mxs.spmv(H, xd).cpu().numpy(), ref) <= 1e-12
+    Hauto = A.split(0.5, "auto", x=xd, reps=3)
+    assert Hauto.format == mxs.HDC and Hauto.tuning["rest_format"] in ("coo", "csr")
+    assert Hauto.parts()[1].format == mxs.FORMATS[Hauto.tuning["rest_format"]]
+    assert rel_maxnorm(mxs.spmv(Hauto, xd).cpu().numpy(), ref) <= 1e-12
