@@ -99,6 +99,8 @@ def _bind(lib):
         "orc_mlp_forward": (None, [P, P, I64, P]),
         "orc_mlp_loss_grad": (D, [P, P, P, I64, P]),
         "orc_adam_step": (None, [I64, P, P, P, P, D, I64, D, D, D]),
+        "orc_symgs": (C.c_int, [I64, P, P, P, P, P, P]),
+        "orc_gs_sweep": (C.c_int, [I64, P, P, P, P, C.c_int, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -302,3 +304,119 @@ def adam_step(w, m, v, g, lr, t, b1=0.9, b2=0.999, eps=1e-8):
         assert a.dtype == np.float64 and a.flags.c_contiguous
     g = _f64(g)
     _load().orc_adam_step(w.shape[0], _p(w), _p(m), _p(v), _p(g), lr, t, b1, b2, eps)
+
+
+# ------------------------------------------------- HPCG's preconditioner
+# Section VII-D: HPCG runs CG preconditioned by a multigrid V-cycle whose
+# smoother is symmetric Gauss-Seidel.  The paper gives no further detail; the
+# cycle below is HPCG's (one pre- and one post-smoothing sweep, injection
+# between a grid and the grid of every second point, the 27-point operator
+# on every level, one sweep on the coarsest level).
+def symgs(irp, aj, av, order, r, x):
+    """One symmetric Gauss-Seidel sweep (forward over `order`, backward over
+    its reverse) on a copy of x; returns (status, x)."""
+    irp, aj, av, order, r = _i32(irp), _i32(aj), _f64(av), _i32(order), _f64(r)
+    x = _f64(x).copy()
+    st = _load().orc_symgs(order.shape[0], _p(irp), _p(aj), _p(av), _p(order), _p(r), _p(x))
+    return int(st), x
+
+
+def gs_sweep(irp, aj, av, order, r, x, direction):
+    """One forward (direction 1) or backward (-1) sweep on a copy of x."""
+    irp, aj, av, order, r = _i32(irp), _i32(aj), _f64(av), _i32(order), _f64(r)
+    x = _f64(x).copy()
+    st = _load().orc_gs_sweep(order.shape[0], _p(irp), _p(aj), _p(av), _p(order), int(direction),
+                              _p(r), _p(x))
+    return int(st), x
+
+
+def grid_colours(n):
+    """Colour of each point of an n^3 grid (x fastest): the parities of its
+    three coordinates, c = (ix & 1) + 2 (iy & 1) + 4 (iz & 1).  Two points of
+    one colour differ by an even amount in every coordinate, so no 27-point
+    coupling joins them."""
+    i = np.arange(n ** 3, dtype=np.int64)
+    ix, iy, iz = i % n, (i // n) % n, i // (n * n)
+    return ((ix & 1) + 2 * (iy & 1) + 4 * (iz & 1)).astype(np.int32)
+
+
+# Sweep order of the colours: colour 0 (the points a coarser grid keeps)
+# last, so the forward sweep of the post-smoother reads the coarse
+# correction before it recomputes those points.
+COLOUR_SWEEP = (1, 2, 3, 4, 5, 6, 7, 0)
+
+
+def colour_order(n):
+    """Row order of the multicolour sweep: colours in COLOUR_SWEEP order,
+    ascending row ids within a colour."""
+    c = grid_colours(n)
+    return np.concatenate([np.flatnonzero(c == k) for k in COLOUR_SWEEP]).astype(np.int32)
+
+
+def coarse_points(n):
+    """Fine row of each coarse point: coarse (i, j, k) of the (n/2)^3 grid is
+    fine (2i, 2j, 2k); listed in coarse row order."""
+    m = n // 2
+    i = np.arange(m ** 3, dtype=np.int64)
+    ci, cj, ck = i % m, (i // m) % m, i // (m * m)
+    return (2 * ci + 2 * cj * n + 2 * ck * n * n).astype(np.int64)
+
+
+def mg_vcycle(levels, r, orders=None):
+    """z = M^{-1} r for HPCG's V-cycle.  levels[l] = (n_l, irp, aj, av), the
+    27-point operator on the n_l^3 grid, finest first, n_{l+1} = n_l / 2.
+    orders[l] is the sweep order of level l (default colour_order)."""
+    orders = orders or [colour_order(lv[0]) for lv in levels]
+
+    def cycle(l, rl):
+        n, irp, aj, av = levels[l]
+        z = np.zeros(n ** 3)
+        st, z = symgs(irp, aj, av, orders[l], rl, z)
+        if st != OK:
+            raise ArithmeticError("zero diagonal")
+        if l == len(levels) - 1:
+            return z
+        f = coarse_points(n)
+        az = csr_spmv(irp, aj, av, z)
+        zc = cycle(l + 1, rl[f] - az[f])
+        z[f] += zc
+        st, z = symgs(irp, aj, av, orders[l], rl, z)
+        return z
+
+    return cycle(0, _f64(r))
+
+
+def pcg(irp, aj, av, b, precond, x0=None, tol=1e-9, maxit=1000):
+    """Preconditioned CG as HPCG runs it: z = M^{-1} r, p = z on the first
+    iteration and z + (r.z / r_old.z_old) p after, alpha = r.z / p.Ap; stop
+    when ||r|| <= tol ||r_0||.  Returns (status, x, iters, rel_resid,
+    true_rel_resid)."""
+    b = _f64(b)
+    x = np.zeros(b.shape[0]) if x0 is None else _f64(x0).copy()
+    r = b - csr_spmv(irp, aj, av, x)
+    rr0 = dot(r, r)
+    rr, k, st = rr0, 0, NOT_CONVERGED
+    if rr0 == 0.0:
+        st = OK
+    p, rz_old = None, 0.0
+    while st == NOT_CONVERGED and k < maxit:
+        z = _f64(precond(r))
+        rz = dot(r, z)
+        p = z.copy() if k == 0 else z + (rz / rz_old) * p
+        rz_old = rz
+        q = csr_spmv(irp, aj, av, p)
+        sigma = dot(p, q)
+        k += 1
+        if not (sigma > 0.0) or not np.isfinite(sigma):
+            st = BREAKDOWN
+            break
+        alpha = rz / sigma
+        x = x + alpha * p
+        r = r - alpha * q
+        rr = dot(r, r)
+        if np.sqrt(rr) <= tol * np.sqrt(rr0):
+            st = OK
+    t = b - csr_spmv(irp, aj, av, x)
+    bn = np.sqrt(dot(b, b))
+    rel = np.sqrt(rr) / np.sqrt(rr0) if rr0 > 0 else 0.0
+    return st, x, k, float(rel), float(np.sqrt(dot(t, t)) / bn if bn > 0 else np.sqrt(dot(t, t)))

@@ -789,3 +789,53 @@ void orc_adam_step(int64_t np, double *w, double *m, double *v, const double *g,
         w[i] -= lr * mh / (sqrt(vh) + eps);
     }
 }
+
+/* ------------------------------------------------------------------------
+ * Symmetric Gauss-Seidel: the smoother of HPCG's preconditioner (Section
+ * VII-D describes HPCG as PCG preconditioned by symmetric Gauss-Seidel
+ * inside a multigrid cycle; the textbook sweep is Saad, Section 4.1).
+ * One forward sweep visits the rows in `order`, one backward sweep visits
+ * them in reverse; row i becomes x_i = (r_i - sum_{j != i} a_ij x_j) / a_ii
+ * with the newest x_j.  The sum runs over row i's entries in storage
+ * order, starting from r_i.  Returns ORC_BREAKDOWN when a visited row holds
+ * no nonzero diagonal entry (x untouched from that row on), else ORC_OK.
+ * ---------------------------------------------------------------------- */
+static int gs_row(const int32_t *irp, const int32_t *aj, const double *av, int32_t i,
+                  const double *r, double *x)
+{
+    double s = r[i], d = 0.0;
+    for (int32_t k = irp[i]; k < irp[i + 1]; ++k) {
+        if (aj[k] == i)
+            d = av[k];
+        else
+            s -= av[k] * x[aj[k]];
+    }
+    if (d == 0.0)
+        return ORC_BREAKDOWN;
+    x[i] = s / d;
+    return ORC_OK;
+}
+
+int orc_symgs(int64_t n, const int32_t *irp, const int32_t *aj, const double *av,
+              const int32_t *order, const double *r, double *x)
+{
+    for (int64_t t = 0; t < n; ++t)
+        if (gs_row(irp, aj, av, order[t], r, x) != ORC_OK)
+            return ORC_BREAKDOWN;
+    for (int64_t t = n - 1; t >= 0; --t)
+        if (gs_row(irp, aj, av, order[t], r, x) != ORC_OK)
+            return ORC_BREAKDOWN;
+    return ORC_OK;
+}
+
+/* One forward (dir = 1) or backward (dir = -1) sweep alone. */
+int orc_gs_sweep(int64_t n, const int32_t *irp, const int32_t *aj, const double *av,
+                 const int32_t *order, int dir, const double *r, double *x)
+{
+    for (int64_t u = 0; u < n; ++u) {
+        const int64_t t = dir > 0 ? u : n - 1 - u;
+        if (gs_row(irp, aj, av, order[t], r, x) != ORC_OK)
+            return ORC_BREAKDOWN;
+    }
+    return ORC_OK;
+}

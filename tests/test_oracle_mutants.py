@@ -8,6 +8,7 @@ import pytest
 
 import oracle as orc
 import test_oracle as pins
+import test_oracle_mg as mg
 
 SRC = os.path.join(os.path.dirname(orc.__file__), "oracle.c")
 
@@ -90,6 +91,14 @@ MUTANTS = [
      "s += h1[j] * w[OFF_W2 + j * NH + k];",
      "s += h1[j] * w[OFF_W2 + k * NH + j];",
      [pins.test_mlp_gradient_matches_finite_differences]),
+    ("symgs_backward_runs_forward",
+     "    for (int64_t t = n - 1; t >= 0; --t)\n        if (gs_row(irp, aj, av, order[t], r, x) != ORC_OK)",
+     "    for (int64_t t = 0; t < n; ++t)\n        if (gs_row(irp, aj, av, order[t], r, x) != ORC_OK)",
+     [lambda: mg.test_gs_sweeps_are_triangular_solves("stencil5", "natural")]),
+    ("gs_diagonal_also_subtracted",
+     "        if (aj[k] == i)\n            d = av[k];\n        else\n            s -= av[k] * x[aj[k]];",
+     "        if (aj[k] == i)\n            d = av[k];\n        s -= av[k] * x[aj[k]];",
+     [lambda: mg.test_gs_sweeps_are_triangular_solves("random60", "permuted")]),
     ("adam_no_bias_correction",
      "double mh = m[i] / c1, vh = v[i] / c2;",
      "double mh = m[i], vh = v[i];",
@@ -111,4 +120,58 @@ def test_planted_mistake_is_caught(tmp_path, name, old, new, catchers):
                 pin()
             except AssertionError:
                 caught += 1
+    assert caught >= 1, f"no pin caught the planted mistake {name}"
+
+
+# Mistakes in the Python part of the oracle (the V-cycle and PCG): a copy of
+# the module with one edit, run through the pins that take the module.
+PY_MUTANTS = [
+    ("coarse_point_odd",
+     "return (2 * ci + 2 * cj * n + 2 * ck * n * n).astype(np.int64)",
+     "return (2 * ci + 1 + 2 * cj * n + 2 * ck * n * n).astype(np.int64)",
+     [lambda m: mg.test_coarse_points_are_even_coordinates(4, m=m),
+      lambda m: mg.test_vcycle_two_levels_by_library_solves(4, m=m)]),
+    ("restriction_drops_Az",
+     "zc = cycle(l + 1, rl[f] - az[f])",
+     "zc = cycle(l + 1, rl[f])",
+     [lambda m: mg.test_vcycle_two_levels_by_library_solves(8, m=m)]),
+    ("prolongation_sign",
+     "z[f] += zc",
+     "z[f] -= zc",
+     [lambda m: mg.test_vcycle_two_levels_by_library_solves(8, m=m)]),
+    ("no_post_smoothing",
+     "        z[f] += zc\n        st, z = symgs(irp, aj, av, orders[l], rl, z)",
+     "        z[f] += zc",
+     [lambda m: mg.test_vcycle_symmetric_positive(8, 2, m=m)]),
+    ("pcg_beta_inverted",
+     "p = z.copy() if k == 0 else z + (rz / rz_old) * p",
+     "p = z.copy() if k == 0 else z + (rz_old / rz) * p",
+     [lambda m: mg.test_pcg_identity_preconditioner_is_cg(6, m=m)]),
+    ("pcg_alpha_from_rr",
+     "alpha = rz / sigma",
+     "alpha = dot(r, r) / sigma",
+     [lambda m: mg.test_pcg_with_vcycle_converges_faster_and_to_ones(m=m)]),
+]
+
+
+@pytest.mark.parametrize("name,old,new,catchers", PY_MUTANTS, ids=[m[0] for m in PY_MUTANTS])
+def test_planted_python_mistake_is_caught(tmp_path, name, old, new, catchers):
+    import importlib.util
+    path = os.path.join(os.path.dirname(orc.__file__), "__init__.py")
+    src = open(path).read()
+    assert src.count(old) == 1, f"mutation site for {name} not unique"
+    # the copy keeps using the real oracle library
+    src = src.replace("_HERE = os.path.dirname(os.path.abspath(__file__))",
+                      f"_HERE = {os.path.dirname(path)!r}")
+    mpath = tmp_path / f"{name}.py"
+    mpath.write_text(src.replace(old, new))
+    spec = importlib.util.spec_from_file_location(f"oracle_mutant_{name}", mpath)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    caught = 0
+    for pin in catchers:
+        try:
+            pin(mod)
+        except AssertionError:
+            caught += 1
     assert caught >= 1, f"no pin caught the planted mistake {name}"
