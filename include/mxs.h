@@ -56,6 +56,7 @@ typedef enum { MXS_F64 = 0, MXS_F32 = 1 } mxs_dtype;
 
 /* Opaque host-side handle of a sparse matrix in one storage format. */
 typedef struct mxs_mat_s *mxs_mat;
+typedef struct mxs_mg_s *mxs_mg; /* multigrid hierarchy of the HPCG problem */
 
 /* Creation flags. */
 #define MXS_BORROW 1u /* reference the caller's arrays instead of copying them;
@@ -251,6 +252,7 @@ typedef struct {
     double t_spmv_ms;      /* timing = 1: summed kernel times per class; else 0 */
     double t_dot_ms;
     double t_axpy_ms;
+    double t_precond_ms;   /* PCG with timing = 1: the preconditioner's time; else 0 */
 } mxs_cg_result;
 
 /* Bytes of device workspace mxs_cg_solve needs for A (n = nrows). */
@@ -304,6 +306,59 @@ mxs_status mxs_split(mxs_mat A, double min_fill, mxs_format rest_format, int32_t
  * each part's implementation can be chosen (mxs_set_impl, mxs_tune); the
  * choice holds for H's product.  MXS_ERR_UNSUPPORTED if H is not MXS_HDC. */
 mxs_status mxs_split_parts(mxs_mat H, mxs_mat *band, mxs_mat *rest);
+
+/* ------------------------------------------------------------------------
+ * HPCG's preconditioner (Section VII-D: CG preconditioned by a multigrid
+ * cycle with a symmetric Gauss-Seidel smoother; HPCG's cycle in full).
+ *
+ * Level l (0 finest) is the 27-point stencil (26 on the diagonal, -1 off it)
+ * on the (n >> l)^3 grid, rows x-fastest.  The smoother is one symmetric
+ * Gauss-Seidel sweep in multicolour order: the colour of a point is the
+ * parity of its coordinates, c = (ix & 1) + 2 (iy & 1) + 4 (iz & 1); the
+ * forward sweep visits colours 1, 2, ..., 7, 0 (ascending rows inside a
+ * colour), the backward sweep the reverse; row i becomes
+ * x_i = (r_i - sum_{j != i} a_ij x_j) / a_ii.  Points of one colour never
+ * couple, so each colour updates in parallel and the sweep equals the
+ * sequential one in that order.  The V-cycle: z = 0, one sweep, coarse
+ * right-hand side r_c = (r - A z) at the points (2i, 2j, 2k) (injection),
+ * the cycle on the next level from zero, z += its result at those points,
+ * one more sweep; on the coarsest level one sweep from zero.
+ * --------------------------------------------------------------------- */
+
+/* Builds the hierarchy [syncs]: n >= 1 divisible by 2^(levels-1), levels
+ * in [1, 12], n^3 rows and (3n-2)^3 entries within int32 (else
+ * MXS_ERR_UNSUPPORTED).  Memory: each level's CSR operator, a copy of its
+ * off-diagonal entries sliced for the smoother, and two vectors per coarse
+ * level.  Calls on one hierarchy must not overlap (they share the coarse
+ * vectors). */
+mxs_status mxs_mg_create(int32_t n, int32_t levels, mxs_mg *out, void *stream);
+mxs_status mxs_mg_destroy(mxs_mg M);
+
+/* Grid edge and operator (an MXS_CSR handle owned by M: mxs_destroy on it
+ * returns MXS_ERR_INVALID_ARG) of level `level` [host only]. */
+mxs_status mxs_mg_level(mxs_mg M, int32_t level, int32_t *n, mxs_mat *A);
+
+/* One symmetric Gauss-Seidel sweep of level `level` on x in place, with
+ * right-hand side r (FP64 device vectors of the level's rows; x and r must
+ * not overlap) [async]. */
+mxs_status mxs_symgs(mxs_mg M, int32_t level, const double *r, double *x, void *stream);
+
+/* z = M^{-1} r, one V-cycle from the finest level (r, z FP64 device
+ * vectors of n^3 entries, not overlapping) [async]. */
+mxs_status mxs_mg_apply(mxs_mg M, const double *r, double *z, void *stream);
+
+/* Bytes of device workspace mxs_pcg_solve needs. */
+mxs_status mxs_pcg_workspace_size(mxs_mg M, size_t *bytes);
+
+/* PCG on A x = b with z = M^{-1} r (HPCG's recurrences: beta = r.z over the
+ * previous r.z, alpha = r.z / p.Ap; stop when ||r_k|| <= rtol ||r_0||)
+ * [syncs].  A is the finest operator in any FP64 format (NULL: M's own CSR
+ * operator); it must be that matrix.  opts: rtol, maxit, check_every and
+ * timing as for mxs_cg_solve; mixed must be 0.  Statuses as mxs_cg_solve,
+ * and MXS_ERR_BREAKDOWN also when r.z <= 0. */
+mxs_status mxs_pcg_solve(mxs_mg M, mxs_mat A, const double *b, double *x,
+                         const mxs_cg_opts *opts, mxs_cg_result *res, void *workspace,
+                         size_t workspace_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
  * HPCG problem setup (Section VII-D: Poisson on a regular 3-D grid)

@@ -56,7 +56,8 @@ class CgOpts(C.Structure):
 class CgResult(C.Structure):
     _fields_ = [("iters", C.c_int64), ("outer_iters", C.c_int64), ("rel_resid", C.c_double),
                 ("true_rel_resid", C.c_double), ("t_spmv_ms", C.c_double),
-                ("t_dot_ms", C.c_double), ("t_axpy_ms", C.c_double)]
+                ("t_dot_ms", C.c_double), ("t_axpy_ms", C.c_double),
+                ("t_precond_ms", C.c_double)]
 
 
 _lib = None
@@ -89,6 +90,13 @@ _SIGS = {
     "mxs_axpby": (I32, [I64, I32, D, P, D, P, P]),
     "mxs_cg_workspace_size": (I32, [P, I32, P]),
     "mxs_cg_solve": (I32, [P, P, P, P, P, P, P, SZ, P]),
+    "mxs_mg_create": (I32, [I32, I32, P, P]),
+    "mxs_mg_destroy": (I32, [P]),
+    "mxs_mg_level": (I32, [P, I32, P, P]),
+    "mxs_symgs": (I32, [P, I32, P, P, P]),
+    "mxs_mg_apply": (I32, [P, P, P, P]),
+    "mxs_pcg_workspace_size": (I32, [P, P]),
+    "mxs_pcg_solve": (I32, [P, P, P, P, P, P, P, SZ, P]),
     "mxs_stencil_nnz": (I64, [I32, I32]),
     "mxs_stencil_coo": (I32, [I32, I32, D, D, P, P, P, I32, P]),
     "mxs_features": (I32, [P, P, P]),
@@ -480,6 +488,71 @@ def cg_solve(A: Matrix, b, x0=None, rtol=1e-9, maxit=10000, mixed=False, A32=Non
     _check(st, "mxs_cg_solve", ok=(0, 1, -8))
     res = {k: getattr(r, k) for k, _ in CgResult._fields_}
     return st, x, res
+
+
+class Multigrid:
+    """HPCG's multigrid preconditioner on the n^3 27-point stencil (levels
+    grids, finest first)."""
+
+    def __init__(self, n, levels=4):
+        h = C.c_void_p()
+        _check(load().mxs_mg_create(int(n), int(levels), C.byref(h), _stream()), "mxs_mg_create")
+        self._h, self.n, self.levels = h, n, levels
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("closed multigrid hierarchy")
+        return self._h
+
+    def level(self, l):
+        """(grid edge, operator Matrix owned by the hierarchy) of level l."""
+        n, a = C.c_int32(), C.c_void_p()
+        _check(load().mxs_mg_level(self.handle, int(l), C.byref(n), C.byref(a)), "mxs_mg_level")
+        return n.value, Matrix(a, [self], owned=False)
+
+    def symgs(self, level, r, x):
+        """One symmetric Gauss-Seidel sweep of `level` on x in place."""
+        _check(load().mxs_symgs(self.handle, int(level), _ptr(r), _ptr(x), _stream()), "mxs_symgs")
+        return x
+
+    def apply(self, r, z=None):
+        """z = M^{-1} r (one V-cycle)."""
+        torch = _torch()
+        if z is None:
+            z = torch.empty_like(r)
+        _check(load().mxs_mg_apply(self.handle, _ptr(r), _ptr(z), _stream()), "mxs_mg_apply")
+        return z
+
+    def pcg_solve(self, b, x0=None, A=None, rtol=1e-9, maxit=10000, check_every=4,
+                  timing=False, workspace=None):
+        """PCG on A x = b preconditioned by this hierarchy (A: the finest
+        operator in any format, default the hierarchy's CSR).  Returns
+        (status, x, CgResult as a dict)."""
+        torch = _torch()
+        x = torch.zeros_like(b) if x0 is None else x0.clone()
+        if workspace is None:
+            nb = C.c_size_t()
+            _check(load().mxs_pcg_workspace_size(self.handle, C.byref(nb)), "mxs_pcg_workspace_size")
+            workspace = torch.empty(max(nb.value, 1), dtype=torch.uint8, device="cuda")
+        o = CgOpts(rtol, maxit, 0, 0, 0.0, check_every, 1 if timing else 0, 0.0)
+        r = CgResult()
+        st = load().mxs_pcg_solve(self.handle, A.handle if A is not None else None, _ptr(b),
+                                  _ptr(x), C.byref(o), C.byref(r), _ptr(workspace),
+                                  workspace.numel(), _stream())
+        _check(st, "mxs_pcg_solve", ok=(0, 1, -8))
+        return st, x, {k: getattr(r, k) for k, _ in CgResult._fields_}
+
+    def close(self):
+        if self._h is not None and _lib is not None:
+            _check(_lib.mxs_mg_destroy(self._h), "mxs_mg_destroy")
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def stencil(n, points=27, diag=None, offdiag=-1.0, dtype=F64, fmt="coo"):

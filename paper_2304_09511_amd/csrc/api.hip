@@ -496,11 +496,87 @@ mxs_status mxs_cg_solve(mxs_mat A, mxs_mat A32, const double *b, double *x, cons
         if (st == MXS_OK && opts->mixed) st = ensure_plan(A32, s);
         if (st != MXS_OK) return st;
         if (A->nrows == 0) {
-            *res = mxs_cg_result{0, 0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            *res = mxs_cg_result{};
             return MXS_OK;
         }
         return cg_solve(A, opts->mixed ? A32 : nullptr, b, x, opts, res, workspace,
                         workspace_bytes, s);
+    });
+}
+
+// ---------------------------------------------------------------------------
+// HPCG's preconditioner
+// ---------------------------------------------------------------------------
+mxs_status mxs_mg_create(int32_t n, int32_t levels, mxs_mg *out, void *stream)
+{
+    if (!out || n < 1 || levels < 1 || levels > 12) return MXS_ERR_INVALID_ARG;
+    if (n % (1 << (levels - 1)) != 0) return MXS_ERR_INVALID_ARG;
+    if ((int64_t)n * n * n > INT32_MAX || mxs_stencil_nnz(n, 27) > INT32_MAX)
+        return MXS_ERR_UNSUPPORTED;
+    return guarded([&] { return mg_create(n, levels, out, S(stream)); });
+}
+
+mxs_status mxs_mg_destroy(mxs_mg M)
+{
+    if (!M) return MXS_OK;
+    return guarded([&] {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipSetDevice(M->device);
+        const hipError_t e = hipDeviceSynchronize();
+        mg_release(M);
+        (void)hipSetDevice(dev);
+        return from_hip(e);
+    });
+}
+
+mxs_status mxs_mg_level(mxs_mg M, int32_t level, int32_t *n, mxs_mat *A)
+{
+    if (!M || level < 0 || level >= (int32_t)M->lv.size()) return MXS_ERR_INVALID_ARG;
+    if (n) *n = M->lv[(size_t)level].n;
+    if (A) *A = M->lv[(size_t)level].A;
+    return MXS_OK;
+}
+
+mxs_status mxs_symgs(mxs_mg M, int32_t level, const double *r, double *x, void *stream)
+{
+    if (!M || level < 0 || level >= (int32_t)M->lv.size()) return MXS_ERR_INVALID_ARG;
+    const size_t rows = (size_t)M->lv[(size_t)level].rows;
+    if (!r || !x || overlaps(r, 8 * rows, x, 8 * rows)) return MXS_ERR_INVALID_ARG;
+    return guarded([&] { return symgs_launch(M, level, r, x, S(stream)); });
+}
+
+mxs_status mxs_mg_apply(mxs_mg M, const double *r, double *z, void *stream)
+{
+    if (!M) return MXS_ERR_INVALID_ARG;
+    const size_t rows = (size_t)M->lv[0].rows;
+    if (!r || !z || overlaps(r, 8 * rows, z, 8 * rows)) return MXS_ERR_INVALID_ARG;
+    return guarded([&] { return mg_apply(M, r, z, nullptr, S(stream)); });
+}
+
+mxs_status mxs_pcg_workspace_size(mxs_mg M, size_t *bytes)
+{
+    if (!M || !bytes) return MXS_ERR_INVALID_ARG;
+    *bytes = pcg_workspace_bytes(M->lv[0].rows);
+    return MXS_OK;
+}
+
+mxs_status mxs_pcg_solve(mxs_mg M, mxs_mat A, const double *b, double *x, const mxs_cg_opts *opts,
+                         mxs_cg_result *res, void *workspace, size_t workspace_bytes, void *stream)
+{
+    if (!M || !opts || !res) return MXS_ERR_INVALID_ARG;
+    if (!A) A = M->lv[0].A;
+    const int64_t n = M->lv[0].rows;
+    if (A->dtype != MXS_F64 || A->nrows != n || A->ncols != n) return MXS_ERR_INVALID_ARG;
+    if (!b || !x || !workspace || overlaps(b, 8 * (size_t)n, x, 8 * (size_t)n))
+        return MXS_ERR_INVALID_ARG;
+    if (opts->mixed != 0 || !(opts->rtol >= 0.0) || opts->maxit < 0) return MXS_ERR_INVALID_ARG;
+    if (workspace_bytes < pcg_workspace_bytes(n)) return MXS_ERR_INVALID_ARG;
+    return guarded([&] {
+        hipStream_t s = S(stream);
+        mxs_status st = ensure_plan(A, s);
+        if (st != MXS_OK) return st;
+        return pcg_solve(M, A, b, x, opts, res, workspace, workspace_bytes, s);
     });
 }
 

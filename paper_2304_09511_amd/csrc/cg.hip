@@ -236,6 +236,70 @@ __global__ __launch_bounds__(kVNT) void cg_p_kernel(int64_t n, const T *__restri
     VEC_LOOP(i, n) p[i] = r[i] + b * p[i];
 }
 
+// ---------------------------------------------------------------------------
+// PCG kernels (HPCG's preconditioned CG)
+// ---------------------------------------------------------------------------
+// partials of r.z
+__global__ __launch_bounds__(kVNT) void pcg_rz_kernel(int64_t n, const double *__restrict__ r,
+                                                      const double *__restrict__ z,
+                                                      double *partials, const CgState *st)
+{
+    __shared__ double red[kVNT / kWave];
+    if (st->done) return;
+    double s = 0.0;
+    VEC_LOOP(i, n) s += r[i] * z[i];
+    const double bs = block_sum<kVNT>(s, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = bs;
+}
+
+// beta = r.z / (previous r.z) (0 on the first iteration); rho = r.z, the
+// numerator of the next alpha.  r.z <= 0 means the preconditioner is not
+// positive definite: breakdown.
+__global__ __launch_bounds__(kFinNT) void pcg_rz_finish_kernel(const double *__restrict__ partials,
+                                                             int64_t nparts, CgState *st)
+{
+    __shared__ double red[kFinNT / kWave];
+    if (st->done) return;
+    const double rz = reduce_partials<kFinNT>(partials, nparts, red);
+    if (threadIdx.x == 0) {
+        if (!(rz > 0.0) || !__builtin_isfinite(rz)) {
+            st->status = (int)MXS_ERR_BREAKDOWN;
+            st->done = 1;
+        } else {
+            st->beta = st->iters > 0 ? rz / st->rho : 0.0;
+            st->rho = rz;
+        }
+    }
+}
+
+// p = z + beta p
+__global__ __launch_bounds__(kVNT) void pcg_p_kernel(int64_t n, const double *__restrict__ z,
+                                                     double *__restrict__ p, const CgState *st)
+{
+    if (st->done) return;
+    const double b = st->beta;
+    VEC_LOOP(i, n) p[i] = z[i] + b * p[i];
+}
+
+// After r.r of the new residual: converged or capped.
+__global__ __launch_bounds__(kFinNT) void pcg_rr_finish_kernel(const double *__restrict__ partials,
+                                                             int64_t nparts, CgState *st)
+{
+    __shared__ double red[kFinNT / kWave];
+    if (st->done) return;
+    const double rr = reduce_partials<kFinNT>(partials, nparts, red);
+    if (threadIdx.x == 0) {
+        st->rr = rr;
+        if (sqrt(rr) <= st->rtol * sqrt(st->rho0)) {
+            st->status = (int)MXS_OK;
+            st->done = 1;
+        } else if (st->iters >= st->maxit) {
+            st->status = (int)MXS_NOT_CONVERGED;
+            st->done = 1;
+        }
+    }
+}
+
 // partials of sum (a - c)^2 (c may be null); with w non-null also w = a - c.
 __global__ __launch_bounds__(kVNT) void diff_norm2_kernel(int64_t n, const double *__restrict__ a,
                                                           const double *__restrict__ c,
@@ -423,10 +487,11 @@ struct Ws {
     CgState *st, *st32;
     Aux *aux;
     double *parts;
-    double *r, *p, *q;
+    double *r, *p, *q, *z;
     float *d32, *r32, *p32, *q32;
 };
 
+// mixed: 0, 1, 2 as in mxs_cg_opts; 3: PCG (one more vector, z)
 static size_t layout(int64_t n, int32_t mixed, char *base, Ws *w)
 {
     size_t o = 0;
@@ -443,8 +508,9 @@ static size_t layout(int64_t n, int32_t mixed, char *base, Ws *w)
     t.r = (double *)take(sizeof(double) * (size_t)n);
     t.p = (double *)take(sizeof(double) * (size_t)n);
     t.q = (double *)take(sizeof(double) * (size_t)n);
+    t.z = mixed == 3 ? (double *)take(sizeof(double) * (size_t)n) : nullptr;
     t.d32 = t.r32 = t.p32 = t.q32 = nullptr;
-    if (mixed) {
+    if (mixed == 1 || mixed == 2) {
         t.d32 = (float *)take(sizeof(float) * (size_t)n);
         t.r32 = (float *)take(sizeof(float) * (size_t)n);
         t.p32 = (float *)take(sizeof(float) * (size_t)n);
@@ -458,6 +524,8 @@ size_t cg_workspace_bytes(int64_t n, int32_t mixed, int64_t, int64_t)
 {
     return layout(n, mixed, nullptr, nullptr);
 }
+
+size_t pcg_workspace_bytes(int64_t n) { return layout(n, 3, nullptr, nullptr); }
 
 // ---------------------------------------------------------------------------
 // Host driver
@@ -477,9 +545,10 @@ CgState *pinned_state()
 
 struct Timer {
     bool on = false;
-    std::vector<hipEvent_t> ev; // 4 marks per iteration
+    std::vector<hipEvent_t> ev; // marks: cls.size() + 1 per iteration
     size_t used = 0;
-    double ms[3] = {0, 0, 0}; // spmv, dot, vector updates
+    double ms[4] = {0, 0, 0, 0}; // spmv, dot, vector updates, preconditioner
+    std::vector<int> cls = {0, 1, 2}; // class of each interval of an iteration
     hipStream_t s = nullptr;
 
     mxs_status mark()
@@ -497,14 +566,13 @@ struct Timer {
     mxs_status collect()
     {
         if (!on) return MXS_OK;
-        for (size_t i = 0; i + 3 < used; i += 4) {
-            float a, b, c;
-            MXS_HIP(hipEventElapsedTime(&a, ev[i], ev[i + 1]));
-            MXS_HIP(hipEventElapsedTime(&b, ev[i + 1], ev[i + 2]));
-            MXS_HIP(hipEventElapsedTime(&c, ev[i + 2], ev[i + 3]));
-            ms[0] += a;
-            ms[1] += b;
-            ms[2] += c;
+        const size_t k = cls.size();
+        for (size_t i = 0; i + k < used; i += k + 1) {
+            for (size_t j = 0; j < k; ++j) {
+                float t;
+                MXS_HIP(hipEventElapsedTime(&t, ev[i + j], ev[i + j + 1]));
+                ms[cls[j]] += t;
+            }
         }
         used = 0;
         return MXS_OK;
@@ -617,7 +685,7 @@ mxs_status cg_solve(const mxs_mat_s *A, const mxs_mat_s *A32, const double *b, d
                     hipStream_t s)
 {
     const int64_t n = A->nrows;
-    *res = mxs_cg_result{0, 0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    *res = mxs_cg_result{};
     if (spmv_dot_parts(A) > kMaxParts || (A32 && spmv_dot_parts(A32) > kMaxParts))
         return MXS_ERR_UNSUPPORTED;
     if (layout(n, o->mixed, nullptr, nullptr) > bytes) return MXS_ERR_INVALID_ARG;
@@ -760,6 +828,97 @@ mxs_status cg_solve(const mxs_mat_s *A, const mxs_mat_s *A32, const double *b, d
     res->t_dot_ms = tm.ms[1];
     res->t_axpy_ms = tm.ms[2];
     return status;
+}
+
+// ---------------------------------------------------------------------------
+// PCG with the multigrid preconditioner, HPCG's recurrences: z = M^{-1} r,
+// beta = r.z / (previous r.z), p = z + beta p, alpha = r.z / p.Ap,
+// x += alpha p, r -= alpha Ap; stop on ||r|| <= rtol ||r_0||.
+// ---------------------------------------------------------------------------
+namespace {
+mxs_status enqueue_pcg_iteration(const mxs_mg_s *M, const mxs_mat_s *A, int64_t n, double *x,
+                                 const Ws &w, Timer &tm, hipStream_t s)
+{
+    mxs_status e;
+    const DotSink ds{w.parts, w.st};
+    const uint32_t g = vec_grid(n);
+    if ((e = tm.mark()) != MXS_OK) return e;
+    if ((e = mg_apply(M, w.r, w.z, &w.st->done, s)) != MXS_OK) return e;
+    if ((e = tm.mark()) != MXS_OK) return e;
+    pcg_rz_kernel<<<g, kVNT, 0, s>>>(n, w.r, w.z, w.parts, w.st);
+    pcg_rz_finish_kernel<<<1, kFinNT, 0, s>>>(w.parts, g, w.st);
+    if ((e = tm.mark()) != MXS_OK) return e;
+    pcg_p_kernel<<<g, kVNT, 0, s>>>(n, w.z, w.p, w.st);
+    if ((e = launch_status()) != MXS_OK) return e;
+    if ((e = tm.mark()) != MXS_OK) return e;
+    if (!tm.on) {
+        if ((e = spmv_launch(A, w.p, w.q, &w.st->done, &ds, s)) != MXS_OK) return e;
+        cg_xr_kernel<double, true><<<g, kVNT, 0, s>>>(n, x, w.r, w.p, w.q, w.parts, w.st);
+        pcg_rr_finish_kernel<<<1, kFinNT, 0, s>>>(w.parts, g, w.st);
+        return launch_status();
+    }
+    // timed: the same steps unfused, one kernel class at a time
+    if ((e = spmv_launch(A, w.p, w.q, &w.st->done, nullptr, s)) != MXS_OK) return e;
+    if ((e = tm.mark()) != MXS_OK) return e;
+    if ((e = dot_sigma_launch(n, MXS_F64, w.p, w.q, &w.st->done, &ds, s)) != MXS_OK) return e;
+    if ((e = tm.mark()) != MXS_OK) return e;
+    cg_xr_kernel<double, false><<<g, kVNT, 0, s>>>(n, x, w.r, w.p, w.q, w.parts, w.st);
+    cg_rr_kernel<double><<<g, kVNT, 0, s>>>(n, w.r, w.parts, w.st);
+    pcg_rr_finish_kernel<<<1, kFinNT, 0, s>>>(w.parts, g, w.st);
+    if ((e = launch_status()) != MXS_OK) return e;
+    return tm.mark();
+}
+}  // namespace
+
+mxs_status pcg_solve(const mxs_mg_s *M, const mxs_mat_s *A, const double *b, double *x,
+                     const mxs_cg_opts *o, mxs_cg_result *res, void *wsp, size_t bytes,
+                     hipStream_t s)
+{
+    const int64_t n = A->nrows;
+    *res = mxs_cg_result{};
+    if (spmv_dot_parts(A) > kMaxParts) return MXS_ERR_UNSUPPORTED;
+    if (layout(n, 3, nullptr, nullptr) > bytes) return MXS_ERR_INVALID_ARG;
+    Ws w;
+    layout(n, 3, (char *)wsp, &w);
+    CgState *host = pinned_state();
+    if (!host) return MXS_ERR_OUT_OF_MEMORY;
+    Timer tm;
+    tm.on = o->timing != 0;
+    tm.s = s;
+    // intervals: preconditioner, r.z, p update, SpMV, p.Ap, x/r updates and r.r
+    tm.cls = {3, 1, 2, 0, 1, 2};
+    const uint32_t g = vec_grid(n);
+    mxs_status e;
+    cg_state_init<<<1, 1, 0, s>>>(w.st, o->rtol, (long long)o->maxit);
+    if ((e = spmv_launch(A, x, w.q, nullptr, nullptr, s)) != MXS_OK) return e;
+    cg_start_kernel<<<g, kVNT, 0, s>>>(n, b, x, w.q, w.r, w.p, w.parts, w.st);
+    start_finish_kernel<<<1, kFinNT, 0, s>>>(w.parts, g, w.st);
+    MXS_HIP(hipGetLastError());
+    if (o->maxit > 0) {
+        if ((e = run_loop(w.st, o->maxit, o->check_every, tm, host, s,
+                          [&] { return enqueue_pcg_iteration(M, A, n, x, w, tm, s); })) != MXS_OK)
+            return e;
+    } else {
+        MXS_HIP(hipMemcpyAsync(host, w.st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+        MXS_HIP(hipStreamSynchronize(s));
+    }
+    const CgState f = *host;
+    if (f.status == (int)MXS_ERR_NONFINITE) return MXS_ERR_NONFINITE;
+    res->iters = f.iters;
+    res->rel_resid = f.rho0 > 0.0 ? std::sqrt(f.rr) / std::sqrt(f.rho0) : 0.0;
+    res->t_spmv_ms = tm.ms[0];
+    res->t_dot_ms = tm.ms[1];
+    res->t_axpy_ms = tm.ms[2];
+    res->t_precond_ms = tm.ms[3];
+    if ((e = spmv_launch(A, x, w.q, nullptr, nullptr, s)) != MXS_OK) return e;
+    if ((e = norm2(n, b, w.q, nullptr, w.parts, &w.aux->norm2[0], s)) != MXS_OK) return e;
+    if ((e = norm2(n, b, nullptr, nullptr, w.parts, &w.aux->norm2[1], s)) != MXS_OK) return e;
+    double nn[2];
+    MXS_HIP(hipMemcpyAsync(nn, w.aux->norm2, sizeof(nn), hipMemcpyDeviceToHost, s));
+    MXS_HIP(hipStreamSynchronize(s));
+    res->true_rel_resid = nn[1] > 0.0 ? std::sqrt(nn[0]) / std::sqrt(nn[1]) : std::sqrt(nn[0]);
+    if (f.status == (int)MXS_ERR_BREAKDOWN) return MXS_ERR_BREAKDOWN;
+    return f.status == (int)MXS_OK ? MXS_OK : MXS_NOT_CONVERGED;
 }
 
 }  // namespace mxs

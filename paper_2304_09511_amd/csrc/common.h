@@ -144,6 +144,30 @@ struct mxs_mat_s {
 };
 
 namespace mxs {
+// One grid of the multigrid hierarchy (mg.hip).
+struct MgLevel {
+    int32_t n = 0, rows = 0;  // grid edge, rows = n^3
+    mxs_mat_s *A = nullptr;   // the level's CSR operator (owned by the hierarchy)
+    int32_t coff[9] = {};     // colour c holds positions [coff[c], coff[c+1]) of order
+    int32_t sfirst[9] = {};   // first slice of colour c (sfirst[8]: slice count)
+    int32_t nslices = 0;
+    int32_t *order = nullptr; // row id at each position (colour order)
+    int64_t *soff = nullptr;  // [nslices+1] first entry of each 64-row slice
+    int32_t *col = nullptr;   // off-diagonal columns, slice column-major, padded
+    double *val = nullptr;    // their values (0 in padding)
+    double *diag = nullptr;   // a_ii at each position
+    double *r = nullptr, *z = nullptr; // right-hand side and correction (coarse levels)
+};
+}  // namespace mxs
+
+struct mxs_mg_s {
+    std::vector<mxs::MgLevel> lv; // finest first
+    int device = 0;
+    std::vector<void *> owned;
+};
+
+
+namespace mxs {
 
 inline size_t dsize(mxs_dtype t) { return t == MXS_F64 ? 8 : 4; }
 
@@ -304,6 +328,9 @@ mxs_status cast_values(const void *src, mxs_dtype from, void *dst, mxs_dtype to,
                        hipStream_t s);
 mxs_status csr_row_index(const int32_t *irp, int32_t nrows, int64_t nnz, int32_t *ai,
                          hipStream_t s);
+// irp[nrows+1] of sorted row ids ai[nnz]
+mxs_status coo_irp_launch(int64_t nnz, int32_t nrows, const int32_t *ai, int32_t *irp,
+                          hipStream_t s);
 
 // cg.hip
 mxs_status dot_launch(int64_t n, mxs_dtype t, const void *a, const void *b, double *result,
@@ -317,6 +344,18 @@ mxs_status cg_solve(const mxs_mat_s *A, const mxs_mat_s *A32, const double *b, d
 
 // features.hip
 mxs_status features(const mxs_mat_s *A, double out[8], hipStream_t s);
+
+// mg.hip: HPCG's multigrid preconditioner.
+mxs_status mg_create(int32_t n, int32_t levels, mxs_mg_s **out, hipStream_t s); // syncs
+void mg_release(mxs_mg_s *M);
+mxs_status symgs_launch(const mxs_mg_s *M, int32_t level, const double *r, double *x,
+                        hipStream_t s);
+// z = V-cycle(r) on the finest level; kernels return at entry when *done.
+mxs_status mg_apply(const mxs_mg_s *M, const double *r, double *z, const int *done, hipStream_t s);
+size_t pcg_workspace_bytes(int64_t n);
+mxs_status pcg_solve(const mxs_mg_s *M, const mxs_mat_s *A, const double *b, double *x,
+                     const mxs_cg_opts *o, mxs_cg_result *r, void *ws, size_t bytes,
+                     hipStream_t s);
 
 // gen.hip
 mxs_status stencil_coo(int32_t n, int32_t points, double diag, double offdiag, int32_t *ai,

@@ -63,8 +63,6 @@ static uint32_t grid_of(int64_t n)
     return (uint32_t)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096));
 }
 
-mxs_status coo_irp_launch(int64_t nnz, int32_t nrows, const int32_t *ai, int32_t *irp,
-                          hipStream_t s);
 
 mxs_status features(const mxs_mat_s *A, double out[8], hipStream_t s)
 {

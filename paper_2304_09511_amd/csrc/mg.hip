@@ -1,0 +1,415 @@
+// HPCG's preconditioner (Section VII-D): a multigrid V-cycle on the
+// 27-point stencil whose smoother is symmetric Gauss-Seidel.
+//
+// Gauss-Seidel is sequential in its row order; on the GPU the rows are
+// ordered by colour instead: the 8 colours of the grid points' coordinate
+// parities, c = (ix & 1) + 2 (iy & 1) + 4 (iz & 1).  No 27-point coupling
+// joins two points of one colour, so all rows of a colour update at once,
+// one launch per colour, and the sweep equals the sequential one in that
+// order.  Colour 0 (the points the next coarser grid keeps) is swept last,
+// so the forward sweep after prolongation reads the coarse correction before
+// it recomputes those points.
+//
+// Storage of a level for the smoother: rows in colour order (colour-id
+// order, ascending row id inside a colour), grouped 64 to a slice (one
+// wavefront, a lane per row); a slice holds its rows' off-diagonal entries
+// column-major, k-th entry of lane l at k*64 + l, padded to the slice's
+// longest row with zero values, so each load of a slice is one contiguous
+// 256-byte (columns) or 512-byte (values) access.  The diagonal is kept
+// apart: a row's update is x_i = (r_i - sum_{j != i} a_ij x_j) / a_ii.
+//
+// Restriction is fused: the coarse right-hand side r_c = (r - A z) at the
+// colour-0 rows is computed from the colour-0 slices and their diagonals,
+// the only rows of A z it needs (1/8 of an SpMV).  Colour-0 rows in colour
+// order are exactly the coarse rows in their natural order.
+#include "common.h"
+
+#include <algorithm>
+
+namespace mxs {
+
+constexpr int kSlice = 64;
+constexpr int kColours = 8;
+constexpr int kMgNT = 256;
+// sweep order of the colours: coarse points (colour 0) last
+constexpr int kSweep[kColours] = {1, 2, 3, 4, 5, 6, 7, 0};
+
+__device__ __forceinline__ int grid_colour(int64_t i, int32_t n)
+{
+    const int64_t ix = i % n, iy = (i / n) % n, iz = i / ((int64_t)n * n);
+    return (int)((ix & 1) + 2 * (iy & 1) + 4 * (iz & 1));
+}
+
+// position of each row: order[pos[i]] = i (closed form: colour c holds the
+// points with those parities, ordered by (iz, iy, ix)).
+struct ColourGeom {
+    int32_t n;
+    int32_t coff[kColours + 1];
+};
+
+__global__ void mg_order_kernel(ColourGeom g, int32_t *__restrict__ order)
+{
+    const int64_t rows = (int64_t)g.n * g.n * g.n;
+    const int32_t h[2] = {(g.n + 1) / 2, g.n / 2}; // points of parity 0 / 1 along an axis
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < rows;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t ix = i % g.n, iy = (i / g.n) % g.n, iz = i / ((int64_t)g.n * g.n);
+        const int px = (int)(ix & 1), py = (int)(iy & 1), pz = (int)(iz & 1);
+        const int c = px + 2 * py + 4 * pz;
+        const int64_t rank = (iz >> 1) * (int64_t)h[py] * h[px] + (iy >> 1) * (int64_t)h[px] + (ix >> 1);
+        order[g.coff[c] + rank] = (int32_t)i;
+    }
+}
+
+// Off-diagonal count of each slice's longest row.
+__global__ void mg_width_kernel(ColourGeom g, const int32_t *__restrict__ slice_colour_first,
+                                const int32_t *__restrict__ order, const int32_t *__restrict__ irp,
+                                int32_t nslices, int32_t *__restrict__ width)
+{
+    const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nslices) return;
+    // colour of slice s: the last c with slice_colour_first[c] <= s
+    int c = 0;
+    for (int k = 1; k < kColours; ++k) c = s >= slice_colour_first[k] ? k : c;
+    const int32_t p0 = g.coff[c] + (s - slice_colour_first[c]) * kSlice;
+    const int32_t p1 = min(p0 + kSlice, g.coff[c + 1]);
+    int32_t w = 0;
+    for (int32_t p = p0; p < p1; ++p) {
+        const int32_t i = order[p];
+        w = max(w, irp[i + 1] - irp[i] - 1);
+    }
+    width[s] = max(w, 0);
+}
+
+__global__ void mg_slice_offsets_kernel(const int32_t *__restrict__ wscan, int32_t nslices,
+                                        int64_t *__restrict__ soff)
+{
+    const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s <= nslices) soff[s] = (int64_t)kSlice * wscan[s];
+}
+
+// Scatters row order[p]'s entries into its slice; flags a row without a
+// nonzero diagonal (bit 0) or with a neighbour of its own colour (bit 1).
+__global__ void mg_fill_kernel(ColourGeom g, const int32_t *__restrict__ slice_colour_first,
+                               const int32_t *__restrict__ order, const int32_t *__restrict__ irp,
+                               const int32_t *__restrict__ aj, const double *__restrict__ av,
+                               const int64_t *__restrict__ soff, int32_t *__restrict__ col,
+                               double *__restrict__ val, double *__restrict__ diag,
+                               int *__restrict__ flags)
+{
+    const int64_t rows = (int64_t)g.n * g.n * g.n;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= rows) return;
+    int c = 0;
+    for (int k = 1; k < kColours; ++k) c = p >= g.coff[k] ? k : c;
+    const int32_t local = (int32_t)p - g.coff[c];
+    const int32_t s = slice_colour_first[c] + local / kSlice;
+    const int lane = local % kSlice;
+    const int64_t base = soff[s];
+    const int32_t w = (int32_t)((soff[s + 1] - base) / kSlice);
+    const int32_t i = order[p];
+    double d = 0.0;
+    int32_t k = 0;
+    int bad = 0;
+    for (int32_t e = irp[i]; e < irp[i + 1]; ++e) {
+        const int32_t j = aj[e];
+        if (j == i) {
+            d = av[e];
+        } else if (k < w) {
+            if (grid_colour(j, g.n) == c) bad |= 2;
+            col[base + (int64_t)k * kSlice + lane] = j;
+            val[base + (int64_t)k * kSlice + lane] = av[e];
+            ++k;
+        }
+    }
+    for (; k < w; ++k) {
+        col[base + (int64_t)k * kSlice + lane] = i;
+        val[base + (int64_t)k * kSlice + lane] = 0.0;
+    }
+    diag[p] = d;
+    if (d == 0.0) bad |= 1;
+    if (bad) atomicOr(flags, bad);
+}
+
+// One colour of a Gauss-Seidel sweep: every row of the colour at once.
+// ZERO: x is zero on entry (the first colour swept from a zero start), so
+// the row sums are r_i alone.
+template <bool ZERO>
+__global__ __launch_bounds__(kMgNT) void symgs_colour_kernel(
+    const int32_t *__restrict__ order, const int64_t *__restrict__ soff,
+    const int32_t *__restrict__ col, const double *__restrict__ val,
+    const double *__restrict__ diag, const double *__restrict__ r, double *__restrict__ x,
+    int32_t p0, int32_t nrows_c, int32_t s0, const int *__restrict__ done)
+{
+    if (done && *done) return;
+    const int32_t t = blockIdx.x * kMgNT + threadIdx.x;
+    if (t >= nrows_c) return;
+    const int32_t s = s0 + t / kSlice;
+    const int lane = t % kSlice;
+    const int32_t i = order[p0 + t];
+    double sum = r[i];
+    if (!ZERO) {
+        const int64_t base = soff[s];
+        const int32_t w = (int32_t)((soff[s + 1] - base) / kSlice);
+        const int32_t *__restrict__ cs = col + base + lane;
+        const double *__restrict__ vs = val + base + lane;
+        int32_t k = 0;
+        for (; k + 4 <= w; k += 4) {
+            int32_t c4[4];
+            double v4[4], x4[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                c4[u] = cs[(k + u) * kSlice];
+                v4[u] = vs[(k + u) * kSlice];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) x4[u] = x[c4[u]];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) sum -= v4[u] * x4[u];
+        }
+        for (; k < w; ++k) sum -= vs[k * kSlice] * x[cs[k * kSlice]];
+    }
+    x[i] = sum / diag[p0 + t];
+}
+
+// r_c[ic] = r[i] - (A z)[i] for the colour-0 row i = order[ic].
+__global__ __launch_bounds__(kMgNT) void mg_restrict_kernel(
+    const int32_t *__restrict__ order, const int64_t *__restrict__ soff,
+    const int32_t *__restrict__ col, const double *__restrict__ val,
+    const double *__restrict__ diag, const double *__restrict__ r, const double *__restrict__ z,
+    int32_t nc, double *__restrict__ rc, const int *__restrict__ done)
+{
+    if (done && *done) return;
+    const int32_t t = blockIdx.x * kMgNT + threadIdx.x;
+    if (t >= nc) return;
+    const int32_t s = t / kSlice;
+    const int lane = t % kSlice;
+    const int32_t i = order[t];
+    const int64_t base = soff[s];
+    const int32_t w = (int32_t)((soff[s + 1] - base) / kSlice);
+    double az = diag[t] * z[i];
+    for (int32_t k = 0; k < w; ++k)
+        az += val[base + (int64_t)k * kSlice + lane] * z[col[base + (int64_t)k * kSlice + lane]];
+    rc[t] = r[i] - az;
+}
+
+// z[order[ic]] += zc[ic]
+__global__ void mg_prolong_kernel(const int32_t *__restrict__ order, const double *__restrict__ zc,
+                                  int32_t nc, double *__restrict__ z, const int *__restrict__ done)
+{
+    if (done && *done) return;
+    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < nc) z[order[t]] += zc[t];
+}
+
+__global__ void mg_zero_kernel(double *__restrict__ z, int64_t n, const int *__restrict__ done)
+{
+    if (done && *done) return;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        z[i] = 0.0;
+}
+
+static uint32_t blocks(int64_t n, int nt = kMgNT) { return (uint32_t)std::max<int64_t>(1, (n + nt - 1) / nt); }
+
+// ---------------------------------------------------------------------------
+// Hierarchy
+// ---------------------------------------------------------------------------
+static mxs_status take(mxs_mg_s *M, void **p, size_t bytes)
+{
+    *p = nullptr;
+    if (bytes == 0) return MXS_OK;
+    const hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? MXS_ERR_OUT_OF_MEMORY : note_hip_error(e, "hipMalloc");
+    M->owned.push_back(*p);
+    return MXS_OK;
+}
+
+static mxs_status build_level(mxs_mg_s *M, MgLevel &L, int32_t n, bool vectors, hipStream_t s)
+{
+    L.n = n;
+    const int64_t rows64 = (int64_t)n * n * n;
+    const int64_t nnz = (3 * (int64_t)n - 2) * (3 * (int64_t)n - 2) * (3 * (int64_t)n - 2);
+    if (rows64 > INT32_MAX || nnz > INT32_MAX) return MXS_ERR_UNSUPPORTED;
+    L.rows = (int32_t)rows64;
+    mxs_status st;
+    // the operator: 27-point stencil, 26 on the diagonal and -1 off it, in CSR
+    int32_t *irp, *aj;
+    double *av;
+    if ((st = take(M, (void **)&irp, sizeof(int32_t) * ((size_t)L.rows + 1))) != MXS_OK) return st;
+    if ((st = take(M, (void **)&aj, sizeof(int32_t) * (size_t)nnz)) != MXS_OK) return st;
+    if ((st = take(M, (void **)&av, sizeof(double) * (size_t)nnz)) != MXS_OK) return st;
+    int32_t *ai = nullptr;
+    MXS_HIP(hipMallocAsync((void **)&ai, sizeof(int32_t) * (size_t)nnz, s));
+    st = stencil_coo(n, 27, 26.0, -1.0, ai, aj, av, MXS_F64, s);
+    if (st == MXS_OK) st = coo_irp_launch(nnz, L.rows, ai, irp, s);
+    (void)hipFreeAsync(ai, s);
+    if (st != MXS_OK) return st;
+    auto *A = new mxs_mat_s;
+    A->fmt = MXS_CSR;
+    A->dtype = MXS_F64;
+    A->nrows = A->ncols = L.rows;
+    A->nnz = nnz;
+    A->idx0 = irp;
+    A->idx1 = aj;
+    A->vals = av;
+    A->device = M->device;
+    A->part = true;
+    L.A = A;
+
+    // colour order (closed form)
+    ColourGeom g{};
+    g.n = n;
+    const int32_t h[2] = {(n + 1) / 2, n / 2};
+    g.coff[0] = 0;
+    for (int c = 0; c < kColours; ++c)
+        g.coff[c + 1] = g.coff[c] + h[c & 1] * h[(c >> 1) & 1] * h[(c >> 2) & 1];
+    std::copy(g.coff, g.coff + kColours + 1, L.coff);
+    if ((st = take(M, (void **)&L.order, sizeof(int32_t) * (size_t)L.rows)) != MXS_OK) return st;
+    mg_order_kernel<<<std::min<uint32_t>(blocks(L.rows), 65536), kMgNT, 0, s>>>(g, L.order);
+    if ((st = launch_status()) != MXS_OK) return st;
+
+    // slices
+    int32_t nsl = 0;
+    for (int c = 0; c < kColours; ++c) {
+        L.sfirst[c] = nsl;
+        nsl += (L.coff[c + 1] - L.coff[c] + kSlice - 1) / kSlice;
+    }
+    L.sfirst[kColours] = nsl;
+    L.nslices = nsl;
+    int32_t *dev_sfirst = nullptr, *width = nullptr, *wscan = nullptr;
+    int *flags = nullptr;
+    if ((st = take(M, (void **)&dev_sfirst, sizeof(int32_t) * (kColours + 1))) != MXS_OK) return st;
+    MXS_HIP(hipMemcpyAsync(dev_sfirst, L.sfirst, sizeof(int32_t) * (kColours + 1),
+                           hipMemcpyHostToDevice, s));
+    if ((st = take(M, (void **)&L.soff, sizeof(int64_t) * ((size_t)nsl + 1))) != MXS_OK) return st;
+    MXS_HIP(hipMallocAsync((void **)&width, sizeof(int32_t) * ((size_t)nsl + 1), s));
+    MXS_HIP(hipMallocAsync((void **)&wscan, sizeof(int32_t) * ((size_t)nsl + 1), s));
+    MXS_HIP(hipMallocAsync((void **)&flags, sizeof(int), s));
+    auto cleanup = [&] {
+        (void)hipFreeAsync(width, s);
+        (void)hipFreeAsync(wscan, s);
+        (void)hipFreeAsync(flags, s);
+    };
+    mg_width_kernel<<<blocks(nsl), kMgNT, 0, s>>>(g, dev_sfirst, L.order, irp, nsl, width);
+    st = launch_status();
+    if (st == MXS_OK) st = scan_i32(width, wscan, nsl, s);
+    if (st == MXS_OK) {
+        mg_slice_offsets_kernel<<<blocks(nsl + 1), kMgNT, 0, s>>>(wscan, nsl, L.soff);
+        st = launch_status();
+    }
+    int32_t total = 0;
+    if (st == MXS_OK && hipMemcpyAsync(&total, wscan + nsl, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess)
+        st = MXS_ERR_HIP;
+    if (st == MXS_OK && hipStreamSynchronize(s) != hipSuccess) st = MXS_ERR_HIP;
+    const size_t entries = (size_t)kSlice * (size_t)total;
+    if (st == MXS_OK) st = take(M, (void **)&L.col, sizeof(int32_t) * entries);
+    if (st == MXS_OK) st = take(M, (void **)&L.val, sizeof(double) * entries);
+    if (st == MXS_OK) st = take(M, (void **)&L.diag, sizeof(double) * (size_t)L.rows);
+    // lanes past a colour's last row are never read; zero them anyway
+    if (st == MXS_OK) st = fill_bytes0(L.col, sizeof(int32_t) * entries, s);
+    if (st == MXS_OK) st = fill_bytes0(L.val, sizeof(double) * entries, s);
+    if (st == MXS_OK) st = fill_bytes0(flags, sizeof(int), s);
+    if (st == MXS_OK) {
+        mg_fill_kernel<<<blocks(L.rows), kMgNT, 0, s>>>(g, dev_sfirst, L.order, irp, aj, av, L.soff,
+                                                        L.col, L.val, L.diag, flags);
+        st = launch_status();
+    }
+    int hf = 0;
+    if (st == MXS_OK && hipMemcpyAsync(&hf, flags, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess)
+        st = MXS_ERR_HIP;
+    cleanup();
+    if (st == MXS_OK && hipStreamSynchronize(s) != hipSuccess) st = MXS_ERR_HIP;
+    if (st != MXS_OK) return st;
+    if (hf) return MXS_ERR_INVALID_ARG; // no such row in the stencil: a build fault
+    if (vectors) {
+        if ((st = take(M, (void **)&L.r, sizeof(double) * (size_t)L.rows)) != MXS_OK) return st;
+        if ((st = take(M, (void **)&L.z, sizeof(double) * (size_t)L.rows)) != MXS_OK) return st;
+    }
+    return MXS_OK;
+}
+
+void mg_release(mxs_mg_s *M)
+{
+    if (!M) return;
+    for (auto &L : M->lv) delete L.A;
+    for (void *p : M->owned)
+        if (p) (void)hipFree(p);
+    delete M;
+}
+
+mxs_status mg_create(int32_t n, int32_t levels, mxs_mg_s **out, hipStream_t s)
+{
+    auto *M = new mxs_mg_s;
+    (void)hipGetDevice(&M->device);
+    M->lv.resize((size_t)levels);
+    mxs_status st = MXS_OK;
+    for (int32_t l = 0; l < levels && st == MXS_OK; ++l)
+        st = build_level(M, M->lv[(size_t)l], n >> l, l > 0, s);
+    if (st != MXS_OK) {
+        (void)hipStreamSynchronize(s);
+        mg_release(M);
+        return st;
+    }
+    *out = M;
+    return MXS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Sweeps and the cycle
+// ---------------------------------------------------------------------------
+static void colour_pass(const MgLevel &L, int c, bool zero, const double *r, double *x,
+                        const int *done, hipStream_t s)
+{
+    const int32_t p0 = L.coff[c], nr = L.coff[c + 1] - L.coff[c];
+    if (nr == 0) return;
+    if (zero)
+        symgs_colour_kernel<true><<<blocks(nr), kMgNT, 0, s>>>(L.order, L.soff, L.col, L.val, L.diag,
+                                                               r, x, p0, nr, L.sfirst[c], done);
+    else
+        symgs_colour_kernel<false><<<blocks(nr), kMgNT, 0, s>>>(L.order, L.soff, L.col, L.val, L.diag,
+                                                                r, x, p0, nr, L.sfirst[c], done);
+}
+
+// Forward over kSweep, backward over its reverse.  The backward sweep's
+// first colour would recompute the forward sweep's last one from the same
+// neighbour values (no colour reads itself): the same numbers, so it is
+// not launched.  zero_start: x is zero on entry.
+static mxs_status symgs_level(const MgLevel &L, const double *r, double *x, bool zero_start,
+                              const int *done, hipStream_t s)
+{
+    for (int k = 0; k < kColours; ++k) colour_pass(L, kSweep[k], zero_start && k == 0, r, x, done, s);
+    for (int k = kColours - 2; k >= 0; --k) colour_pass(L, kSweep[k], false, r, x, done, s);
+    return launch_status();
+}
+
+mxs_status symgs_launch(const mxs_mg_s *M, int32_t level, const double *r, double *x,
+                        hipStream_t s)
+{
+    return symgs_level(M->lv[(size_t)level], r, x, false, nullptr, s);
+}
+
+static mxs_status vcycle(const mxs_mg_s *M, size_t l, const double *r, double *z, const int *done,
+                         hipStream_t s)
+{
+    const MgLevel &L = M->lv[l];
+    mg_zero_kernel<<<std::min<uint32_t>(blocks(L.rows), 8192), kMgNT, 0, s>>>(z, L.rows, done);
+    mxs_status st = symgs_level(L, r, z, true, done, s);
+    if (st != MXS_OK || l + 1 == M->lv.size()) return st;
+    const MgLevel &C = M->lv[l + 1];
+    const int32_t nc = L.coff[1]; // colour-0 rows = coarse rows
+    mg_restrict_kernel<<<blocks(nc), kMgNT, 0, s>>>(L.order, L.soff, L.col, L.val, L.diag, r, z, nc,
+                                                    C.r, done);
+    if ((st = launch_status()) != MXS_OK) return st;
+    if ((st = vcycle(M, l + 1, C.r, C.z, done, s)) != MXS_OK) return st;
+    mg_prolong_kernel<<<blocks(nc), kMgNT, 0, s>>>(L.order, C.z, nc, z, done);
+    if ((st = launch_status()) != MXS_OK) return st;
+    return symgs_level(L, r, z, false, done, s);
+}
+
+mxs_status mg_apply(const mxs_mg_s *M, const double *r, double *z, const int *done, hipStream_t s)
+{
+    return vcycle(M, 0, r, z, done, s);
+}
+
+}  // namespace mxs

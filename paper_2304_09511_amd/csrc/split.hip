@@ -248,8 +248,6 @@ mxs_status split_size(const mxs_mat_s *A, double min_fill, int32_t *band_ndiag, 
     return MXS_OK;
 }
 
-mxs_status coo_irp_launch(int64_t nnz, int32_t nrows, const int32_t *ai, int32_t *irp,
-                          hipStream_t s);
 
 mxs_status split(const mxs_mat_s *A, double min_fill, mxs_format rest_fmt, int32_t *band_doff,
                  void *band_vals, int32_t *rest_idx0, int32_t *rest_idx1, void *rest_vals,

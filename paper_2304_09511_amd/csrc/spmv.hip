@@ -1218,8 +1218,6 @@ __global__ void tile_rows_max_kernel(const int32_t *__restrict__ tile_row, int64
     if (t < ntiles) atomicMax(out, tile_row[t + 1] - tile_row[t]);
 }
 
-mxs_status coo_irp_launch(int64_t nnz, int32_t nrows, const int32_t *ai, int32_t *irp,
-                          hipStream_t s);
 
 // COO plan: the CSR tiling derived from the row ids through a temporary row
 // pointer array (freed here), kept when every tile owns at most kCooRowsMax
