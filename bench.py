@@ -140,6 +140,82 @@ def cg_runs(torch, mxs, mats, rtol, label):
     return res, bn
 
 
+def symgs_bytes(nn):
+    """Algorithmic bytes of one symmetric sweep on the nn^3 stencil: every
+    colour pass reads its rows' off-diagonal entries (4-byte column, 8-byte
+    value), diagonal, right-hand side and row id, writes their x, and reads
+    x once; 15 passes (the backward sweep repeats no colour)."""
+    import oracle as orc
+    rows = nn ** 3
+    col = orc.grid_colours(nn)
+    # off-diagonal entries per row of the 27-point stencil: (product of
+    # neighbours in range along each axis) - 1
+    i = np.arange(rows)
+    ax = [i % nn, (i // nn) % nn, i // (nn * nn)]
+    span = np.ones(rows, np.int64)
+    for a in ax:
+        span *= 1 + (a > 0) + (a < nn - 1)
+    offd = span - 1
+    total = 0
+    passes = list(orc.COLOUR_SWEEP) + list(reversed(orc.COLOUR_SWEEP[:-1]))
+    for c in passes:
+        sel = col == c
+        total += int(offd[sel].sum()) * 12 + int(sel.sum()) * (8 + 8 + 4 + 8) + rows * 8
+    return total
+
+
+def pcg_runs(torch, mxs, n, levels, rtol, mats_for_spmv):
+    """PCG with HPCG's V-cycle to rtol: time to tolerance after a warm-up
+    solve, the timed split per kernel class, one V-cycle and one finest-level
+    sweep timed on their own, and the solution against the oracle's run."""
+    M = mxs.Multigrid(n, levels)
+    _, A0 = M.level(0)
+    b = mxs.spmv(A0, torch.ones(A0.nrows, dtype=torch.float64, device="cuda"))
+    out = {"config": f"27-point stencil {n}^3, {levels} levels, b = A*1, x0 = 0, PCG to {rtol} "
+                     f"(||r_k|| / ||r_0||), one V-cycle per iteration: one symmetric "
+                     f"multicolour Gauss-Seidel sweep before and after the coarse correction"}
+    for name, A in (("csr", None), ("dia", mats_for_spmv.get("dia"))):
+        if name != "csr" and A is None:
+            continue
+        M.pcg_solve(b, A=A, rtol=rtol, maxit=1000)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, x, r = M.pcg_solve(b, A=A, rtol=rtol, maxit=1000)
+        torch.cuda.synchronize()
+        t_tol = (time.perf_counter() - t0) * 1e3
+        _, _, rt = M.pcg_solve(b, A=A, rtol=rtol, maxit=1000, timing=True)
+        rec = {"status": st, "iters": r["iters"], "time_to_tol_ms": round(t_tol, 3),
+               "ms_per_iter": round(t_tol / max(r["iters"], 1), 4),
+               "true_rel_resid": r["true_rel_resid"],
+               "max_abs_err_vs_ones": float((x - 1.0).abs().max()),
+               "timed_split_ms": {k: round(rt["t_" + k + "_ms"], 3)
+                                  for k in ("precond", "spmv", "dot", "axpy")}}
+        g = load_golden(f"pcg_mg{levels}_stencil{n}_tol{rtol:.0e}".replace("e-0", "e-"))
+        if g is not None:
+            idx = torch.tensor(g["sample_idx"], device="cuda")
+            xo = np.array(g["x_sample"])
+            rec["oracle_iters"] = g["iters"]
+            rec["max_rel_err_vs_oracle_sample"] = float(np.max(np.abs(x[idx].cpu().numpy() - xo))
+                                                        / np.max(np.abs(xo)))
+        out["spmv_" + name] = rec
+        log(f"[bench] PCG-MG {n}^3 ({name} SpMV): {r['iters']} it, {t_tol:.1f} ms, "
+            f"split {rec['timed_split_ms']}")
+    r0 = torch.rand(A0.nrows, dtype=torch.float64, device="cuda")
+    z0 = torch.empty_like(r0)
+    tc = time_calls(torch, lambda: M.apply(r0, z0), batches=5, per_batch=20)
+    out["vcycle_ms"] = round(tc["median_ms"], 4)
+    xs = torch.zeros_like(r0)
+    tc = time_calls(torch, lambda: M.symgs(0, r0, xs), batches=5, per_batch=20)
+    sb = symgs_bytes(n)
+    out["symgs_finest"] = {"ms": round(tc["median_ms"], 4), "algorithmic_bytes": sb,
+                           "GBps": round(sb / (tc["median_ms"] * 1e-3) / 1e9, 1),
+                           "launches": 15}
+    log(f"[bench] V-cycle {out['vcycle_ms']} ms; finest symmetric sweep {tc['median_ms']:.4f} ms, "
+        f"{out['symgs_finest']['GBps']} GB/s")
+    M.close()
+    return out
+
+
 MIXED_VARIANTS = (("fp64", {}),
                   ("ir_inner1e-4", dict(mixed="ir", inner_rtol=1e-4, max_outer=20)),
                   ("ir_inner1e-5", dict(mixed="ir", inner_rtol=1e-5, max_outer=20)),
@@ -449,6 +525,7 @@ def main():
     ap.add_argument("--mixed-n", type=int, default=192)
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cg", action="store_true")
+    ap.add_argument("--no-pcg", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-irregular", action="store_true")
     ap.add_argument("--no-selector", action="store_true")
@@ -553,6 +630,8 @@ def main():
         out["cg"], _ = cg_runs(torch, mxs, mats, 1e-9, f"{args.n}^3")
         out["cg"]["config"] = f"b = A*1, x0 = 0, unpreconditioned CG to 1e-9 (||r_k|| / ||r_0||)"
         compare_golden(out["cg"], f"cg_stencil{args.n}_tol1e-9")
+    if not args.no_pcg:
+        out["pcg_mg"] = pcg_runs(torch, mxs, args.n, 4, 1e-9, mats)
     for A in mats.values():
         A.close()
     del ys

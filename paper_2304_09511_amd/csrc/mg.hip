@@ -31,6 +31,19 @@ namespace mxs {
 constexpr int kSlice = 64;
 constexpr int kColours = 8;
 constexpr int kMgNT = 256;
+// Colour passes of a large level (at least kBigRows rows) are bandwidth
+// bound: 256-thread workgroups, 16 entries a step, slice entries streamed
+// with non-temporal loads.  Those of a smaller level are latency bound and
+// its slices stay in cache between passes: 64-thread workgroups (more CUs
+// for a few rows), 32 entries a step, cached loads.
+constexpr int32_t kBigRows = 1 << 20;
+
+template <bool STREAM, typename T>
+__device__ __forceinline__ T ld_slice(const T *p)
+{
+    if constexpr (STREAM) return __builtin_nontemporal_load(p);
+    else return *p;
+}
 // sweep order of the colours: coarse points (colour 0) last
 constexpr int kSweep[kColours] = {1, 2, 3, 4, 5, 6, 7, 0};
 
@@ -132,9 +145,7 @@ __global__ void mg_fill_kernel(ColourGeom g, const int32_t *__restrict__ slice_c
 }
 
 // One colour of a Gauss-Seidel sweep: every row of the colour at once.
-// ZERO: x is zero on entry (the first colour swept from a zero start), so
-// the row sums are r_i alone.
-template <bool ZERO>
+template <int U, bool STREAM>
 __global__ __launch_bounds__(kMgNT) void symgs_colour_kernel(
     const int32_t *__restrict__ order, const int64_t *__restrict__ soff,
     const int32_t *__restrict__ col, const double *__restrict__ val,
@@ -142,34 +153,52 @@ __global__ __launch_bounds__(kMgNT) void symgs_colour_kernel(
     int32_t p0, int32_t nrows_c, int32_t s0, const int *__restrict__ done)
 {
     if (done && *done) return;
-    const int32_t t = blockIdx.x * kMgNT + threadIdx.x;
+    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nrows_c) return;
     const int32_t s = s0 + t / kSlice;
     const int lane = t % kSlice;
     const int32_t i = order[p0 + t];
     double sum = r[i];
-    if (!ZERO) {
+    {
         const int64_t base = soff[s];
         const int32_t w = (int32_t)((soff[s + 1] - base) / kSlice);
         const int32_t *__restrict__ cs = col + base + lane;
         const double *__restrict__ vs = val + base + lane;
-        int32_t k = 0;
-        for (; k + 4 <= w; k += 4) {
-            int32_t c4[4];
-            double v4[4], x4[4];
+        // U entries per step, all loads of a step issued together; entries
+        // past the slice width are skipped (column i, value 0: no load)
+        for (int32_t k = 0; k < w; k += U) {
+            int32_t cu[U];
+            double vu[U], xu[U];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                c4[u] = cs[(k + u) * kSlice];
-                v4[u] = vs[(k + u) * kSlice];
+            for (int u = 0; u < U; ++u) {
+                const bool in = k + u < w;
+                cu[u] = in ? ld_slice<STREAM>(&cs[(k + u) * kSlice]) : i;
+                vu[u] = in ? ld_slice<STREAM>(&vs[(k + u) * kSlice]) : 0.0;
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) x4[u] = x[c4[u]];
+            for (int u = 0; u < U; ++u) xu[u] = x[cu[u]];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) sum -= v4[u] * x4[u];
+            for (int u = 0; u < U; ++u) sum -= vu[u] * xu[u];
         }
-        for (; k < w; ++k) sum -= vs[k * kSlice] * x[cs[k * kSlice]];
     }
     x[i] = sum / diag[p0 + t];
+}
+
+// The first colour pass of a sweep from z = 0 with the zeroing folded in:
+// rows of the first colour (positions [q0, q1)) get r_i / a_ii (their
+// neighbours are all zero), every other row gets 0.
+__global__ __launch_bounds__(kMgNT) void mg_start_kernel(const int32_t *__restrict__ order,
+                                                         const double *__restrict__ diag,
+                                                         const double *__restrict__ r,
+                                                         double *__restrict__ z, int32_t rows,
+                                                         int32_t q0, int32_t q1,
+                                                         const int *__restrict__ done)
+{
+    if (done && *done) return;
+    for (int32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < rows; p += gridDim.x * blockDim.x) {
+        const int32_t i = order[p];
+        z[i] = p >= q0 && p < q1 ? r[i] / diag[p] : 0.0;
+    }
 }
 
 // r_c[ic] = r[i] - (A z)[i] for the colour-0 row i = order[ic].
@@ -180,7 +209,7 @@ __global__ __launch_bounds__(kMgNT) void mg_restrict_kernel(
     int32_t nc, double *__restrict__ rc, const int *__restrict__ done)
 {
     if (done && *done) return;
-    const int32_t t = blockIdx.x * kMgNT + threadIdx.x;
+    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nc) return;
     const int32_t s = t / kSlice;
     const int lane = t % kSlice;
@@ -200,14 +229,6 @@ __global__ void mg_prolong_kernel(const int32_t *__restrict__ order, const doubl
     if (done && *done) return;
     const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < nc) z[order[t]] += zc[t];
-}
-
-__global__ void mg_zero_kernel(double *__restrict__ z, int64_t n, const int *__restrict__ done)
-{
-    if (done && *done) return;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        z[i] = 0.0;
 }
 
 static uint32_t blocks(int64_t n, int nt = kMgNT) { return (uint32_t)std::max<int64_t>(1, (n + nt - 1) / nt); }
@@ -358,28 +379,33 @@ mxs_status mg_create(int32_t n, int32_t levels, mxs_mg_s **out, hipStream_t s)
 // ---------------------------------------------------------------------------
 // Sweeps and the cycle
 // ---------------------------------------------------------------------------
-static void colour_pass(const MgLevel &L, int c, bool zero, const double *r, double *x,
+static void colour_pass(const MgLevel &L, int c, const double *r, double *x,
                         const int *done, hipStream_t s)
 {
     const int32_t p0 = L.coff[c], nr = L.coff[c + 1] - L.coff[c];
     if (nr == 0) return;
-    if (zero)
-        symgs_colour_kernel<true><<<blocks(nr), kMgNT, 0, s>>>(L.order, L.soff, L.col, L.val, L.diag,
-                                                               r, x, p0, nr, L.sfirst[c], done);
-    else
-        symgs_colour_kernel<false><<<blocks(nr), kMgNT, 0, s>>>(L.order, L.soff, L.col, L.val, L.diag,
-                                                                r, x, p0, nr, L.sfirst[c], done);
+    const bool big = L.rows >= kBigRows;
+    const int nt = big ? 256 : 64;
+    auto kern = big ? symgs_colour_kernel<16, true> : symgs_colour_kernel<32, false>;
+    kern<<<blocks(nr, nt), nt, 0, s>>>(L.order, L.soff, L.col, L.val, L.diag, r, x, p0, nr,
+                                       L.sfirst[c], done);
 }
 
 // Forward over kSweep, backward over its reverse.  The backward sweep's
 // first colour would recompute the forward sweep's last one from the same
 // neighbour values (no colour reads itself): the same numbers, so it is
-// not launched.  zero_start: x is zero on entry.
+// not launched.  zero_start: x is set to zero first (folded into the first
+// colour's pass, whose rows then read only zeros).
 static mxs_status symgs_level(const MgLevel &L, const double *r, double *x, bool zero_start,
                               const int *done, hipStream_t s)
 {
-    for (int k = 0; k < kColours; ++k) colour_pass(L, kSweep[k], zero_start && k == 0, r, x, done, s);
-    for (int k = kColours - 2; k >= 0; --k) colour_pass(L, kSweep[k], false, r, x, done, s);
+    if (zero_start) {
+        const int c = kSweep[0];
+        mg_start_kernel<<<std::min<uint32_t>(blocks(L.rows, 256), 8192), 256, 0, s>>>(
+            L.order, L.diag, r, x, L.rows, L.coff[c], L.coff[c + 1], done);
+    }
+    for (int k = zero_start ? 1 : 0; k < kColours; ++k) colour_pass(L, kSweep[k], r, x, done, s);
+    for (int k = kColours - 2; k >= 0; --k) colour_pass(L, kSweep[k], r, x, done, s);
     return launch_status();
 }
 
@@ -393,16 +419,16 @@ static mxs_status vcycle(const mxs_mg_s *M, size_t l, const double *r, double *z
                          hipStream_t s)
 {
     const MgLevel &L = M->lv[l];
-    mg_zero_kernel<<<std::min<uint32_t>(blocks(L.rows), 8192), kMgNT, 0, s>>>(z, L.rows, done);
     mxs_status st = symgs_level(L, r, z, true, done, s);
     if (st != MXS_OK || l + 1 == M->lv.size()) return st;
     const MgLevel &C = M->lv[l + 1];
     const int32_t nc = L.coff[1]; // colour-0 rows = coarse rows
-    mg_restrict_kernel<<<blocks(nc), kMgNT, 0, s>>>(L.order, L.soff, L.col, L.val, L.diag, r, z, nc,
-                                                    C.r, done);
+    const int nt = L.rows >= kBigRows ? 256 : 64;
+    mg_restrict_kernel<<<blocks(nc, nt), nt, 0, s>>>(L.order, L.soff, L.col, L.val, L.diag, r, z, nc,
+                                                     C.r, done);
     if ((st = launch_status()) != MXS_OK) return st;
     if ((st = vcycle(M, l + 1, C.r, C.z, done, s)) != MXS_OK) return st;
-    mg_prolong_kernel<<<blocks(nc), kMgNT, 0, s>>>(L.order, C.z, nc, z, done);
+    mg_prolong_kernel<<<blocks(nc, nt), nt, 0, s>>>(L.order, C.z, nc, z, done);
     if ((st = launch_status()) != MXS_OK) return st;
     return symgs_level(L, r, z, false, done, s);
 }

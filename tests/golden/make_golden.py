@@ -9,7 +9,9 @@ solution x at 4,096 seeded sample indices (plus the first and last rows).
 Cited method: unpreconditioned conjugate gradients on the HPCG 27-point
 operator with b = A*1 and x0 = 0 (Section VII-D), stopping on the recursive
 relative residual; mixed-precision refinement with an FP32 inner CG and an
-FP64 outer residual and update (the mixed precision named in Section I).
+FP64 outer residual and update (the mixed precision named in Section I);
+PCG with HPCG's multigrid V-cycle (symmetric Gauss-Seidel smoother; Section
+VII-D describes HPCG's preconditioner).
 """
 import argparse
 import json
@@ -63,7 +65,26 @@ def mixed_case(n, tol, inner_rtol, max_outer):
             "oracle_seconds": round(time.time() - t, 1)}
 
 
+def pcg_case(n, levels, tol):
+    lv = []
+    for l in range(levels):
+        a = wl.stencil(n >> l)
+        lv.append((n >> l, orc.coo_to_csr(a.nrows, a.ai), a.aj, a.av))
+    _, irp, aj, av = lv[0]
+    b = orc.csr_spmv(irp, aj, av, np.ones(n ** 3))
+    t = time.time()
+    st, x, iters, rel, true_rel = orc.pcg(irp, aj, av, b, lambda r: orc.mg_vcycle(lv, r), tol=tol,
+                                          maxit=1000)
+    idx = sample_indices(n ** 3)
+    return {"what": f"oracle PCG with HPCG's {levels}-level V-cycle (multicolour symmetric "
+                    f"Gauss-Seidel), 27-point stencil {n}^3, b = A*1, x0 = 0, tol {tol}",
+            "n": n, "levels": levels, "rows": n ** 3, "tol": tol, "status": st, "iters": iters,
+            "rel_resid": rel, "true_rel_resid": true_rel, "sample_idx": idx.tolist(),
+            "x_sample": x[idx].tolist(), "oracle_seconds": round(time.time() - t, 1)}
+
+
 CASES = {
+    "pcg_mg4_stencil128_tol1e-9": lambda: pcg_case(128, 4, 1e-9),
     "cg_stencil128_tol1e-9": lambda: cg_case(128, 1e-9),
     "cg_stencil192_tol1e-10": lambda: cg_case(192, 1e-10),
     "mixed_stencil192_tol1e-10": lambda: mixed_case(192, 1e-10, 1e-4, 20),

@@ -8,6 +8,7 @@
   oracle on 2,000 seeded rows.
 * 192^3 stencil (7,077,888 rows): FP64 CG and mixed refinement to 1e-10
   against the oracle's stored solutions at 4,098 sampled rows.
+* 128^3 PCG with HPCG's 4-level multigrid V-cycle against the oracle's run.
 
 Stored oracle results come from tests/golden/make_golden.py.
 """
@@ -122,6 +123,27 @@ def test_irregular_4M_spmv_sampled_rows(gpu, family):
         assert np.all(np.isfinite(y)), fmt
     for B in mats.values():
         B.close()
+
+
+def test_stencil128_pcg_multigrid_matches_oracle_run(gpu):
+    """PCG with HPCG's 4-level V-cycle on 128^3 against the oracle's stored
+    run: iterations within 2, sampled x within 1e-5, true residual 2 tol."""
+    import torch
+    g = golden("pcg_mg4_stencil128_tol1e-9")
+    M = gpu.Multigrid(128, 4)
+    _, A = M.level(0)
+    b = gpu.spmv(A, torch.ones(A.nrows, dtype=torch.float64, device="cuda"))
+    idx = torch.tensor(g["sample_idx"], device="cuda")
+    xo = np.array(g["x_sample"])
+    D = gpu.stencil(128, fmt="coo").convert("dia")
+    for B in (None, D):
+        st, x, r = M.pcg_solve(b, A=B, rtol=1e-9, maxit=1000)
+        assert st == 0 and abs(r["iters"] - g["iters"]) <= 2, (r["iters"], g["iters"])
+        assert r["true_rel_resid"] <= 2e-9
+        err = np.max(np.abs(x[idx].cpu().numpy() - xo)) / np.max(np.abs(xo))
+        assert err <= 1e-5, err
+    D.close()
+    M.close()
 
 
 @pytest.fixture(scope="module")
