@@ -66,8 +66,25 @@ def split_bytes(H, rest):
     return 8 * band_slots + 4 * H.ndiag + rest_bytes + 8 * (H.ncols + H.nrows)
 
 
-def source_sha():
-    return hashlib.sha256(open(SPMV_SRC, "rb").read()).hexdigest()[:16]
+def source_sha(path=None):
+    return hashlib.sha256(open(path or SPMV_SRC, "rb").read()).hexdigest()[:16]
+
+
+MG_SRC = os.path.join(ROOT, "paper_2304_09511_amd", "csrc", "mg.hip")
+
+
+def symgs_traffic_from_profile(n):
+    """HBM bytes of one finest-level symmetric sweep from the committed
+    counter summary, if it was taken on the current mg.hip."""
+    path = os.path.join(ROOT, "profiles", f"symgs_sweep_stencil{n}_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_sha = re.search(r"^source_sha256_16:\s*(\w+)", text, re.M)
+    m_b = re.search(r"^hbm_bytes_per_sweep:\s*([0-9.eE+]+)", text, re.M)
+    if not m_sha or not m_b or m_sha.group(1) != source_sha(MG_SRC):
+        return None
+    return float(m_b.group(1))
 
 
 def traffic_from_profile(fmt, workload_tag):
@@ -209,7 +226,8 @@ def pcg_runs(torch, mxs, n, levels, rtol, mats_for_spmv):
     sb = symgs_bytes(n)
     out["symgs_finest"] = {"ms": round(tc["median_ms"], 4), "algorithmic_bytes": sb,
                            "GBps": round(sb / (tc["median_ms"] * 1e-3) / 1e9, 1),
-                           "launches": 15}
+                           "frac_of_peak": round(sb / (tc["median_ms"] * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                           "launches": 15, "traffic": symgs_traffic_from_profile(n)}
     log(f"[bench] V-cycle {out['vcycle_ms']} ms; finest symmetric sweep {tc['median_ms']:.4f} ms, "
         f"{out['symgs_finest']['GBps']} GB/s")
     M.close()
@@ -500,18 +518,30 @@ def pmc_mode(args):
 
     import paper_2304_09511_amd as mxs
     mxs.load()
-    mats = build_matrices(mxs, args.n)
-    A = mats[args.pmc]
-    x = torch.from_numpy(np.random.Generator(np.random.PCG64(1)).uniform(-1, 1, A.ncols)).cuda()
-    y = torch.empty(A.nrows, dtype=torch.float64, device="cuda")
-    for _ in range(args.steps):
-        mxs.spmv(A, x, y)
+    if args.pmc == "symgs":
+        M = mxs.Multigrid(args.n, 4)
+        r = torch.from_numpy(np.random.Generator(np.random.PCG64(1)).uniform(-1, 1, args.n ** 3)).cuda()
+        x = torch.zeros_like(r)
+        for _ in range(args.steps):
+            M.symgs(0, r, x)
+    else:
+        mats = build_matrices(mxs, args.n)
+        A = mats[args.pmc]
+        x = torch.from_numpy(np.random.Generator(np.random.PCG64(1)).uniform(-1, 1, A.ncols)).cuda()
+        y = torch.empty(A.nrows, dtype=torch.float64, device="cuda")
+        for _ in range(args.steps):
+            mxs.spmv(A, x, y)
     # calibration: a plain copy of 1 GiB (reads 1 GiB, writes 1 GiB)
     src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(3):
         dst.copy_(src)
     torch.cuda.synchronize()
+    if args.pmc == "symgs":
+        print(json.dumps({"pmc": "symgs", "bytes_per_sweep": symgs_bytes(args.n),
+                          "copy_bytes_each_way": src.numel() * 8,
+                          "source_sha256_16": source_sha(MG_SRC)}))
+        return
     print(json.dumps({"pmc": args.pmc, "bytes_per_launch": algorithmic_bytes(A, args.pmc),
                       "copy_bytes_each_way": src.numel() * 8, "source_sha256_16": source_sha()}))
 
@@ -530,7 +560,7 @@ def main():
     ap.add_argument("--no-irregular", action="store_true")
     ap.add_argument("--no-selector", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--pmc", choices=FORMATS, default=None)
+    ap.add_argument("--pmc", choices=FORMATS + ("symgs",), default=None)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
