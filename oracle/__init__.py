@@ -100,6 +100,13 @@ def _bind(lib):
         "orc_mlp_loss_grad": (D, [P, P, P, I64, P]),
         "orc_adam_step": (None, [I64, P, P, P, P, D, I64, D, D, D]),
         "orc_symgs": (C.c_int, [I64, P, P, P, P, P, P]),
+        "orc_ell_width": (I64, [I64, P]),
+        "orc_csr_to_ell": (None, [I64, P, P, P, I64, P, P]),
+        "orc_ell_spmv": (None, [I64, I64, P, P, P, P]),
+        "orc_sell_perm": (None, [I64, P, I64, P]),
+        "orc_sell_offsets": (I64, [I64, P, P, I64, P]),
+        "orc_csr_to_sell": (None, [I64, P, P, P, I64, P, P, P, P]),
+        "orc_sell_spmv": (None, [I64, I64, P, P, P, P, P, P]),
         "orc_gs_sweep": (C.c_int, [I64, P, P, P, P, C.c_int, P, P]),
     }
     for name, (res, args) in sig.items():
@@ -304,6 +311,82 @@ def adam_step(w, m, v, g, lr, t, b1=0.9, b2=0.999, eps=1e-8):
         assert a.dtype == np.float64 and a.flags.c_contiguous
     g = _f64(g)
     _load().orc_adam_step(w.shape[0], _p(w), _p(m), _p(v), _p(g), lr, t, b1, b2, eps)
+
+
+# ------------------------------------------- ELL and SELL-C-sigma (Sec. IX)
+def csr_to_ell(irp, aj, av):
+    """(K, col[K*nrows], val[K*nrows]): ELL, column-major, padding col -1."""
+    irp, aj, av = _i32(irp), _i32(aj), _f64(av)
+    n = irp.shape[0] - 1
+    lib = _load()
+    K = int(lib.orc_ell_width(n, _p(irp)))
+    col = np.empty(K * n, np.int32)
+    val = np.empty(K * n, np.float64)
+    lib.orc_csr_to_ell(n, _p(irp), _p(aj), _p(av), K, _p(col), _p(val))
+    return K, col, val
+
+
+def ell_spmv(nrows, K, col, val, x):
+    col, val, x = _i32(col), _f64(val), _f64(x)
+    y = np.empty(nrows, np.float64)
+    _load().orc_ell_spmv(nrows, K, _p(col), _p(val), _p(x), _p(y))
+    return y
+
+
+def ell_to_csr(nrows, K, col, val):
+    """Back to canonical CSR: a row's non-padding slots in slot order."""
+    col = np.asarray(col).reshape(K, nrows)
+    val = np.asarray(val).reshape(K, nrows)
+    keep = col >= 0
+    lens = keep.sum(axis=0)
+    irp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    return irp, col.T[keep.T].astype(np.int32), val.T[keep.T].astype(np.float64)
+
+
+def sell_layout(irp, C, sigma):
+    """(perm, cs) of SELL-C-sigma for the row lengths of irp."""
+    irp = _i32(irp)
+    n = irp.shape[0] - 1
+    lib = _load()
+    perm = np.empty(n, np.int32)
+    lib.orc_sell_perm(n, _p(irp), sigma, _p(perm))
+    cs = np.empty((n + C - 1) // C + 1, np.int64)
+    lib.orc_sell_offsets(n, _p(irp), _p(perm), C, _p(cs))
+    return perm, cs
+
+
+def csr_to_sell(irp, aj, av, C, sigma):
+    """(perm, cs, col[cs[-1]], val[cs[-1]]) of SELL-C-sigma."""
+    irp, aj, av = _i32(irp), _i32(aj), _f64(av)
+    n = irp.shape[0] - 1
+    perm, cs = sell_layout(irp, C, sigma)
+    col = np.empty(int(cs[-1]), np.int32)
+    val = np.empty(int(cs[-1]), np.float64)
+    _load().orc_csr_to_sell(n, _p(irp), _p(aj), _p(av), C, _p(perm), _p(cs), _p(col), _p(val))
+    return perm, cs, col, val
+
+
+def sell_spmv(nrows, C, perm, cs, col, val, x):
+    perm, cs, col, val, x = _i32(perm), np.ascontiguousarray(cs, np.int64), _i32(col), _f64(val), _f64(x)
+    y = np.empty(nrows, np.float64)
+    _load().orc_sell_spmv(nrows, C, _p(perm), _p(cs), _p(col), _p(val), _p(x), _p(y))
+    return y
+
+
+def sell_to_csr(nrows, C, perm, cs, col, val):
+    """Back to canonical CSR (rows in their original order)."""
+    rows_c, rows_v = [None] * nrows, [None] * nrows
+    for p in range(nrows):
+        s, r = divmod(p, C)
+        w = (int(cs[s + 1]) - int(cs[s])) // C
+        q = int(cs[s]) + np.arange(w) * C + r
+        keep = col[q] >= 0
+        rows_c[perm[p]] = col[q][keep]
+        rows_v[perm[p]] = val[q][keep]
+    lens = np.array([len(c) for c in rows_c], np.int64)
+    irp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    cat = lambda parts, t: np.concatenate(parts).astype(t) if nrows else np.zeros(0, t)
+    return irp, cat(rows_c, np.int32), cat(rows_v, np.float64)
 
 
 # ------------------------------------------------- HPCG's preconditioner

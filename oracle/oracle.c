@@ -839,3 +839,122 @@ int orc_gs_sweep(int64_t n, const int32_t *irp, const int32_t *aj, const double 
     }
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------------------
+ * Padded formats named as further work in Section IX.
+ *
+ * ELL (ELLPACK): every row gets K = (longest row) slots, stored column-major:
+ * slot k of row i at k*nrows + i holds the row's k-th entry (columns
+ * ascending); slots past the row's length hold column -1 and value +0.0.
+ *
+ * SELL-C-sigma (Kreutzer et al., SIAM J. Sci. Comput. 36(5), 2014): rows are
+ * sorted by descending length, stably, inside windows of sigma consecutive
+ * rows; perm[p] is the row at sorted position p.  Positions are cut into
+ * slices of C; slice s is as wide as its longest row and starts at cs[s]
+ * (cs[s+1] = cs[s] + C * width_s); slot k of position p in slice s is at
+ * cs[s] + k*C + (p - s*C), padded as ELL (positions past the last row too).
+ * ---------------------------------------------------------------------- */
+int64_t orc_ell_width(int64_t nrows, const int32_t *irp)
+{
+    int64_t k = 0;
+    for (int64_t i = 0; i < nrows; ++i)
+        if (irp[i + 1] - irp[i] > k)
+            k = irp[i + 1] - irp[i];
+    return k;
+}
+
+void orc_csr_to_ell(int64_t nrows, const int32_t *irp, const int32_t *aj, const double *av,
+                    int64_t K, int32_t *ecol, double *eval)
+{
+    for (int64_t i = 0; i < nrows; ++i)
+        for (int64_t k = 0; k < K; ++k) {
+            const int64_t len = irp[i + 1] - irp[i];
+            ecol[k * nrows + i] = k < len ? aj[irp[i] + k] : -1;
+            eval[k * nrows + i] = k < len ? av[irp[i] + k] : 0.0;
+        }
+}
+
+/* y_i = sum over the row's slots, k ascending, of value * x[column]; padding
+ * slots (column -1) are skipped. */
+void orc_ell_spmv(int64_t nrows, int64_t K, const int32_t *ecol, const double *eval,
+                  const double *x, double *y)
+{
+    for (int64_t i = 0; i < nrows; ++i) {
+        double sum = 0.0;
+        for (int64_t k = 0; k < K; ++k)
+            if (ecol[k * nrows + i] >= 0)
+                sum += eval[k * nrows + i] * x[ecol[k * nrows + i]];
+        y[i] = sum;
+    }
+}
+
+/* perm: stable descending-length order inside each window of sigma rows,
+ * by counting: longer rows first, equal lengths in row order. */
+void orc_sell_perm(int64_t nrows, const int32_t *irp, int64_t sigma, int32_t *perm)
+{
+    for (int64_t w0 = 0; w0 < nrows; w0 += sigma) {
+        const int64_t w1 = w0 + sigma < nrows ? w0 + sigma : nrows;
+        int64_t maxlen = 0;
+        for (int64_t i = w0; i < w1; ++i)
+            if (irp[i + 1] - irp[i] > maxlen)
+                maxlen = irp[i + 1] - irp[i];
+        int64_t p = w0;
+        for (int64_t len = maxlen; len >= 0; --len)
+            for (int64_t i = w0; i < w1; ++i)
+                if (irp[i + 1] - irp[i] == len)
+                    perm[p++] = (int32_t)i;
+    }
+}
+
+/* cs[0..nslices] for slices of C positions; returns nslices. */
+int64_t orc_sell_offsets(int64_t nrows, const int32_t *irp, const int32_t *perm, int64_t C,
+                         int64_t *cs)
+{
+    const int64_t ns = (nrows + C - 1) / C;
+    cs[0] = 0;
+    for (int64_t s = 0; s < ns; ++s) {
+        int64_t w = 0;
+        for (int64_t p = s * C; p < (s + 1) * C && p < nrows; ++p) {
+            const int64_t len = irp[perm[p] + 1] - irp[perm[p]];
+            if (len > w)
+                w = len;
+        }
+        cs[s + 1] = cs[s] + C * w;
+    }
+    return ns;
+}
+
+void orc_csr_to_sell(int64_t nrows, const int32_t *irp, const int32_t *aj, const double *av,
+                     int64_t C, const int32_t *perm, const int64_t *cs, int32_t *scol, double *sval)
+{
+    const int64_t ns = (nrows + C - 1) / C;
+    for (int64_t s = 0; s < ns; ++s) {
+        const int64_t w = (cs[s + 1] - cs[s]) / C;
+        for (int64_t r = 0; r < C; ++r) {
+            const int64_t p = s * C + r;
+            const int64_t i = p < nrows ? perm[p] : -1;
+            const int64_t len = i >= 0 ? irp[i + 1] - irp[i] : 0;
+            for (int64_t k = 0; k < w; ++k) {
+                scol[cs[s] + k * C + r] = k < len ? aj[irp[i] + k] : -1;
+                sval[cs[s] + k * C + r] = k < len ? av[irp[i] + k] : 0.0;
+            }
+        }
+    }
+}
+
+/* y[perm[p]] = sum over position p's slots, k ascending (padding skipped). */
+void orc_sell_spmv(int64_t nrows, int64_t C, const int32_t *perm, const int64_t *cs,
+                   const int32_t *scol, const double *sval, const double *x, double *y)
+{
+    for (int64_t p = 0; p < nrows; ++p) {
+        const int64_t s = p / C, r = p % C;
+        const int64_t w = (cs[s + 1] - cs[s]) / C;
+        double sum = 0.0;
+        for (int64_t k = 0; k < w; ++k) {
+            const int64_t q = cs[s] + k * C + r;
+            if (scol[q] >= 0)
+                sum += sval[q] * x[scol[q]];
+        }
+        y[perm[p]] = sum;
+    }
+}

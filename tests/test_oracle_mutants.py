@@ -9,6 +9,7 @@ import pytest
 import oracle as orc
 import test_oracle as pins
 import test_oracle_mg as mg
+import test_oracle_sell as sell
 
 SRC = os.path.join(os.path.dirname(orc.__file__), "oracle.c")
 
@@ -99,6 +100,23 @@ MUTANTS = [
      "        if (aj[k] == i)\n            d = av[k];\n        else\n            s -= av[k] * x[aj[k]];",
      "        if (aj[k] == i)\n            d = av[k];\n        s -= av[k] * x[aj[k]];",
      [lambda: mg.test_gs_sweeps_are_triangular_solves("random60", "permuted")]),
+    ("ell_row_major",
+     "            ecol[k * nrows + i] = k < len ? aj[irp[i] + k] : -1;\n            eval[k * nrows + i] = k < len ? av[irp[i] + k] : 0.0;",
+     "            ecol[i * K + k] = k < len ? aj[irp[i] + k] : -1;\n            eval[i * K + k] = k < len ? av[irp[i] + k] : 0.0;",
+     [sell.test_ell_hand_built_layout]),
+    ("sell_sorted_ascending",
+     "for (int64_t len = maxlen; len >= 0; --len)",
+     "for (int64_t len = 0; len <= maxlen; ++len)",
+     [lambda: sell.test_sell_perm_sorts_windows_stably(64)]),
+    ("sell_width_of_first_row",
+     "            if (len > w)\n                w = len;\n        }\n        cs[s + 1]",
+     "            if (p == s * C)\n                w = len;\n        }\n        cs[s + 1]",
+     [lambda: sell.test_spmv_integer_bruteforce(4, 1, (17, 17), 0.3),
+      lambda: sell.test_sell_perm_sorts_windows_stably(1)]),
+    ("sell_result_unpermuted",
+     "        y[perm[p]] = sum;",
+     "        y[p] = sum;",
+     [lambda: sell.test_spmv_integer_bruteforce(4, 8, (17, 17), 0.3)]),
     ("adam_no_bias_correction",
      "double mh = m[i] / c1, vh = v[i] / c2;",
      "double mh = m[i], vh = v[i];",
