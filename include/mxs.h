@@ -51,7 +51,7 @@ typedef enum {
     MXS_ERR_UNSUPPORTED = -10    /* operation not defined for this format/dtype/shape */
 } mxs_status;
 
-typedef enum { MXS_COO = 0, MXS_CSR = 1, MXS_DIA = 2, MXS_HDC = 3 } mxs_format;
+typedef enum { MXS_COO = 0, MXS_CSR = 1, MXS_DIA = 2, MXS_HDC = 3, MXS_ELL = 4, MXS_SELL = 5 } mxs_format;
 typedef enum { MXS_F64 = 0, MXS_F32 = 1 } mxs_dtype;
 
 /* Opaque host-side handle of a sparse matrix in one storage format. */
@@ -137,6 +137,11 @@ mxs_status mxs_arrays(mxs_mat A, const int32_t **idx0, const int32_t **idx1,
  *   dst DIA:     *ndiag = number of distinct offsets j - i, *count =
  *                ndiag*nrows (length of av).  Refused with
  *                MXS_ERR_DIA_TOO_SPARSE when ndiag*nrows > 8*nnz.
+ *   dst ELL:     (sources COO, CSR, ELL) *ndiag = K, the longest row's
+ *                length, *count = K*nrows.  Refused with
+ *                MXS_ERR_DIA_TOO_SPARSE when K*nrows > 8*nnz.
+ * ELL and SELL sources convert to COO and CSR only, SELL is reached
+ * through mxs_to_sell (MXS_ERR_UNSUPPORTED otherwise).
  * count or ndiag may be NULL. */
 mxs_status mxs_convert_size(mxs_mat src, mxs_format dst, int64_t *count, int32_t *ndiag,
                             void *stream);
@@ -146,11 +151,34 @@ mxs_status mxs_convert_size(mxs_mat src, mxs_format dst, int64_t *count, int32_t
  *   dst COO: idx0 = ai[count], idx1 = aj[count], vals = av[count]
  *   dst CSR: idx0 = irp[nrows+1], idx1 = aj[count], vals = av[count]
  *   dst DIA: idx0 = doff[ndiag], idx1 unused (may be NULL), vals = av[count]
+ *   dst ELL: idx0 = col[K*nrows], idx1 unused, vals = val[K*nrows]: ELL
+ *            (Section IX's further formats), column-major: slot k of row i
+ *            at k*nrows + i holds the row's k-th entry; slots past the row's
+ *            length hold column -1 and +0.0.  mxs_info reports K as ndiag.
  * with sizes from mxs_convert_size.  Output is canonical: rows ascending,
  * columns ascending within a row, DIA offsets ascending with +0.0 in slots
  * that hold no entry.  Values are moved, never recomputed: bit-exact. */
 mxs_status mxs_convert(mxs_mat src, mxs_format dst, int32_t *idx0, int32_t *idx1, void *vals,
                        mxs_mat *out, void *stream);
+
+/* SELL-C-sigma (Section IX's further formats; Kreutzer et al., 2014) with
+ * C = 64, one wavefront per slice, from a COO or CSR source.  Rows are sorted
+ * by descending length, stably, inside windows of `sigma` >= 1 consecutive
+ * rows: perm[p] = row at sorted position p.  Slice s (positions
+ * [64s, 64s+64)) is as wide as its longest row and starts at cs[s]
+ * (cs[s+1] = cs[s] + 64*width_s); slot k of position p in slice s is at
+ * cs[s] + 64k + (p - 64s), padded as ELL (positions past the last row too).
+ * mxs_sell_size [syncs]: *slots = cs[nslices], *nslices = ceil(nrows/64);
+ *   refused with MXS_ERR_DIA_TOO_SPARSE when slots > 8*nnz.
+ * mxs_to_sell [syncs]: writes perm[nrows], cs[nslices+1], col[slots],
+ *   vals[slots] (caller-allocated) and returns a handle that borrows them;
+ *   mxs_info reports the slice count as ndiag.  Values are moved
+ *   (bit-exact).  SpMV, CG (FP64, also as the FP32 operand of mixed
+ *   solves after mxs_cast), conversion to COO/CSR and cast accept ELL and
+ *   SELL handles; features and splits do not (MXS_ERR_UNSUPPORTED). */
+mxs_status mxs_sell_size(mxs_mat A, int32_t sigma, int64_t *slots, int32_t *nslices, void *stream);
+mxs_status mxs_to_sell(mxs_mat A, int32_t sigma, int32_t *perm, int64_t *cs, int32_t *col,
+                       void *vals, mxs_mat *out, void *stream);
 
 /* Same structure, values rounded to nearest (even) in `dtype` into
  * caller-allocated `vals` (as many values as src stores) [async].  The new handle borrows src's

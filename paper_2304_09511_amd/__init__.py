@@ -22,12 +22,12 @@ __all__ = [
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = os.path.join(_HERE, "libmxs.so")
 
-COO, CSR, DIA, HDC = 0, 1, 2, 3
+COO, CSR, DIA, HDC, ELL, SELL = 0, 1, 2, 3, 4, 5
 F64, F32 = 0, 1
 BORROW = 1
 NPARAM = 4931
-FORMATS = {"coo": COO, "csr": CSR, "dia": DIA}
-FORMAT_NAMES = {COO: "coo", CSR: "csr", DIA: "dia", HDC: "hdc"}
+FORMATS = {"coo": COO, "csr": CSR, "dia": DIA, "ell": ELL}
+FORMAT_NAMES = {COO: "coo", CSR: "csr", DIA: "dia", HDC: "hdc", ELL: "ell", SELL: "sell"}
 
 STATUS = {
     0: "MXS_OK", 1: "MXS_NOT_CONVERGED", -1: "MXS_ERR_INVALID_ARG", -2: "MXS_ERR_INDEX_RANGE",
@@ -79,6 +79,8 @@ _SIGS = {
     "mxs_split_size": (I32, [P, D, P, P, P]),
     "mxs_split": (I32, [P, D, I32, P, P, P, P, P, P, P]),
     "mxs_split_parts": (I32, [P, P, P]),
+    "mxs_sell_size": (I32, [P, I32, P, P, P]),
+    "mxs_to_sell": (I32, [P, I32, P, P, P, P, P, P]),
     "mxs_cast": (I32, [P, I32, P, P, P]),
     "mxs_optimize": (I32, [P, P]),
     "mxs_impl_count": (I32, [P]),
@@ -278,6 +280,9 @@ class Matrix:
         elif f == CSR:
             i0 = torch.empty(self.nrows + 1, dtype=torch.int32, device=dev)
             i1 = torch.empty(cnt, dtype=torch.int32, device=dev)
+        elif f == ELL:
+            i0 = torch.empty(cnt, dtype=torch.int32, device=dev)
+            i1 = None
         else:
             i0 = torch.empty(nd, dtype=torch.int32, device=dev)
             i1 = None
@@ -333,20 +338,46 @@ class Matrix:
                                 C.byref(h), _stream()), "mxs_split")
         return Matrix(h, [doff, band, i0, i1, vals])
 
+    def sell_size(self, sigma=1):
+        sl, ns = C.c_int64(), C.c_int32()
+        _check(load().mxs_sell_size(self._h, int(sigma), C.byref(sl), C.byref(ns), _stream()),
+               "mxs_sell_size")
+        return sl.value, ns.value
+
+    def to_sell(self, sigma=1):
+        """SELL-64-sigma on fresh tensors, kept as [perm, cs, col, vals]."""
+        torch = _torch()
+        slots, ns = self.sell_size(sigma)
+        perm = torch.empty(max(self.nrows, 1), dtype=torch.int32, device="cuda")
+        cs = torch.empty(ns + 1, dtype=torch.int64, device="cuda")
+        col = torch.empty(max(slots, 1), dtype=torch.int32, device="cuda")
+        vals = torch.empty(max(slots, 1), dtype=_torch_dtype(self.dtype), device="cuda")
+        h = C.c_void_p()
+        _check(load().mxs_to_sell(self._h, int(sigma), _ptr(perm), _ptr(cs), _ptr(col), _ptr(vals),
+                                  C.byref(h), _stream()), "mxs_to_sell")
+        M = Matrix(h, [perm[:self.nrows], cs, col[:slots], vals[:slots]])
+        M._slots = slots
+        return M
+
     def cast(self, dtype):
         torch = _torch()
         code = F32 if dtype in (F32, torch.float32, np.float32, "f32") else F64
-        n = self.ndiag * self.nrows if self.format == DIA else self.nnz
+        n = (self.ndiag * self.nrows if self.format in (DIA, ELL) else
+             self._slots if self.format == SELL else self.nnz)
         vals = torch.empty(n, dtype=_torch_dtype(code), device="cuda")
         h = C.c_void_p()
         _check(load().mxs_cast(self._h, code, _ptr(vals) if n else None, C.byref(h), _stream()),
                "mxs_cast")
-        return Matrix(h, [vals, self])
+        M = Matrix(h, [vals, self])
+        if self.format == SELL:
+            M._slots = self._slots
+        return M
 
     def export(self):
         """Copies of the canonical arrays as CPU numpy arrays: COO (ai, aj, av),
-        CSR (irp, aj, av), DIA (doff, av)."""
-        B = self.convert(self.format)
+        CSR (irp, aj, av), DIA (doff, av), ELL (col, val); SELL exports its
+        CSR form (irp, aj, av)."""
+        B = self.convert(CSR if self.format == SELL else self.format)
         out = [t.cpu().numpy() for t in B._keep]
         B.close()
         return tuple(out)

@@ -34,7 +34,10 @@ namespace {
 hipStream_t S(void *stream) { return (hipStream_t)stream; }
 
 bool valid_dtype(mxs_dtype t) { return t == MXS_F64 || t == MXS_F32; }
-bool valid_format(mxs_format f) { return f == MXS_COO || f == MXS_CSR || f == MXS_DIA; }
+bool valid_format(mxs_format f)
+{
+    return f == MXS_COO || f == MXS_CSR || f == MXS_DIA || f == MXS_ELL || f == MXS_SELL;
+}
 
 // Every entry point that touches the GPU runs its body through guarded():
 // an error another library left pending in HIP's per-thread error slot is
@@ -82,7 +85,9 @@ mxs_status own_copy(mxs_mat_s *A, const void *src, size_t bytes, void **dst, hip
 
 int64_t value_count(const mxs_mat_s *A)
 {
-    return A->fmt == MXS_DIA ? (int64_t)A->ndiag * A->nrows : A->nnz;
+    if (A->fmt == MXS_DIA || A->fmt == MXS_ELL) return (int64_t)A->ndiag * A->nrows;
+    if (A->fmt == MXS_SELL) return A->slots;
+    return A->nnz;
 }
 
 mxs_status ensure_plan(mxs_mat_s *A, hipStream_t s)
@@ -317,8 +322,9 @@ mxs_status mxs_convert(mxs_mat src, mxs_format dst, int32_t *idx0, int32_t *idx1
         int32_t nd = 0;
         mxs_status st = convert_size(src, dst, &count, &nd, s);
         if (st != MXS_OK) return st;
-        const bool need0 = dst == MXS_CSR || (dst == MXS_COO && count > 0) || (dst == MXS_DIA && nd > 0);
-        const bool need1 = dst != MXS_DIA && count > 0;
+        const bool need0 = dst == MXS_CSR || ((dst == MXS_COO || dst == MXS_ELL) && count > 0) ||
+                           (dst == MXS_DIA && nd > 0);
+        const bool need1 = (dst == MXS_COO || dst == MXS_CSR) && count > 0;
         if ((need0 && !idx0) || (need1 && !idx1) || (count > 0 && !vals))
             return MXS_ERR_INVALID_ARG;
         if ((st = convert(src, dst, idx0, idx1, vals, count, nd, s)) != MXS_OK) return st;
@@ -329,11 +335,14 @@ mxs_status mxs_convert(mxs_mat src, mxs_format dst, int32_t *idx0, int32_t *idx1
         B->ncols = src->ncols;
         B->device = src->device;
         B->idx0 = idx0;
-        B->idx1 = dst == MXS_DIA ? nullptr : idx1;
+        B->idx1 = dst == MXS_COO || dst == MXS_CSR ? idx1 : nullptr;
         B->vals = vals;
         if (dst == MXS_DIA) {
             B->ndiag = nd;
             if ((st = dia_slot_count(B, &B->nnz, s)) != MXS_OK) return release(B), st;
+        } else if (dst == MXS_ELL) {
+            B->ndiag = nd;
+            B->nnz = src->nnz; // entries (COO/CSR/ELL source)
         } else {
             B->nnz = count;
         }
@@ -363,6 +372,55 @@ mxs_status mxs_cast(mxs_mat src, mxs_dtype dtype, void *vals, mxs_mat *out, void
         B->idx0 = src->idx0;
         B->idx1 = src->idx1;
         B->vals = vals;
+        B->sell_cs = src->sell_cs;
+        B->slots = src->slots;
+        B->sigma = src->sigma;
+        *out = B;
+        return MXS_OK;
+    });
+}
+
+mxs_status mxs_sell_size(mxs_mat A, int32_t sigma, int64_t *slots, int32_t *nslices, void *stream)
+{
+    if (!A || sigma < 1) return MXS_ERR_INVALID_ARG;
+    if (A->fmt != MXS_COO && A->fmt != MXS_CSR) return MXS_ERR_UNSUPPORTED;
+    return guarded([&] {
+        int64_t h = 0;
+        mxs_status st = sell_size(A, sigma, &h, S(stream));
+        if (st != MXS_OK) return st;
+        if (slots) *slots = h;
+        if (nslices) *nslices = (int32_t)(((int64_t)A->nrows + 63) / 64);
+        return MXS_OK;
+    });
+}
+
+mxs_status mxs_to_sell(mxs_mat A, int32_t sigma, int32_t *perm, int64_t *cs, int32_t *col, void *vals,
+                       mxs_mat *out, void *stream)
+{
+    if (!A || sigma < 1 || !out || !cs || (A->nrows > 0 && !perm)) return MXS_ERR_INVALID_ARG;
+    if (A->fmt != MXS_COO && A->fmt != MXS_CSR) return MXS_ERR_UNSUPPORTED;
+    return guarded([&] {
+        hipStream_t s = S(stream);
+        int64_t slots = 0;
+        mxs_status st = sell_size(A, sigma, &slots, s);
+        if (st != MXS_OK) return st;
+        if (slots > 0 && (!col || !vals)) return MXS_ERR_INVALID_ARG;
+        if ((st = sell_build(A, sigma, perm, cs, col, vals, s)) != MXS_OK) return st;
+        mxs_mat_s *B = new mxs_mat_s;
+        B->fmt = MXS_SELL;
+        B->dtype = A->dtype;
+        B->nrows = A->nrows;
+        B->ncols = A->ncols;
+        B->nnz = A->nnz;
+        B->ndiag = (int32_t)(((int64_t)A->nrows + 63) / 64);
+        B->device = A->device;
+        B->idx0 = col;
+        B->idx1 = perm;
+        B->vals = vals;
+        B->sell_cs = cs;
+        B->slots = slots;
+        B->sigma = sigma;
+        MXS_HIP(hipStreamSynchronize(s));
         *out = B;
         return MXS_OK;
     });
@@ -644,7 +702,7 @@ mxs_status mxs_stencil_coo(int32_t n, int32_t points, double diag, double offdia
 mxs_status mxs_features(mxs_mat A, double out[8], void *stream)
 {
     if (!A || !out) return MXS_ERR_INVALID_ARG;
-    if (A->fmt == MXS_HDC) return MXS_ERR_UNSUPPORTED;
+    if (A->fmt != MXS_COO && A->fmt != MXS_CSR && A->fmt != MXS_DIA) return MXS_ERR_UNSUPPORTED;
     return guarded([&] { return features(A, out, S(stream)); });
 }
 

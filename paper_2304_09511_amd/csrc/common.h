@@ -141,6 +141,11 @@ struct mxs_mat_s {
     mxs_mat_s *band = nullptr; // HDC: the DIA band (owned by this handle)
     mxs_mat_s *rest = nullptr; // HDC: the COO or CSR remainder (owned)
     bool part = false;         // the band or remainder of a split (its parent owns it)
+    // ELL: ndiag = slots per row.  SELL: idx0 = columns, idx1 = perm,
+    // sell_cs = slice offsets, slots = sell_cs[nslices], sigma = sort window.
+    const int64_t *sell_cs = nullptr;
+    int64_t slots = 0;
+    int32_t sigma = 0;
 };
 
 namespace mxs {
@@ -344,6 +349,19 @@ mxs_status cg_solve(const mxs_mat_s *A, const mxs_mat_s *A32, const double *b, d
 
 // features.hip
 mxs_status features(const mxs_mat_s *A, double out[8], hipStream_t s);
+
+// ell.hip: ELL and SELL-C-sigma (C = 64).
+mxs_status ell_width(const mxs_mat_s *A, int32_t *K, hipStream_t s); // syncs; refuses > 8 slots/entry
+mxs_status ell_build(const mxs_mat_s *A, int32_t K, int32_t *col, void *vals, hipStream_t s);
+mxs_status sell_size(const mxs_mat_s *A, int32_t sigma, int64_t *slots, hipStream_t s); // syncs
+mxs_status sell_build(const mxs_mat_s *A, int32_t sigma, int32_t *perm, int64_t *cs, int32_t *col,
+                      void *vals, hipStream_t s);
+// ELL/SELL -> COO (idx0 = row ids) or CSR (idx0 = row pointers)
+mxs_status padded_to_rows(const mxs_mat_s *A, mxs_format dst, int32_t *idx0, int32_t *idx1,
+                          void *vals, hipStream_t s);
+mxs_status padded_spmv(const mxs_mat_s *A, const void *x, void *y, const int *done, double *parts,
+                       hipStream_t s);
+int64_t padded_grid(const mxs_mat_s *A, bool dot);
 
 // mg.hip: HPCG's multigrid preconditioner.
 mxs_status mg_create(int32_t n, int32_t levels, mxs_mg_s **out, hipStream_t s); // syncs

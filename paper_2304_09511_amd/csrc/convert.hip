@@ -372,6 +372,26 @@ mxs_status convert_size(const mxs_mat_s *A, mxs_format dst, int64_t *count, int3
 {
     *count = 0;
     *ndiag = 0;
+    if (dst == MXS_SELL) return MXS_ERR_UNSUPPORTED; // needs sigma: sell_size
+    if (A->fmt == MXS_ELL || A->fmt == MXS_SELL) {
+        if (dst == MXS_ELL && A->fmt == MXS_ELL) {
+            *ndiag = A->ndiag;
+            *count = (int64_t)A->ndiag * A->nrows;
+            return MXS_OK;
+        }
+        if (dst != MXS_COO && dst != MXS_CSR) return MXS_ERR_UNSUPPORTED;
+        *count = A->nnz;
+        return MXS_OK;
+    }
+    if (dst == MXS_ELL) {
+        if (A->fmt != MXS_COO && A->fmt != MXS_CSR) return MXS_ERR_UNSUPPORTED;
+        int32_t K = 0;
+        mxs_status st = ell_width(A, &K, s);
+        if (st != MXS_OK) return st;
+        *ndiag = K;
+        *count = (int64_t)K * A->nrows;
+        return MXS_OK;
+    }
     if (dst == MXS_DIA) {
         if (A->fmt == MXS_DIA) {
             *ndiag = A->ndiag;
@@ -415,6 +435,17 @@ static mxs_status convert_typed(const mxs_mat_s *A, mxs_format dst, int32_t *idx
 {
     const size_t vb = sizeof(T);
     mxs_status st = MXS_OK;
+    if (dst == MXS_ELL) {
+        if (A->fmt == MXS_ELL) {
+            if (count) {
+                MXS_HIP(hipMemcpyAsync(idx0, A->idx0, sizeof(int32_t) * count, hipMemcpyDeviceToDevice, s));
+                MXS_HIP(hipMemcpyAsync(vals, A->vals, vb * count, hipMemcpyDeviceToDevice, s));
+            }
+            return MXS_OK;
+        }
+        return ell_build(A, ndiag, idx0, vals, s);
+    }
+    if (A->fmt == MXS_ELL || A->fmt == MXS_SELL) return padded_to_rows(A, dst, idx0, idx1, vals, s);
     if (A->fmt == dst) {
         if (dst == MXS_DIA) {
             if (ndiag) MXS_HIP(hipMemcpyAsync(idx0, A->idx0, sizeof(int32_t) * ndiag, hipMemcpyDeviceToDevice, s));

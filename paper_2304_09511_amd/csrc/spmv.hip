@@ -1084,6 +1084,7 @@ int64_t spmv_dot_parts(const mxs_mat_s *A)
 {
     if (A->fmt == MXS_COO || A->fmt == MXS_HDC) return kDotGridMax;
     if (A->fmt == MXS_CSR && A->csr.rowwise) return rowwise_grid(A->nrows);
+    if (A->fmt == MXS_ELL || A->fmt == MXS_SELL) return padded_grid(A, true);
     uint32_t grid;
     int64_t per;
     if (A->dtype == MXS_F64) spmv_grid<double>(A, true, &grid, &per);
@@ -1285,6 +1286,7 @@ static mxs_status build_coo_plan(mxs_mat_s *A, hipStream_t s)
 // ---------------------------------------------------------------------------
 int32_t impl_count(const mxs_mat_s *A)
 {
+    if (A->fmt == MXS_ELL || A->fmt == MXS_SELL) return 1;
     return A->fmt == MXS_DIA || A->fmt == MXS_CSR ? 3 : A->fmt == MXS_COO ? 2 : 0;
 }
 
@@ -1299,6 +1301,8 @@ bool impl_ok(const mxs_mat_s *A, int32_t impl)
         if (impl == 0) return A->dia.blk != nullptr && A->dia.triples;
         if (impl == 1) return A->dia.blk != nullptr;
         return true;
+    case MXS_ELL:
+    case MXS_SELL: return true;
     default: return false;
     }
 }
@@ -1309,6 +1313,8 @@ static int32_t default_impl(const mxs_mat_s *A)
     case MXS_COO: return impl_ok(A, 0) ? 0 : 1;
     case MXS_CSR: return A->csr.rowwise ? 1 : MXS_CSR_GX_DEFAULT ? 2 : 0;
     case MXS_DIA: return impl_ok(A, 0) ? 0 : impl_ok(A, 1) ? 1 : 2;
+    case MXS_ELL:
+    case MXS_SELL: return 0;
     default: return -1;
     }
 }
@@ -1389,7 +1395,7 @@ mxs_status build_plan(mxs_mat_s *A, hipStream_t s)
         st = build_csr_plan(A, s);
     } else if (A->fmt == MXS_DIA) {
         st = build_dia_plan(A, s);
-    } else {
+    } else if (A->fmt == MXS_COO) {
         st = build_coo_plan(A, s);
     }
     if (st == MXS_OK) {
@@ -1519,6 +1525,14 @@ static mxs_status spmv_typed(const mxs_mat_s *A, const T *x, T *y, const int *do
         MXS_HIP(hipGetLastError());
         if (dot) return dot_sigma_typed<T>(A->nrows, x, y, done, dot, s);
         return MXS_OK;
+    }
+    case MXS_ELL:
+    case MXS_SELL: {
+        if (acc) return MXS_ERR_UNSUPPORTED;
+        mxs_status st = padded_spmv(A, x, y, done, parts, s);
+        if (st != MXS_OK) return st;
+        nparts = padded_grid(A, dot != nullptr);
+        break;
     }
     default:
         return MXS_ERR_UNSUPPORTED;
