@@ -157,6 +157,42 @@ def cg_runs(torch, mxs, mats, rtol, label):
     return res, bn
 
 
+def padded_bytes(A, nnz, s=8):
+    """Algorithmic bytes of an ELL or SELL SpMV: the entries (column and
+    value; padding slots are the format's overhead, not the operation's),
+    SELL's permutation and slice offsets, x read once and y written once."""
+    b = nnz * (4 + s) + s * (A.ncols + A.nrows)
+    if A.format == 5:
+        b += 4 * A.nrows + 8 * (A.ndiag + 1)
+    return b
+
+
+def other_formats(torch, mxs, coo, x, y, label):
+    """ELL and SELL-64-sigma SpMV (Section IX's further formats): protocol
+    median of 10 x 100 calls, GB/s of algorithmic bytes, stored slots."""
+    out = {}
+    for name, make in (("ell", lambda: coo.convert("ell")), ("sell_sigma1", lambda: coo.to_sell(1)),
+                       ("sell_sigma4096", lambda: coo.to_sell(4096))):
+        try:
+            B = make()
+        except mxs.MxsError as e:
+            if e.status != -5:
+                raise
+            out[name] = {"refused": "MXS_ERR_DIA_TOO_SPARSE (more than 8 slots per entry)"}
+            continue
+        tc = time_calls(torch, lambda: mxs.spmv(B, x, y))
+        nb = padded_bytes(B, coo.nnz)
+        slots = B.ndiag * B.nrows if name == "ell" else int(B._slots)
+        med = tc["median_ms"] * 1e-3
+        out[name] = {"us_per_call": round(med * 1e6, 2), "algorithmic_bytes": nb,
+                     "GBps": round(nb / med / 1e9, 1), "frac_of_peak": round(nb / med / 1e9 / PEAK_HBM_GBS, 4),
+                     "slots_per_entry": round(slots / max(coo.nnz, 1), 4)}
+        log(f"[bench] {label} {name}: {out[name]['us_per_call']} us, {out[name]['GBps']} GB/s, "
+            f"{out[name]['slots_per_entry']} slots/entry")
+        B.close()
+    return out
+
+
 def symgs_bytes(nn):
     """Algorithmic bytes of one symmetric sweep on the nn^3 stencil: every
     colour pass reads its rows' off-diagonal entries (4-byte column, 8-byte
@@ -448,6 +484,7 @@ def irregular_runs(torch, mxs, checks):
                 log(f"[bench]   tuned parts: {rec[fmt]['tuned']}")
             if A is not coo:
                 A.close()
+        rec["other_formats"] = other_formats(torch, mxs, coo, x, y, name)
         coo.close()
         del coo, ai, aj, av, x, y, irp, sel
         torch.cuda.empty_cache()
@@ -635,6 +672,8 @@ def main():
         per[f]["implementations"] = impl_report(mxs, mats[f], x, ys[f])
         log(f"[bench]   {f} implementations (median us): {per[f]['implementations']['median_us']}")
 
+    out_other = other_formats(torch, mxs, mats["coo"], x, ys["coo"], f"stencil{args.n}")
+
     # dominant kernel of the step and its roofline
     dom = max(FORMATS, key=lambda f: per[f]["us_per_call"])
     achieved = bytes_f[dom] / (per[dom]["us_per_call"] * 1e-6) / 1e9
@@ -654,7 +693,7 @@ def main():
                                   f"FP64 values 26/-1, int32 indices), resident in HBM; one step = one "
                                   f"SpMV in each of COO, CSR, DIA",
                       "x": "U[-1,1) seed 1", "formats": list(FORMATS)},
-           "per_format": per, "roofline": roofline}
+           "per_format": per, "other_formats": out_other, "roofline": roofline}
 
     if not args.no_cg:
         out["cg"], _ = cg_runs(torch, mxs, mats, 1e-9, f"{args.n}^3")
