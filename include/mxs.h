@@ -406,11 +406,13 @@ mxs_status mxs_stencil_coo(int32_t n, int32_t points, double diag, double offdia
 /* ------------------------------------------------------------------------
  * Format selection (the run-first tuner of Section VII-D and the dynamic
  * selection named as further work in Section IX): matrix features and a
- * small MLP 8-64-64-3 (FP32) with its training step.
+ * small MLP 8-64-64-5 (FP32) with its training step.  Its outputs are the
+ * label set's formats in this order: COO, CSR, DIA, ELL, SELL-64-1.
  * --------------------------------------------------------------------- */
 
 #define MXS_NFEAT 8
-#define MXS_MLP_NPARAM 4931
+#define MXS_NCLASS 5
+#define MXS_MLP_NPARAM 5061
 
 /* Eight features of A's stored entries into host out[8] [syncs]:
  *   0 rows, 1 nnz, 2 mean row length, 3 population variance of row lengths,
@@ -432,13 +434,13 @@ mxs_status mxs_mlp_inputs(const double *raw, int32_t n, const float *mu, const f
 mxs_status mxs_mlp_norm_stats(const double *raw, int32_t n, float *mu, float *sd,
                               void *stream);
 
-/* Logits[n][3] of the MLP with parameters w[MXS_MLP_NPARAM] laid out as
- * W1[8][64], b1[64], W2[64][64], b2[64], W3[64][3], b3[3] (row-major,
+/* Logits[n][5] of the MLP with parameters w[MXS_MLP_NPARAM] laid out as
+ * W1[8][64], b1[64], W2[64][64], b2[64], W3[64][5], b3[5] (row-major,
  * input index first), ReLU hidden layers [async]. */
 mxs_status mxs_mlp_forward(const float *w, const float *X, int32_t n, float *logits,
                            void *stream);
 
-/* fmt_out[s] = argmax over formats f with feasible[s*3+f] != 0 of the
+/* fmt_out[s] = argmax over formats f with feasible[s*5+f] != 0 of the
  * logits (feasible may be NULL: all allowed); -1 if none is feasible [async]. */
 mxs_status mxs_mlp_predict(const float *w, const float *X, int32_t n, const uint8_t *feasible,
                            int32_t *fmt_out, void *stream);
@@ -447,7 +449,7 @@ mxs_status mxs_mlp_predict(const float *w, const float *X, int32_t n, const uint
  * samples (per-sample activations and deltas, then the gradient). */
 size_t mxs_mlp_workspace_size(int32_t n);
 
-/* Mean softmax cross-entropy over n samples (labels in {0,1,2}) into the
+/* Mean softmax cross-entropy over n samples (labels in {0,...,4}) into the
  * device float *loss and its gradient grad[MXS_MLP_NPARAM] [async].
  * Deterministic. */
 mxs_status mxs_mlp_grad(const float *w, const float *X, const int32_t *labels, int32_t n,

@@ -25,7 +25,8 @@ _LIB = os.path.join(_HERE, "libmxs.so")
 COO, CSR, DIA, HDC, ELL, SELL = 0, 1, 2, 3, 4, 5
 F64, F32 = 0, 1
 BORROW = 1
-NPARAM = 4931
+NPARAM = 5061  # MXS_MLP_NPARAM: MLP 8-64-64-5
+NCLASS = 5     # MXS_NCLASS: outputs (COO, CSR, DIA, ELL, SELL)
 FORMATS = {"coo": COO, "csr": CSR, "dia": DIA, "ell": ELL}
 FORMAT_NAMES = {COO: "coo", CSR: "csr", DIA: "dia", HDC: "hdc", ELL: "ell", SELL: "sell"}
 
@@ -629,9 +630,19 @@ def mlp_inputs(raw, mu, sd):
     return X
 
 
+def _mlp_shapes(w, X, feasible=None):
+    """The ABI takes raw pointers: check sizes here so no kernel reads or
+    writes past an array."""
+    if w.numel() != NPARAM or X.dim() != 2 or X.shape[1] != 8:
+        raise ValueError("w must hold NPARAM values and X be [n][8]")
+    if feasible is not None and feasible.numel() != X.shape[0] * NCLASS:
+        raise ValueError("feasible must be [n][NCLASS]")
+
+
 def mlp_forward(w, X):
     torch = _torch()
-    z = torch.empty(X.shape[0], 3, dtype=torch.float32, device="cuda")
+    _mlp_shapes(w, X)
+    z = torch.empty(X.shape[0], NCLASS, dtype=torch.float32, device="cuda")
     _check(load().mxs_mlp_forward(_ptr(w), _ptr(X), X.shape[0], _ptr(z), _stream()),
            "mxs_mlp_forward")
     return z
@@ -639,6 +650,7 @@ def mlp_forward(w, X):
 
 def mlp_predict(w, X, feasible=None):
     torch = _torch()
+    _mlp_shapes(w, X, feasible)
     out = torch.empty(X.shape[0], dtype=torch.int32, device="cuda")
     _check(load().mxs_mlp_predict(_ptr(w), _ptr(X), X.shape[0], _ptr(feasible), _ptr(out),
                                   _stream()), "mxs_mlp_predict")
@@ -653,6 +665,7 @@ def mlp_workspace(n):
 def mlp_grad(w, X, labels, workspace=None):
     torch = _torch()
     n = X.shape[0]
+    _mlp_shapes(w, X)
     ws = workspace if workspace is not None else mlp_workspace(n)
     g = torch.empty(NPARAM, dtype=torch.float32, device="cuda")
     loss = torch.empty(1, dtype=torch.float32, device="cuda")
@@ -669,6 +682,7 @@ def mlp_adam(w, m, v, g, lr, t, b1=0.9, b2=0.999, eps=1e-8):
 def mlp_train_step(w, m, v, X, labels, lr, t, workspace=None):
     torch = _torch()
     n = X.shape[0]
+    _mlp_shapes(w, X)
     ws = workspace if workspace is not None else mlp_workspace(n)
     loss = torch.empty(1, dtype=torch.float32, device="cuda")
     _check(load().mxs_mlp_train_step(_ptr(w), _ptr(m), _ptr(v), _ptr(X), _ptr(labels), n, lr, t,

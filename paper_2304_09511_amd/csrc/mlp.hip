@@ -1,7 +1,7 @@
-// The format selector's network: MLP 8-64-64-3 (ReLU, softmax cross-entropy)
-// in FP32 with forward, backward and Adam kernels.  Parameter layout
-// (row-major, input index first): W1[8][64], b1[64], W2[64][64], b2[64],
-// W3[64][3], b3[3].  Reductions over samples run in sample order with FP64
+// The format selector's network: MLP 8-64-64-5 (ReLU, softmax cross-entropy;
+// one output per format: COO, CSR, DIA, ELL, SELL) in FP32 with forward,
+// backward and Adam kernels.  Parameter layout (row-major, input index
+// first): W1[8][64], b1[64], W2[64][64], b2[64], W3[64][5], b3[5].  Reductions over samples run in sample order with FP64
 // accumulators, so gradients are deterministic.
 #include <hip/hip_runtime.h>
 
@@ -12,12 +12,12 @@
 
 namespace mxs {
 
-constexpr int NI = 8, NH = 64, NO = 3;
+constexpr int NI = 8, NH = 64, NO = MXS_NCLASS;
 constexpr int OW1 = 0, OB1 = OW1 + NI * NH, OW2 = OB1 + NH, OB2 = OW2 + NH * NH,
               OW3 = OB2 + NH, OB3 = OW3 + NH * NO, NPAR = OB3 + NO;
 static_assert(NPAR == MXS_MLP_NPARAM, "parameter count");
 
-// per-sample scratch of the backward pass: H1, H2, DH1, DH2 [64], DZ [3], loss
+// per-sample scratch of the backward pass: H1, H2, DH1, DH2 [64], DZ [NO], loss
 constexpr int kSampleScratch = 4 * NH + NO + 1;
 
 // ---------------------------------------------------------------------------
@@ -148,7 +148,7 @@ __global__ __launch_bounds__(64) void mlp_sample_kernel(const float *__restrict_
             den += e[c];
         }
         const int y = labels[s];
-        const bool ok = y >= 0 && y < NO; // a label outside {0,1,2} gives a NaN loss
+        const bool ok = y >= 0 && y < NO; // a label outside {0, ..., NO-1} gives a NaN loss
         for (int c = 0; c < NO; ++c) {
             dz[c] = (e[c] / den - (c == y ? 1.0f : 0.0f)) / (float)n;
             o[4 * NH + c] = dz[c];

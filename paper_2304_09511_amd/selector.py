@@ -7,10 +7,14 @@ provides both:
 
 * ``exhaustive_select`` -- the run-first tuner: time one SpMV in every
   feasible format (median of repeats) and keep the fastest;
-* ``Selector`` -- an MLP 8-64-64-3 over eight matrix features
+* ``Selector`` -- an MLP 8-64-64-5 over eight matrix features
   (``mxs.features``), trained and evaluated on the GPU by the library's own
-  kernels (``mlp_train_step``, ``mlp_predict``), with DIA masked out where the
-  container refuses it.  Without a model, selection falls back to the tuner.
+  kernels (``mlp_train_step``, ``mlp_predict``), with the formats the
+  containers refuse masked out.  Without a model, selection falls back to
+  the tuner.
+
+The label set is COO, CSR, DIA and the padded formats of Section IX's
+further work, ELL and SELL-64-1 (slices of 64 rows, no sorting).
 
 The dataset builder labels synthetic matrices (5 families, rows log-uniform
 in [1e4, 1e7]) by the tuner's timings; labels are written as JSON lines and
@@ -38,8 +42,9 @@ DATA_DIR = pathlib.Path(__file__).resolve().parent / "selector_data"
 DATA_PATH = DATA_DIR / "labels.jsonl"
 MODEL_PATH = DATA_DIR / "model.json"
 FAMILIES = ("stencil7", "stencil27", "banded", "zipf", "block")
-FORMATS = ("coo", "csr", "dia")
-TIE_ORDER = ("csr", "dia", "coo")  # equal medians: the general-purpose format first
+FORMATS = ("coo", "csr", "dia", "ell", "sell")
+TIE_ORDER = ("csr", "dia", "ell", "sell", "coo")  # equal medians: the general-purpose format first
+SELL_SIGMA = 1
 
 
 # ---------------------------------------------------------------------------
@@ -62,8 +67,18 @@ def time_spmv(A, x, y, reps=10, warm=3):
     return statistics.median(ts)
 
 
+def convert_to(A_coo, f):
+    """A_coo in format f (a new Matrix), or None where the container refuses."""
+    try:
+        return A_coo.to_sell(SELL_SIGMA) if f == "sell" else A_coo.convert(f)
+    except mxs.MxsError as e:
+        if e.status == -5:
+            return None
+        raise
+
+
 def time_formats(A_coo, reps=10, warm=3, seed=1):
-    """Median SpMV time per format (inf where DIA is refused)."""
+    """Median SpMV time per format (inf where the format is refused)."""
     import torch
     g = torch.Generator(device="cuda")
     g.manual_seed(seed)
@@ -72,16 +87,10 @@ def time_formats(A_coo, reps=10, warm=3, seed=1):
     y = torch.empty(A_coo.nrows, device="cuda", dtype=dt)
     out = {}
     for f in FORMATS:
-        if f == "coo":
-            B = A_coo
-        else:
-            try:
-                B = A_coo.convert(f)
-            except mxs.MxsError as e:
-                if e.status == -5:
-                    out[f] = math.inf
-                    continue
-                raise
+        B = A_coo if f == "coo" else convert_to(A_coo, f)
+        if B is None:
+            out[f] = math.inf
+            continue
         B.optimize()
         out[f] = time_spmv(B, x, y, reps, warm)
         if B is not A_coo:
@@ -204,12 +213,12 @@ def regret(T, choice):
 # ---------------------------------------------------------------------------
 # The network
 # ---------------------------------------------------------------------------
-NI, NH, NO = 8, 64, 3
+NI, NH, NO = 8, 64, len(FORMATS)
 
 
 def he_init(seed=6):
     """He-normal weights (std sqrt(2/fan_in)), zero biases, in the layout of
-    mxs_mlp_forward: W1[8][64], b1, W2[64][64], b2, W3[64][3], b3."""
+    mxs_mlp_forward: W1[8][64], b1, W2[64][64], b2, W3[64][5], b3."""
     g = np.random.Generator(np.random.PCG64(seed))
     parts = [g.standard_normal(NI * NH) * math.sqrt(2.0 / NI), np.zeros(NH),
              g.standard_normal(NH * NH) * math.sqrt(2.0 / NH), np.zeros(NH),
@@ -220,7 +229,7 @@ def he_init(seed=6):
 
 
 class Selector:
-    """MLP 8-64-64-3 format selector; parameters and normalisation live on
+    """MLP 8-64-64-5 format selector; parameters and normalisation live on
     the device while training and predicting."""
 
     def __init__(self, w=None, mu=None, sd=None):
@@ -264,7 +273,7 @@ class Selector:
         return self
 
     def predict(self, F, feasible=None):
-        """Format index per row of F (raw features); feasible: bool [n][3]."""
+        """Format index per row of F (raw features); feasible: bool [n][5]."""
         import torch
         raw = self._dev(np.atleast_2d(F).astype(np.float64))
         X = mxs.mlp_inputs(raw, self._dev(self.mu), self._dev(self.sd))
@@ -274,13 +283,26 @@ class Selector:
         return out.cpu().numpy()
 
     def select(self, A):
-        """Format name for a Matrix (DIA masked when the container refuses it)."""
+        """Format name for a COO/CSR Matrix.  DIA and ELL are masked by the
+        containers' refusal rules, which the features decide; SELL's rule
+        depends on slice maxima, so a refused SELL choice is masked and the
+        network asked again."""
         f = mxs.features(A)
-        feas = [True, True, dia_feasible(f)]
-        return FORMATS[int(self.predict(f[None, :], [feas])[0])]
+        feas = [True, True, dia_feasible(f), ell_feasible(f), True]
+        name = FORMATS[int(self.predict(f[None, :], [feas])[0])]
+        if name == "sell":
+            try:
+                A.sell_size(SELL_SIGMA)
+            except mxs.MxsError as e:
+                if e.status != -5:
+                    raise
+                feas[4] = False
+                name = FORMATS[int(self.predict(f[None, :], [feas])[0])]
+        return name
 
     def save(self, path):
-        json.dump({"layout": "W1[8][64] b1 W2[64][64] b2 W3[64][3] b3", "w": self.w.tolist(),
+        json.dump({"layout": "W1[8][64] b1 W2[64][64] b2 W3[64][5] b3",
+                   "formats": list(FORMATS), "sell_sigma": SELL_SIGMA, "w": self.w.tolist(),
                    "mu": self.mu.tolist(), "sd": self.sd.tolist(),
                    "loss_curve": self.loss_curve}, open(path, "w"))
 
@@ -297,6 +319,11 @@ def dia_feasible(features):
     return features[5] * features[0] <= 8 * features[1]
 
 
+def ell_feasible(features):
+    """ELL's refusal rule: (longest row) * rows <= 8 * nnz."""
+    return features[4] * features[0] <= 8 * features[1]
+
+
 def select_format(A, model=None):
     """The learned choice when a model is given, else the run-first tuner."""
     if model is not None:
@@ -311,7 +338,7 @@ def evaluate(model, F, T):
     best = np.array([FORMATS.index(best_format(dict(zip(FORMATS, t)))) for t in T])
     return {"n": int(F.shape[0]), "accuracy": float(np.mean(choice == best)),
             "mean_regret": regret(T, choice), "always_csr_regret": regret(T, np.ones(len(T), int)),
-            "exhaustive_cost_x_one_spmv": 3.0}
+            "exhaustive_cost_x_one_spmv": float(len(FORMATS))}
 
 
 def main(argv=None):

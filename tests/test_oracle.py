@@ -469,43 +469,45 @@ def test_features_banded_closed_form():
 
 
 # --------------------------------------------------------------------------
-# MLP 8-64-64-3
+# MLP 8-64-64-5
 # --------------------------------------------------------------------------
 def test_mlp_zero_weights_uniform_softmax():
     w = np.zeros(orc.NPARAM)
     X = wl.rng(1).standard_normal((10, 8))
-    y = np.array([0, 1, 2, 0, 1, 2, 0, 0, 1, 2], np.int32)
+    K = orc.NCLASS
+    y = np.array([0, 1, 2, 3, 4, 2, 0, 0, 1, 4], np.int32)
     loss, g = orc.mlp_loss_grad(w, X, y)
-    assert loss == pytest.approx(math.log(3.0), rel=1e-15)
-    # dL/db3 = mean(p - onehot) with p = 1/3
-    onehot = np.eye(3)[y]
-    assert np.allclose(g[-3:], (1 / 3 - onehot).mean(axis=0), atol=1e-15)
-    assert not g[:-3].any()  # hidden layers are all zero, so no other gradient
+    assert loss == pytest.approx(math.log(K), rel=1e-15)
+    # dL/db3 = mean(p - onehot) with p = 1/K
+    onehot = np.eye(K)[y]
+    assert np.allclose(g[-K:], (1 / K - onehot).mean(axis=0), atol=1e-15)
+    assert not g[:-K].any()  # hidden layers are all zero, so no other gradient
 
 
 def test_mlp_forward_special_network():
-    # h1 = relu(x) in units 0..7, h2 = h1, logits = (h2_0, h2_1, h2_2) + b3.
+    # h1 = relu(x) in units 0..7, h2 = h1, logits = (h2_0, ..., h2_4) + b3.
+    K = orc.NCLASS
     w = np.zeros(orc.NPARAM)
     for i in range(8):
         w[i * 64 + i] = 1.0                       # W1
         w[512 + 64 + i * 64 + i] = 1.0            # W2
-    for c in range(3):
-        w[512 + 64 + 4096 + 64 + c * 3 + c] = 1.0  # W3
-    w[-3:] = [0.5, -0.5, 2.0]
-    X = np.array([[1.0, -2.0, 3.0, 0, 0, 0, 0, 0], [-1.0, 4.0, -3.0, 1, 1, 1, 1, 1]])
+    for c in range(K):
+        w[512 + 64 + 4096 + 64 + c * K + c] = 1.0  # W3
+    w[-K:] = [0.5, -0.5, 2.0, 1.0, -1.0]
+    X = np.array([[1.0, -2.0, 3.0, 0, 2.0, 0, 0, 0], [-1.0, 4.0, -3.0, 1, 1, 1, 1, 1]])
     z = orc.mlp_forward(w, X)
-    assert z.tolist() == [[1.5, -0.5, 5.0], [0.5, 3.5, 2.0]]
+    assert z.tolist() == [[1.5, -0.5, 5.0, 1.0, 1.0], [0.5, 3.5, 2.0, 2.0, 0.0]]
 
 
 def test_mlp_gradient_matches_finite_differences():
     g0 = wl.rng(3)
     w = g0.standard_normal(orc.NPARAM) * 0.3
     X = g0.standard_normal((16, 8))
-    y = g0.integers(0, 3, 16).astype(np.int32)
+    y = g0.integers(0, orc.NCLASS, 16).astype(np.int32)
     loss, g = orc.mlp_loss_grad(w, X, y)
     h = 1e-6
     idx = np.concatenate([np.arange(0, 512, 37), np.arange(512, 576, 5), np.arange(576, 4672, 97),
-                          np.arange(4672, 4736, 7), np.arange(4736, 4931, 11)])
+                          np.arange(4672, 4736, 7), np.arange(4736, orc.NPARAM, 11)])
     for i in idx:
         wp, wm = w.copy(), w.copy()
         wp[i] += h

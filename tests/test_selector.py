@@ -35,9 +35,12 @@ def test_dataset_spec_is_deterministic_and_balanced():
 
 
 def test_best_format_tie_order_and_regret():
-    assert S.best_format({"coo": 1.0, "csr": 1.0, "dia": 1.0}) == "csr"
-    assert S.best_format({"coo": 1.0, "csr": 2.0, "dia": 1.0}) == "dia"
-    assert S.best_format({"coo": 0.5, "csr": 2.0, "dia": math.inf}) == "coo"
+    inf = math.inf
+    assert S.best_format({"coo": 1.0, "csr": 1.0, "dia": 1.0, "ell": 1.0, "sell": 1.0}) == "csr"
+    assert S.best_format({"coo": 1.0, "csr": 2.0, "dia": 1.0, "ell": 1.0, "sell": 1.0}) == "dia"
+    assert S.best_format({"coo": 1.0, "csr": 2.0, "dia": inf, "ell": 1.0, "sell": 1.0}) == "ell"
+    assert S.best_format({"coo": 1.0, "csr": 2.0, "dia": inf, "ell": inf, "sell": 1.0}) == "sell"
+    assert S.best_format({"coo": 0.5, "csr": 2.0, "dia": inf, "ell": inf, "sell": 0.7}) == "coo"
     T = np.array([[3.0, 2.0, 1.0], [1.0, 2.0, np.inf], [2.0, 2.0, 4.0]])
     best = np.array([2, 0, 0])
     assert S.regret(T, best) == 0.0
@@ -55,7 +58,7 @@ def test_he_init_layout_and_scale():
     assert w.dtype == np.float32 and w.size == orc.NPARAM
     W1, b1 = w[:512], w[512:576]
     W2, b2 = w[576:576 + 4096], w[4672:4736]
-    W3, b3 = w[4736:4928], w[4928:]
+    W3, b3 = w[4736:4736 + 64 * S.NO], w[4736 + 64 * S.NO:]
     assert not b1.any() and not b2.any() and not b3.any()
     assert np.std(W1) == pytest.approx(math.sqrt(2 / 8), rel=0.15)
     assert np.std(W2) == pytest.approx(math.sqrt(2 / 64), rel=0.05)
@@ -72,6 +75,15 @@ def test_dia_feasibility_rule_matches_oracle_slot_count():
     assert S.dia_feasible(orc.features(*(lambda c: (c.nrows, c.ncols, c.ai, c.aj))(wl.stencil(6))))
     z = wl.zipf_rows(3000, seed=2)
     assert not S.dia_feasible(orc.features(z.nrows, z.ncols, z.ai, z.aj))
+
+
+def test_ell_feasibility_rule_matches_oracle_width():
+    """ELL's mask is its refusal rule with the oracle's width (longest row)."""
+    for coo in (wl.stencil(6), wl.banded(3000, 11, 200, seed=3),
+                wl.zipf_rows(3000, seed=2), wl.block_random(200, seed=5)):
+        f = orc.features(coo.nrows, coo.ncols, coo.ai, coo.aj)
+        K, _, _ = orc.csr_to_ell(orc.coo_to_csr(coo.nrows, coo.ai), coo.aj, coo.av)
+        assert f[4] == K and S.ell_feasible(f) == (K * coo.nrows <= 8 * coo.nnz)
 
 
 @pytest.mark.parametrize("fam", ["banded", "zipf", "block"])
@@ -110,6 +122,7 @@ def test_committed_labels_are_consistent():
         t = {f: (math.inf if r["times_ms"][f] is None else r["times_ms"][f]) for f in S.FORMATS}
         assert r["label"] == S.best_format(t)
         assert (r["times_ms"]["dia"] is None) == (not S.dia_feasible(r["features"]))
+        assert (r["times_ms"]["ell"] is None) == (not S.ell_feasible(r["features"]))
         assert dict((k, v) for k, v in r.items() if k in S.matrix_spec(r["i"])) == S.matrix_spec(r["i"])
     # stencils are deterministic and banded features depend only on the
     # offsets (numpy-seeded), so these regenerate identically on the CPU;
