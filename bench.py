@@ -40,7 +40,10 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 METRIC = "SpMV effective HBM GB/s (% of peak) per format; mixed vs FP64 CG time-to-tol"
 FORMATS = ("coo", "csr", "dia")
-KERNEL_NAMES = {"coo": "coo_rows_kernel", "csr": "csr_spmv_kernel", "dia": "dia_spmv_kernel"}
+# kernel of each format's implementation (ids as in mxs_set_impl)
+KERNEL_NAMES = {"coo": ("coo_rows_kernel", "coo_spmv_kernel"),
+                "csr": ("csr_spmv_kernel", "csr_rowwise_kernel", "csr_spmv_kernel", "ell_spmv_kernel"),
+                "dia": ("dia_spmv_kernel",) * 3}
 SPMV_SRC = os.path.join(ROOT, "paper_2304_09511_amd", "csrc", "spmv.hip")
 
 
@@ -395,7 +398,7 @@ def impl_report(mxs, A, x, y, reps=20):
     default = A.impl
     best, ms = A.tune(x, y, reps=reps)
     A.impl = default
-    return {"default": names[default], "fastest": names[best],
+    return {"default": names[default], "default_id": default, "fastest": names[best],
             "median_us": {names[i]: (None if m is None else round(m * 1e3, 2))
                           for i, m in enumerate(ms)}}
 
@@ -679,7 +682,7 @@ def main():
     achieved = bytes_f[dom] / (per[dom]["us_per_call"] * 1e-6) / 1e9
     tag = f"stencil{args.n}"
     traffic = traffic_from_profile(dom, tag)
-    roofline = {"kernel": KERNEL_NAMES[dom],
+    roofline = {"kernel": KERNEL_NAMES[dom][per[dom]["implementations"]["default_id"]],
                 "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                 "traffic": traffic,

@@ -203,12 +203,16 @@ mxs_status mxs_optimize(mxs_mat A, void *stream);
  *           when no tile owns more than 512 rows)
  *        1: segmented-scan tiles (always applicable)
  *   CSR  0: tiles of a fixed number of entries   1: a thread per row
+ *        2: entry tiles, columns and values staged in LDS, x gathered per
+ *           row   3: a lane per row over an ELL copy made by mxs_optimize
+ *           (applicable when that copy adds at most 5% slots)
  *   DIA  0: row-blocked values, one x load per run of three consecutive
  *           offsets (needs the row-blocked copy and offsets in such runs)
  *        1: row-blocked values (needs the copy)
  *        2: diagonal-major values as stored (always applicable)
- * After mxs_optimize the default is: COO 0 where applicable, else 1; CSR 1
- * when nrows > 2*nnz, else 0; DIA the lowest applicable id.
+ * After mxs_optimize the default is: COO 0 where applicable, else 1; CSR 3
+ * where applicable, else 1 when nrows > 2*nnz, else 0; DIA the lowest
+ * applicable id; ELL and SELL have one implementation, 0.
  * mxs_impl_count: number of ids of A's format (0 for split matrices).
  * mxs_set_impl [syncs: builds the plan]: MXS_ERR_UNSUPPORTED for an id that
  *   is not applicable to A or a split matrix.

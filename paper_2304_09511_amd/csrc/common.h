@@ -90,6 +90,12 @@ struct CsrPlan {
     bool fixup = false;          // some row reaches past its owner's overflow window
     bool rowwise = false;        // a thread per row (default when rows outnumber entries 2:1)
     bool gx = false;             // entry tiles, x gathered per row from LDS-staged columns
+    // ELL copy (implementation 3), made when it adds at most 5% slots:
+    // K slots per row, column-major, padding column -1
+    int32_t ell_k = 0;
+    int32_t *ell_col = nullptr;
+    void *ell_val = nullptr;
+    bool ell = false;            // the active implementation reads it
 };
 
 struct DiaPlan {
@@ -362,6 +368,10 @@ mxs_status padded_to_rows(const mxs_mat_s *A, mxs_format dst, int32_t *idx0, int
 mxs_status padded_spmv(const mxs_mat_s *A, const void *x, void *y, const int *done, double *parts,
                        hipStream_t s);
 int64_t padded_grid(const mxs_mat_s *A, bool dot);
+// ELL kernel on raw arrays (the CSR plan's ELL copy)
+mxs_status ell_launch(int32_t nrows, int32_t K, const int32_t *col, const void *vals, mxs_dtype t,
+                      const void *x, void *y, const int *done, double *parts, hipStream_t s);
+int64_t ell_grid(int32_t nrows, bool dot);
 
 // mg.hip: HPCG's multigrid preconditioner.
 mxs_status mg_create(int32_t n, int32_t levels, mxs_mg_s **out, hipStream_t s); // syncs

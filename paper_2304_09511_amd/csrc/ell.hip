@@ -456,6 +456,33 @@ __global__ __launch_bounds__(256) void sell_spmv_kernel(int32_t nrows, int64_t n
     }
 }
 
+int64_t ell_grid(int32_t nrows, bool dot)
+{
+    return (int64_t)pad_grid(grid_of(nrows, dot ? 65536 : (1 << 30)));
+}
+
+template <typename T>
+static mxs_status ell_typed(int32_t nrows, int32_t K, const int32_t *col, const T *val, const T *x, T *y,
+                            const int *done, double *parts, hipStream_t s)
+{
+    const uint32_t g = (uint32_t)ell_grid(nrows, parts != nullptr);
+    if (parts)
+        ell_spmv_kernel<T, true><<<g, 256, 0, s>>>(nrows, K, col, val, x, y, done, parts);
+    else
+        ell_spmv_kernel<T, false><<<g, 256, 0, s>>>(nrows, K, col, val, x, y, done, nullptr);
+    return launch_status();
+}
+
+mxs_status ell_launch(int32_t nrows, int32_t K, const int32_t *col, const void *vals, mxs_dtype t,
+                      const void *x, void *y, const int *done, double *parts, hipStream_t s)
+{
+    if (t == MXS_F64)
+        return ell_typed<double>(nrows, K, col, (const double *)vals, (const double *)x, (double *)y,
+                                 done, parts, s);
+    return ell_typed<float>(nrows, K, col, (const float *)vals, (const float *)x, (float *)y, done,
+                            parts, s);
+}
+
 static int64_t padded_units(const mxs_mat_s *A)
 {
     return A->fmt == MXS_ELL ? A->nrows : ((int64_t)A->nrows + kSellC - 1) / kSellC * kSellC;

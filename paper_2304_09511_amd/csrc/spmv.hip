@@ -1083,6 +1083,7 @@ static uint32_t fixup_grid(int64_t ntiles) { return (uint32_t)std::max<int64_t>(
 int64_t spmv_dot_parts(const mxs_mat_s *A)
 {
     if (A->fmt == MXS_COO || A->fmt == MXS_HDC) return kDotGridMax;
+    if (A->fmt == MXS_CSR && A->csr.ell) return ell_grid(A->nrows, true);
     if (A->fmt == MXS_CSR && A->csr.rowwise) return rowwise_grid(A->nrows);
     if (A->fmt == MXS_ELL || A->fmt == MXS_SELL) return padded_grid(A, true);
     uint32_t grid;
@@ -1127,6 +1128,26 @@ static mxs_status build_csr_plan(mxs_mat_s *A, hipStream_t s)
     MXS_HIP(hipMalloc(&carry, 2 * (size_t)nt * dsize(A->dtype)));
     A->owned.push_back(carry);
     A->csr.carry = carry;
+    // ELL copy for rows of near-equal length: lanes of a wave then hold
+    // neighbouring rows, and their gathers of x neighbouring addresses
+    int32_t K = 0;
+    const mxs_status st_w = ell_width(A, &K, s);
+    if (st_w == MXS_ERR_DIA_TOO_SPARSE) return MXS_OK;
+    if (st_w != MXS_OK) return st_w;
+    if (K > 0 && (double)K * A->nrows <= 1.05 * (double)A->nnz) {
+        const size_t slots = (size_t)K * A->nrows;
+        void *buf = nullptr;
+        MXS_HIP(hipMalloc(&buf, slots * (sizeof(int32_t) + dsize(A->dtype))));
+        A->owned.push_back(buf);
+        int32_t *col = (int32_t *)buf;
+        void *val = (char *)buf + slots * sizeof(int32_t);
+        mxs_status st_b = ell_build(A, K, col, val, s);
+        if (st_b != MXS_OK) return st_b;
+        MXS_HIP(hipStreamSynchronize(s));
+        A->csr.ell_k = K;
+        A->csr.ell_col = col;
+        A->csr.ell_val = val;
+    }
     return MXS_OK;
 }
 
@@ -1281,13 +1302,15 @@ static mxs_status build_coo_plan(mxs_mat_s *A, hipStream_t s)
 //       1: segmented-scan tiles
 //   CSR 0: entry tiles           1: a thread per row
 //       2: entry tiles, x gathered per row from LDS-staged columns
+//       3: a lane per row over an ELL copy made by the plan (rows of
+//          near-equal length: at most 5% padding)
 //   DIA 0: row-blocked values, x shared over runs of three offsets
 //       1: row-blocked values    2: diagonal-major values (no copy), x shared
 // ---------------------------------------------------------------------------
 int32_t impl_count(const mxs_mat_s *A)
 {
     if (A->fmt == MXS_ELL || A->fmt == MXS_SELL) return 1;
-    return A->fmt == MXS_DIA || A->fmt == MXS_CSR ? 3 : A->fmt == MXS_COO ? 2 : 0;
+    return A->fmt == MXS_CSR ? 4 : A->fmt == MXS_DIA ? 3 : A->fmt == MXS_COO ? 2 : 0;
 }
 
 bool impl_ok(const mxs_mat_s *A, int32_t impl)
@@ -1296,7 +1319,7 @@ bool impl_ok(const mxs_mat_s *A, int32_t impl)
     if (A->nnz == 0) return true;
     switch (A->fmt) {
     case MXS_COO: return impl == 1 || A->coo.rows_ok;
-    case MXS_CSR: return true;
+    case MXS_CSR: return impl != 3 || A->csr.ell_col != nullptr;
     case MXS_DIA:
         if (impl == 0) return A->dia.blk != nullptr && A->dia.triples;
         if (impl == 1) return A->dia.blk != nullptr;
@@ -1311,7 +1334,7 @@ static int32_t default_impl(const mxs_mat_s *A)
 {
     switch (A->fmt) {
     case MXS_COO: return impl_ok(A, 0) ? 0 : 1;
-    case MXS_CSR: return A->csr.rowwise ? 1 : MXS_CSR_GX_DEFAULT ? 2 : 0;
+    case MXS_CSR: return A->csr.ell_col ? 3 : A->csr.rowwise ? 1 : MXS_CSR_GX_DEFAULT ? 2 : 0;
     case MXS_DIA: return impl_ok(A, 0) ? 0 : impl_ok(A, 1) ? 1 : 2;
     case MXS_ELL:
     case MXS_SELL: return 0;
@@ -1331,6 +1354,7 @@ void set_impl(mxs_mat_s *A, int32_t impl)
     case MXS_CSR:
         A->csr.rowwise = impl == 1;
         A->csr.gx = impl == 2;
+        A->csr.ell = impl == 3;
         break;
     case MXS_DIA:
         A->dia.use_blk = impl != 2 && A->dia.blk != nullptr;
@@ -1442,6 +1466,13 @@ static mxs_status spmv_typed(const mxs_mat_s *A, const T *x, T *y, const int *do
             MXS_HIP(hipGetLastError());
             if (dot) return dot_sigma_typed<T>(A->nrows, x, y, done, dot, s);
             return MXS_OK;
+        }
+        if (A->csr.ell && !acc) {
+            mxs_status st = ell_launch(A->nrows, A->csr.ell_k, A->csr.ell_col, A->csr.ell_val, A->dtype,
+                                       x, y, done, parts, s);
+            if (st != MXS_OK) return st;
+            nparts = ell_grid(A->nrows, dot != nullptr);
+            break;
         }
         if (A->csr.rowwise) {
             grid = rowwise_grid(A->nrows);
