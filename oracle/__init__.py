@@ -101,6 +101,9 @@ def _bind(lib):
         "orc_adam_step": (None, [I64, P, P, P, P, D, I64, D, D, D]),
         "orc_symgs": (C.c_int, [I64, P, P, P, P, P, P]),
         "orc_ell_width": (I64, [I64, P]),
+        "orc_hyb_width": (I64, [I64, P]),
+        "orc_hyb_rest": (I64, [I64, P, I64]),
+        "orc_csr_to_hyb": (None, [I64, P, P, P, I64, P, P, P, P, P]),
         "orc_csr_to_ell": (None, [I64, P, P, P, I64, P, P]),
         "orc_ell_spmv": (None, [I64, I64, P, P, P, P]),
         "orc_sell_perm": (None, [I64, P, I64, P]),
@@ -341,6 +344,25 @@ def ell_to_csr(nrows, K, col, val):
     lens = keep.sum(axis=0)
     irp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
     return irp, col.T[keep.T].astype(np.int32), val.T[keep.T].astype(np.float64)
+
+
+def hyb_width(irp):
+    """HYB's ELL width by the rule of Bell and Garland."""
+    irp = _i32(irp)
+    return int(_load().orc_hyb_width(irp.shape[0] - 1, _p(irp)))
+
+
+def csr_to_hyb(irp, aj, av, K=None):
+    """(K, ELL col, ELL val, COO ai, aj, av of the remainder)."""
+    irp, aj, av = _i32(irp), _i32(aj), _f64(av)
+    n = irp.shape[0] - 1
+    lib = _load()
+    K = hyb_width(irp) if K is None else int(K)
+    nr = int(lib.orc_hyb_rest(n, _p(irp), K))
+    ecol, evals = np.empty(K * n, np.int32), np.empty(K * n, np.float64)
+    ri, rj, rv = np.empty(nr, np.int32), np.empty(nr, np.int32), np.empty(nr, np.float64)
+    lib.orc_csr_to_hyb(n, _p(irp), _p(aj), _p(av), K, _p(ecol), _p(evals), _p(ri), _p(rj), _p(rv))
+    return K, ecol, evals, ri, rj, rv
 
 
 def sell_layout(irp, C, sigma):

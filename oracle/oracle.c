@@ -959,3 +959,56 @@ void orc_sell_spmv(int64_t nrows, int64_t C, const int32_t *perm, const int64_t 
         y[perm[p]] = sum;
     }
 }
+
+/* ------------------------------------------------------------------------
+ * HYB (Bell and Garland, SC'09): the first K entries of each row in ELL,
+ * the rest in COO (canonical order).  The width rule keeps ELL dense: K is
+ * the largest k such that at least max(4096, nrows/3) rows (all rows when
+ * fewer) hold k or more entries (0 for an empty matrix).
+ * ---------------------------------------------------------------------- */
+int64_t orc_hyb_width(int64_t nrows, const int32_t *irp)
+{
+    int64_t need = nrows / 3 > 4096 ? nrows / 3 : 4096;
+    if (need > nrows)
+        need = nrows;
+    int64_t best = 0;
+    for (int64_t k = 1;; ++k) {
+        int64_t rows = 0;
+        for (int64_t i = 0; i < nrows; ++i)
+            if (irp[i + 1] - irp[i] >= k)
+                ++rows;
+        if (rows < need || rows == 0)
+            break;
+        best = k;
+    }
+    return best;
+}
+
+/* Number of entries past the K-th of their row. */
+int64_t orc_hyb_rest(int64_t nrows, const int32_t *irp, int64_t K)
+{
+    int64_t r = 0;
+    for (int64_t i = 0; i < nrows; ++i)
+        if (irp[i + 1] - irp[i] > K)
+            r += irp[i + 1] - irp[i] - K;
+    return r;
+}
+
+void orc_csr_to_hyb(int64_t nrows, const int32_t *irp, const int32_t *aj, const double *av,
+                    int64_t K, int32_t *ecol, double *eval, int32_t *ri, int32_t *rj, double *rv)
+{
+    int64_t q = 0;
+    for (int64_t i = 0; i < nrows; ++i) {
+        const int64_t len = irp[i + 1] - irp[i];
+        for (int64_t k = 0; k < K; ++k) {
+            ecol[k * nrows + i] = k < len ? aj[irp[i] + k] : -1;
+            eval[k * nrows + i] = k < len ? av[irp[i] + k] : 0.0;
+        }
+        for (int64_t k = K; k < len; ++k) {
+            ri[q] = (int32_t)i;
+            rj[q] = aj[irp[i] + k];
+            rv[q] = av[irp[i] + k];
+            ++q;
+        }
+    }
+}

@@ -101,8 +101,8 @@ MUTANTS = [
      "        if (aj[k] == i)\n            d = av[k];\n        s -= av[k] * x[aj[k]];",
      [lambda: mg.test_gs_sweeps_are_triangular_solves("random60", "permuted")]),
     ("ell_row_major",
-     "            ecol[k * nrows + i] = k < len ? aj[irp[i] + k] : -1;\n            eval[k * nrows + i] = k < len ? av[irp[i] + k] : 0.0;",
-     "            ecol[i * K + k] = k < len ? aj[irp[i] + k] : -1;\n            eval[i * K + k] = k < len ? av[irp[i] + k] : 0.0;",
+     "irp[i];\n            ecol[k * nrows + i] = k < len ? aj[irp[i] + k] : -1;\n            eval[k * nrows + i] = k < len ? av[irp[i] + k] : 0.0;",
+     "irp[i];\n            ecol[i * K + k] = k < len ? aj[irp[i] + k] : -1;\n            eval[i * K + k] = k < len ? av[irp[i] + k] : 0.0;",
      [sell.test_ell_hand_built_layout]),
     ("sell_sorted_ascending",
      "for (int64_t len = maxlen; len >= 0; --len)",
@@ -117,6 +117,14 @@ MUTANTS = [
      "        y[perm[p]] = sum;",
      "        y[p] = sum;",
      [lambda: sell.test_spmv_integer_bruteforce(4, 8, (17, 17), 0.3)]),
+    ("hyb_no_row_floor",
+     "int64_t need = nrows / 3 > 4096 ? nrows / 3 : 4096;",
+     "int64_t need = nrows / 3;",
+     [sell.test_hyb_width_rule_hand_built]),
+    ("hyb_rest_skips_an_entry",
+     "        for (int64_t k = K; k < len; ++k) {\n            ri[q]",
+     "        for (int64_t k = K + 1; k < len; ++k) {\n            ri[q]",
+     [lambda: sell.test_hyb_partition_and_spmv("random37x53", sell.CASES[1][1], 1)]),
     ("adam_no_bias_correction",
      "double mh = m[i] / c1, vh = v[i] / c2;",
      "double mh = m[i], vh = v[i];",

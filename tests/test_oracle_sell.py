@@ -113,3 +113,51 @@ def test_round_trips_to_csr(name, a, C, sigma, m=orc):
     perm, cs, col, val = m.csr_to_sell(irp, aj, av, C, sigma)
     r = m.sell_to_csr(a.nrows, C, perm, cs, col, val)
     assert all(np.array_equal(u, v) for u, v in zip(r, (irp, aj, av)))
+
+
+# ------------------------------------------------------------------ HYB
+def test_hyb_width_rule_hand_built(m=orc):
+    # 9000 rows: 3000 with 5 entries, 3000 with 2, 3000 with 1.  need =
+    # max(4096, 3000) = 4096 rows with >= k entries: k = 2 (6000 rows), not
+    # k = 3 (3000 rows).
+    lens = np.repeat([5, 2, 1], 3000)
+    irp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    assert m.hyb_width(irp) == 2
+    # fewer than 4096 rows: every row must reach k -> the shortest row
+    irp_small = np.concatenate([[0], np.cumsum([4, 3, 7])]).astype(np.int32)
+    assert m.hyb_width(irp_small) == 3
+    assert m.hyb_width(np.zeros(6, np.int32)) == 0
+
+
+@pytest.mark.parametrize("name,a", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("K", [None, 0, 1, 3, 100])
+def test_hyb_partition_and_spmv(name, a, K, m=orc):
+    """ELL part + COO remainder hold exactly the matrix's entries (each row's
+    first K in ELL), and their products sum to the matrix's on integer
+    data."""
+    irp, aj, av = csr_of(a)
+    K_, ecol, evals, ri, rj, rv = m.csr_to_hyb(irp, aj, av, K)
+    if K is None:
+        assert K_ == m.hyb_width(irp)
+    lens = np.diff(irp)
+    assert ri.size == int(np.maximum(lens - K_, 0).sum())
+    e_irp, e_aj, e_av = orc.ell_to_csr(a.nrows, K_, ecol, evals) if a.nrows else (irp, aj, av)
+    # the union, merged row by row, is the original CSR
+    rows = []
+    for i in range(a.nrows):
+        e = list(zip(e_aj[e_irp[i]:e_irp[i + 1]], e_av[e_irp[i]:e_irp[i + 1]]))
+        rsel = ri == i
+        r = list(zip(rj[rsel], rv[rsel]))
+        assert len(e) == min(lens[i], K_)
+        rows += e + r
+    if a.nrows:
+        assert np.array_equal(np.array([c for c, _ in rows], np.int32), aj)
+        assert np.array_equal(np.array([v for _, v in rows]), av)
+    g = wl.rng(a.nrows + 7)
+    x = g.integers(-6, 7, a.ncols).astype(float)
+    D = np.zeros((a.nrows, a.ncols))
+    D[a.ai, a.aj] = np.round(a.av * 4)
+    iv = np.round(evals * 4)
+    y = m.ell_spmv(a.nrows, K_, ecol, iv, x) if a.nrows else np.zeros(0)
+    y = y + (orc.coo_spmv(a.nrows, ri, rj, np.round(rv * 4), x) if ri.size else 0.0)
+    assert np.array_equal(y, D @ x)
