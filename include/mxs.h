@@ -51,7 +51,9 @@ typedef enum {
     MXS_ERR_UNSUPPORTED = -10    /* operation not defined for this format/dtype/shape */
 } mxs_status;
 
-typedef enum { MXS_COO = 0, MXS_CSR = 1, MXS_DIA = 2, MXS_HDC = 3, MXS_ELL = 4, MXS_SELL = 5 } mxs_format;
+typedef enum {
+    MXS_COO = 0, MXS_CSR = 1, MXS_DIA = 2, MXS_HDC = 3, MXS_ELL = 4, MXS_SELL = 5, MXS_HYB = 6
+} mxs_format;
 typedef enum { MXS_F64 = 0, MXS_F32 = 1 } mxs_dtype;
 
 /* Opaque host-side handle of a sparse matrix in one storage format. */
@@ -331,12 +333,28 @@ mxs_status mxs_split(mxs_mat A, double min_fill, mxs_format rest_format, int32_t
                      void *band_vals, int32_t *rest_idx0, int32_t *rest_idx1, void *rest_vals,
                      mxs_mat *out, void *stream);
 
-/* The two parts of a split matrix H as handles of their own [host only]:
- * *band (MXS_DIA) and *rest (MXS_COO or MXS_CSR), either pointer may be
- * NULL.  They stay valid until H is destroyed and belong to H: mxs_destroy
+/* HYB (Section IX's hybrid formats; Bell and Garland, 2009): each row's
+ * first K entries in ELL (column-major, padding column -1 and +0.0), the
+ * rest in COO (canonical order).  K < 0 asks for the width rule: the
+ * largest k such that at least max(4096, nrows/3) rows (all rows when
+ * fewer) hold k or more entries.
+ * mxs_hyb_size [syncs]: *K_out, and *rest_nnz entries past the K-th of
+ *   their row; refused with MXS_ERR_DIA_TOO_SPARSE when K*nrows > 8*nnz.
+ * mxs_to_hyb [syncs]: writes ell_col, ell_val [K*nrows] and rest_ai,
+ *   rest_aj, rest_av [rest_nnz] (caller-allocated) and returns an MXS_HYB
+ *   handle that borrows them (ndiag = K); SpMV and FP64 CG accept it, and
+ *   mxs_split_parts gives its ELL and COO parts; conversion, cast, features
+ *   and mixed solves do not (MXS_ERR_UNSUPPORTED).  A is COO or CSR. */
+mxs_status mxs_hyb_size(mxs_mat A, int32_t K, int32_t *K_out, int64_t *rest_nnz, void *stream);
+mxs_status mxs_to_hyb(mxs_mat A, int32_t K, int32_t *ell_col, void *ell_val, int32_t *rest_ai,
+                      int32_t *rest_aj, void *rest_av, mxs_mat *out, void *stream);
+
+/* The two parts of a split or HYB matrix H as handles of their own [host
+ * only]: *band (MXS_DIA for a split, MXS_ELL for HYB) and *rest (MXS_COO or
+ * MXS_CSR), either pointer may be NULL.  They stay valid until H is destroyed and belong to H: mxs_destroy
  * on a part returns MXS_ERR_INVALID_ARG.  Every other call accepts them, so
  * each part's implementation can be chosen (mxs_set_impl, mxs_tune); the
- * choice holds for H's product.  MXS_ERR_UNSUPPORTED if H is not MXS_HDC. */
+ * choice holds for H's product.  MXS_ERR_UNSUPPORTED if H is neither MXS_HDC nor MXS_HYB. */
 mxs_status mxs_split_parts(mxs_mat H, mxs_mat *band, mxs_mat *rest);
 
 /* ------------------------------------------------------------------------

@@ -22,13 +22,13 @@ __all__ = [
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = os.path.join(_HERE, "libmxs.so")
 
-COO, CSR, DIA, HDC, ELL, SELL = 0, 1, 2, 3, 4, 5
+COO, CSR, DIA, HDC, ELL, SELL, HYB = 0, 1, 2, 3, 4, 5, 6
 F64, F32 = 0, 1
 BORROW = 1
 NPARAM = 5061  # MXS_MLP_NPARAM: MLP 8-64-64-5
 NCLASS = 5     # MXS_NCLASS: outputs (COO, CSR, DIA, ELL, SELL)
 FORMATS = {"coo": COO, "csr": CSR, "dia": DIA, "ell": ELL}
-FORMAT_NAMES = {COO: "coo", CSR: "csr", DIA: "dia", HDC: "hdc", ELL: "ell", SELL: "sell"}
+FORMAT_NAMES = {COO: "coo", CSR: "csr", DIA: "dia", HDC: "hdc", ELL: "ell", SELL: "sell", HYB: "hyb"}
 
 STATUS = {
     0: "MXS_OK", 1: "MXS_NOT_CONVERGED", -1: "MXS_ERR_INVALID_ARG", -2: "MXS_ERR_INDEX_RANGE",
@@ -81,6 +81,8 @@ _SIGS = {
     "mxs_split": (I32, [P, D, I32, P, P, P, P, P, P, P]),
     "mxs_split_parts": (I32, [P, P, P]),
     "mxs_sell_size": (I32, [P, I32, P, P, P]),
+    "mxs_hyb_size": (I32, [P, I32, P, P, P]),
+    "mxs_to_hyb": (I32, [P, I32, P, P, P, P, P, P, P]),
     "mxs_to_sell": (I32, [P, I32, P, P, P, P, P, P]),
     "mxs_cast": (I32, [P, I32, P, P, P]),
     "mxs_optimize": (I32, [P, P]),
@@ -339,6 +341,29 @@ class Matrix:
                                 C.byref(h), _stream()), "mxs_split")
         return Matrix(h, [doff, band, i0, i1, vals])
 
+    def hyb_size(self, K=-1):
+        k, r = C.c_int32(), C.c_int64()
+        _check(load().mxs_hyb_size(self._h, int(K), C.byref(k), C.byref(r), _stream()),
+               "mxs_hyb_size")
+        return k.value, r.value
+
+    def to_hyb(self, K=-1):
+        """HYB on fresh tensors (K < 0: the width rule), kept as
+        [ell_col, ell_val, rest_ai, rest_aj, rest_av]."""
+        torch = _torch()
+        k, r = self.hyb_size(K)
+        dt = _torch_dtype(self.dtype)
+        ecol = torch.empty(max(k * self.nrows, 1), dtype=torch.int32, device="cuda")
+        ev = torch.empty(max(k * self.nrows, 1), dtype=dt, device="cuda")
+        ri = torch.empty(max(r, 1), dtype=torch.int32, device="cuda")
+        rj = torch.empty(max(r, 1), dtype=torch.int32, device="cuda")
+        rv = torch.empty(max(r, 1), dtype=dt, device="cuda")
+        h = C.c_void_p()
+        _check(load().mxs_to_hyb(self._h, int(K), _ptr(ecol), _ptr(ev), _ptr(ri), _ptr(rj), _ptr(rv),
+                                 C.byref(h), _stream()), "mxs_to_hyb")
+        n = k * self.nrows
+        return Matrix(h, [ecol[:n], ev[:n], ri[:r], rj[:r], rv[:r]])
+
     def sell_size(self, sigma=1):
         sl, ns = C.c_int64(), C.c_int32()
         _check(load().mxs_sell_size(self._h, int(sigma), C.byref(sl), C.byref(ns), _stream()),
@@ -406,7 +431,7 @@ class Matrix:
         return load().mxs_impl_count(self._h)
 
     def parts(self):
-        """(band, rest) of a split matrix: handles owned by this one."""
+        """(band, rest) of a split or HYB matrix: handles owned by this one."""
         b, r = C.c_void_p(), C.c_void_p()
         _check(load().mxs_split_parts(self._h, C.byref(b), C.byref(r)), "mxs_split_parts")
         return Matrix(b, [self], owned=False), Matrix(r, [self], owned=False)

@@ -36,7 +36,7 @@ hipStream_t S(void *stream) { return (hipStream_t)stream; }
 bool valid_dtype(mxs_dtype t) { return t == MXS_F64 || t == MXS_F32; }
 bool valid_format(mxs_format f)
 {
-    return f == MXS_COO || f == MXS_CSR || f == MXS_DIA || f == MXS_ELL || f == MXS_SELL;
+    return f == MXS_COO || f == MXS_CSR || f == MXS_DIA || f == MXS_ELL || f == MXS_SELL || f == MXS_HYB;
 }
 
 // Every entry point that touches the GPU runs its body through guarded():
@@ -285,7 +285,7 @@ mxs_status mxs_info(mxs_mat A, mxs_format *fmt, mxs_dtype *dtype, int32_t *nrows
 mxs_status mxs_arrays(mxs_mat A, const int32_t **idx0, const int32_t **idx1, const void **vals)
 {
     if (!A) return MXS_ERR_INVALID_ARG;
-    if (A->fmt == MXS_HDC) return MXS_ERR_UNSUPPORTED;
+    if (is_split(A)) return MXS_ERR_UNSUPPORTED;
     if (idx0) *idx0 = A->idx0;
     if (idx1) *idx1 = A->idx1;
     if (vals) *vals = A->vals;
@@ -299,7 +299,7 @@ mxs_status mxs_convert_size(mxs_mat src, mxs_format dst, int64_t *count, int32_t
                             void *stream)
 {
     if (!src || !valid_format(dst)) return MXS_ERR_INVALID_ARG;
-    if (src->fmt == MXS_HDC) return MXS_ERR_UNSUPPORTED;
+    if (is_split(src)) return MXS_ERR_UNSUPPORTED;
     return guarded([&] {
         int64_t c = 0;
         int32_t nd = 0;
@@ -315,7 +315,7 @@ mxs_status mxs_convert(mxs_mat src, mxs_format dst, int32_t *idx0, int32_t *idx1
                        mxs_mat *out, void *stream)
 {
     if (!src || !valid_format(dst) || !out) return MXS_ERR_INVALID_ARG;
-    if (src->fmt == MXS_HDC) return MXS_ERR_UNSUPPORTED;
+    if (is_split(src)) return MXS_ERR_UNSUPPORTED;
     return guarded([&] {
         hipStream_t s = S(stream);
         int64_t count = 0;
@@ -355,7 +355,7 @@ mxs_status mxs_convert(mxs_mat src, mxs_format dst, int32_t *idx0, int32_t *idx1
 mxs_status mxs_cast(mxs_mat src, mxs_dtype dtype, void *vals, mxs_mat *out, void *stream)
 {
     if (!src || !valid_dtype(dtype) || !out) return MXS_ERR_INVALID_ARG;
-    if (src->fmt == MXS_HDC) return MXS_ERR_UNSUPPORTED;
+    if (is_split(src)) return MXS_ERR_UNSUPPORTED;
     const int64_t n = value_count(src);
     if (n > 0 && !vals) return MXS_ERR_INVALID_ARG;
     return guarded([&] {
@@ -376,6 +376,73 @@ mxs_status mxs_cast(mxs_mat src, mxs_dtype dtype, void *vals, mxs_mat *out, void
         B->slots = src->slots;
         B->sigma = src->sigma;
         *out = B;
+        return MXS_OK;
+    });
+}
+
+mxs_status mxs_hyb_size(mxs_mat A, int32_t K, int32_t *K_out, int64_t *rest_nnz, void *stream)
+{
+    if (!A) return MXS_ERR_INVALID_ARG;
+    if (A->fmt != MXS_COO && A->fmt != MXS_CSR) return MXS_ERR_UNSUPPORTED;
+    return guarded([&] {
+        int32_t k = K;
+        int64_t r = 0;
+        mxs_status st = hyb_size(A, &k, &r, S(stream));
+        if (st != MXS_OK) return st;
+        if (K_out) *K_out = k;
+        if (rest_nnz) *rest_nnz = r;
+        return MXS_OK;
+    });
+}
+
+mxs_status mxs_to_hyb(mxs_mat A, int32_t K, int32_t *ell_col, void *ell_val, int32_t *rest_ai,
+                      int32_t *rest_aj, void *rest_av, mxs_mat *out, void *stream)
+{
+    if (!A || !out) return MXS_ERR_INVALID_ARG;
+    if (A->fmt != MXS_COO && A->fmt != MXS_CSR) return MXS_ERR_UNSUPPORTED;
+    return guarded([&] {
+        hipStream_t s = S(stream);
+        int32_t k = K;
+        int64_t r = 0;
+        mxs_status st = hyb_size(A, &k, &r, s);
+        if (st != MXS_OK) return st;
+        if ((k > 0 && A->nrows > 0 && (!ell_col || !ell_val)) || (r > 0 && (!rest_ai || !rest_aj || !rest_av)))
+            return MXS_ERR_INVALID_ARG;
+        if ((st = hyb_build(A, k, ell_col, ell_val, rest_ai, rest_aj, rest_av, s)) != MXS_OK) return st;
+        MXS_HIP(hipStreamSynchronize(s));
+        auto *band = new mxs_mat_s;
+        band->fmt = MXS_ELL;
+        band->dtype = A->dtype;
+        band->nrows = A->nrows;
+        band->ncols = A->ncols;
+        band->ndiag = k;
+        band->nnz = A->nnz - r;
+        band->idx0 = ell_col;
+        band->vals = ell_val;
+        band->device = A->device;
+        band->part = true;
+        auto *rest = new mxs_mat_s;
+        rest->fmt = MXS_COO;
+        rest->dtype = A->dtype;
+        rest->nrows = A->nrows;
+        rest->ncols = A->ncols;
+        rest->nnz = r;
+        rest->idx0 = rest_ai;
+        rest->idx1 = rest_aj;
+        rest->vals = rest_av;
+        rest->device = A->device;
+        rest->part = true;
+        auto *h = new mxs_mat_s;
+        h->fmt = MXS_HYB;
+        h->dtype = A->dtype;
+        h->nrows = A->nrows;
+        h->ncols = A->ncols;
+        h->nnz = A->nnz;
+        h->ndiag = k;
+        h->device = A->device;
+        h->band = band;
+        h->rest = rest;
+        *out = h;
         return MXS_OK;
     });
 }
@@ -438,7 +505,7 @@ mxs_status mxs_optimize(mxs_mat A, void *stream)
 mxs_status mxs_split_parts(mxs_mat H, mxs_mat *band, mxs_mat *rest)
 {
     if (!H) return MXS_ERR_INVALID_ARG;
-    if (H->fmt != MXS_HDC) return MXS_ERR_UNSUPPORTED;
+    if (!is_split(H)) return MXS_ERR_UNSUPPORTED;
     if (band) *band = H->band;
     if (rest) *rest = H->rest;
     return MXS_OK;
@@ -452,7 +519,7 @@ int32_t mxs_impl_count(mxs_mat A)
 mxs_status mxs_set_impl(mxs_mat A, int32_t impl, void *stream)
 {
     if (!A) return MXS_ERR_INVALID_ARG;
-    if (A->fmt == MXS_HDC) return MXS_ERR_UNSUPPORTED;
+    if (is_split(A)) return MXS_ERR_UNSUPPORTED;
     return guarded([&] {
         mxs_status st = ensure_plan(A, S(stream));
         if (st != MXS_OK) return st;
@@ -466,7 +533,7 @@ mxs_status mxs_set_impl(mxs_mat A, int32_t impl, void *stream)
 mxs_status mxs_get_impl(mxs_mat A, int32_t *impl, void *stream)
 {
     if (!A || !impl) return MXS_ERR_INVALID_ARG;
-    if (A->fmt == MXS_HDC) return MXS_ERR_UNSUPPORTED;
+    if (is_split(A)) return MXS_ERR_UNSUPPORTED;
     return guarded([&] {
         mxs_status st = ensure_plan(A, S(stream));
         if (st == MXS_OK) *impl = A->impl;
@@ -478,7 +545,7 @@ mxs_status mxs_tune(mxs_mat A, const void *x, void *y, int32_t reps, int32_t *im
                     void *stream)
 {
     if (!A || reps < 1 || reps > 10000) return MXS_ERR_INVALID_ARG;
-    if (A->fmt == MXS_HDC) return MXS_ERR_UNSUPPORTED;
+    if (is_split(A)) return MXS_ERR_UNSUPPORTED;
     const size_t es = dsize(A->dtype);
     if ((A->ncols > 0 && !x) || (A->nrows > 0 && !y)) return MXS_ERR_INVALID_ARG;
     if (overlaps(x, es * A->ncols, y, es * A->nrows)) return MXS_ERR_INVALID_ARG;
@@ -541,7 +608,7 @@ mxs_status mxs_cg_solve(mxs_mat A, mxs_mat A32, const double *b, double *x, cons
                         A32->ncols != A->ncols))
         return MXS_ERR_INVALID_ARG;
     if (opts->mixed < 0 || opts->mixed > 2) return MXS_ERR_INVALID_ARG;
-    if (opts->mixed && A->fmt == MXS_HDC) return MXS_ERR_UNSUPPORTED;
+    if (opts->mixed && is_split(A)) return MXS_ERR_UNSUPPORTED;
     if (!(opts->rtol >= 0.0) || opts->maxit < 0 || (opts->mixed == 1 && opts->max_outer < 0))
         return MXS_ERR_INVALID_ARG;
     if (opts->mixed == 2 && !(opts->ru_delta >= 0.0 && opts->ru_delta <= 1.0))

@@ -127,6 +127,10 @@ struct CooPlan {
 
 }  // namespace mxs
 
+struct mxs_mat_s;
+// a split (DIA band) or HYB (ELL part) handle: two parts, band then rest
+inline bool is_split(const mxs_mat_s *A);
+
 struct mxs_mat_s {
     mxs_format fmt = MXS_CSR;
     mxs_dtype dtype = MXS_F64;
@@ -153,6 +157,8 @@ struct mxs_mat_s {
     int64_t slots = 0;
     int32_t sigma = 0;
 };
+
+inline bool is_split(const mxs_mat_s *A) { return A->fmt == MXS_HDC || A->fmt == MXS_HYB; }
 
 namespace mxs {
 // One grid of the multigrid hierarchy (mg.hip).
@@ -360,6 +366,10 @@ mxs_status features(const mxs_mat_s *A, double out[8], hipStream_t s);
 mxs_status ell_width(const mxs_mat_s *A, int32_t *K, hipStream_t s); // syncs; refuses > 8 slots/entry
 mxs_status ell_build(const mxs_mat_s *A, int32_t K, int32_t *col, void *vals, hipStream_t s);
 mxs_status sell_size(const mxs_mat_s *A, int32_t sigma, int64_t *slots, hipStream_t s); // syncs
+// HYB: *K < 0 on entry asks for the width rule; *rest = entries past the K-th
+mxs_status hyb_size(const mxs_mat_s *A, int32_t *K, int64_t *rest, hipStream_t s); // syncs
+mxs_status hyb_build(const mxs_mat_s *A, int32_t K, int32_t *ell_col, void *ell_val, int32_t *ri,
+                     int32_t *rj, void *rv, hipStream_t s);
 mxs_status sell_build(const mxs_mat_s *A, int32_t sigma, int32_t *perm, int64_t *cs, int32_t *col,
                       void *vals, hipStream_t s);
 // ELL/SELL -> COO (idx0 = row ids) or CSR (idx0 = row pointers)

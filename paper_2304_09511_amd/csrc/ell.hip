@@ -20,6 +20,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <vector>
 
 namespace mxs {
 
@@ -126,6 +127,149 @@ mxs_status ell_build(const mxs_mat_s *A, int32_t K, int32_t *col, void *vals, hi
                 A->nrows, K, irp, A->idx1, (const float *)A->vals, col, (float *)vals);
         st = launch_status();
     }
+    if (tmp) (void)hipFreeAsync(tmp, s);
+    return st;
+}
+
+// ---------------------------------------------------------------------------
+// HYB: each row's first K entries in ELL, the rest in COO
+// ---------------------------------------------------------------------------
+__global__ void len_hist_kernel(int32_t nrows, const int32_t *__restrict__ irp, int *__restrict__ hist)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nrows;
+         i += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&hist[irp[i + 1] - irp[i]], 1);
+}
+
+__global__ void hyb_rest_count_kernel(int32_t nrows, const int32_t *__restrict__ irp, int32_t K,
+                                      int32_t *__restrict__ cnt)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nrows;
+         i += (int64_t)gridDim.x * blockDim.x)
+        cnt[i] = max(irp[i + 1] - irp[i] - K, 0);
+}
+
+template <typename T>
+__global__ void hyb_rest_fill_kernel(int32_t nrows, const int32_t *__restrict__ irp,
+                                     const int32_t *__restrict__ aj, const T *__restrict__ av, int32_t K,
+                                     const int32_t *__restrict__ off, int32_t *__restrict__ ri,
+                                     int32_t *__restrict__ rj, T *__restrict__ rv)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nrows;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t b = irp[i], e = irp[i + 1];
+        int32_t q = off[i];
+        for (int32_t k = b + K; k < e; ++k, ++q) {
+            ri[q] = (int32_t)i;
+            rj[q] = aj[k];
+            rv[q] = av[k];
+        }
+    }
+}
+
+mxs_status hyb_size(const mxs_mat_s *A, int32_t *K, int64_t *rest, hipStream_t s)
+{
+    const int32_t n = A->nrows;
+    const int32_t *irp;
+    int32_t *tmp;
+    mxs_status st = source_irp(A, &irp, &tmp, s);
+    int32_t maxlen = 0;
+    if (st == MXS_OK) st = longest_row(n, irp, &maxlen, s);
+    if (st == MXS_OK && *K < 0) {
+        // width rule: the largest k with at least max(4096, n/3) rows (all
+        // rows when fewer) holding k or more entries
+        int *hist = nullptr;
+        std::vector<int> h((size_t)maxlen + 1, 0);
+        if (hipMallocAsync((void **)&hist, sizeof(int) * ((size_t)maxlen + 1), s) != hipSuccess)
+            st = MXS_ERR_OUT_OF_MEMORY;
+        if (st == MXS_OK) st = fill_bytes0(hist, sizeof(int) * ((size_t)maxlen + 1), s);
+        if (st == MXS_OK && n > 0) {
+            len_hist_kernel<<<grid_of(n, 4096), 256, 0, s>>>(n, irp, hist);
+            st = launch_status();
+        }
+        if (st == MXS_OK &&
+            hipMemcpyAsync(h.data(), hist, sizeof(int) * h.size(), hipMemcpyDeviceToHost, s) != hipSuccess)
+            st = MXS_ERR_HIP;
+        if (hist) (void)hipFreeAsync(hist, s);
+        if (st == MXS_OK && hipStreamSynchronize(s) != hipSuccess) st = MXS_ERR_HIP;
+        const int64_t need = std::min<int64_t>(n, std::max<int64_t>(4096, n / 3));
+        int64_t ge = 0;
+        int32_t k = 0;
+        for (int32_t l = maxlen; l >= 1 && st == MXS_OK; --l) {
+            ge += h[l];
+            if (ge >= need && ge > 0) {
+                k = l;
+                break;
+            }
+        }
+        *K = k;
+    }
+    int64_t r = 0;
+    if (st == MXS_OK && n > 0) {
+        // entries past the K-th of their row: sum of max(len - K, 0)
+        int32_t *cnt = nullptr, *off = nullptr;
+        if (hipMallocAsync((void **)&cnt, sizeof(int32_t) * ((size_t)n + 1) * 2, s) != hipSuccess)
+            st = MXS_ERR_OUT_OF_MEMORY;
+        off = cnt ? cnt + n + 1 : nullptr;
+        if (st == MXS_OK) {
+            hyb_rest_count_kernel<<<grid_of(n, 65536), 256, 0, s>>>(n, irp, *K, cnt);
+            st = launch_status();
+        }
+        if (st == MXS_OK) st = scan_i32(cnt, off, n, s);
+        int32_t h = 0;
+        if (st == MXS_OK && hipMemcpyAsync(&h, off + n, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess)
+            st = MXS_ERR_HIP;
+        if (cnt) (void)hipFreeAsync(cnt, s);
+        if (st == MXS_OK && hipStreamSynchronize(s) != hipSuccess) st = MXS_ERR_HIP;
+        r = h;
+    }
+    if (tmp) (void)hipFreeAsync(tmp, s);
+    if (hipStreamSynchronize(s) != hipSuccess && st == MXS_OK) st = MXS_ERR_HIP;
+    if (st != MXS_OK) return st;
+    if ((int64_t)*K * n > 8 * A->nnz) return MXS_ERR_DIA_TOO_SPARSE;
+    *rest = r;
+    return MXS_OK;
+}
+
+mxs_status hyb_build(const mxs_mat_s *A, int32_t K, int32_t *ell_col, void *ell_val, int32_t *ri,
+                     int32_t *rj, void *rv, hipStream_t s)
+{
+    const int32_t n = A->nrows;
+    if (n == 0) return MXS_OK;
+    const int32_t *irp;
+    int32_t *tmp;
+    mxs_status st = source_irp(A, &irp, &tmp, s);
+    if (st == MXS_OK && K > 0) {
+        // ell_fill keeps each row's first K entries
+        if (A->dtype == MXS_F64)
+            ell_fill_kernel<double><<<grid_of(n, 65536), 256, 0, s>>>(n, K, irp, A->idx1,
+                                                                      (const double *)A->vals,
+                                                                      ell_col, (double *)ell_val);
+        else
+            ell_fill_kernel<float><<<grid_of(n, 65536), 256, 0, s>>>(n, K, irp, A->idx1,
+                                                                     (const float *)A->vals,
+                                                                     ell_col, (float *)ell_val);
+        st = launch_status();
+    }
+    int32_t *cnt = nullptr;
+    if (st == MXS_OK && hipMallocAsync((void **)&cnt, sizeof(int32_t) * ((size_t)n + 1) * 2, s) != hipSuccess)
+        st = MXS_ERR_OUT_OF_MEMORY;
+    int32_t *off = cnt ? cnt + n + 1 : nullptr;
+    if (st == MXS_OK) {
+        hyb_rest_count_kernel<<<grid_of(n, 65536), 256, 0, s>>>(n, irp, K, cnt);
+        st = launch_status();
+    }
+    if (st == MXS_OK) st = scan_i32(cnt, off, n, s);
+    if (st == MXS_OK) {
+        if (A->dtype == MXS_F64)
+            hyb_rest_fill_kernel<double><<<grid_of(n, 65536), 256, 0, s>>>(
+                n, irp, A->idx1, (const double *)A->vals, K, off, ri, rj, (double *)rv);
+        else
+            hyb_rest_fill_kernel<float><<<grid_of(n, 65536), 256, 0, s>>>(
+                n, irp, A->idx1, (const float *)A->vals, K, off, ri, rj, (float *)rv);
+        st = launch_status();
+    }
+    if (cnt) (void)hipFreeAsync(cnt, s);
     if (tmp) (void)hipFreeAsync(tmp, s);
     return st;
 }

@@ -1082,7 +1082,7 @@ static uint32_t fixup_grid(int64_t ntiles) { return (uint32_t)std::max<int64_t>(
 
 int64_t spmv_dot_parts(const mxs_mat_s *A)
 {
-    if (A->fmt == MXS_COO || A->fmt == MXS_HDC) return kDotGridMax;
+    if (A->fmt == MXS_COO || is_split(A)) return kDotGridMax;
     if (A->fmt == MXS_CSR && A->csr.ell) return ell_grid(A->nrows, true);
     if (A->fmt == MXS_CSR && A->csr.rowwise) return rowwise_grid(A->nrows);
     if (A->fmt == MXS_ELL || A->fmt == MXS_SELL) return padded_grid(A, true);
@@ -1412,7 +1412,7 @@ mxs_status build_plan(mxs_mat_s *A, hipStream_t s)
 {
     if (A->optimized) return MXS_OK;
     mxs_status st = MXS_OK;
-    if (A->fmt == MXS_HDC) {
+    if (is_split(A)) {
         st = build_plan(A->band, s);
         if (st == MXS_OK) st = build_plan(A->rest, s);
     } else if (A->fmt == MXS_CSR) {
@@ -1423,7 +1423,7 @@ mxs_status build_plan(mxs_mat_s *A, hipStream_t s)
         st = build_coo_plan(A, s);
     }
     if (st == MXS_OK) {
-        if (A->fmt != MXS_HDC) set_impl(A, default_impl(A));
+        if (!is_split(A)) set_impl(A, default_impl(A));
         A->optimized = true;
     }
     return st;
@@ -1587,8 +1587,8 @@ mxs_status spmv_acc_launch(const mxs_mat_s *A, const void *x, void *y, const int
 mxs_status spmv_launch(const mxs_mat_s *A, const void *x, void *y, const int *done,
                        const DotSink *dot, hipStream_t s)
 {
-    if (A->fmt == MXS_HDC) {
-        // the band writes every row; the remainder adds onto it
+    if (is_split(A)) {
+        // the band (DIA) or ELL part writes every row; the remainder adds onto it
         mxs_status st = spmv_launch(A->band, x, y, done, nullptr, s);
         if (st == MXS_OK && A->rest->nnz > 0) st = spmv_acc_launch(A->rest, x, y, done, s);
         if (st == MXS_OK && dot) st = dot_sigma_launch(A->nrows, A->dtype, y, x, done, dot, s);
