@@ -175,7 +175,7 @@ def other_formats(torch, mxs, coo, x, y, label):
     median of 10 x 100 calls, GB/s of algorithmic bytes, stored slots."""
     out = {}
     for name, make in (("ell", lambda: coo.convert("ell")), ("sell_sigma1", lambda: coo.to_sell(1)),
-                       ("sell_sigma4096", lambda: coo.to_sell(4096))):
+                       ("sell_sigma4096", lambda: coo.to_sell(4096)), ("hyb", lambda: coo.to_hyb())):
         try:
             B = make()
         except mxs.MxsError as e:
@@ -185,7 +185,10 @@ def other_formats(torch, mxs, coo, x, y, label):
             continue
         tc = time_calls(torch, lambda: mxs.spmv(B, x, y))
         nb = padded_bytes(B, coo.nnz)
-        slots = B.ndiag * B.nrows if name == "ell" else int(B._slots)
+        if name == "hyb":
+            nb += 4 * B._keep[2].numel()   # the remainder's row ids
+        slots = (B.ndiag * B.nrows + (B._keep[2].numel() if name == "hyb" else 0)
+                 if name in ("ell", "hyb") else int(B._slots))
         med = tc["median_ms"] * 1e-3
         out[name] = {"us_per_call": round(med * 1e6, 2), "algorithmic_bytes": nb,
                      "GBps": round(nb / med / 1e9, 1), "frac_of_peak": round(nb / med / 1e9 / PEAK_HBM_GBS, 4),

@@ -2,7 +2,7 @@
 
 * 128^3 stencil (2,097,152 rows, 55,742,968 entries): the device-built
   matrix equals the host generator's bit for bit; SpMV in every format
-  (COO, CSR, DIA, ELL, SELL-64-4096)
+  (COO, CSR, DIA, ELL, SELL-64-4096, HYB)
   within 1e-12 of the oracle over the whole vector; CG to 1e-9 in every
   format against the oracle's stored run (iterations within 2, sampled x).
 * Zipf and banded, 4,000,000 rows: SpMV in every accepted format against the
@@ -39,9 +39,10 @@ def to_dev(a):
 
 def formats_of(mxs, A):
     out = {"coo": A}
-    for f in ("csr", "dia", "ell", "sell"):
+    for f in ("csr", "dia", "ell", "sell", "hyb"):
         try:
-            out[f] = A.to_sell(4096) if f == "sell" else A.convert(f)
+            out[f] = (A.to_sell(4096) if f == "sell" else A.to_hyb() if f == "hyb" else
+                      A.convert(f))
         except mxs.MxsError as e:
             if e.status != -5:
                 raise
@@ -117,7 +118,7 @@ def test_irregular_4M_spmv_sampled_rows(gpu, family):
     A = gpu.Matrix.coo(a.nrows, a.ncols, a.ai, a.aj, a.av)
     mats = formats_of(gpu, A)
     assert ("dia" in mats) == (family == "banded") and ("ell" in mats) == (family == "banded")
-    assert "sell" in mats
+    assert "sell" in mats and "hyb" in mats
     xd = to_dev(x)
     for fmt, B in mats.items():
         y = gpu.spmv(B, xd).cpu().numpy()
