@@ -93,6 +93,20 @@ def test_calls_reject_null_handles_and_bad_enums(lib):
     assert lib.mxs_optimize(None, None) == -1
     assert lib.mxs_impl_count(None) == 0
     assert lib.mxs_split_parts(None, None, None) == -1
+    assert lib.mxs_sell_size(None, 1, None, None, None) == -1
+    assert lib.mxs_to_sell(None, 1, FAKE, FAKE, FAKE, FAKE, FAKE, None) == -1
+    assert lib.mxs_hyb_size(None, -1, None, None, None) == -1
+    assert lib.mxs_to_hyb(None, -1, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, None) == -1
+    assert lib.mxs_mg_create(8, 2, None, None) == -1          # no output pointer
+    assert lib.mxs_mg_create(6, 3, FAKE, None) == -1          # 6 not divisible by 4
+    assert lib.mxs_mg_create(8, 13, FAKE, None) == -1
+    assert lib.mxs_mg_create(2048, 1, FAKE, None) == -10      # rows beyond int32
+    assert lib.mxs_mg_destroy(None) == 0
+    assert lib.mxs_mg_level(None, 0, None, None) == -1
+    assert lib.mxs_symgs(None, 0, FAKE, FAKE, None) == -1
+    assert lib.mxs_mg_apply(None, FAKE, FAKE, None) == -1
+    assert lib.mxs_pcg_workspace_size(None, FAKE) == -1
+    assert lib.mxs_pcg_solve(None, None, FAKE, FAKE, FAKE, FAKE, FAKE, 8, None) == -1
     assert lib.mxs_set_impl(None, 0, None) == -1
     assert lib.mxs_get_impl(None, FAKE, None) == -1
     assert lib.mxs_tune(None, FAKE, FAKE, 5, None, None, None) == -1
