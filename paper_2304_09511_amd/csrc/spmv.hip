@@ -1137,7 +1137,11 @@ static mxs_status build_csr_plan(mxs_mat_s *A, hipStream_t s)
     if (K > 0 && (double)K * A->nrows <= 1.05 * (double)A->nnz) {
         const size_t slots = (size_t)K * A->nrows;
         void *buf = nullptr;
-        MXS_HIP(hipMalloc(&buf, slots * (sizeof(int32_t) + dsize(A->dtype))));
+        // the copy is optional: without memory for it, the entry tiles run
+        if (hipMalloc(&buf, slots * (sizeof(int32_t) + dsize(A->dtype))) != hipSuccess) {
+            (void)hipGetLastError();
+            return MXS_OK;
+        }
         A->owned.push_back(buf);
         int32_t *col = (int32_t *)buf;
         void *val = (char *)buf + slots * sizeof(int32_t);
@@ -1200,17 +1204,24 @@ static mxs_status build_dia_plan(mxs_mat_s *A, hipStream_t s)
         const int64_t nb = dia_blocks(A);
         const size_t elems = (size_t)nb * nd * R;
         void *blk = nullptr;
-        MXS_HIP(hipMalloc(&blk, elems * dsize(A->dtype)));
-        A->owned.push_back(blk);
-        const uint32_t g = (uint32_t)std::min<int64_t>(((int64_t)elems + 255) / 256, 65536);
-        if (A->dtype == MXS_F64)
-            dia_block_copy_kernel<double><<<g, 256, 0, s>>>((const double *)A->vals, A->nrows, nd, R,
-                                                            (int64_t)elems, (double *)blk);
-        else
-            dia_block_copy_kernel<float><<<g, 256, 0, s>>>((const float *)A->vals, A->nrows, nd, R,
-                                                           (int64_t)elems, (float *)blk);
-        MXS_HIP(hipGetLastError());
-        A->dia.blk = blk;
+        // the copy is optional: without memory for it, the diagonal-major
+        // values are read
+        if (hipMalloc(&blk, elems * dsize(A->dtype)) != hipSuccess) {
+            (void)hipGetLastError();
+            blk = nullptr;
+        }
+        if (blk) {
+            A->owned.push_back(blk);
+            const uint32_t g = (uint32_t)std::min<int64_t>(((int64_t)elems + 255) / 256, 65536);
+            if (A->dtype == MXS_F64)
+                dia_block_copy_kernel<double><<<g, 256, 0, s>>>((const double *)A->vals, A->nrows, nd, R,
+                                                                (int64_t)elems, (double *)blk);
+            else
+                dia_block_copy_kernel<float><<<g, 256, 0, s>>>((const float *)A->vals, A->nrows, nd, R,
+                                                               (int64_t)elems, (float *)blk);
+            MXS_HIP(hipGetLastError());
+            A->dia.blk = blk;
+        }
     }
 #endif
     const int64_t nruns = (int64_t)runs.size() / 3;
