@@ -91,8 +91,8 @@ def test_split_matches_definition_and_oracle(gpu, name, a, src, min_fill, rest):
     if rest == "coo":
         assert np.array_equal(i0, rai)
     else:
-        assert np.array_equal(i0, orc.coo_to_csr(a.nrows, rai)[0] if False else
-                              np.concatenate([[0], np.cumsum(np.bincount(rai, minlength=a.nrows))]))
+        rows_ptr = np.concatenate([[0], np.cumsum(np.bincount(rai, minlength=a.nrows))])
+        assert np.array_equal(i0, rows_ptr)
     assert np.array_equal(i1, raj) and np.array_equal(vals, rav)
     x = wl.uniform_vector(a.ncols, seed=5)
     y = to_dev(np.full(a.nrows, np.nan))
@@ -162,8 +162,8 @@ def test_split_unsupported_and_invalid(gpu):
     A = mxs.Matrix.coo(a.nrows, a.ncols, a.ai, a.aj, a.av)
     H = A.split()
     for call in (lambda: H.convert("csr"), lambda: H.cast(mxs.F32), lambda: mxs.features(H),
-                 lambda: H.split(), lambda: A.convert("dia").split() if False else
-                 mxs.Matrix.coo(*_stencil_arrays()).convert("dia").split()):
+                 lambda: H.split(),
+                 lambda: mxs.Matrix.coo(*_stencil_arrays()).convert("dia").split()):
         with pytest.raises(mxs.MxsError) as e:
             call()
         assert e.value.status == -10
