@@ -142,6 +142,8 @@ struct CsrCfg<float> {
 // Per-tile flags of the plan.
 constexpr int kCsrHeadCarry = 1 << 16; // head piece goes to the carry array
 constexpr int kCsrLastCarry = 1 << 17; // last owned row reaches past EXT: tail piece carried
+constexpr int kCsrLongRows = 1 << 18;  // an owned row has more than kLongRow entries
+constexpr int kLongRow = 64;           // longer rows are reduced by a whole wave
 
 // tile_row[t] = first row whose first entry is at position >= t*TILE
 // (lower bound over irp); tile_row[ntiles] = nrows.
@@ -165,7 +167,8 @@ __global__ void csr_tile_rows_kernel(const int32_t *__restrict__ irp, int32_t nr
 }
 
 // tile_info[t]: entries the owner reads past its tile (low 16 bits) and the
-// two carry flags; *any_carry is set when a fix-up pass is needed.
+// two carry flags; *any_carry is set when a fix-up pass is needed.  The
+// long-row flag is added by csr_long_rows_kernel.
 __global__ void csr_tile_info_kernel(const int32_t *__restrict__ irp, const int32_t *__restrict__ tile_row,
                                      int64_t nnz, int64_t ntiles, int tile, int ext,
                                      int32_t *__restrict__ info, int *__restrict__ any_carry)
@@ -190,6 +193,56 @@ __global__ void csr_tile_info_kernel(const int32_t *__restrict__ irp, const int3
     }
     info[t] = v;
     if (v & kCsrLastCarry) atomicOr(any_carry, 1);
+}
+
+// Flags the tiles that own a row longer than kLongRow (a thread per row).
+__global__ void csr_long_rows_kernel(const int32_t *__restrict__ irp, int32_t nrows, int tile,
+                                     int32_t *__restrict__ info)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrows) return;
+    const int32_t b = irp[r];
+    if (irp[r + 1] - b > kLongRow) atomicOr(&info[b / tile], kCsrLongRows);
+}
+
+// Reduces a tile's owned rows [0, nr), whose products (or staged values) sit
+// in LDS: lane groups of G lanes, the largest power of two with G*nr <= NT,
+// take a row each.  With `queue` set, rows of more than kLongRow entries are
+// put on an LDS list instead and then reduced by whole waves, so that one
+// long row does not hold the workgroup for len/G steps while the other lanes
+// wait.  lo(r) / hi(r) give a row's local entry range, part(b, e, lane, g)
+// a lane's partial sum over [b, e) with stride g, put(r, sum) stores the row.
+// A row's summation order depends only on its length and position.
+template <typename T, int NT, int CAP, typename Lo, typename Hi, typename Part, typename Put>
+__device__ __forceinline__ void reduce_tile_rows(int nr, bool queue, int32_t *longq, int *nlong,
+                                                 Lo lo, Hi hi, Part part, Put put)
+{
+    const int tid = threadIdx.x;
+    int G = 64;
+    while (G > 1 && G * nr > NT) G >>= 1;
+    queue = queue && G < kWave;
+    const int lane = tid & (G - 1);
+    for (int r = tid / G; r < nr; r += NT / G) {
+        const int b = lo(r), e = hi(r);
+        if (queue && e - b > kLongRow) {
+            if (lane == 0) longq[min(atomicAdd(nlong, 1), CAP - 1)] = r;
+            continue;
+        }
+        T sum = part(b, e, lane, G);
+        for (int off = G >> 1; off > 0; off >>= 1) sum += __shfl_xor(sum, off, kWave);
+        if (lane == 0) put(r, sum);
+    }
+    if (queue) {
+        __syncthreads();
+        const int nl = min(*nlong, CAP);
+        const int wl = tid & (kWave - 1);
+        for (int q = tid / kWave; q < nl; q += NT / kWave) {
+            const int r = longq[q];
+            T sum = part(lo(r), hi(r), wl, kWave);
+            for (int off = kWave >> 1; off > 0; off >>= 1) sum += __shfl_xor(sum, off, kWave);
+            if (wl == 0) put(r, sum);
+        }
+    }
 }
 
 #ifndef MXS_CSR_TRIM
@@ -236,6 +289,9 @@ __global__ __launch_bounds__(256) MXS_CSR_ATTR void csr_spmv_kernel(
     __shared__ int32_t scol[GX ? TILE + EXT : 1];
     __shared__ int32_t lrp[RMAX + 1];
     __shared__ double red[NT / kWave];
+    constexpr int LCAP = (TILE + EXT) / kLongRow;
+    __shared__ int32_t longq[LCAP];
+    __shared__ int nlong;
     if (done && *done) return;
     const int tid = threadIdx.x;
     const int64_t g = xcd_remap(blockIdx.x, gridDim.x);
@@ -307,6 +363,7 @@ __global__ __launch_bounds__(256) MXS_CSR_ATTR void csr_spmv_kernel(
             if (tid <= nr) lrp[tid] = lr - (int32_t)k0;
             if (tid + NT <= nr) lrp[tid + NT] = lr_hi - (int32_t)k0;
         }
+        if (tid == 0) nlong = 0;
         __syncthreads();
         auto rp = [&](int r) -> int32_t { return staged ? lrp[r] : irp[r_lo + r] - (int32_t)k0; };
         if (head_carry) {
@@ -317,39 +374,37 @@ __global__ __launch_bounds__(256) MXS_CSR_ATTR void csr_spmv_kernel(
             const double tot = block_sum<NT>((double)hs, red);
             if (tid == 0) carry[2 * tile] = (T)tot;
         }
-        // Lane-group size: the largest power of two G <= 64 with G*nr <= NT.
-        int G = 64;
-        while (G > 1 && G * nr > NT) G >>= 1;
-        const int lane = tid & (G - 1);
-        const int ngrp = NT / G;
         const int32_t lim = n + n_ext; // local end of the entries loaded
-        for (int r = tid / G; r < nr; r += ngrp) {
-            T sum = T(0);
-            const int e = min(rp(r + 1), lim);
-            if constexpr (GX) {
-                // U entries per lane per step; lanes past the row's end
-                // re-read its last entry with a zero value
-                constexpr int U = MXS_CSR_GXU;
-                for (int k0l = rp(r) + lane; k0l < e; k0l += U * G) {
-                    int32_t c[U];
-                    T v[U], xg[U];
+        reduce_tile_rows<T, NT, LCAP>(
+            nr, (info & kCsrLongRows) != 0, longq, &nlong, [&](int r) { return rp(r); },
+            [&](int r) { return min(rp(r + 1), lim); },
+            [&](int b, int e, int lane, int G) {
+                T sum = T(0);
+                if constexpr (GX) {
+                    // U entries per lane per step; lanes past the row's end
+                    // re-read its last entry with a zero value
+                    constexpr int U = MXS_CSR_GXU;
+                    for (int k0l = b + lane; k0l < e; k0l += U * G) {
+                        int32_t c[U];
+                        T v[U], xg[U];
 #pragma unroll
-                    for (int u = 0; u < U; ++u) {
-                        const int k = k0l + u * G;
-                        const int kk = min(k, e - 1);
-                        c[u] = scol[kk];
-                        v[u] = k < e ? prod[kk] : T(0);
+                        for (int u = 0; u < U; ++u) {
+                            const int k = k0l + u * G;
+                            const int kk = min(k, e - 1);
+                            c[u] = scol[kk];
+                            v[u] = k < e ? prod[kk] : T(0);
+                        }
+#pragma unroll
+                        for (int u = 0; u < U; ++u) xg[u] = x[(uint32_t)c[u]];
+#pragma unroll
+                        for (int u = 0; u < U; ++u) sum += v[u] * xg[u];
                     }
-#pragma unroll
-                    for (int u = 0; u < U; ++u) xg[u] = x[(uint32_t)c[u]];
-#pragma unroll
-                    for (int u = 0; u < U; ++u) sum += v[u] * xg[u];
+                } else {
+                    for (int k = b + lane; k < e; k += G) sum += prod[k];
                 }
-            } else {
-                for (int k = rp(r) + lane; k < e; k += G) sum += prod[k];
-            }
-            for (int off = G >> 1; off > 0; off >>= 1) sum += __shfl_xor(sum, off, kWave);
-            if (lane == 0) {
+                return sum;
+            },
+            [&](int r, T sum) {
                 if (last_carry && r == nr - 1) {
                     carry[2 * tile + 1] = sum;
                 } else {
@@ -357,8 +412,7 @@ __global__ __launch_bounds__(256) MXS_CSR_ATTR void csr_spmv_kernel(
                     y[r_lo + r] = yv;
                     if (DOT) dpart += (double)yv * (double)x[r_lo + r];
                 }
-            }
-        }
+            });
         __syncthreads();
     }
     if (DOT) {
@@ -877,6 +931,9 @@ __global__ __launch_bounds__(256) void coo_rows_kernel(
     __shared__ int32_t srow[TILE];
     __shared__ int32_t lrp[RM + 1];
     __shared__ double red[NT / kWave];
+    constexpr int LCAP = (TILE + EXT) / kLongRow;
+    __shared__ int32_t longq[LCAP];
+    __shared__ int nlong;
     if (done && *done) return;
     const int tid = threadIdx.x;
     const int64_t g = xcd_remap(blockIdx.x, gridDim.x);
@@ -924,6 +981,7 @@ __global__ __launch_bounds__(256) void coo_rows_kernel(
         }
         // owned rows without a start in the tile are the empty rows at the end
         for (int q = tid; q <= nr; q += NT) lrp[q] = lim;
+        if (tid == 0) nlong = 0;
         __syncthreads();
         for (int j = tid; j < n; j += NT) {
             const int32_t R = srow[j];
@@ -942,21 +1000,18 @@ __global__ __launch_bounds__(256) void coo_rows_kernel(
             const double tot = block_sum<NT>((double)hs, red);
             if (tid == 0) carry[2 * tile] = (T)tot;
         }
-        // lane-group size: the largest power of two G <= 64 with G*nr <= NT
-        int G = 64;
-        while (G > 1 && G * nr > NT) G >>= 1;
-        const int lane = tid & (G - 1);
-        const int ngrp = NT / G;
-        for (int r = tid / G; r < nr; r += ngrp) {
-            T sum = T(0);
-            const int e = min(lrp[r + 1], lim);
-            for (int k = lrp[r] + lane; k < e; k += G) sum += prod[k];
-            for (int off = G >> 1; off > 0; off >>= 1) sum += __shfl_xor(sum, off, kWave);
-            if (lane == 0) {
+        reduce_tile_rows<T, NT, LCAP>(
+            nr, (info & kCsrLongRows) != 0, longq, &nlong, [&](int r) { return lrp[r]; },
+            [&](int r) { return min(lrp[r + 1], lim); },
+            [&](int b, int e, int lane, int G) {
+                T sum = T(0);
+                for (int k = b + lane; k < e; k += G) sum += prod[k];
+                return sum;
+            },
+            [&](int r, T sum) {
                 if (last_carry && r == nr - 1) carry[2 * tile + 1] = sum;
                 else y[r_lo + r] = acc ? y[r_lo + r] + sum : sum;
-            }
-        }
+            });
         __syncthreads();
     }
 }
@@ -1116,6 +1171,9 @@ static mxs_status build_csr_plan(mxs_mat_s *A, hipStream_t s)
     const int ext = A->dtype == MXS_F64 ? CsrCfg<double>::EXT : CsrCfg<float>::EXT;
     csr_tile_rows_kernel<<<g, 256, 0, s>>>(A->idx0, A->nrows, nt, tile, tile_row);
     csr_tile_info_kernel<<<g, 256, 0, s>>>(A->idx0, tile_row, A->nnz, nt, tile, ext, info, flag);
+    if (A->nrows > 0)
+        csr_long_rows_kernel<<<(uint32_t)(((int64_t)A->nrows + 255) / 256), 256, 0, s>>>(
+            A->idx0, A->nrows, tile, info);
     MXS_HIP(hipGetLastError());
     int any = 0;
     MXS_HIP(hipMemcpyAsync(&any, flag, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -1282,6 +1340,9 @@ static mxs_status build_coo_plan(mxs_mat_s *A, hipStream_t s)
         const int ext = A->dtype == MXS_F64 ? CsrCfg<double>::EXT : CsrCfg<float>::EXT;
         csr_tile_rows_kernel<<<g, 256, 0, s>>>(irp, A->nrows, nt, tile, tile_row);
         csr_tile_info_kernel<<<g, 256, 0, s>>>(irp, tile_row, A->nnz, nt, tile, ext, info, flags);
+        if (A->nrows > 0)
+            csr_long_rows_kernel<<<(uint32_t)(((int64_t)A->nrows + 255) / 256), 256, 0, s>>>(
+                irp, A->nrows, tile, info);
         tile_rows_max_kernel<<<g, 256, 0, s>>>(tile_row, nt, flags + 1);
         st = launch_status();
         if (st == MXS_OK &&

@@ -174,3 +174,105 @@ def test_cg_with_every_impl_matches_oracle(gpu, fmt):
         st, x, res = mxs.cg_solve(A, to_dev(b), rtol=1e-10, maxit=2000)
         assert st == 0 and abs(res["iters"] - it_o) <= 2, (i, res["iters"], it_o)
         assert np.max(np.abs(x.cpu().numpy() - x_o)) <= 1e-8, i
+
+
+def long_rows(seed, ncols=30000, integer=False, dtype=np.float64):
+    """Short rows (0-10 entries) around runs of long rows: 40 rows of 65
+    entries (a tile then owns about 32 long rows), lengths at the wave path's
+    threshold (64, 65, 66) and at the FP64 tile and extension edges (2,047 to
+    2,305), and rows of up to 5,000 entries that span tiles."""
+    g = wl.rng(seed)
+    lens = list(g.integers(0, 11, 300))
+    lens += [65] * 40 + list(g.integers(0, 11, 50))
+    for L in (64, 65, 66, 100, 127, 128, 129, 300, 1000, 2000, 2047, 2048, 2049,
+              2303, 2304, 2305, 2500, 4095, 4096, 4097, 4999, 5000):
+        lens += [int(L)] + list(g.integers(0, 11, int(g.integers(1, 40))))
+    lens += [65, 66, 64, 200] * 20 + list(g.integers(0, 11, 200))
+    L = np.array(lens, np.int64)
+    ai = np.repeat(np.arange(L.size, dtype=np.int32), L)
+    aj = wl._distinct_sorted_columns(g, ai, L, ncols)
+    av = (g.integers(-4, 5, ai.size).astype(np.float64) if integer
+          else g.standard_normal(ai.size)).astype(dtype)
+    if integer:
+        av[av == 0] = 3.0
+    return wl.Coo(L.size, ncols, ai, aj, av)
+
+
+def wave_path_ids(mxs, fmt):
+    """Implementations whose rows go through the tile reduction with the
+    long-row wave path: COO row tiles; CSR entry tiles and staged gather."""
+    return {"coo": [0], "csr": [0, 2]}[fmt]
+
+
+@pytest.mark.parametrize("fmt", ["coo", "csr"])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "int"])
+def test_long_rows_reduced_by_waves(gpu, fmt, dtype):
+    mxs = gpu
+    a = long_rows(5, integer=dtype == "int", dtype=np.float32 if dtype == "f32" else np.float64)
+    print(f"[long rows] {fmt} {dtype} {a.nrows} rows nnz={a.nnz}", flush=True)
+    A = build(mxs, a, fmt)
+    x = (wl.integer_vector(a.ncols, seed=3) if dtype == "int"
+         else wl.uniform_vector(a.ncols, seed=3))
+    if dtype == "f32":
+        x = x.astype(np.float32)
+    ref = orc.coo_spmv(a.nrows, a.ai, a.aj, a.av.astype(np.float64), x.astype(np.float64))
+    for i in wave_path_ids(mxs, fmt):
+        A.impl = i
+        y = to_dev(np.full(a.nrows, np.nan, dtype=x.dtype))
+        mxs.spmv(A, to_dev(x), y)
+        y1 = y.cpu().numpy().astype(np.float64)
+        if dtype == "int":
+            assert np.array_equal(y1, ref), i
+        elif dtype == "f64":
+            assert rel_maxnorm(y1, ref) <= 1e-12, i
+            assert np.all(np.abs(y1 - ref) <= row_bound(a, x, U64) + 1e-300), i
+        else:
+            from _cases import U32
+            a64 = wl.Coo(a.nrows, a.ncols, a.ai, a.aj, a.av.astype(np.float64))
+            assert np.all(np.abs(y1 - ref) <= row_bound(a64, x.astype(np.float64), U32) + 1e-30), i
+        assert np.array_equal(mxs.spmv(A, to_dev(x)).cpu().numpy(), y.cpu().numpy()), i
+
+
+def hub_spd(n=6000, hubs=12, seed=7):
+    """Symmetric, strictly diagonally dominant (hence SPD): a tridiagonal
+    -1 chain plus hub rows coupled with -0.01 to 100-3,000 random columns
+    (and back), diagonal 1 + the row's absolute off-diagonal sum."""
+    g = wl.rng(seed)
+    i = np.arange(n - 1)
+    rows = [i, i + 1]
+    cols = [i + 1, i]
+    vals = [np.full(n - 1, -1.0)] * 2
+    for h in g.choice(n, hubs, replace=False):
+        c = g.choice(n, int(g.integers(100, 3001)), replace=False)
+        c = c[np.abs(c - h) > 1]
+        rows += [np.full(c.size, h), c]
+        cols += [c, np.full(c.size, h)]
+        vals += [np.full(c.size, -0.01)] * 2
+    r, c, v = (np.concatenate(t) for t in (rows, cols, vals))
+    key = r.astype(np.int64) * n + c
+    key, first = np.unique(key, return_index=True)
+    r, c, v = r[first], c[first], v[first]
+    d = 1.0 + np.bincount(r, weights=np.abs(v), minlength=n)
+    r = np.concatenate([r, np.arange(n)])
+    c = np.concatenate([c, np.arange(n)])
+    v = np.concatenate([v, d])
+    o = np.lexsort((c, r))
+    return wl.Coo(n, n, r[o].astype(np.int32), c[o].astype(np.int32), v[o])
+
+
+@pytest.mark.parametrize("fmt", ["coo", "csr"])
+def test_cg_on_long_rows_matches_oracle(gpu, fmt):
+    """The fused SpMV + p.Ap of the tile kernels when hub rows take the wave path."""
+    mxs = gpu
+    a = hub_spd()
+    assert np.bincount(a.ai).max() > 1000
+    # (A 1 = 1 here, so b = A 1 would converge in one step)
+    b = orc.coo_spmv(a.nrows, a.ai, a.aj, a.av, wl.uniform_vector(a.ncols, seed=2))
+    st_o, x_o, it_o, _, _ = orc.cg(a.nrows, a.ai, a.aj, a.av, b, tol=1e-10, maxit=5000)
+    assert st_o == 0
+    A = build(mxs, a, fmt)
+    for i in wave_path_ids(mxs, fmt):
+        A.impl = i
+        st, x, res = mxs.cg_solve(A, to_dev(b), rtol=1e-10, maxit=5000)
+        assert st == 0 and abs(res["iters"] - it_o) <= 2, (i, res["iters"], it_o)
+        assert np.max(np.abs(x.cpu().numpy() - x_o)) <= 1e-8, i
