@@ -236,7 +236,9 @@ mxs_status mxs_tune(mxs_mat A, const void *x, void *y, int32_t reps, int32_t *im
  * cleared first, which is what Algorithms 2 and 3 compute).  Summation
  * order differs from a sequential loop; results are deterministic (no
  * floating-point atomics).  x and y must not overlap (MXS_ERR_INVALID_ARG).
- * Rows without entries get 0. */
+ * Rows without entries get 0.  The plan's carry buffer (partial sums of rows
+ * that span tiles) belongs to the handle: calls on one handle issued to
+ * different streams must not overlap; calls on one stream are ordered. */
 mxs_status mxs_spmv(mxs_mat A, const void *x, void *y, void *stream);
 
 /* Dot product a.b of n values of `dtype`, accumulated in FP64, written to
