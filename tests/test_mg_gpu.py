@@ -73,7 +73,8 @@ def test_symgs_on_a_coarse_level(gpu):
     M.close()
 
 
-@pytest.mark.parametrize("n,L", [(2, 2), (8, 2), (8, 4), (16, 3), (16, 4), (32, 4)])
+@pytest.mark.parametrize("n,L", [(2, 2), (8, 2), (8, 4), (16, 3), (16, 4), (32, 4), (40, 3),
+                                 (64, 3), (64, 4)])
 def test_vcycle_matches_oracle(gpu, n, L):
     print(f"[vcycle] n={n} L={L}", flush=True)
     M = gpu.Multigrid(n, L)
