@@ -208,12 +208,20 @@ mxs_status mxs_optimize(mxs_mat A, void *stream);
  *        2: entry tiles, columns and values staged in LDS, x gathered per
  *           row   3: a lane per row over an ELL copy made by mxs_optimize
  *           (applicable when that copy adds at most 5% slots)
+ *        4: column blocks: mxs_optimize splits the entries by column range
+ *           into K full-height CSR blocks whose part of x fits one XCD's
+ *           4 MiB L2 (K = ceil(x bytes / 4 MiB), at most 32) and runs them
+ *           in turn, the first writing y and the others adding to it
+ *           (applicable when x is at least 8 MiB and at least half of the
+ *           entries lie half a block or more from the diagonal; the copy
+ *           takes as much memory as the entries plus K row-pointer arrays)
  *   DIA  0: row-blocked values, one x load per run of three consecutive
  *           offsets (needs the row-blocked copy and offsets in such runs)
  *        1: row-blocked values (needs the copy)
  *        2: diagonal-major values as stored (always applicable)
- * After mxs_optimize the default is: COO 0 where applicable, else 1; CSR 3
- * where applicable, else 1 when nrows > 2*nnz, else 0; DIA the lowest
+ * After mxs_optimize the default is: COO 0 where applicable, else 1; CSR 4
+ * where applicable, else 3 where applicable, else 1 when nrows > 2*nnz,
+ * else 0; DIA the lowest
  * applicable id; ELL and SELL have one implementation, 0.
  * mxs_impl_count: number of ids of A's format (0 for split matrices).
  * mxs_set_impl [syncs: builds the plan]: MXS_ERR_UNSUPPORTED for an id that

@@ -414,7 +414,7 @@ class Matrix:
 
     # SpMV implementations of the format (ids as in mxs_set_impl)
     IMPL_NAMES = {COO: ("row_tiles", "segmented"),
-                  CSR: ("entry_tiles", "row_per_thread", "staged_gather", "ell_copy"),
+                  CSR: ("entry_tiles", "row_per_thread", "staged_gather", "ell_copy", "column_blocks"),
                   DIA: ("blocked_shared_x", "blocked", "diagonal_major")}
 
     @property

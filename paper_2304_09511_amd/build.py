@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libmxs.so")
 
-SOURCES = ["api.hip", "spmv.hip", "scan.hip", "convert.hip", "sort.hip", "split.hip", "cg.hip", "mg.hip", "ell.hip", "gen.hip",
+SOURCES = ["api.hip", "spmv.hip", "scan.hip", "convert.hip", "sort.hip", "split.hip", "cg.hip", "mg.hip", "ell.hip", "colblk.hip", "gen.hip",
            "features.hip", "mlp.hip"]
 
 ARCH = os.environ.get("MXS_OFFLOAD_ARCH", "gfx950")

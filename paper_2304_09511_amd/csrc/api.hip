@@ -27,6 +27,17 @@ mxs_status note_hip_error(hipError_t e, const char *where)
     return from_hip(e);
 }
 
+void release(mxs_mat_s *A)
+{
+    if (!A) return;
+    release(A->band);
+    release(A->rest);
+    for (mxs_mat_s *B : A->csr.cblk) release(B);
+    for (void *p : A->owned)
+        if (p) (void)hipFree(p);
+    delete A;
+}
+
 }  // namespace mxs
 
 namespace {
@@ -62,15 +73,6 @@ mxs_status guarded(F &&f)
     }
 }
 
-void release(mxs_mat_s *A)
-{
-    if (!A) return;
-    release(A->band);
-    release(A->rest);
-    for (void *p : A->owned)
-        if (p) (void)hipFree(p);
-    delete A;
-}
 
 // Copies `bytes` from a caller array into memory the handle owns.
 mxs_status own_copy(mxs_mat_s *A, const void *src, size_t bytes, void **dst, hipStream_t s)

@@ -82,6 +82,10 @@ struct DotSink {
 // ---------------------------------------------------------------------------
 // The matrix handle
 // ---------------------------------------------------------------------------
+}  // namespace mxs
+struct mxs_mat_s;
+namespace mxs {
+
 struct CsrPlan {
     int32_t *tile_row = nullptr; // [ntiles+1] first row owned by each tile (sentinel nrows)
     int32_t *tile_info = nullptr; // [ntiles] overflow length and carry flags
@@ -96,6 +100,10 @@ struct CsrPlan {
     int32_t *ell_col = nullptr;
     void *ell_val = nullptr;
     bool ell = false;            // the active implementation reads it
+    // Column blocks (implementation 4, colblk.hip): the entries split by
+    // column range into full-height CSR part handles, run in turn.
+    std::vector<mxs_mat_s *> cblk;
+    bool colblk = false;         // the active implementation runs them
 };
 
 struct DiaPlan {
@@ -382,6 +390,11 @@ int64_t padded_grid(const mxs_mat_s *A, bool dot);
 mxs_status ell_launch(int32_t nrows, int32_t K, const int32_t *col, const void *vals, mxs_dtype t,
                       const void *x, void *y, const int *done, double *parts, hipStream_t s);
 int64_t ell_grid(int32_t nrows, bool dot);
+
+// Frees a handle, its parts and the device memory it owns (api.hip).
+void release(mxs_mat_s *A);
+// colblk.hip: CSR column blocks (built by mxs_optimize when they apply).
+mxs_status colblk_build(mxs_mat_s *A, hipStream_t s);
 
 // mg.hip: HPCG's multigrid preconditioner.
 mxs_status mg_create(int32_t n, int32_t levels, mxs_mg_s **out, hipStream_t s); // syncs

@@ -353,7 +353,9 @@ static mxs_status build_level(mxs_mg_s *M, MgLevel &L, int32_t n, bool vectors, 
 void mg_release(mxs_mg_s *M)
 {
     if (!M) return;
-    for (auto &L : M->lv) delete L.A;
+    // the level operators' arrays belong to the hierarchy; plans that
+    // mxs_optimize or mxs_tune built on them belong to the operators
+    for (auto &L : M->lv) release(L.A);
     for (void *p : M->owned)
         if (p) (void)hipFree(p);
     delete M;

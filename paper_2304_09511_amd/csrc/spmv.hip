@@ -1137,7 +1137,7 @@ static uint32_t fixup_grid(int64_t ntiles) { return (uint32_t)std::max<int64_t>(
 
 int64_t spmv_dot_parts(const mxs_mat_s *A)
 {
-    if (A->fmt == MXS_COO || is_split(A)) return kDotGridMax;
+    if (A->fmt == MXS_COO || is_split(A) || (A->fmt == MXS_CSR && A->csr.colblk)) return kDotGridMax;
     if (A->fmt == MXS_CSR && A->csr.ell) return ell_grid(A->nrows, true);
     if (A->fmt == MXS_CSR && A->csr.rowwise) return rowwise_grid(A->nrows);
     if (A->fmt == MXS_ELL || A->fmt == MXS_SELL) return padded_grid(A, true);
@@ -1190,27 +1190,27 @@ static mxs_status build_csr_plan(mxs_mat_s *A, hipStream_t s)
     // neighbouring rows, and their gathers of x neighbouring addresses
     int32_t K = 0;
     const mxs_status st_w = ell_width(A, &K, s);
-    if (st_w == MXS_ERR_DIA_TOO_SPARSE) return MXS_OK;
-    if (st_w != MXS_OK) return st_w;
-    if (K > 0 && (double)K * A->nrows <= 1.05 * (double)A->nnz) {
+    if (st_w != MXS_OK && st_w != MXS_ERR_DIA_TOO_SPARSE) return st_w;
+    if (st_w == MXS_OK && K > 0 && (double)K * A->nrows <= 1.05 * (double)A->nnz) {
         const size_t slots = (size_t)K * A->nrows;
         void *buf = nullptr;
         // the copy is optional: without memory for it, the entry tiles run
         if (hipMalloc(&buf, slots * (sizeof(int32_t) + dsize(A->dtype))) != hipSuccess) {
             (void)hipGetLastError();
-            return MXS_OK;
+        } else {
+            A->owned.push_back(buf);
+            int32_t *col = (int32_t *)buf;
+            void *val = (char *)buf + slots * sizeof(int32_t);
+            mxs_status st_b = ell_build(A, K, col, val, s);
+            if (st_b != MXS_OK) return st_b;
+            MXS_HIP(hipStreamSynchronize(s));
+            A->csr.ell_k = K;
+            A->csr.ell_col = col;
+            A->csr.ell_val = val;
         }
-        A->owned.push_back(buf);
-        int32_t *col = (int32_t *)buf;
-        void *val = (char *)buf + slots * sizeof(int32_t);
-        mxs_status st_b = ell_build(A, K, col, val, s);
-        if (st_b != MXS_OK) return st_b;
-        MXS_HIP(hipStreamSynchronize(s));
-        A->csr.ell_k = K;
-        A->csr.ell_col = col;
-        A->csr.ell_val = val;
     }
-    return MXS_OK;
+    // column blocks for scattered columns over a large x
+    return colblk_build(A, s);
 }
 
 // Row-blocked copy: out[(b*nd + d)*R + r] = av[d*nrows + b*R + r] (0 past the last row).
@@ -1382,7 +1382,7 @@ static mxs_status build_coo_plan(mxs_mat_s *A, hipStream_t s)
 int32_t impl_count(const mxs_mat_s *A)
 {
     if (A->fmt == MXS_ELL || A->fmt == MXS_SELL) return 1;
-    return A->fmt == MXS_CSR ? 4 : A->fmt == MXS_DIA ? 3 : A->fmt == MXS_COO ? 2 : 0;
+    return A->fmt == MXS_CSR ? 5 : A->fmt == MXS_DIA ? 3 : A->fmt == MXS_COO ? 2 : 0;
 }
 
 bool impl_ok(const mxs_mat_s *A, int32_t impl)
@@ -1391,7 +1391,7 @@ bool impl_ok(const mxs_mat_s *A, int32_t impl)
     if (A->nnz == 0) return true;
     switch (A->fmt) {
     case MXS_COO: return impl == 1 || A->coo.rows_ok;
-    case MXS_CSR: return impl != 3 || A->csr.ell_col != nullptr;
+    case MXS_CSR: return impl == 3 ? A->csr.ell_col != nullptr : impl == 4 ? !A->csr.cblk.empty() : true;
     case MXS_DIA:
         if (impl == 0) return A->dia.blk != nullptr && A->dia.triples;
         if (impl == 1) return A->dia.blk != nullptr;
@@ -1406,7 +1406,8 @@ static int32_t default_impl(const mxs_mat_s *A)
 {
     switch (A->fmt) {
     case MXS_COO: return impl_ok(A, 0) ? 0 : 1;
-    case MXS_CSR: return A->csr.ell_col ? 3 : A->csr.rowwise ? 1 : MXS_CSR_GX_DEFAULT ? 2 : 0;
+    case MXS_CSR:
+        return !A->csr.cblk.empty() ? 4 : A->csr.ell_col ? 3 : A->csr.rowwise ? 1 : MXS_CSR_GX_DEFAULT ? 2 : 0;
     case MXS_DIA: return impl_ok(A, 0) ? 0 : impl_ok(A, 1) ? 1 : 2;
     case MXS_ELL:
     case MXS_SELL: return 0;
@@ -1427,6 +1428,7 @@ void set_impl(mxs_mat_s *A, int32_t impl)
         A->csr.rowwise = impl == 1;
         A->csr.gx = impl == 2;
         A->csr.ell = impl == 3;
+        A->csr.colblk = impl == 4;
         break;
     case MXS_DIA:
         A->dia.use_blk = impl != 2 && A->dia.blk != nullptr;
@@ -1536,6 +1538,16 @@ static mxs_status spmv_typed(const mxs_mat_s *A, const T *x, T *y, const int *do
         if (nt == 0) {
             if (!acc) fill_kernel<T><<<fill_g, 256, 0, s>>>(y, T(0), A->nrows, done);
             MXS_HIP(hipGetLastError());
+            if (dot) return dot_sigma_typed<T>(A->nrows, x, y, done, dot, s);
+            return MXS_OK;
+        }
+        if (A->csr.colblk) {
+            // the first block writes y (unless accumulating), the rest add to it
+            for (size_t b = 0; b < A->csr.cblk.size(); ++b) {
+                const mxs_status st = spmv_typed<T>(A->csr.cblk[b], x, y, done, nullptr, s,
+                                                    acc || b > 0 ? 1 : 0);
+                if (st != MXS_OK) return st;
+            }
             if (dot) return dot_sigma_typed<T>(A->nrows, x, y, done, dot, s);
             return MXS_OK;
         }
