@@ -41,7 +41,7 @@ PEAK_HBM_GBS = 8000.0
 METRIC = "SpMV effective HBM GB/s (% of peak) per format; mixed vs FP64 CG time-to-tol"
 FORMATS = ("coo", "csr", "dia")
 # kernel of each format's implementation (ids as in mxs_set_impl)
-KERNEL_NAMES = {"coo": ("coo_rows_kernel", "coo_spmv_kernel"),
+KERNEL_NAMES = {"coo": ("coo_rows_kernel", "coo_spmv_kernel", "coo_spmv_kernel"),
                 "csr": ("csr_spmv_kernel", "csr_rowwise_kernel", "csr_spmv_kernel", "ell_spmv_kernel",
                         "csr_spmv_kernel"),
                 "dia": ("dia_spmv_kernel",) * 3}

@@ -204,6 +204,7 @@ mxs_status mxs_optimize(mxs_mat A, void *stream);
  *   COO  0: row tiles (the CSR tiling rebuilt from the row ids; applicable
  *           when no tile owns more than 512 rows)
  *        1: segmented-scan tiles (always applicable)
+ *        2: column blocks, as CSR's 4 below, each block a COO matrix
  *   CSR  0: tiles of a fixed number of entries   1: a thread per row
  *        2: entry tiles, columns and values staged in LDS, x gathered per
  *           row   3: a lane per row over an ELL copy made by mxs_optimize
@@ -214,12 +215,14 @@ mxs_status mxs_optimize(mxs_mat A, void *stream);
  *           in turn, the first writing y and the others adding to it
  *           (applicable when x is at least 8 MiB and at least half of the
  *           entries lie half a block or more from the diagonal; the copy
- *           takes as much memory as the entries plus K row-pointer arrays)
+ *           takes as much memory as the entries, plus K row-pointer arrays
+ *           for CSR)
  *   DIA  0: row-blocked values, one x load per run of three consecutive
  *           offsets (needs the row-blocked copy and offsets in such runs)
  *        1: row-blocked values (needs the copy)
  *        2: diagonal-major values as stored (always applicable)
- * After mxs_optimize the default is: COO 0 where applicable, else 1; CSR 4
+ * After mxs_optimize the default is: COO 2 where applicable, else 0 where
+ * applicable, else 1; CSR 4
  * where applicable, else 3 where applicable, else 1 when nrows > 2*nnz,
  * else 0; DIA the lowest
  * applicable id; ELL and SELL have one implementation, 0.

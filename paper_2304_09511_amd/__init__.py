@@ -413,7 +413,7 @@ class Matrix:
         return self
 
     # SpMV implementations of the format (ids as in mxs_set_impl)
-    IMPL_NAMES = {COO: ("row_tiles", "segmented"),
+    IMPL_NAMES = {COO: ("row_tiles", "segmented", "column_blocks"),
                   CSR: ("entry_tiles", "row_per_thread", "staged_gather", "ell_copy", "column_blocks"),
                   DIA: ("blocked_shared_x", "blocked", "diagonal_major")}
 

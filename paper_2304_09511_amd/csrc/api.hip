@@ -32,7 +32,7 @@ void release(mxs_mat_s *A)
     if (!A) return;
     release(A->band);
     release(A->rest);
-    for (mxs_mat_s *B : A->csr.cblk) release(B);
+    for (mxs_mat_s *B : A->cblk) release(B);
     for (void *p : A->owned)
         if (p) (void)hipFree(p);
     delete A;

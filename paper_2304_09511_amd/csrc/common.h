@@ -100,10 +100,6 @@ struct CsrPlan {
     int32_t *ell_col = nullptr;
     void *ell_val = nullptr;
     bool ell = false;            // the active implementation reads it
-    // Column blocks (implementation 4, colblk.hip): the entries split by
-    // column range into full-height CSR part handles, run in turn.
-    std::vector<mxs_mat_s *> cblk;
-    bool colblk = false;         // the active implementation runs them
 };
 
 struct DiaPlan {
@@ -156,6 +152,10 @@ struct mxs_mat_s {
     mxs::CsrPlan csr;
     mxs::CooPlan coo;
     mxs::DiaPlan dia;
+    // COO and CSR column blocks (colblk.hip): the entries split by column
+    // range into full-height part handles of the same format, run in turn
+    std::vector<mxs_mat_s *> cblk;
+    bool colblk = false;       // the active implementation runs them
     mxs_mat_s *band = nullptr; // HDC: the DIA band (owned by this handle)
     mxs_mat_s *rest = nullptr; // HDC: the COO or CSR remainder (owned)
     bool part = false;         // the band or remainder of a split (its parent owns it)
@@ -393,7 +393,7 @@ int64_t ell_grid(int32_t nrows, bool dot);
 
 // Frees a handle, its parts and the device memory it owns (api.hip).
 void release(mxs_mat_s *A);
-// colblk.hip: CSR column blocks (built by mxs_optimize when they apply).
+// colblk.hip: COO and CSR column blocks (built by mxs_optimize when they apply).
 mxs_status colblk_build(mxs_mat_s *A, hipStream_t s);
 
 // mg.hip: HPCG's multigrid preconditioner.

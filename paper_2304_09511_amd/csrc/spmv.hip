@@ -1137,7 +1137,7 @@ static uint32_t fixup_grid(int64_t ntiles) { return (uint32_t)std::max<int64_t>(
 
 int64_t spmv_dot_parts(const mxs_mat_s *A)
 {
-    if (A->fmt == MXS_COO || is_split(A) || (A->fmt == MXS_CSR && A->csr.colblk)) return kDotGridMax;
+    if (A->fmt == MXS_COO || is_split(A) || (A->fmt == MXS_CSR && A->colblk)) return kDotGridMax;
     if (A->fmt == MXS_CSR && A->csr.ell) return ell_grid(A->nrows, true);
     if (A->fmt == MXS_CSR && A->csr.rowwise) return rowwise_grid(A->nrows);
     if (A->fmt == MXS_ELL || A->fmt == MXS_SELL) return padded_grid(A, true);
@@ -1193,14 +1193,15 @@ static mxs_status build_csr_plan(mxs_mat_s *A, hipStream_t s)
     if (st_w != MXS_OK && st_w != MXS_ERR_DIA_TOO_SPARSE) return st_w;
     if (st_w == MXS_OK && K > 0 && (double)K * A->nrows <= 1.05 * (double)A->nnz) {
         const size_t slots = (size_t)K * A->nrows;
+        const size_t vbase = (slots * sizeof(int32_t) + 255) / 256 * 256; // values 256-byte aligned
         void *buf = nullptr;
         // the copy is optional: without memory for it, the entry tiles run
-        if (hipMalloc(&buf, slots * (sizeof(int32_t) + dsize(A->dtype))) != hipSuccess) {
+        if (hipMalloc(&buf, vbase + slots * dsize(A->dtype)) != hipSuccess) {
             (void)hipGetLastError();
         } else {
             A->owned.push_back(buf);
             int32_t *col = (int32_t *)buf;
-            void *val = (char *)buf + slots * sizeof(int32_t);
+            void *val = (char *)buf + vbase;
             mxs_status st_b = ell_build(A, K, col, val, s);
             if (st_b != MXS_OK) return st_b;
             MXS_HIP(hipStreamSynchronize(s));
@@ -1365,24 +1366,26 @@ static mxs_status build_coo_plan(mxs_mat_s *A, hipStream_t s)
     MXS_HIP(hipMalloc(&carry, 2 * (size_t)nc * dsize(A->dtype)));
     A->owned.push_back(carry);
     A->coo.carry_rows = A->coo.carry_seg = carry;
-    return MXS_OK;
+    // column blocks for scattered columns over a large x
+    return colblk_build(A, s);
 }
 
 // ---------------------------------------------------------------------------
 // Implementations of each format's SpMV (no single one wins on every matrix):
 //   COO 0: row tiles (the CSR tiling rebuilt from the row ids)
-//       1: segmented-scan tiles
+//       1: segmented-scan tiles  2: column blocks (colblk.hip)
 //   CSR 0: entry tiles           1: a thread per row
 //       2: entry tiles, x gathered per row from LDS-staged columns
 //       3: a lane per row over an ELL copy made by the plan (rows of
 //          near-equal length: at most 5% padding)
+//       4: column blocks (colblk.hip)
 //   DIA 0: row-blocked values, x shared over runs of three offsets
 //       1: row-blocked values    2: diagonal-major values (no copy), x shared
 // ---------------------------------------------------------------------------
 int32_t impl_count(const mxs_mat_s *A)
 {
     if (A->fmt == MXS_ELL || A->fmt == MXS_SELL) return 1;
-    return A->fmt == MXS_CSR ? 5 : A->fmt == MXS_DIA ? 3 : A->fmt == MXS_COO ? 2 : 0;
+    return A->fmt == MXS_CSR ? 5 : A->fmt == MXS_DIA ? 3 : A->fmt == MXS_COO ? 3 : 0;
 }
 
 bool impl_ok(const mxs_mat_s *A, int32_t impl)
@@ -1390,8 +1393,8 @@ bool impl_ok(const mxs_mat_s *A, int32_t impl)
     if (impl < 0 || impl >= impl_count(A)) return false;
     if (A->nnz == 0) return true;
     switch (A->fmt) {
-    case MXS_COO: return impl == 1 || A->coo.rows_ok;
-    case MXS_CSR: return impl == 3 ? A->csr.ell_col != nullptr : impl == 4 ? !A->csr.cblk.empty() : true;
+    case MXS_COO: return impl == 2 ? !A->cblk.empty() : impl == 1 || A->coo.rows_ok;
+    case MXS_CSR: return impl == 3 ? A->csr.ell_col != nullptr : impl == 4 ? !A->cblk.empty() : true;
     case MXS_DIA:
         if (impl == 0) return A->dia.blk != nullptr && A->dia.triples;
         if (impl == 1) return A->dia.blk != nullptr;
@@ -1405,9 +1408,9 @@ bool impl_ok(const mxs_mat_s *A, int32_t impl)
 static int32_t default_impl(const mxs_mat_s *A)
 {
     switch (A->fmt) {
-    case MXS_COO: return impl_ok(A, 0) ? 0 : 1;
+    case MXS_COO: return !A->cblk.empty() ? 2 : impl_ok(A, 0) ? 0 : 1;
     case MXS_CSR:
-        return !A->csr.cblk.empty() ? 4 : A->csr.ell_col ? 3 : A->csr.rowwise ? 1 : MXS_CSR_GX_DEFAULT ? 2 : 0;
+        return !A->cblk.empty() ? 4 : A->csr.ell_col ? 3 : A->csr.rowwise ? 1 : MXS_CSR_GX_DEFAULT ? 2 : 0;
     case MXS_DIA: return impl_ok(A, 0) ? 0 : impl_ok(A, 1) ? 1 : 2;
     case MXS_ELL:
     case MXS_SELL: return 0;
@@ -1423,12 +1426,13 @@ void set_impl(mxs_mat_s *A, int32_t impl)
         A->coo.rows = impl == 0 && A->coo.rows_ok;
         A->coo.ntiles = A->coo.rows ? A->coo.nt_rows : A->coo.nt_seg;
         A->coo.carry = A->coo.rows ? A->coo.carry_rows : A->coo.carry_seg;
+        A->colblk = impl == 2 && !A->cblk.empty();
         break;
     case MXS_CSR:
         A->csr.rowwise = impl == 1;
         A->csr.gx = impl == 2;
         A->csr.ell = impl == 3;
-        A->csr.colblk = impl == 4;
+        A->colblk = impl == 4 && !A->cblk.empty();
         break;
     case MXS_DIA:
         A->dia.use_blk = impl != 2 && A->dia.blk != nullptr;
@@ -1532,22 +1536,21 @@ static mxs_status spmv_typed(const mxs_mat_s *A, const T *x, T *y, const int *do
     double *parts = dot ? dot->partials : nullptr;
     int64_t nparts = 0;
     const uint32_t fill_g = (uint32_t)std::min<int64_t>((A->nrows + 255) / 256, 4096);
+    if (A->colblk) {
+        // column blocks: the first writes y (unless accumulating), the rest add to it
+        for (size_t b = 0; b < A->cblk.size(); ++b) {
+            const mxs_status st = spmv_typed<T>(A->cblk[b], x, y, done, nullptr, s, acc || b > 0 ? 1 : 0);
+            if (st != MXS_OK) return st;
+        }
+        if (dot) return dot_sigma_typed<T>(A->nrows, x, y, done, dot, s);
+        return MXS_OK;
+    }
     switch (A->fmt) {
     case MXS_CSR: {
         const int64_t nt = A->csr.ntiles;
         if (nt == 0) {
             if (!acc) fill_kernel<T><<<fill_g, 256, 0, s>>>(y, T(0), A->nrows, done);
             MXS_HIP(hipGetLastError());
-            if (dot) return dot_sigma_typed<T>(A->nrows, x, y, done, dot, s);
-            return MXS_OK;
-        }
-        if (A->csr.colblk) {
-            // the first block writes y (unless accumulating), the rest add to it
-            for (size_t b = 0; b < A->csr.cblk.size(); ++b) {
-                const mxs_status st = spmv_typed<T>(A->csr.cblk[b], x, y, done, nullptr, s,
-                                                    acc || b > 0 ? 1 : 0);
-                if (st != MXS_OK) return st;
-            }
             if (dot) return dot_sigma_typed<T>(A->nrows, x, y, done, dot, s);
             return MXS_OK;
         }

@@ -1,6 +1,7 @@
-"""CSR column blocks (implementation 4) against the CPU oracle, through the
-C ABI: matrices whose x exceeds 8 MiB and whose entries mostly lie far from
-the diagonal, where mxs_optimize splits the entries by column range.
+"""Column blocks (COO implementation 2, CSR 4) against the CPU oracle,
+through the C ABI: matrices whose x exceeds 8 MiB and whose entries mostly
+lie far from the diagonal, where mxs_optimize splits the entries by column
+range.
 
 Bars as for SpMV: FP64 within 1e-12 relative max-norm of the oracle and
 within the per-row rounding bound; FP32 within the FP32 bound; integer data
@@ -15,7 +16,7 @@ from _cases import U32, U64, rel_maxnorm, row_bound
 
 pytestmark = pytest.mark.gpu
 UNSUPPORTED = -10
-COLBLK = 4
+COLBLK = {"csr": 4, "coo": 2}
 
 
 def to_dev(a):
@@ -38,8 +39,9 @@ def fixed_rows(nrows, ncols, k, seed, lo=0, hi=None, integer=False, dtype=np.flo
     return wl.Coo(nrows, ncols, ai, aj, av.astype(dtype))
 
 
-def csr_of(mxs, a):
-    return mxs.Matrix.coo(a.nrows, a.ncols, a.ai, a.aj, a.av).convert("csr").optimize()
+def build(mxs, a, fmt):
+    A = mxs.Matrix.coo(a.nrows, a.ncols, a.ai, a.aj, a.av)
+    return (A.convert("csr") if fmt == "csr" else A).optimize()
 
 
 CASES = {
@@ -49,6 +51,8 @@ CASES = {
     "uniform_1.5M": lambda: fixed_rows(1_500_000, 1_500_000, 6, seed=22),
     # wide: 300,000 rows, x 24 MB (6 blocks)
     "wide_300k_x_3M": lambda: fixed_rows(300_000, 3_000_000, 12, seed=23),
+    # x 160 MB: the block count is capped at 32 (5 MB of x per block)
+    "very_wide_100k_x_20M": lambda: fixed_rows(100_000, 20_000_000, 8, seed=30),
     # columns only in the first half: the last two of four blocks are empty
     "left_half_2M": lambda: fixed_rows(2_000_000, 2_000_000, 4, seed=24, hi=1_000_000),
     # columns only in the second half: the first block (which writes y) is empty
@@ -56,13 +60,14 @@ CASES = {
 }
 
 
+@pytest.mark.parametrize("fmt", ["csr", "coo"])
 @pytest.mark.parametrize("name", list(CASES))
-def test_column_blocks_match_oracle(gpu, name):
+def test_column_blocks_match_oracle(gpu, name, fmt):
     mxs = gpu
     a = CASES[name]()
-    print(f"[colblk] {name} {a.nrows}x{a.ncols} nnz={a.nnz}", flush=True)
-    C = csr_of(mxs, a)
-    assert C.impl == COLBLK     # the default where it applies
+    print(f"[colblk] {name} {fmt} {a.nrows}x{a.ncols} nnz={a.nnz}", flush=True)
+    C = build(mxs, a, fmt)
+    assert C.impl == COLBLK[fmt]     # the default where it applies
     x = wl.uniform_vector(a.ncols, seed=1)
     xd = to_dev(x)
     ref = orc.coo_spmv(a.nrows, a.ai, a.aj, a.av, x)
@@ -74,7 +79,7 @@ def test_column_blocks_match_oracle(gpu, name):
     assert np.array_equal(mxs.spmv(C, xd).cpu().numpy(), y1)
     # every other implementation on the same handle agrees with the oracle
     for i in range(C.impl_count()):
-        if i == COLBLK:
+        if i == COLBLK[fmt]:
             continue
         try:
             C.impl = i
@@ -85,24 +90,26 @@ def test_column_blocks_match_oracle(gpu, name):
     C.close()
 
 
-def test_column_blocks_integer_data_bit_exact(gpu):
+@pytest.mark.parametrize("fmt", ["csr", "coo"])
+def test_column_blocks_integer_data_bit_exact(gpu, fmt):
     mxs = gpu
     a = fixed_rows(1_200_000, 1_200_000, 9, seed=26, integer=True)
-    C = csr_of(mxs, a)
-    assert C.impl == COLBLK
+    C = build(mxs, a, fmt)
+    assert C.impl == COLBLK[fmt]
     x = wl.integer_vector(a.ncols, seed=3)
     ref = orc.coo_spmv(a.nrows, a.ai, a.aj, a.av, x)
     assert np.array_equal(mxs.spmv(C, to_dev(x)).cpu().numpy(), ref)
     C.close()
 
 
-def test_column_blocks_fp32(gpu):
+@pytest.mark.parametrize("fmt", ["csr", "coo"])
+def test_column_blocks_fp32(gpu, fmt):
     """FP32 values and x: 2.2M columns make an 8.8 MB x again (3 blocks)."""
     mxs = gpu
     a = fixed_rows(2_200_000, 2_200_000, 5, seed=27)
     a32 = wl.Coo(a.nrows, a.ncols, a.ai, a.aj, a.av.astype(np.float32))
-    C = mxs.Matrix.coo(a.nrows, a.ncols, a32.ai, a32.aj, a32.av).convert("csr").optimize()
-    assert C.impl == COLBLK
+    C = build(mxs, a32, fmt)
+    assert C.impl == COLBLK[fmt]
     x = wl.uniform_vector(a.ncols, seed=2).astype(np.float32)
     y = mxs.spmv(C, to_dev(x)).cpu().numpy().astype(np.float64)
     a64 = wl.Coo(a.nrows, a.ncols, a.ai, a.aj, a32.av.astype(np.float64))
@@ -111,28 +118,30 @@ def test_column_blocks_fp32(gpu):
     C.close()
 
 
-def test_column_blocks_not_built_where_they_do_not_apply(gpu):
-    """Near-diagonal entries (banded) or an x below 8 MiB: no blocks, id 4
-    refused, defaults as before."""
+@pytest.mark.parametrize("fmt", ["csr", "coo"])
+def test_column_blocks_not_built_where_they_do_not_apply(gpu, fmt):
+    """Near-diagonal entries (banded) or an x below 8 MiB: no blocks, their
+    id refused, defaults as before."""
     mxs = gpu
     for a in (wl.banded(1_500_000, ndiag=11, max_offset=2000, seed=3),
               fixed_rows(900_000, 900_000, 6, seed=28)):
-        C = csr_of(mxs, a)
-        assert C.impl != COLBLK
+        C = build(mxs, a, fmt)
+        assert C.impl != COLBLK[fmt]
         with pytest.raises(mxs.MxsError) as e:
-            C.impl = COLBLK
+            C.impl = COLBLK[fmt]
         assert e.value.status == UNSUPPORTED
         C.close()
 
 
-def test_column_blocks_tune(gpu):
+@pytest.mark.parametrize("fmt", ["csr", "coo"])
+def test_column_blocks_tune(gpu, fmt):
     mxs = gpu
     a = CASES["uniform_1.5M"]()
-    C = csr_of(mxs, a)
+    C = build(mxs, a, fmt)
     x = wl.uniform_vector(a.ncols, seed=4)
     y = to_dev(np.full(a.nrows, np.nan))
     best, ms = C.tune(to_dev(x), y, reps=5)
-    assert len(ms) == 5 and ms[COLBLK] is not None and ms[COLBLK] > 0
+    assert len(ms) == C.impl_count() and ms[COLBLK[fmt]] is not None and ms[COLBLK[fmt]] > 0
     assert best == min((m, i) for i, m in enumerate(ms) if m is not None)[1]
     ref = orc.coo_spmv(a.nrows, a.ai, a.aj, a.av, x)
     assert rel_maxnorm(y.cpu().numpy(), ref) <= 1e-12
@@ -164,12 +173,13 @@ def scattered_spd(n, k=2, seed=29):
     return wl.Coo(n, n, r[o].astype(np.int32), c[o].astype(np.int32), v[o])
 
 
-def test_cg_with_column_blocks_matches_oracle(gpu):
+@pytest.mark.parametrize("fmt", ["csr", "coo"])
+def test_cg_with_column_blocks_matches_oracle(gpu, fmt):
     """The SpMV + p.Ap of the blocks inside CG (x 9.6 MB: 3 blocks)."""
     mxs = gpu
     a = scattered_spd(1_200_000)
-    C = csr_of(mxs, a)
-    assert C.impl == COLBLK
+    C = build(mxs, a, fmt)
+    assert C.impl == COLBLK[fmt]
     b = orc.coo_spmv(a.nrows, a.ai, a.aj, a.av, wl.uniform_vector(a.ncols, seed=5))
     st_o, x_o, it_o, _, _ = orc.cg(a.nrows, a.ai, a.aj, a.av, b, tol=1e-10, maxit=2000)
     st, x, res = mxs.cg_solve(C, to_dev(b), rtol=1e-10, maxit=2000)
