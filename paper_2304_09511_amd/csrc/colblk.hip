@@ -77,7 +77,7 @@ __global__ void colblk_fill_kernel(const int32_t *__restrict__ irp, const int32_
             const int32_t bk = aj[k] / cb;
             if (bk != b) {
                 b = bk;
-                dst = boff[b] + bip[(int64_t)b * (nrows + 1) + r];
+                dst = boff[b] + bip[(int64_t)b * ((int64_t)nrows + 1) + r];
             }
             if (oi) oi[dst] = (int32_t)r;
             oj[dst] = aj[k];
