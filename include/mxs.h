@@ -214,7 +214,8 @@ mxs_status mxs_optimize(mxs_mat A, void *stream);
  *           4 MiB L2 (K = ceil(x bytes / 4 MiB), at most 32) and runs them
  *           in turn, the first writing y and the others adding to it
  *           (applicable when x is at least 8 MiB and at least half of the
- *           entries lie half a block or more from the diagonal; the copy
+ *           entries lie half a block or more from the diagonal and read x
+ *           from another 128-byte line than the row's previous entry; the copy
  *           takes as much memory as the entries, plus K row-pointer arrays
  *           for CSR)
  *   DIA  0: row-blocked values, one x load per run of three consecutive

@@ -22,15 +22,26 @@ constexpr int64_t kColBlkX = 4ll << 20;     // bytes of x per block (one XCD's L
 constexpr int64_t kColBlkMinX = 8ll << 20;  // x smaller than this: no blocks
 constexpr int kColBlkMax = 32;
 
-// Entries with |j - i| >= half (half a block's width), summed into *far.
+// Scattered entries, summed into *far: |j - i| >= half (half a block's
+// width) and x[j] in another 128-byte line than the row's previous entry's
+// x (lpl columns per line).  Entries that share lines (dense sub-blocks,
+// say) gather cheaply however far they lie, and blocks would only add
+// passes over y.
 __global__ void colblk_far_kernel(const int32_t *__restrict__ irp, const int32_t *__restrict__ aj,
-                                  int32_t nrows, int64_t half, unsigned long long *__restrict__ far)
+                                  int32_t nrows, int64_t half, int32_t lpl,
+                                  unsigned long long *__restrict__ far)
 {
     __shared__ unsigned long long red[256 / kWave];
     unsigned long long c = 0;
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nrows;
-         r += (int64_t)gridDim.x * blockDim.x)
-        for (int32_t k = irp[r]; k < irp[r + 1]; ++k) c += (uint64_t)(aj[k] - r >= half || r - aj[k] >= half);
+         r += (int64_t)gridDim.x * blockDim.x) {
+        int32_t prev_line = -1;
+        for (int32_t k = irp[r]; k < irp[r + 1]; ++k) {
+            const int32_t line = aj[k] / lpl;
+            c += (uint64_t)((aj[k] - r >= half || r - aj[k] >= half) && line != prev_line);
+            prev_line = line;
+        }
+    }
     for (int off = kWave / 2; off > 0; off >>= 1) c += __shfl_xor(c, off, kWave);
     if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = c;
     __syncthreads();
@@ -90,8 +101,7 @@ __global__ void colblk_fill_kernel(const int32_t *__restrict__ irp, const int32_
 static uint32_t row_grid(int32_t nrows) { return (uint32_t)std::clamp<int64_t>(((int64_t)nrows + 255) / 256, 1, 16384); }
 
 // Builds the blocks of COO or CSR matrix A when x exceeds kColBlkMinX bytes
-// and at least half of the entries lie half a block or more from the
-// diagonal.  Optional: without memory for the copy the matrix keeps its
+// and at least half of the entries are scattered (colblk_far_kernel).  Optional: without memory for the copy the matrix keeps its
 // other implementations.  The blocks are part handles owned by A.
 static mxs_status colblk_make(mxs_mat_s *A, const int32_t *irp, hipStream_t s)
 {
@@ -105,7 +115,8 @@ static mxs_status colblk_make(mxs_mat_s *A, const int32_t *irp, hipStream_t s)
     MXS_HIP(hipMallocAsync((void **)&far, sizeof(unsigned long long), s));
     mxs_status st = fill_bytes0(far, sizeof(unsigned long long), s);
     if (st == MXS_OK) {
-        colblk_far_kernel<<<row_grid(n), 256, 0, s>>>(irp, A->idx1, n, cb / 2, far);
+        colblk_far_kernel<<<row_grid(n), 256, 0, s>>>(irp, A->idx1, n, cb / 2,
+                                                      (int32_t)(128 / dsize(A->dtype)), far);
         st = launch_status();
     }
     unsigned long long h_far = 0;
