@@ -189,3 +189,22 @@ def test_cg_with_column_blocks_matches_oracle(gpu, fmt):
     assert st == 0 and st_o == 0 and abs(res["iters"] - it_o) <= 2
     assert np.max(np.abs(x.cpu().numpy() - x_o)) <= 1e-8
     C.close()
+
+
+@pytest.mark.parametrize("fmt", ["csr", "coo"])
+def test_mixed_precision_with_column_blocks(gpu, fmt):
+    """FP32 inner CG on the FP32 copy (its own column blocks: x of 4.8 MB in
+    FP32 is below the threshold at 1.2M rows, so 2.4M rows are used) with
+    FP64 reliable updates reaches the FP64 tolerance."""
+    mxs = gpu
+    a = scattered_spd(2_400_000)
+    A = build(mxs, a, fmt)
+    A32 = A.cast(mxs.F32).optimize()
+    assert A.impl == COLBLK[fmt] and A32.impl == COLBLK[fmt]
+    b = orc.coo_spmv(a.nrows, a.ai, a.aj, a.av, wl.uniform_vector(a.ncols, seed=6))
+    st, x, res = mxs.cg_solve(A, to_dev(b), rtol=1e-10, maxit=5000, mixed="ru", A32=A32)
+    assert st == 0 and res["true_rel_resid"] <= 1e-10, res
+    r = b - orc.coo_spmv(a.nrows, a.ai, a.aj, a.av, x.cpu().numpy())
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= 1.5e-10
+    A32.close()
+    A.close()
