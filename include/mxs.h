@@ -442,13 +442,15 @@ mxs_status mxs_stencil_coo(int32_t n, int32_t points, double diag, double offdia
 /* ------------------------------------------------------------------------
  * Format selection (the run-first tuner of Section VII-D and the dynamic
  * selection named as further work in Section IX): matrix features and a
- * small MLP 8-64-64-5 (FP32) with its training step.  Its outputs are the
- * label set's formats in this order: COO, CSR, DIA, ELL, SELL-64-1.
+ * small MLP 8-64-64-7 (FP32) with its training step.  Its outputs are the
+ * label set's formats in this order: COO, CSR, DIA, ELL, SELL-64-1, HYB,
+ * HDC (a DIA band of the diagonals at least half full plus a COO
+ * remainder).
  * --------------------------------------------------------------------- */
 
 #define MXS_NFEAT 8
-#define MXS_NCLASS 5
-#define MXS_MLP_NPARAM 5061
+#define MXS_NCLASS 7
+#define MXS_MLP_NPARAM 5191
 
 /* Eight features of A's stored entries into host out[8] [syncs]:
  *   0 rows, 1 nnz, 2 mean row length, 3 population variance of row lengths,
@@ -471,7 +473,7 @@ mxs_status mxs_mlp_norm_stats(const double *raw, int32_t n, float *mu, float *sd
                               void *stream);
 
 /* Logits[n][5] of the MLP with parameters w[MXS_MLP_NPARAM] laid out as
- * W1[8][64], b1[64], W2[64][64], b2[64], W3[64][5], b3[5] (row-major,
+ * W1[8][64], b1[64], W2[64][64], b2[64], W3[64][7], b3[7] (row-major,
  * input index first), ReLU hidden layers [async]. */
 mxs_status mxs_mlp_forward(const float *w, const float *X, int32_t n, float *logits,
                            void *stream);

@@ -21,9 +21,9 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 OK, NOT_CONVERGED, INDEX_RANGE, UNSORTED, DUPLICATE, BREAKDOWN, NONFINITE = 0, 1, -2, -3, -4, -8, -9
-NPARAM = 5061
+NPARAM = 5191
 NFEAT = 8
-NCLASS = 5
+NCLASS = 7
 
 
 def build(out: str | None = None, src: str | None = None) -> str:

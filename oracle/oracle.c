@@ -672,14 +672,15 @@ void orc_features(int64_t nrows, int64_t ncols, int64_t nnz, const int32_t *ai,
 }
 
 /* ======================================================================
- * Selector network: MLP 8-64-64-5 with ReLU, softmax cross-entropy, Adam;
- * one output per format of the label set (COO, CSR, DIA, ELL, SELL).
+ * Selector network: MLP 8-64-64-7 with ReLU, softmax cross-entropy, Adam;
+ * one output per format of the label set (COO, CSR, DIA, ELL, SELL, HYB,
+ * HDC).
  * Parameter layout (row-major, input index first):
- *   W1[8][64], b1[64], W2[64][64], b2[64], W3[64][5], b3[5]  (5061 values)
+ *   W1[8][64], b1[64], W2[64][64], b2[64], W3[64][7], b3[7]  (5191 values)
  * ==================================================================== */
 #define NI 8
 #define NH 64
-#define NO 5
+#define NO 7
 #define OFF_W1 0
 #define OFF_B1 (OFF_W1 + NI * NH)
 #define OFF_W2 (OFF_B1 + NH)

@@ -25,8 +25,8 @@ _LIB = os.path.join(_HERE, "libmxs.so")
 COO, CSR, DIA, HDC, ELL, SELL, HYB = 0, 1, 2, 3, 4, 5, 6
 F64, F32 = 0, 1
 BORROW = 1
-NPARAM = 5061  # MXS_MLP_NPARAM: MLP 8-64-64-5
-NCLASS = 5     # MXS_NCLASS: outputs (COO, CSR, DIA, ELL, SELL)
+NPARAM = 5191  # MXS_MLP_NPARAM: MLP 8-64-64-7
+NCLASS = 7     # MXS_NCLASS: outputs (COO, CSR, DIA, ELL, SELL, HYB, HDC)
 FORMATS = {"coo": COO, "csr": CSR, "dia": DIA, "ell": ELL}
 FORMAT_NAMES = {COO: "coo", CSR: "csr", DIA: "dia", HDC: "hdc", ELL: "ell", SELL: "sell", HYB: "hyb"}
 

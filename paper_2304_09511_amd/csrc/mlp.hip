@@ -1,7 +1,7 @@
-// The format selector's network: MLP 8-64-64-5 (ReLU, softmax cross-entropy;
+// The format selector's network: MLP 8-64-64-7 (ReLU, softmax cross-entropy;
 // one output per format: COO, CSR, DIA, ELL, SELL) in FP32 with forward,
 // backward and Adam kernels.  Parameter layout (row-major, input index
-// first): W1[8][64], b1[64], W2[64][64], b2[64], W3[64][5], b3[5].  Reductions over samples run in sample order with FP64
+// first): W1[8][64], b1[64], W2[64][64], b2[64], W3[64][7], b3[7].  Reductions over samples run in sample order with FP64
 // accumulators, so gradients are deterministic.
 #include <hip/hip_runtime.h>
 

@@ -7,14 +7,16 @@ provides both:
 
 * ``exhaustive_select`` -- the run-first tuner: time one SpMV in every
   feasible format (median of repeats) and keep the fastest;
-* ``Selector`` -- an MLP 8-64-64-5 over eight matrix features
+* ``Selector`` -- an MLP 8-64-64-7 over eight matrix features
   (``mxs.features``), trained and evaluated on the GPU by the library's own
   kernels (``mlp_train_step``, ``mlp_predict``), with the formats the
   containers refuse masked out.  Without a model, selection falls back to
   the tuner.
 
-The label set is COO, CSR, DIA and the padded formats of Section IX's
-further work, ELL and SELL-64-1 (slices of 64 rows, no sorting).
+The label set is COO, CSR, DIA and the further formats Section IX names:
+ELL, SELL-64-1 (slices of 64 rows, no sorting), HYB (ELL part plus COO
+remainder) and HDC (the diagonals at least half full as a DIA band plus a
+COO remainder, the local/remote split of Table III on one GPU).
 
 The dataset builder labels synthetic matrices (5 families, rows log-uniform
 in [1e4, 1e7]) by the tuner's timings; labels are written as JSON lines and
@@ -42,9 +44,11 @@ DATA_DIR = pathlib.Path(__file__).resolve().parent / "selector_data"
 DATA_PATH = DATA_DIR / "labels.jsonl"
 MODEL_PATH = DATA_DIR / "model.json"
 FAMILIES = ("stencil7", "stencil27", "banded", "zipf", "block")
-FORMATS = ("coo", "csr", "dia", "ell", "sell")
-TIE_ORDER = ("csr", "dia", "ell", "sell", "coo")  # equal medians: the general-purpose format first
+FORMATS = ("coo", "csr", "dia", "ell", "sell", "hyb", "hdc")
+# equal medians: the general-purpose format first, the two-part ones last
+TIE_ORDER = ("csr", "dia", "ell", "sell", "coo", "hyb", "hdc")
 SELL_SIGMA = 1
+HDC_MIN_FILL = 0.5  # band diagonals hold at least this share of their slots
 
 
 # ---------------------------------------------------------------------------
@@ -67,10 +71,24 @@ def time_spmv(A, x, y, reps=10, warm=3):
     return statistics.median(ts)
 
 
+def two_part_feasible(A, f):
+    """HYB and HDC count only with both parts non-empty: an empty remainder
+    leaves ELL (HYB) or DIA (HDC), an empty first part COO."""
+    k, rest = A.hyb_size() if f == "hyb" else A.split_size(HDC_MIN_FILL)
+    return k > 0 and rest > 0
+
+
 def convert_to(A_coo, f):
-    """A_coo in format f (a new Matrix), or None where the container refuses."""
+    """A_coo in format f (a new Matrix), or None where the container refuses
+    or a two-part format would have an empty part."""
     try:
-        return A_coo.to_sell(SELL_SIGMA) if f == "sell" else A_coo.convert(f)
+        if f == "sell":
+            return A_coo.to_sell(SELL_SIGMA)
+        if f in ("hyb", "hdc"):
+            if not two_part_feasible(A_coo, f):
+                return None
+            return A_coo.to_hyb() if f == "hyb" else A_coo.split(HDC_MIN_FILL, "coo")
+        return A_coo.convert(f)
     except mxs.MxsError as e:
         if e.status == -5:
             return None
@@ -101,7 +119,7 @@ def time_formats(A_coo, reps=10, warm=3, seed=1):
 def best_format(times):
     m = min(times.values())
     for f in TIE_ORDER:
-        if times[f] == m:
+        if times.get(f, math.inf) == m:
             return f
     return "csr"
 
@@ -218,7 +236,7 @@ NI, NH, NO = 8, 64, len(FORMATS)
 
 def he_init(seed=6):
     """He-normal weights (std sqrt(2/fan_in)), zero biases, in the layout of
-    mxs_mlp_forward: W1[8][64], b1, W2[64][64], b2, W3[64][5], b3."""
+    mxs_mlp_forward: W1[8][64], b1, W2[64][64], b2, W3[64][7], b3."""
     g = np.random.Generator(np.random.PCG64(seed))
     parts = [g.standard_normal(NI * NH) * math.sqrt(2.0 / NI), np.zeros(NH),
              g.standard_normal(NH * NH) * math.sqrt(2.0 / NH), np.zeros(NH),
@@ -229,7 +247,7 @@ def he_init(seed=6):
 
 
 class Selector:
-    """MLP 8-64-64-5 format selector; parameters and normalisation live on
+    """MLP 8-64-64-7 format selector; parameters and normalisation live on
     the device while training and predicting."""
 
     def __init__(self, w=None, mu=None, sd=None):
@@ -273,7 +291,7 @@ class Selector:
         return self
 
     def predict(self, F, feasible=None):
-        """Format index per row of F (raw features); feasible: bool [n][5]."""
+        """Format index per row of F (raw features); feasible: bool [n][7]."""
         import torch
         raw = self._dev(np.atleast_2d(F).astype(np.float64))
         X = mxs.mlp_inputs(raw, self._dev(self.mu), self._dev(self.sd))
@@ -284,24 +302,28 @@ class Selector:
 
     def select(self, A):
         """Format name for a COO/CSR Matrix.  DIA and ELL are masked by the
-        containers' refusal rules, which the features decide; SELL's rule
-        depends on slice maxima, so a refused SELL choice is masked and the
-        network asked again."""
+        containers' refusal rules, which the features decide.  SELL's rule
+        depends on slice maxima, HYB's and HDC's on the sizes of their parts,
+        so a refused choice of these is masked and the network asked again."""
         f = mxs.features(A)
-        feas = [True, True, dia_feasible(f), ell_feasible(f), True]
-        name = FORMATS[int(self.predict(f[None, :], [feas])[0])]
-        if name == "sell":
-            try:
-                A.sell_size(SELL_SIGMA)
-            except mxs.MxsError as e:
-                if e.status != -5:
-                    raise
-                feas[4] = False
-                name = FORMATS[int(self.predict(f[None, :], [feas])[0])]
-        return name
+        feas = [True, True, dia_feasible(f), ell_feasible(f), True, True, True]
+        while True:
+            name = FORMATS[int(self.predict(f[None, :], [feas])[0])]
+            if name == "sell":
+                try:
+                    A.sell_size(SELL_SIGMA)
+                except mxs.MxsError as e:
+                    if e.status != -5:
+                        raise
+                    feas[FORMATS.index("sell")] = False
+                    continue
+            if name in ("hyb", "hdc") and not two_part_feasible(A, name):
+                feas[FORMATS.index(name)] = False
+                continue
+            return name
 
     def save(self, path):
-        json.dump({"layout": "W1[8][64] b1 W2[64][64] b2 W3[64][5] b3",
+        json.dump({"layout": "W1[8][64] b1 W2[64][64] b2 W3[64][7] b3",
                    "formats": list(FORMATS), "sell_sigma": SELL_SIGMA, "w": self.w.tolist(),
                    "mu": self.mu.tolist(), "sd": self.sd.tolist(),
                    "loss_curve": self.loss_curve}, open(path, "w"))

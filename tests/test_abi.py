@@ -132,7 +132,7 @@ def test_mlp_calls_reject_bad_arguments(lib):
     assert lib.mxs_mlp_grad(FAKE, FAKE, FAKE, 4, FAKE, FAKE, FAKE, 0, None) == -1  # workspace too small
     assert lib.mxs_mlp_adam(FAKE, FAKE, FAKE, FAKE, 1e-3, 0, 0.9, 0.999, 1e-8, None) == -1
     assert lib.mxs_mlp_train_step(FAKE, FAKE, FAKE, FAKE, FAKE, 4, 1e-3, 1, FAKE, FAKE, 8, None) == -1
-    assert lib.mxs_mlp_workspace_size(128) >= 128 * (4 * 64 + 5 + 1) * 4 + 5061 * 4
+    assert lib.mxs_mlp_workspace_size(128) >= 128 * (4 * 64 + 7 + 1) * 4 + 5191 * 4
     assert lib.mxs_mlp_inputs(None, 3, FAKE, FAKE, FAKE, None) == -1
     assert lib.mxs_mlp_norm_stats(FAKE, 3, None, FAKE, None) == -1
 

@@ -469,13 +469,13 @@ def test_features_banded_closed_form():
 
 
 # --------------------------------------------------------------------------
-# MLP 8-64-64-5
+# MLP 8-64-64-7
 # --------------------------------------------------------------------------
 def test_mlp_zero_weights_uniform_softmax():
     w = np.zeros(orc.NPARAM)
     X = wl.rng(1).standard_normal((10, 8))
     K = orc.NCLASS
-    y = np.array([0, 1, 2, 3, 4, 2, 0, 0, 1, 4], np.int32)
+    y = np.array([0, 1, 2, 3, 4, 5, 6, 0, 1, 6], np.int32)
     loss, g = orc.mlp_loss_grad(w, X, y)
     assert loss == pytest.approx(math.log(K), rel=1e-15)
     # dL/db3 = mean(p - onehot) with p = 1/K
@@ -485,7 +485,7 @@ def test_mlp_zero_weights_uniform_softmax():
 
 
 def test_mlp_forward_special_network():
-    # h1 = relu(x) in units 0..7, h2 = h1, logits = (h2_0, ..., h2_4) + b3.
+    # h1 = relu(x) in units 0..7, h2 = h1, logits = (h2_0, ..., h2_6) + b3.
     K = orc.NCLASS
     w = np.zeros(orc.NPARAM)
     for i in range(8):
@@ -493,10 +493,10 @@ def test_mlp_forward_special_network():
         w[512 + 64 + i * 64 + i] = 1.0            # W2
     for c in range(K):
         w[512 + 64 + 4096 + 64 + c * K + c] = 1.0  # W3
-    w[-K:] = [0.5, -0.5, 2.0, 1.0, -1.0]
+    w[-K:] = [0.5, -0.5, 2.0, 1.0, -1.0, 0.25, -2.0]
     X = np.array([[1.0, -2.0, 3.0, 0, 2.0, 0, 0, 0], [-1.0, 4.0, -3.0, 1, 1, 1, 1, 1]])
     z = orc.mlp_forward(w, X)
-    assert z.tolist() == [[1.5, -0.5, 5.0, 1.0, 1.0], [0.5, 3.5, 2.0, 2.0, 0.0]]
+    assert z.tolist() == [[1.5, -0.5, 5.0, 1.0, 1.0, 0.25, -2.0], [0.5, 3.5, 2.0, 2.0, 0.0, 1.25, -1.0]]
 
 
 def test_mlp_gradient_matches_finite_differences():

@@ -240,12 +240,29 @@ def test_exhaustive_tuner_times_every_feasible_format(gpu):
     a = wl.banded(200000, 11, 2000, seed=3)
     A = mxs.Matrix.coo(a.nrows, a.ncols, a.ai, a.aj, a.av)
     fmt, t = S.exhaustive_select(A, reps=5, warm=2)
-    assert set(t) == set(S.FORMATS) and all(math.isfinite(v) and v > 0 for v in t.values())
+    assert set(t) == set(S.FORMATS)
+    # every row of the banded matrix fits HYB's ELL part and every entry the
+    # DIA band: the two-part formats would have an empty remainder
+    assert math.isinf(t["hdc"]) and math.isinf(t["hyb"])
+    assert all(math.isfinite(v) and v > 0 for f, v in t.items() if f not in ("hdc", "hyb"))
+    # scattered entries added: both parts non-empty (DIA itself is refused:
+    # each scattered entry opens a diagonal)
+    from test_split_gpu import merge
+    g = wl.rng(5)
+    rows = np.sort(g.choice(a.nrows, 4000, replace=False)).astype(np.int32)
+    extra = wl.Coo(a.nrows, a.ncols, rows, g.integers(0, a.ncols, rows.size).astype(np.int32),
+                   g.standard_normal(rows.size))
+    bn = merge(a, extra)
+    B = mxs.Matrix.coo(bn.nrows, bn.ncols, bn.ai, bn.aj, bn.av)
+    fb, tb = S.exhaustive_select(B, reps=3, warm=1)
+    assert math.isinf(tb["dia"]) and tb[fb] == min(tb.values())
+    assert all(math.isfinite(v) and v > 0 for f, v in tb.items() if f != "dia")
     assert t[fmt] == min(t.values())
     z = wl.zipf_rows(100000, seed=2)
     Z = mxs.Matrix.coo(z.nrows, z.ncols, z.ai, z.aj, z.av)
     fz, tz = S.exhaustive_select(Z, reps=3, warm=1)
-    assert math.isinf(tz["dia"]) and math.isinf(tz["ell"]) and fz in ("coo", "csr", "sell")
+    assert math.isinf(tz["dia"]) and math.isinf(tz["ell"]) and math.isinf(tz["hdc"])
+    assert fz in ("coo", "csr", "sell", "hyb")
 
 
 def test_device_dataset_generators_match_oracle_features(gpu):
