@@ -302,13 +302,25 @@ class Matrix:
                "mxs_split_size")
         return nd.value, rn.value
 
-    def split(self, min_fill=0.5, rest="csr", x=None, reps=10):
+    def split(self, min_fill=0.5, rest="csr", x=None, reps=10, model=None):
         """A DIA band (diagonals at least min_fill full) plus the remaining
         entries in `rest` ("coo" or "csr"), as an HDC Matrix on fresh tensors.
         rest="auto" splits both ways, tunes each (tune(), on x or a seeded
         uniform vector) and keeps the faster split; its choice is in
-        .tuning."""
+        .tuning.  rest="select" asks the format selector's network (`model`,
+        default the committed one) for COO or CSR on the remainder's
+        features; its choice is in .selection."""
         torch = _torch()
+        if rest == "select":
+            from . import selector as S
+            m = model if model is not None else S.Selector.load(str(S.MODEL_PATH))
+            H = self.split(min_fill, "coo")
+            r = S.select_rest(m, H.parts()[1])
+            if r != "coo":
+                H.close()
+                H = self.split(min_fill, r)
+            H.selection = {"rest_format": r}
+            return H
         if rest == "auto":
             if x is None:
                 g = torch.Generator(device="cuda")

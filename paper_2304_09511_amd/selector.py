@@ -346,6 +346,14 @@ def ell_feasible(features):
     return features[4] * features[0] <= 8 * features[1]
 
 
+def select_rest(model, R):
+    """COO or CSR for the remainder R of a split (a COO part handle): the
+    network's choice on R's features with every other format masked."""
+    f = mxs.features(R)
+    feas = [f_ in ("coo", "csr") for f_ in FORMATS]
+    return FORMATS[int(model.predict(f[None, :], [feas])[0])]
+
+
 def select_format(A, model=None):
     """The learned choice when a model is given, else the run-first tuner."""
     if model is not None:

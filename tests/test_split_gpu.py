@@ -233,3 +233,29 @@ def test_split_tune_and_auto_rest(gpu):
     assert Hauto.format == mxs.HDC and Hauto.tuning["rest_format"] in ("coo", "csr")
     assert Hauto.parts()[1].format == mxs.FORMATS[Hauto.tuning["rest_format"]]
     assert rel_maxnorm(mxs.spmv(Hauto, xd).cpu().numpy(), ref) <= 1e-12
+
+
+@pytest.mark.parametrize("extra", [4000, 400000])
+def test_split_rest_chosen_by_selector(gpu, extra):
+    """rest="select": the remainder's format (COO or CSR) is the selector
+    network's choice on the remainder's features; the product is the
+    oracle's."""
+    mxs = gpu
+    from paper_2304_09511_amd import selector as S
+    a = wl.banded(200000, ndiag=11, max_offset=2000, seed=12)
+    g = wl.rng(13)
+    rows = np.sort(g.integers(0, a.nrows, extra)).astype(np.int32)
+    noise = wl.Coo(a.nrows, a.ncols, rows, g.integers(0, a.ncols, extra).astype(np.int32),
+                   g.standard_normal(extra))
+    m = merge(a, noise)
+    A = mxs.Matrix.coo(m.nrows, m.ncols, m.ai, m.aj, m.av)
+    model = S.Selector.load(str(S.MODEL_PATH))
+    H = A.split(0.5, "select", model=model)
+    r = H.selection["rest_format"]
+    assert H.format == mxs.HDC and H.ndiag == 11 and r in ("coo", "csr")
+    assert H.parts()[1].format == mxs.FORMATS[r]
+    Hc = A.split(0.5, "coo")
+    assert S.select_rest(model, Hc.parts()[1]) == r
+    x = wl.uniform_vector(m.ncols, seed=4)
+    ref = orc.coo_spmv(m.nrows, m.ai, m.aj, m.av, x)
+    assert rel_maxnorm(mxs.spmv(H, to_dev(x)).cpu().numpy(), ref) <= 1e-12
