@@ -32,9 +32,19 @@ def merge(a, b):
     return wl.Coo(a.nrows, a.ncols, ai[order].copy(), aj[order].copy(), av[order].copy())
 
 
+def scattered(n, density, seed):
+    """About n*n*density entries at uniform random positions (duplicates
+    merged), N(0,1) values; drawn without an n-by-n mask."""
+    g = wl.rng(seed)
+    k = int(g.binomial(n * n, density))
+    ai = g.integers(0, n, k).astype(np.int32)
+    aj = g.integers(0, n, k).astype(np.int32)
+    return wl.Coo(n, n, ai, aj, g.standard_normal(k))
+
+
 def banded_noise(n, seed, ndiag=11, width=300, density=2e-4, integer=False):
     a = wl.banded(n, ndiag=ndiag, max_offset=width, seed=seed)
-    b = wl.random_coo(n, n, density, seed=seed + 1)
+    b = scattered(n, density, seed + 1)
     m = merge(a, b)
     if integer:
         g = wl.rng(seed + 2)
