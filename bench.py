@@ -43,7 +43,7 @@ FORMATS = ("coo", "csr", "dia")
 # kernel of each format's implementation (ids as in mxs_set_impl)
 KERNEL_NAMES = {"coo": ("coo_rows_kernel", "coo_spmv_kernel", "coo_spmv_kernel"),
                 "csr": ("csr_spmv_kernel", "csr_rowwise_kernel", "csr_spmv_kernel", "ell_spmv_kernel",
-                        "csr_spmv_kernel"),
+                        "csr_spmv_kernel", "csr_vector_kernel"),
                 "dia": ("dia_spmv_kernel",) * 3}
 SPMV_SRC = os.path.join(ROOT, "paper_2304_09511_amd", "csrc", "spmv.hip")
 

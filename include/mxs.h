@@ -217,7 +217,7 @@ mxs_status mxs_optimize(mxs_mat A, void *stream);
  *           entries lie half a block or more from the diagonal and read x
  *           from another 128-byte line than the row's previous entry; the copy
  *           takes as much memory as the entries, plus K row-pointer arrays
- *           for CSR)
+ *           for CSR)   5: a wavefront per row (lanes stride over the row)
  *   DIA  0: row-blocked values, one x load per run of three consecutive
  *           offsets (needs the row-blocked copy and offsets in such runs)
  *        1: row-blocked values (needs the copy)

@@ -426,7 +426,8 @@ class Matrix:
 
     # SpMV implementations of the format (ids as in mxs_set_impl)
     IMPL_NAMES = {COO: ("row_tiles", "segmented", "column_blocks"),
-                  CSR: ("entry_tiles", "row_per_thread", "staged_gather", "ell_copy", "column_blocks"),
+                  CSR: ("entry_tiles", "row_per_thread", "staged_gather", "ell_copy", "column_blocks",
+                        "wave_per_row"),
                   DIA: ("blocked_shared_x", "blocked", "diagonal_major")}
 
     @property

@@ -100,6 +100,7 @@ struct CsrPlan {
     int32_t *ell_col = nullptr;
     void *ell_val = nullptr;
     bool ell = false;            // the active implementation reads it
+    bool vec = false;            // a wavefront per row (implementation 5)
 };
 
 struct DiaPlan {

@@ -456,6 +456,34 @@ static uint32_t rowwise_grid(int32_t nrows)
     return (uint32_t)std::clamp<int64_t>(((int64_t)nrows + 255) / 256, 1, kRowwiseGridMax);
 }
 
+// A wavefront per row (the "vector" CSR kernel): the lanes stride over the
+// row's entries and a wave reduction sums them, so a long row is spread
+// over 64 lanes; short rows leave most lanes idle.
+constexpr int64_t kVectorGridMax = 16384;
+
+template <typename T>
+__global__ __launch_bounds__(256) void csr_vector_kernel(
+    const int32_t *__restrict__ irp, const int32_t *__restrict__ aj, const T *__restrict__ av,
+    const T *__restrict__ x, T *__restrict__ y, int32_t nrows, const int *__restrict__ done, int acc)
+{
+    if (done && *done) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x / kWave);
+    for (int64_t r = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; r < nrows;
+         r += nw) {
+        const int32_t b = irp[r], e = irp[r + 1];
+        T s = T(0);
+        for (int32_t k = b + lane; k < e; k += kWave) s += av[k] * x[aj[k]];
+        for (int off = kWave >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
+        if (lane == 0) y[r] = acc ? y[r] + s : s;
+    }
+}
+
+static uint32_t vector_grid(int32_t nrows)
+{
+    return (uint32_t)std::clamp<int64_t>(((int64_t)nrows + 3) / 4, 1, kVectorGridMax);
+}
+
 // Rows too long for their owner's overflow window: owner's tail piece plus
 // the head pieces of the following tiles, in tile order.
 template <typename T, bool DOT>
@@ -1137,7 +1165,8 @@ static uint32_t fixup_grid(int64_t ntiles) { return (uint32_t)std::max<int64_t>(
 
 int64_t spmv_dot_parts(const mxs_mat_s *A)
 {
-    if (A->fmt == MXS_COO || is_split(A) || (A->fmt == MXS_CSR && A->colblk)) return kDotGridMax;
+    if (A->fmt == MXS_COO || is_split(A) || (A->fmt == MXS_CSR && (A->colblk || A->csr.vec)))
+        return kDotGridMax;
     if (A->fmt == MXS_CSR && A->csr.ell) return ell_grid(A->nrows, true);
     if (A->fmt == MXS_CSR && A->csr.rowwise) return rowwise_grid(A->nrows);
     if (A->fmt == MXS_ELL || A->fmt == MXS_SELL) return padded_grid(A, true);
@@ -1378,14 +1407,14 @@ static mxs_status build_coo_plan(mxs_mat_s *A, hipStream_t s)
 //       2: entry tiles, x gathered per row from LDS-staged columns
 //       3: a lane per row over an ELL copy made by the plan (rows of
 //          near-equal length: at most 5% padding)
-//       4: column blocks (colblk.hip)
+//       4: column blocks (colblk.hip)   5: a wavefront per row
 //   DIA 0: row-blocked values, x shared over runs of three offsets
 //       1: row-blocked values    2: diagonal-major values (no copy), x shared
 // ---------------------------------------------------------------------------
 int32_t impl_count(const mxs_mat_s *A)
 {
     if (A->fmt == MXS_ELL || A->fmt == MXS_SELL) return 1;
-    return A->fmt == MXS_CSR ? 5 : A->fmt == MXS_DIA ? 3 : A->fmt == MXS_COO ? 3 : 0;
+    return A->fmt == MXS_CSR ? 6 : A->fmt == MXS_DIA ? 3 : A->fmt == MXS_COO ? 3 : 0;
 }
 
 bool impl_ok(const mxs_mat_s *A, int32_t impl)
@@ -1433,6 +1462,7 @@ void set_impl(mxs_mat_s *A, int32_t impl)
         A->csr.gx = impl == 2;
         A->csr.ell = impl == 3;
         A->colblk = impl == 4 && !A->cblk.empty();
+        A->csr.vec = impl == 5;
         break;
     case MXS_DIA:
         A->dia.use_blk = impl != 2 && A->dia.blk != nullptr;
@@ -1560,6 +1590,13 @@ static mxs_status spmv_typed(const mxs_mat_s *A, const T *x, T *y, const int *do
             if (st != MXS_OK) return st;
             nparts = ell_grid(A->nrows, dot != nullptr);
             break;
+        }
+        if (A->csr.vec) {
+            csr_vector_kernel<T><<<vector_grid(A->nrows), 256, 0, s>>>(
+                A->idx0, A->idx1, (const T *)A->vals, x, y, A->nrows, done, acc);
+            MXS_HIP(hipGetLastError());
+            if (dot) return dot_sigma_typed<T>(A->nrows, x, y, done, dot, s);
+            return MXS_OK;
         }
         if (A->csr.rowwise) {
             grid = rowwise_grid(A->nrows);

@@ -111,7 +111,7 @@ def test_applicability_rules(gpu):
     M = build(mxs, _diagonals(5000, [-2, -1, 0, 7, 8], seed=1), "dia")
     assert M.impl == 1 and applicable(mxs, M) == [1, 2]
     C = build(mxs, sparse, "csr")
-    assert C.impl == 1 and applicable(mxs, C) == [0, 1, 2]     # rows > 2 nnz: a thread per row
+    assert C.impl == 1 and applicable(mxs, C) == [0, 1, 2, 5]  # rows > 2 nnz: a thread per row
     assert build(mxs, wl.stencil(16), "csr").impl == 0
     for B in (A, S):
         with pytest.raises(mxs.MxsError) as e:
