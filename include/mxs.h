@@ -193,12 +193,15 @@ mxs_status mxs_cast(mxs_mat src, mxs_dtype dtype, void *vals, mxs_mat *out, void
 
 /* Builds the format's execution plan [syncs]: CSR and COO tiles of a fixed
  * number of entries with their row starts and carries, a row-blocked copy of
- * the DIA values (when its padding stays within nrows/8 rows), and what every
- * implementation below needs.  Idempotent.  mxs_spmv runs it on first use if
- * not called. */
+ * the DIA values (when its padding stays within nrows/8 rows), an ELL copy
+ * of CSR rows of near-equal length, COO and CSR column blocks for scattered
+ * columns over a large x, and what every other implementation below needs.
+ * The copies are optional: without memory for one, its implementation is
+ * not applicable.  Idempotent.  mxs_spmv runs it on first use if not
+ * called. */
 mxs_status mxs_optimize(mxs_mat A, void *stream);
 
-/* SpMV implementations (Section 3 keeps one kernel per format; no single
+/* SpMV implementations (Section III keeps one kernel per format; no single
  * kernel wins on every matrix, so each format here has several, all giving
  * the same sums within rounding):
  *   COO  0: row tiles (the CSR tiling rebuilt from the row ids; applicable
