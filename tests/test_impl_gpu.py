@@ -276,3 +276,33 @@ def test_cg_on_long_rows_matches_oracle(gpu, fmt):
         st, x, res = mxs.cg_solve(A, to_dev(b), rtol=1e-10, maxit=5000)
         assert st == 0 and abs(res["iters"] - it_o) <= 2, (i, res["iters"], it_o)
         assert np.max(np.abs(x.cpu().numpy() - x_o)) <= 1e-8, i
+
+
+@pytest.mark.parametrize("fmt", ["coo", "csr", "dia"])
+@pytest.mark.parametrize("name", ["stencil16", "gappy_long", "random300x200", "dense_rows", "zipf20k",
+                                  "banded50k"])
+def test_every_impl_fp32_within_rounding_bound(gpu, name, fmt):
+    """The FP32 kernels of every implementation: within the per-row FP32
+    rounding bound of the oracle's FP64 product of the same FP32 values."""
+    from _cases import U32
+    mxs = gpu
+    cases = dict(CASES)
+    if name == "stencil16":
+        a = wl.stencil(16)
+    elif name in cases:
+        a = cases[name]
+    else:
+        from test_spmv_gpu import _gappy
+        a = _gappy(4000, seed=2, long_rows={500, 501, 2200})
+    a32 = wl.Coo(a.nrows, a.ncols, a.ai, a.aj, a.av.astype(np.float32))
+    A = build(mxs, a32, fmt)
+    if A is None:
+        pytest.skip("DIA refused (more than 8 slots per non-zero)")
+    x = wl.uniform_vector(a.ncols, seed=7).astype(np.float32)
+    a64 = wl.Coo(a.nrows, a.ncols, a.ai, a.aj, a32.av.astype(np.float64))
+    ref = orc.coo_spmv(a.nrows, a.ai, a.aj, a64.av, x.astype(np.float64))
+    bound = row_bound(a64, x.astype(np.float64), U32) + 1e-30
+    for i in applicable(mxs, A):
+        A.impl = i
+        y = mxs.spmv(A, to_dev(x)).cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(y - ref) <= bound), (name, fmt, i)
