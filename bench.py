@@ -568,17 +568,19 @@ def pmc_mode(args):
         x = torch.zeros_like(r)
         for _ in range(args.steps):
             M.symgs(0, r, x)
-    elif args.pmc.startswith("zipf-csr"):
-        # the 4M-row Zipf matrix of the irregular runs, CSR, one implementation
+    elif args.pmc.startswith("zipf-"):
+        # the 4M-row Zipf matrix of the irregular runs, COO or CSR, one implementation
         import workloads as wl
+        fmt, impl = args.pmc[len("zipf-"):len("zipf-") + 3], int(args.pmc[len("zipf-") + 3:])
         nr, nc, ai, aj, av = wl.device_zipf_rows(4_000_000, seed=2)
-        A = mxs.Matrix.coo(nr, nc, ai, aj, av, borrow=True).convert("csr").optimize()
-        A.impl = int(args.pmc[len("zipf-csr"):])
+        A = mxs.Matrix.coo(nr, nc, ai, aj, av, borrow=True)
+        A = (A.convert("csr") if fmt == "csr" else A).optimize()
+        A.impl = impl
         x = torch.from_numpy(np.random.Generator(np.random.PCG64(1)).uniform(-1, 1, A.ncols)).cuda()
         y = torch.empty(A.nrows, dtype=torch.float64, device="cuda")
         for _ in range(args.steps):
             mxs.spmv(A, x, y)
-        args.pmc = "csr"
+        args.pmc = fmt
     else:
         mats = build_matrices(mxs, args.n)
         A = mats[args.pmc]
@@ -615,7 +617,7 @@ def main():
     ap.add_argument("--no-irregular", action="store_true")
     ap.add_argument("--no-selector", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--pmc", choices=FORMATS + ("symgs", "zipf-csr0", "zipf-csr4"), default=None)
+    ap.add_argument("--pmc", choices=FORMATS + ("symgs", "zipf-csr0", "zipf-csr4", "zipf-coo0", "zipf-coo2"), default=None)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
