@@ -475,13 +475,13 @@ mxs_status mxs_mlp_inputs(const double *raw, int32_t n, const float *mu, const f
 mxs_status mxs_mlp_norm_stats(const double *raw, int32_t n, float *mu, float *sd,
                               void *stream);
 
-/* Logits[n][5] of the MLP with parameters w[MXS_MLP_NPARAM] laid out as
+/* Logits[n][MXS_NCLASS] of the MLP with parameters w[MXS_MLP_NPARAM] laid out as
  * W1[8][64], b1[64], W2[64][64], b2[64], W3[64][7], b3[7] (row-major,
  * input index first), ReLU hidden layers [async]. */
 mxs_status mxs_mlp_forward(const float *w, const float *X, int32_t n, float *logits,
                            void *stream);
 
-/* fmt_out[s] = argmax over formats f with feasible[s*5+f] != 0 of the
+/* fmt_out[s] = argmax over formats f with feasible[s*MXS_NCLASS+f] != 0 of the
  * logits (feasible may be NULL: all allowed); -1 if none is feasible [async]. */
 mxs_status mxs_mlp_predict(const float *w, const float *X, int32_t n, const uint8_t *feasible,
                            int32_t *fmt_out, void *stream);
@@ -490,7 +490,7 @@ mxs_status mxs_mlp_predict(const float *w, const float *X, int32_t n, const uint
  * samples (per-sample activations and deltas, then the gradient). */
 size_t mxs_mlp_workspace_size(int32_t n);
 
-/* Mean softmax cross-entropy over n samples (labels in {0,...,4}) into the
+/* Mean softmax cross-entropy over n samples (labels in {0,...,MXS_NCLASS-1}) into the
  * device float *loss and its gradient grad[MXS_MLP_NPARAM] [async].
  * Deterministic. */
 mxs_status mxs_mlp_grad(const float *w, const float *X, const int32_t *labels, int32_t n,

@@ -1,5 +1,5 @@
 // The format selector's network: MLP 8-64-64-7 (ReLU, softmax cross-entropy;
-// one output per format: COO, CSR, DIA, ELL, SELL) in FP32 with forward,
+// one output per format: COO, CSR, DIA, ELL, SELL-64-1, HYB, HDC) in FP32 with forward,
 // backward and Adam kernels.  Parameter layout (row-major, input index
 // first): W1[8][64], b1[64], W2[64][64], b2[64], W3[64][7], b3[7].  Reductions over samples run in sample order with FP64
 // accumulators, so gradients are deterministic.
@@ -141,7 +141,9 @@ __global__ __launch_bounds__(64) void mlp_sample_kernel(const float *__restrict_
     }
     __syncthreads();
     if (j == 0) {
-        const float m = fmaxf(z[0], fmaxf(z[1], z[2]));
+        // shift by the largest logit so that no exponent overflows
+        float m = z[0];
+        for (int c = 1; c < NO; ++c) m = fmaxf(m, z[c]);
         float e[NO], den = 0.0f;
         for (int c = 0; c < NO; ++c) {
             e[c] = expf(z[c] - m);

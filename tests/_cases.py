@@ -44,6 +44,18 @@ def many_empty_rows(nrows=10000, live=100, seed=5):
     return wl.Coo(nrows, nrows, ai, aj, g.standard_normal(ai.shape[0]))
 
 
+def sparse_rows(nrows=200000, live=3000, seed=7):
+    """Rows of 1-3 entries about 66 rows apart: a COO tile of 1,024 entries
+    meets hundreds of runs of empty rows (more than its queue of long runs
+    holds), and the last live row leaves a long run to the end."""
+    g = wl.rng(seed)
+    rows = np.sort(g.choice(nrows - 5000, live, replace=False))
+    lens = g.integers(1, 4, live)
+    ai = np.repeat(rows, lens).astype(np.int32)
+    aj = np.concatenate([np.sort(g.choice(nrows, k, replace=False)) for k in lens]).astype(np.int32)
+    return wl.Coo(nrows, nrows, ai, aj, g.standard_normal(ai.shape[0]))
+
+
 def dense_row(ncols=10000, seed=6):
     g = wl.rng(seed)
     return wl.Coo(3, ncols, np.repeat(np.array([0, 1, 2], np.int32), [ncols, 5, ncols]),
@@ -70,6 +82,7 @@ def small_cases():
     cases.append(("banded50k", wl.banded(50000, ndiag=11, max_offset=2000, seed=12)))
     cases.append(("block3000", wl.block_random(3000, seed=13)))
     cases.append(("empty_rows", many_empty_rows()))
+    cases.append(("sparse_rows", sparse_rows()))
     cases.append(("dense_rows", dense_row()))
     cases.append(("one_column", single_column()))
     return cases

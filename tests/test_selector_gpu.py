@@ -151,6 +151,26 @@ def test_gradient_matches_oracle(gpu, n):
     assert np.max(np.abs(g - gref)) <= 1e-4 * np.max(np.abs(gref))
 
 
+@pytest.mark.parametrize("lead", [3, 4, 5, 6])
+def test_gradient_with_a_dominant_late_logit(gpu, lead):
+    """One of the formats after the first three (ELL, SELL, HYB, HDC) leads
+    every other logit by more than 100: a softmax shifted by anything but the
+    largest logit overflows FP32's exponential there (e^100 > FLT_MAX)."""
+    mxs = gpu
+    w = _net(12)
+    w[orc.NPARAM - orc.NCLASS + lead] = np.float32(150.0)
+    X, y = _data(64, 70 + lead)
+    z = orc.mlp_forward(w.astype(np.float64), X.astype(np.float64)).reshape(-1, orc.NCLASS)
+    others = np.delete(z, lead, axis=1)
+    assert np.min(z[:, lead] - others.max(axis=1)) > 100.0
+    loss, g = mxs.mlp_grad(dev(w), dev(X), dev(y))
+    lref, gref = orc.mlp_loss_grad(w.astype(np.float64), X.astype(np.float64), y)
+    g = g.cpu().numpy()
+    assert np.all(np.isfinite(g)) and math.isfinite(float(loss.cpu()))
+    assert float(loss.cpu()) == pytest.approx(lref, rel=1e-5)
+    assert np.max(np.abs(g - gref)) <= 1e-4 * np.max(np.abs(gref))
+
+
 def test_gradient_deterministic(gpu):
     mxs = gpu
     w = _net(9)
