@@ -295,7 +295,11 @@ def mixed_vs_fp64(torch, mxs, n, fmts=("dia", "csr")):
                        f"b = A*1, x0 = 0, tol 1e-10 on ||b - A x|| / ||b|| (FP64 CG: recursive)"}
     ones = torch.ones(mats["csr"].nrows, dtype=torch.float64, device="cuda")
     b = mxs.spmv(mats["csr"], ones)
-    gold = {"fp64": load_golden(f"cg_stencil{n}_tol1e-10"), "ir": load_golden(f"mixed_stencil{n}_tol1e-10")}
+    gold = {"fp64": load_golden(f"cg_stencil{n}_tol1e-10"), "ir": load_golden(f"mixed_stencil{n}_tol1e-10"),
+            "ru_delta0.1": load_golden(f"mixed_ru_stencil{n}_tol1e-10_delta0.1"),
+            "ru_delta0.01": load_golden(f"mixed_ru_stencil{n}_tol1e-10_delta0.01")}
+    # the oracle's run of the same method (iterative refinement: inner 1e-4 only)
+    same = {"fp64": "fp64", "ir_inner1e-4": "ir", "ru_delta0.1": "ru_delta0.1", "ru_delta0.01": "ru_delta0.01"}
     for fmt in fmts:
         A = mats[fmt]
         A32 = A.cast(mxs.F32)
@@ -323,6 +327,16 @@ def mixed_vs_fp64(torch, mxs, n, fmts=("dia", "csr")):
                 idx = torch.tensor(g["sample_idx"], dtype=torch.int64, device="cuda")
                 xo = torch.tensor(g["x_sample"], dtype=torch.float64, device="cuda")
                 rec["max_rel_err_vs_oracle_fp64_x_sampled"] = float((x[idx] - xo).abs().max() / xo.abs().max())
+            gs = gold.get(same.get(name, ""))
+            if gs is not None:
+                idx = torch.tensor(gs["sample_idx"], dtype=torch.int64, device="cuda")
+                xo = torch.tensor(gs["x_sample"], dtype=torch.float64, device="cuda")
+                rec["oracle_same_method"] = {
+                    "iters": gs.get("iters", gs.get("inner_iters")),
+                    "updates_or_corrections": gs.get("updates", gs.get("outer_iters")),
+                    "true_rel_resid": gs["true_rel_resid"],
+                    "max_rel_err_x_sampled": float((x[idx] - xo).abs().max() / xo.abs().max()),
+                    "source": "tests/golden/" + gs["_file"]}
             rows[name] = rec
         fp = rows["fp64"]["time_to_tol_ms"]
         for name in rows:
@@ -335,7 +349,8 @@ def mixed_vs_fp64(torch, mxs, n, fmts=("dia", "csr")):
             f"{k} {v['time_to_tol_ms']:.1f} ms ({v['iters']} it)" for k, v in rows.items() if isinstance(v, dict)))
         A32.close()
     out["oracle"] = {k: (None if g is None else {kk: g.get(kk) for kk in ("iters", "outer_iters", "inner_iters",
-                                                                          "true_rel_resid", "inner_rtol")})
+                                                                          "updates", "true_rel_resid",
+                                                                          "inner_rtol", "delta")})
                      for k, g in gold.items()}
     out["oracle"]["source"] = "tests/golden/*.json (tests/golden/make_golden.py, oracle only)"
     for A in mats.values():
@@ -378,7 +393,11 @@ GOLDEN = os.path.join(ROOT, "tests", "golden")
 
 def load_golden(name):
     path = os.path.join(GOLDEN, name + ".json")
-    return json.load(open(path)) if os.path.exists(path) else None
+    if not os.path.exists(path):
+        return None
+    g = json.load(open(path))
+    g["_file"] = name + ".json"
+    return g
 
 
 def compare_golden(section, name, x_by_fmt=None):

@@ -12,6 +12,15 @@ def gamma(n, u):
     return n * u / (1 - n * u)
 
 
+def stencil_kappa(n):
+    """Condition number of the 27-point operator (26 / -1) on an n^3 grid
+    from its closed-form spectrum: A = 27 I - T (x) T (x) T with T the n x n
+    tridiagonal (1, 1, 1), whose eigenvalues are 1 + 2 cos(k pi / (n + 1))."""
+    t = 1.0 + 2.0 * np.cos(np.arange(1, n + 1) * np.pi / (n + 1))
+    lam = 27.0 - (t[None, None, :] * t[None, :, None] * t[:, None, None]).ravel()
+    return float(lam.max() / lam.min())
+
+
 def rel_maxnorm(y, ref):
     y = np.asarray(y, np.float64)
     ref = np.asarray(ref, np.float64)

@@ -525,3 +525,18 @@ def test_adam_first_step_is_signed_lr():
     orc.adam_step(w, m, v, g, lr=0.1, t=1)
     assert np.allclose(w, 1.0 - 0.1 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
     assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+
+
+def test_stencil_kappa_closed_form_matches_dense_spectrum():
+    """The condition number used by the solution bars of the GPU tests: the
+    closed form equals the dense eigen-decomposition on small grids, and
+    gives the figures 39.0, 2,248 and 5,032 at 16^3, 128^3 and 192^3."""
+    from _cases import stencil_kappa
+    for n in (2, 3, 5):
+        a = wl.stencil(n)
+        D = np.zeros((a.nrows, a.ncols))
+        D[a.ai, a.aj] = a.av
+        lam = np.linalg.eigvalsh(D)
+        assert stencil_kappa(n) == pytest.approx(lam.max() / lam.min(), rel=1e-12)
+    assert round(stencil_kappa(16), 1) == 39.0
+    assert round(stencil_kappa(128)) == 2248 and round(stencil_kappa(192)) == 5032
