@@ -73,7 +73,8 @@ int32_t mxs_version(void);
 /* Detail of the last HIP failure seen by this thread (HIP error name and
  * message, the failing call and, if one was pending, the error another
  * library left in HIP's per-thread error slot, which every entry point
- * clears on entry).  Empty if none; valid until the thread's next failure. */
+ * clears on entry), or of the last size a fixed scratch array refused.
+ * Empty if none; valid until the thread's next failure. */
 const char *mxs_last_error(void);
 
 /* ------------------------------------------------------------------------
@@ -260,6 +261,20 @@ mxs_status mxs_spmv(mxs_mat A, const void *x, void *y, void *stream);
  * the device double *result [async].  Deterministic. */
 mxs_status mxs_dot(int64_t n, mxs_dtype dtype, const void *a, const void *b, double *result,
                    void *stream);
+
+/* mxs_dot without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc) [async].  Same arguments, kernels and result, bit for bit, as
+ * mxs_dot; the workgroup partials go to a fixed array of 8,192 FP64 values
+ * (64 KiB) that the library keeps on each GPU it runs on until the process
+ * ends, instead of a buffer allocated per call.  A call that would need more
+ * partials than the array holds is refused with MXS_ERR_UNSUPPORTED (detail
+ * in mxs_last_error); the grid is capped below that, so no n is refused
+ * today.  Calls that overlap on one GPU (different streams, or threads
+ * without ordering) share the array and race; calls on one stream are
+ * ordered.  The first call on a device looks up the array's address there. */
+mxs_status mxs_dot_noalloc(int64_t n, mxs_dtype dtype, const void *a, const void *b,
+                           double *result, void *stream);
 
 /* y = alpha*x + beta*y over n values of `dtype` [async]. */
 mxs_status mxs_axpby(int64_t n, mxs_dtype dtype, double alpha, const void *x, double beta,

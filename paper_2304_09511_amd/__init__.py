@@ -92,6 +92,7 @@ _SIGS = {
     "mxs_tune": (I32, [P, P, P, I32, P, P, P]),
     "mxs_spmv": (I32, [P, P, P, P]),
     "mxs_dot": (I32, [I64, I32, P, P, P, P]),
+    "mxs_dot_noalloc": (I32, [I64, I32, P, P, P, P]),
     "mxs_axpby": (I32, [I64, I32, D, P, D, P, P]),
     "mxs_cg_workspace_size": (I32, [P, I32, P]),
     "mxs_cg_solve": (I32, [P, P, P, P, P, P, P, SZ, P]),
@@ -521,6 +522,18 @@ def dot(a, b):
     out = torch.empty(1, dtype=torch.float64, device=a.device)
     _check(load().mxs_dot(a.numel(), _dtype_code(a), _ptr(a), _ptr(b), _ptr(out), _stream()),
            "mxs_dot")
+    return out
+
+
+def dot_noalloc(a, b, out):
+    """a.b into the caller's FP64 device tensor `out` (one element) through
+    the allocation-free entry point (no device memory is allocated)."""
+    if a.numel() != b.numel() or _dtype_code(a) != _dtype_code(b):
+        raise ValueError("a and b must have the same length and dtype")
+    if out.numel() < 1 or _dtype_code(out) != 0:
+        raise TypeError("out must be an FP64 device tensor with at least one element")
+    _check(load().mxs_dot_noalloc(a.numel(), _dtype_code(a), _ptr(a), _ptr(b), _ptr(out),
+                                  _stream()), "mxs_dot_noalloc", ok=(0,))
     return out
 
 

@@ -582,6 +582,14 @@ mxs_status mxs_dot(int64_t n, mxs_dtype dtype, const void *a, const void *b, dou
     return guarded([&] { return dot_launch(n, dtype, a, b, result, S(stream)); });
 }
 
+mxs_status mxs_dot_noalloc(int64_t n, mxs_dtype dtype, const void *a, const void *b, double *result,
+                           void *stream)
+{
+    if (n < 0 || !valid_dtype(dtype) || !result || (n > 0 && (!a || !b)))
+        return MXS_ERR_INVALID_ARG;
+    return guarded([&] { return dot_noalloc_launch(n, dtype, a, b, result, S(stream)); });
+}
+
 mxs_status mxs_axpby(int64_t n, mxs_dtype dtype, double alpha, const void *x, double beta, void *y,
                      void *stream)
 {

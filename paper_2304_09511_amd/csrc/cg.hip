@@ -15,6 +15,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -76,6 +78,67 @@ mxs_status dot_launch(int64_t n, mxs_dtype t, const void *a, const void *b, doub
     total_kernel<<<1, kFinNT, 0, s>>>(parts, g, result);
     MXS_HIP(hipGetLastError());
     MXS_HIP(hipFreeAsync(parts, s));
+    return MXS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free dot product (mxs_dot_noalloc): the same two kernels, with
+// the workgroup partials in a fixed device array instead of a buffer
+// allocated per call.  Every GPU the library runs on holds its own copy of
+// the array, at its own address, until the process ends.  In host code the
+// array's name is not a device address: kernels get the address that
+// hipGetSymbolAddress returns for the current device, fetched once per
+// device and kept.  Calls that overlap on one GPU share the array and race.
+// ---------------------------------------------------------------------------
+constexpr int kScratchParts = 8192; // 64 KiB of FP64 partials per device
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) double scratch[kScratchParts];
+
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[kScratchDevices] = {};
+
+static mxs_status scratch_address(double **out)
+{
+    int dev = 0;
+    MXS_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kScratchDevices) {
+        snprintf(g_last_error, sizeof g_last_error,
+                 "mxs_dot_noalloc: device %d is beyond the %d devices the scratch table covers", dev,
+                 kScratchDevices);
+        return MXS_ERR_UNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        MXS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = (double *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return MXS_OK;
+}
+
+mxs_status dot_noalloc_launch(int64_t n, mxs_dtype t, const void *a, const void *b, double *result,
+                              hipStream_t s)
+{
+    const uint32_t g = vec_grid(n);
+    if ((int64_t)g > kScratchParts) {
+        snprintf(g_last_error, sizeof g_last_error,
+                 "mxs_dot_noalloc: %u workgroup partials exceed the scratch array's %d", g,
+                 kScratchParts);
+        return MXS_ERR_UNSUPPORTED;
+    }
+    double *parts = nullptr;
+    const mxs_status st = scratch_address(&parts);
+    if (st != MXS_OK) return st;
+    // every workgroup writes its own partial and the total reads exactly g:
+    // nothing in the array needs clearing between calls
+    if (t == MXS_F64)
+        dot_kernel<double><<<g, kVNT, 0, s>>>(n, (const double *)a, (const double *)b, parts);
+    else
+        dot_kernel<float><<<g, kVNT, 0, s>>>(n, (const float *)a, (const float *)b, parts);
+    MXS_HIP(hipGetLastError());
+    total_kernel<<<1, kFinNT, 0, s>>>(parts, g, result);
+    MXS_HIP(hipGetLastError());
     return MXS_OK;
 }
 

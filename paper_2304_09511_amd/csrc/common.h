@@ -21,6 +21,8 @@ constexpr int kNumXcd = 8; // MI355X: 8 accelerator complex dies, 32 CUs each
 // Records a failed HIP call (error name, message and source position) for
 // mxs_last_error(); returns the status it maps to.
 mxs_status note_hip_error(hipError_t e, const char *where);
+// The text mxs_last_error() returns (per thread).
+extern thread_local char g_last_error[512];
 
 #define MXS_STR2(x) #x
 #define MXS_STR(x) MXS_STR2(x)
@@ -361,6 +363,8 @@ mxs_status coo_irp_launch(int64_t nnz, int32_t nrows, const int32_t *ai, int32_t
 // cg.hip
 mxs_status dot_launch(int64_t n, mxs_dtype t, const void *a, const void *b, double *result,
                       hipStream_t s);
+mxs_status dot_noalloc_launch(int64_t n, mxs_dtype t, const void *a, const void *b, double *result,
+                              hipStream_t s);
 mxs_status axpby_launch(int64_t n, mxs_dtype t, double alpha, const void *x, double beta,
                         void *y, hipStream_t s);
 size_t cg_workspace_bytes(int64_t n, int32_t mixed, int64_t parts64, int64_t parts32);

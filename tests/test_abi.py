@@ -121,6 +121,9 @@ def test_calls_reject_null_handles_and_bad_enums(lib):
     assert lib.mxs_destroy(None) == 0
     assert lib.mxs_dot(-1, 0, None, None, None, None) == -1
     assert lib.mxs_dot(4, 3, FAKE, FAKE, FAKE, None) == -1
+    assert lib.mxs_dot_noalloc(-1, 0, None, None, None, None) == -1
+    assert lib.mxs_dot_noalloc(4, 3, FAKE, FAKE, FAKE, None) == -1
+    assert lib.mxs_dot_noalloc(4, 0, FAKE, FAKE, None, None) == -1
     assert lib.mxs_axpby(4, 0, 1.0, None, 0.0, FAKE, None) == -1
     assert lib.mxs_stencil_coo(4, 9, 26.0, -1.0, FAKE, FAKE, FAKE, 0, None) == -1
     assert lib.mxs_stencil_coo(2000, 27, 26.0, -1.0, FAKE, FAKE, FAKE, 0, None) == -10
