@@ -21,10 +21,10 @@
  *     mxs_dtype; vectors passed with a matrix have that matrix's dtype.
  *   - A call that fails validation leaves its outputs untouched.
  *   - Memory: the library allocates device memory only for the arrays a
- *     handle owns (copies made without MXS_BORROW, analysis plans) and for
- *     temporaries of conversions, checks and feature extraction; all of it
- *     is freed by mxs_destroy or before the call returns.  Outputs and CG
- *     workspaces are allocated by the caller.
+ *     handle owns (copies made without MXS_BORROW) and for temporaries of
+ *     conversions, checks, plan sizing and feature extraction; all of it is
+ *     freed by mxs_destroy or before the call returns.  Execution plans,
+ *     outputs and CG workspaces are allocated by the caller.
  */
 #ifndef MXS_H
 #define MXS_H
@@ -48,7 +48,8 @@ typedef enum {
     MXS_ERR_HIP = -7,            /* a HIP runtime error, including device faults */
     MXS_ERR_BREAKDOWN = -8,      /* CG: p.Ap <= 0 or not finite (A not SPD) */
     MXS_ERR_NONFINITE = -9,      /* NaN or Inf in a CG right-hand side or start vector */
-    MXS_ERR_UNSUPPORTED = -10    /* operation not defined for this format/dtype/shape */
+    MXS_ERR_UNSUPPORTED = -10,   /* operation not defined for this format/dtype/shape */
+    MXS_ERR_NO_PLAN = -11        /* the handle has no plan: call mxs_optimize first */
 } mxs_status;
 
 typedef enum {
@@ -192,15 +193,45 @@ mxs_status mxs_cast(mxs_mat src, mxs_dtype dtype, void *vals, mxs_mat *out, void
  * SpMV (Algorithms 1-3)
  * --------------------------------------------------------------------- */
 
-/* Builds the format's execution plan [syncs]: CSR and COO tiles of a fixed
- * number of entries with their row starts and carries, a row-blocked copy of
- * the DIA values (when its padding stays within nrows/8 rows), an ELL copy
- * of CSR rows of near-equal length, COO and CSR column blocks for scattered
- * columns over a large x, and what every other implementation below needs.
- * The copies are optional: without memory for one, its implementation is
- * not applicable.  Idempotent.  mxs_spmv runs it on first use if not
- * called. */
-mxs_status mxs_optimize(mxs_mat A, void *stream);
+/* Execution plans (the optimize stage of Section VI-A's Table I: create,
+ * optimize, execute, destroy).  A plan lives in device memory the CALLER
+ * allocates and keeps alive, unchanged, until mxs_destroy or the next
+ * mxs_optimize of the handle; the library allocates none of it.  It holds:
+ *   COO, CSR: tiles of a fixed number of entries with their first rows and
+ *     flags, and the carries mxs_spmv puts the partial sums of rows that span
+ *     tiles in;
+ *   CSR: an ELL copy when rows have near-equal lengths (at most 5% padding
+ *     slots; skipped with MXS_PLAN_NO_ELL);
+ *   COO, CSR: column blocks when x is large and the entries scattered
+ *     (see implementation CSR 4 below; skipped with MXS_PLAN_NO_COLBLK);
+ *   DIA: a row-blocked copy of the values, only with MXS_PLAN_DIA_BLOCKED
+ *     (measured within 3% of the diagonal-major kernel on the stencil);
+ *   split and HYB handles: their two parts' plans; ELL, SELL: nothing. */
+#define MXS_PLAN_NO_ELL 1u      /* CSR: no ELL copy (implementation 3 not applicable) */
+#define MXS_PLAN_NO_COLBLK 2u   /* COO, CSR: no column blocks */
+#define MXS_PLAN_DIA_BLOCKED 4u /* DIA: make the row-blocked copy (implementations 0, 1) */
+
+/* Bytes of workspace mxs_optimize(A, opts, ...) needs [syncs].  It measures
+ * what the layout depends on (longest row, scattered entries, entries per
+ * column block) on the device with a 4 KiB temporary it frees before
+ * returning.  The bytes include temporaries used only while the plan is
+ * built.  Parts of split matrices and column blocks are planned with their
+ * parent: MXS_ERR_INVALID_ARG for them, and for unknown option bits. */
+mxs_status mxs_plan_size(mxs_mat A, unsigned opts, size_t *bytes, void *stream);
+
+/* Builds A's plan in workspace[bytes] (device memory, 256-byte aligned,
+ * bytes >= mxs_plan_size(A, opts)) [syncs]; allocates nothing.  A plan built
+ * earlier is dropped first (its memory may be reused as this workspace, or
+ * freed once this returns); no other call on A may be in flight meanwhile.
+ * MXS_ERR_INVALID_ARG for a workspace that is too small or misaligned; on
+ * any failure A is left without a plan.
+ * Every call below that runs SpMV kernels on A returns MXS_ERR_NO_PLAN until
+ * A has a plan: mxs_spmv, mxs_spmv_ws, mxs_set_impl, mxs_get_impl,
+ * mxs_tune, mxs_cg_solve (A and A32), mxs_pcg_solve. */
+mxs_status mxs_optimize(mxs_mat A, unsigned opts, void *workspace, size_t bytes, void *stream);
+
+/* Whether A has a plan, and its options [host only]; either pointer may be NULL. */
+mxs_status mxs_plan_info(mxs_mat A, int32_t *optimized, unsigned *opts);
 
 /* SpMV implementations (Section III keeps one kernel per format; no single
  * kernel wins on every matrix, so each format here has several, all giving
@@ -232,9 +263,9 @@ mxs_status mxs_optimize(mxs_mat A, void *stream);
  * else 0; DIA the lowest
  * applicable id; ELL and SELL have one implementation, 0.
  * mxs_impl_count: number of ids of A's format (0 for split matrices).
- * mxs_set_impl [syncs: builds the plan]: MXS_ERR_UNSUPPORTED for an id that
- *   is not applicable to A or a split matrix.
- * mxs_get_impl [syncs: builds the plan]: the active id.
+ * mxs_set_impl [host only]: MXS_ERR_UNSUPPORTED for an id that is not
+ *   applicable to A or a split matrix.
+ * mxs_get_impl [host only]: the active id.
  * mxs_tune [syncs]: runs every applicable implementation (3 untimed calls,
  *   then `reps` >= 1 timed calls y = A*x each), keeps the one with the
  *   smallest median time and returns its id; ms[mxs_impl_count] (may be
@@ -252,10 +283,24 @@ mxs_status mxs_tune(mxs_mat A, const void *x, void *y, int32_t reps, int32_t *im
  * cleared first, which is what Algorithms 2 and 3 compute).  Summation
  * order differs from a sequential loop; results are deterministic (no
  * floating-point atomics).  x and y must not overlap (MXS_ERR_INVALID_ARG).
- * Rows without entries get 0.  The plan's carry buffer (partial sums of rows
- * that span tiles) belongs to the handle: calls on one handle issued to
- * different streams must not overlap; calls on one stream are ordered. */
+ * Rows without entries get 0.  Never builds a plan (MXS_ERR_NO_PLAN without
+ * one) and allocates nothing.  The plan's carries (partial sums of rows that
+ * span tiles) are shared by every mxs_spmv on the handle: calls on one
+ * handle issued to different streams must not overlap (use mxs_spmv_ws);
+ * calls on one stream are ordered. */
 mxs_status mxs_spmv(mxs_mat A, const void *x, void *y, void *stream);
+
+/* Bytes of scratch mxs_spmv_ws needs for A's carries (0 when none) [host
+ * only; MXS_ERR_NO_PLAN without a plan]. */
+mxs_status mxs_spmv_scratch_size(mxs_mat A, size_t *bytes);
+
+/* mxs_spmv with the carries in the caller's scratch[bytes] (device, not
+ * overlapping x or y; may be NULL when mxs_spmv_scratch_size gives 0)
+ * instead of the plan's [async].  Calls on one handle from different streams
+ * may overlap when each has its own scratch; the results equal mxs_spmv's
+ * bit for bit. */
+mxs_status mxs_spmv_ws(mxs_mat A, const void *x, void *y, void *scratch, size_t bytes,
+                       void *stream);
 
 /* Dot product a.b of n values of `dtype`, accumulated in FP64, written to
  * the device double *result [async].  Deterministic. */
@@ -407,13 +452,22 @@ mxs_status mxs_split_parts(mxs_mat H, mxs_mat *band, mxs_mat *rest);
  * one more sweep; on the coarsest level one sweep from zero.
  * --------------------------------------------------------------------- */
 
-/* Builds the hierarchy [syncs]: n >= 1 divisible by 2^(levels-1), levels
- * in [1, 12], n^3 rows and (3n-2)^3 entries within int32 (else
- * MXS_ERR_UNSUPPORTED).  Memory: each level's CSR operator, a copy of its
- * off-diagonal entries sliced for the smoother, and two vectors per coarse
- * level.  Calls on one hierarchy must not overlap (they share the coarse
- * vectors). */
-mxs_status mxs_mg_create(int32_t n, int32_t levels, mxs_mg *out, void *stream);
+/* Bytes of device workspace the hierarchy of mxs_mg_create(n, levels) needs
+ * [host only]: each level's CSR operator, a copy of its off-diagonal entries
+ * sliced for the smoother, its diagonal and colour order, two vectors per
+ * coarse level, and temporaries used only while it is built.  Shape rules
+ * as for mxs_mg_create. */
+mxs_status mxs_mg_size(int32_t n, int32_t levels, size_t *bytes);
+
+/* Builds the hierarchy [syncs] in the caller's workspace[bytes] (device,
+ * 256-byte aligned, bytes >= mxs_mg_size; kept alive and unchanged until
+ * mxs_mg_destroy); allocates no device memory.  n >= 1 divisible by
+ * 2^(levels-1), levels in [1, 12] (MXS_ERR_INVALID_ARG otherwise, and for a
+ * workspace that is too small); n^3 rows and (3n-2)^3 entries within int32
+ * (else MXS_ERR_UNSUPPORTED).  Calls on one hierarchy must not overlap
+ * (they share the coarse vectors). */
+mxs_status mxs_mg_create(int32_t n, int32_t levels, void *workspace, size_t bytes, mxs_mg *out,
+                         void *stream);
 mxs_status mxs_mg_destroy(mxs_mg M);
 
 /* Grid edge and operator (an MXS_CSR handle owned by M: mxs_destroy on it
@@ -435,7 +489,8 @@ mxs_status mxs_pcg_workspace_size(mxs_mg M, size_t *bytes);
 /* PCG on A x = b with z = M^{-1} r (HPCG's recurrences: beta = r.z over the
  * previous r.z, alpha = r.z / p.Ap; stop when ||r_k|| <= rtol ||r_0||)
  * [syncs].  A is the finest operator in any FP64 format (NULL: M's own CSR
- * operator); it must be that matrix.  opts: rtol, maxit, check_every and
+ * operator from mxs_mg_level, which then needs a plan of its own); it must
+ * be that matrix.  opts: rtol, maxit, check_every and
  * timing as for mxs_cg_solve; mixed must be 0.  Statuses as mxs_cg_solve,
  * and MXS_ERR_BREAKDOWN also when r.z <= 0. */
 mxs_status mxs_pcg_solve(mxs_mg M, mxs_mat A, const double *b, double *x,

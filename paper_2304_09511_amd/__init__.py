@@ -34,8 +34,10 @@ STATUS = {
     0: "MXS_OK", 1: "MXS_NOT_CONVERGED", -1: "MXS_ERR_INVALID_ARG", -2: "MXS_ERR_INDEX_RANGE",
     -3: "MXS_ERR_UNSORTED", -4: "MXS_ERR_DUPLICATE", -5: "MXS_ERR_DIA_TOO_SPARSE",
     -6: "MXS_ERR_OUT_OF_MEMORY", -7: "MXS_ERR_HIP", -8: "MXS_ERR_BREAKDOWN",
-    -9: "MXS_ERR_NONFINITE", -10: "MXS_ERR_UNSUPPORTED",
+    -9: "MXS_ERR_NONFINITE", -10: "MXS_ERR_UNSUPPORTED", -11: "MXS_ERR_NO_PLAN",
 }
+# plan options (mxs_plan_size, mxs_optimize)
+PLAN_NO_ELL, PLAN_NO_COLBLK, PLAN_DIA_BLOCKED = 1, 2, 4
 
 
 class MxsError(RuntimeError):
@@ -85,7 +87,11 @@ _SIGS = {
     "mxs_to_hyb": (I32, [P, I32, P, P, P, P, P, P, P]),
     "mxs_to_sell": (I32, [P, I32, P, P, P, P, P, P]),
     "mxs_cast": (I32, [P, I32, P, P, P]),
-    "mxs_optimize": (I32, [P, P]),
+    "mxs_plan_size": (I32, [P, U32, P, P]),
+    "mxs_optimize": (I32, [P, U32, P, SZ, P]),
+    "mxs_plan_info": (I32, [P, P, P]),
+    "mxs_spmv_scratch_size": (I32, [P, P]),
+    "mxs_spmv_ws": (I32, [P, P, P, P, SZ, P]),
     "mxs_impl_count": (I32, [P]),
     "mxs_set_impl": (I32, [P, I32, P]),
     "mxs_get_impl": (I32, [P, P, P]),
@@ -96,7 +102,8 @@ _SIGS = {
     "mxs_axpby": (I32, [I64, I32, D, P, D, P, P]),
     "mxs_cg_workspace_size": (I32, [P, I32, P]),
     "mxs_cg_solve": (I32, [P, P, P, P, P, P, P, SZ, P]),
-    "mxs_mg_create": (I32, [I32, I32, P, P]),
+    "mxs_mg_size": (I32, [I32, I32, P]),
+    "mxs_mg_create": (I32, [I32, I32, P, SZ, P, P]),
     "mxs_mg_destroy": (I32, [P]),
     "mxs_mg_level": (I32, [P, I32, P, P]),
     "mxs_symgs": (I32, [P, I32, P, P, P]),
@@ -204,6 +211,7 @@ class Matrix:
         self._h = handle
         self._keep = list(keep)
         self._owned = owned  # False for the parts of a split matrix
+        self._plan = None    # the plan's workspace (device memory the handle reads)
         lib = load()
         fmt, dt, nr, nc, nnz, nd = (C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(),
                                     C.c_int64(), C.c_int32())
@@ -421,9 +429,44 @@ class Matrix:
         B.close()
         return tuple(out)
 
-    def optimize(self):
-        _check(load().mxs_optimize(self._h, _stream()), "mxs_optimize")
+    def plan_size(self, opts=0):
+        """Bytes of device workspace the plan needs with these options."""
+        n = C.c_size_t()
+        _check(load().mxs_plan_size(self._h, int(opts), C.byref(n), _stream()), "mxs_plan_size")
+        return n.value
+
+    def optimize(self, opts=0, workspace=None):
+        """Builds the plan in a torch tensor (allocated here unless given),
+        kept with this Matrix until close() or the next optimize()."""
+        torch = _torch()
+        n = self.plan_size(opts)
+        if workspace is None:
+            workspace = torch.empty(max(n, 1), dtype=torch.uint8, device="cuda")
+        if workspace.numel() * workspace.element_size() < n:
+            raise ValueError("plan workspace too small")
+        _check(load().mxs_optimize(self._h, int(opts), _ptr(workspace),
+                                   workspace.numel() * workspace.element_size(), _stream()),
+               "mxs_optimize")
+        self._plan = workspace
         return self
+
+    @property
+    def optimized(self):
+        v = C.c_int32()
+        _check(load().mxs_plan_info(self._h, C.byref(v), None), "mxs_plan_info")
+        return bool(v.value)
+
+    def ensure_plan(self):
+        """Builds the default plan if the handle has none (the C library never
+        builds one implicitly)."""
+        if not self.optimized:
+            self.optimize()
+        return self
+
+    def spmv_scratch_size(self):
+        n = C.c_size_t()
+        _check(load().mxs_spmv_scratch_size(self._h, C.byref(n)), "mxs_spmv_scratch_size")
+        return n.value
 
     # SpMV implementations of the format (ids as in mxs_set_impl)
     IMPL_NAMES = {COO: ("row_tiles", "segmented", "column_blocks"),
@@ -433,12 +476,14 @@ class Matrix:
 
     @property
     def impl(self):
+        self.ensure_plan()
         v = C.c_int32()
         _check(load().mxs_get_impl(self._h, C.byref(v), _stream()), "mxs_get_impl")
         return v.value
 
     @impl.setter
     def impl(self, i):
+        self.ensure_plan()
         _check(load().mxs_set_impl(self._h, int(i), _stream()), "mxs_set_impl")
 
     def impl_count(self):
@@ -446,6 +491,7 @@ class Matrix:
 
     def parts(self):
         """(band, rest) of a split or HYB matrix: handles owned by this one."""
+        self.ensure_plan()  # the parts are planned with this matrix
         b, r = C.c_void_p(), C.c_void_p()
         _check(load().mxs_split_parts(self._h, C.byref(b), C.byref(r)), "mxs_split_parts")
         return Matrix(b, [self], owned=False), Matrix(r, [self], owned=False)
@@ -467,6 +513,7 @@ class Matrix:
             raise TypeError("x and y must have the matrix's dtype")
         if x.numel() != self.ncols or y.numel() != self.nrows:
             raise ValueError("vector lengths do not match the matrix")
+        self.ensure_plan()
         n = max(self.impl_count(), 1)
         ms = (C.c_double * n)()
         best = C.c_int32()
@@ -479,6 +526,7 @@ class Matrix:
             _check(_lib.mxs_destroy(self._h), "mxs_destroy")
         self._h = None
         self._keep = []
+        self._plan = None
 
     def __del__(self):
         try:
@@ -503,8 +551,11 @@ def _median_ms(torch, fn, reps):
 
 
 # --------------------------------------------------------------- operations
-def spmv(A: Matrix, x, y=None):
-    """y = A x on the device (y allocated when not given)."""
+def spmv(A: Matrix, x, y=None, scratch=None):
+    """y = A x on the device (y allocated when not given; A's default plan
+    built first if it has none).  With `scratch` (a device tensor of at least
+    A.spmv_scratch_size() bytes) the carries go there (mxs_spmv_ws), so calls
+    on A from several streams may overlap."""
     torch = _torch()
     if y is None:
         y = torch.empty(A.nrows, dtype=x.dtype, device=x.device)
@@ -512,7 +563,13 @@ def spmv(A: Matrix, x, y=None):
         raise TypeError("x and y must have the matrix's dtype")
     if x.numel() != A.ncols or y.numel() != A.nrows:
         raise ValueError("vector lengths do not match the matrix")
-    _check(load().mxs_spmv(A.handle, _ptr(x), _ptr(y), _stream()), "mxs_spmv")
+    A.ensure_plan()
+    if scratch is None:
+        _check(load().mxs_spmv(A.handle, _ptr(x), _ptr(y), _stream()), "mxs_spmv")
+    else:
+        nb = scratch.numel() * scratch.element_size()
+        _check(load().mxs_spmv_ws(A.handle, _ptr(x), _ptr(y), _ptr(scratch) if nb else None, nb,
+                                  _stream()), "mxs_spmv_ws")
     return y
 
 
@@ -562,6 +619,9 @@ def cg_solve(A: Matrix, b, x0=None, rtol=1e-9, maxit=10000, mixed=False, A32=Non
     updates).  Returns (status, x, CgResult as a dict)."""
     torch = _torch()
     mode = MIXED_MODES[mixed]
+    A.ensure_plan()
+    if A32 is not None:
+        A32.ensure_plan()
     x = torch.zeros_like(b) if x0 is None else x0.clone()
     ws = workspace if workspace is not None else cg_workspace(A, mode)
     o = CgOpts(rtol, maxit, mode, max_outer, inner_rtol, check_every, 1 if timing else 0, delta)
@@ -578,9 +638,15 @@ class Multigrid:
     grids, finest first)."""
 
     def __init__(self, n, levels=4):
+        torch = _torch()
+        nb = C.c_size_t()
+        _check(load().mxs_mg_size(int(n), int(levels), C.byref(nb)), "mxs_mg_size")
+        self._ws = torch.empty(max(nb.value, 1), dtype=torch.uint8, device="cuda")
         h = C.c_void_p()
-        _check(load().mxs_mg_create(int(n), int(levels), C.byref(h), _stream()), "mxs_mg_create")
+        _check(load().mxs_mg_create(int(n), int(levels), _ptr(self._ws), nb.value, C.byref(h),
+                                    _stream()), "mxs_mg_create")
         self._h, self.n, self.levels = h, n, levels
+        self._lv = {}  # level -> (n, operator Matrix), kept: a plan built on one lives here
 
     @property
     def handle(self):
@@ -590,9 +656,11 @@ class Multigrid:
 
     def level(self, l):
         """(grid edge, operator Matrix owned by the hierarchy) of level l."""
-        n, a = C.c_int32(), C.c_void_p()
-        _check(load().mxs_mg_level(self.handle, int(l), C.byref(n), C.byref(a)), "mxs_mg_level")
-        return n.value, Matrix(a, [self], owned=False)
+        if l not in self._lv or self._lv[l][1]._h is None:
+            n, a = C.c_int32(), C.c_void_p()
+            _check(load().mxs_mg_level(self.handle, int(l), C.byref(n), C.byref(a)), "mxs_mg_level")
+            self._lv[l] = (n.value, Matrix(a, [], owned=False))
+        return self._lv[l]
 
     def symgs(self, level, r, x):
         """One symmetric Gauss-Seidel sweep of `level` on x in place."""
@@ -618,6 +686,7 @@ class Multigrid:
             nb = C.c_size_t()
             _check(load().mxs_pcg_workspace_size(self.handle, C.byref(nb)), "mxs_pcg_workspace_size")
             workspace = torch.empty(max(nb.value, 1), dtype=torch.uint8, device="cuda")
+        (A if A is not None else self.level(0)[1]).ensure_plan()
         o = CgOpts(rtol, maxit, 0, 0, 0.0, check_every, 1 if timing else 0, 0.0)
         r = CgResult()
         st = load().mxs_pcg_solve(self.handle, A.handle if A is not None else None, _ptr(b),
@@ -630,6 +699,10 @@ class Multigrid:
         if self._h is not None and _lib is not None:
             _check(_lib.mxs_mg_destroy(self._h), "mxs_mg_destroy")
         self._h = None
+        for _, m in self._lv.values():
+            m._h, m._plan = None, None
+        self._lv = {}
+        self._ws = None
 
     def __del__(self):
         try:

@@ -92,11 +92,19 @@ int64_t value_count(const mxs_mat_s *A)
     return A->nnz;
 }
 
-mxs_status ensure_plan(mxs_mat_s *A, hipStream_t s)
+// Calls that run SpMV kernels need the plan mxs_optimize builds: it is
+// never built implicitly.
+inline mxs_status need_plan(const mxs_mat_s *A) { return A->optimized ? MXS_OK : MXS_ERR_NO_PLAN; }
+
+// Sizing pass of A's plan (see PlanCtx); `tiny` holds the measurement counters.
+mxs_status plan_layout(mxs_mat_s *A, unsigned opts, void *tiny, PlanCtx *out, hipStream_t s)
 {
-    if (A->optimized) return MXS_OK;
-    std::lock_guard<std::mutex> lk(A->mu);
-    return build_plan(A, s);
+    PlanCtx c;
+    c.opts = opts;
+    c.tiny = tiny;
+    const mxs_status st = plan_walk(A, c, s);
+    *out = c;
+    return st;
 }
 
 bool overlaps(const void *a, size_t na, const void *b, size_t nb)
@@ -124,6 +132,7 @@ const char *mxs_status_string(mxs_status s)
     case MXS_ERR_BREAKDOWN: return "MXS_ERR_BREAKDOWN";
     case MXS_ERR_NONFINITE: return "MXS_ERR_NONFINITE";
     case MXS_ERR_UNSUPPORTED: return "MXS_ERR_UNSUPPORTED";
+    case MXS_ERR_NO_PLAN: return "MXS_ERR_NO_PLAN";
     }
     return "MXS_UNKNOWN_STATUS";
 }
@@ -422,7 +431,7 @@ mxs_status mxs_to_hyb(mxs_mat A, int32_t K, int32_t *ell_col, void *ell_val, int
         band->idx0 = ell_col;
         band->vals = ell_val;
         band->device = A->device;
-        band->part = true;
+        band->part = band->sub = true;
         auto *rest = new mxs_mat_s;
         rest->fmt = MXS_COO;
         rest->dtype = A->dtype;
@@ -433,7 +442,7 @@ mxs_status mxs_to_hyb(mxs_mat A, int32_t K, int32_t *ell_col, void *ell_val, int
         rest->idx1 = rest_aj;
         rest->vals = rest_av;
         rest->device = A->device;
-        rest->part = true;
+        rest->part = rest->sub = true;
         auto *h = new mxs_mat_s;
         h->fmt = MXS_HYB;
         h->dtype = A->dtype;
@@ -498,10 +507,65 @@ mxs_status mxs_to_sell(mxs_mat A, int32_t sigma, int32_t *perm, int64_t *cs, int
 // ---------------------------------------------------------------------------
 // SpMV and BLAS-1
 // ---------------------------------------------------------------------------
-mxs_status mxs_optimize(mxs_mat A, void *stream)
+constexpr unsigned kPlanOpts = MXS_PLAN_NO_ELL | MXS_PLAN_NO_COLBLK | MXS_PLAN_DIA_BLOCKED;
+
+mxs_status mxs_plan_size(mxs_mat A, unsigned opts, size_t *bytes, void *stream)
+{
+    if (!A || !bytes || (opts & ~kPlanOpts) || A->sub) return MXS_ERR_INVALID_ARG;
+    return guarded([&] {
+        hipStream_t s = S(stream);
+        std::lock_guard<std::mutex> lk(A->mu);
+        void *tiny = nullptr;
+        MXS_HIP(hipMallocAsync(&tiny, kTinyBytes, s));
+        PlanCtx c;
+        mxs_status st = plan_layout(A, opts, tiny, &c, s);
+        (void)hipFreeAsync(tiny, s);
+        if (hipStreamSynchronize(s) != hipSuccess && st == MXS_OK) st = MXS_ERR_HIP;
+        if (st == MXS_OK) *bytes = c.total();
+        return st;
+    });
+}
+
+mxs_status mxs_optimize(mxs_mat A, unsigned opts, void *workspace, size_t bytes, void *stream)
+{
+    if (!A || (opts & ~kPlanOpts) || A->sub || (bytes > 0 && !workspace)) return MXS_ERR_INVALID_ARG;
+    if ((uintptr_t)workspace % kPlanAlign != 0) return MXS_ERR_INVALID_ARG;
+    return guarded([&] {
+        hipStream_t s = S(stream);
+        std::lock_guard<std::mutex> lk(A->mu);
+        // the earlier plan (if any) is dropped first: the workspace may be its memory
+        plan_reset(A);
+        // the layout, its counters in the workspace's first bytes
+        PlanCtx z;
+        mxs_status st = plan_layout(A, opts, bytes >= kTinyBytes ? workspace : nullptr, &z, s);
+        if (st != MXS_OK) return st;
+        if (bytes < z.total()) return MXS_ERR_INVALID_ARG;
+        // then the plan itself
+        PlanCtx c;
+        c.opts = opts;
+        c.build = true;
+        c.keep_base = (char *)workspace;
+        char *t = (char *)workspace + PlanCtx::up(z.keep_used);
+        c.tiny = z.tiny_used ? (void *)t : nullptr;
+        c.tmp_base = t + (z.tiny_used ? kTinyBytes : 0);
+        st = plan_walk(A, c, s);
+        if (st == MXS_OK && hipStreamSynchronize(s) != hipSuccess) st = MXS_ERR_HIP;
+        if (st == MXS_OK && (c.keep_used != z.keep_used || c.total() > z.total())) {
+            snprintf(g_last_error, sizeof g_last_error,
+                     "plan layout differs between its sizing and build passes");
+            st = MXS_ERR_HIP;
+        }
+        if (st != MXS_OK) plan_reset(A);
+        return st;
+    });
+}
+
+mxs_status mxs_plan_info(mxs_mat A, int32_t *optimized, unsigned *opts)
 {
     if (!A) return MXS_ERR_INVALID_ARG;
-    return guarded([&] { return ensure_plan(A, S(stream)); });
+    if (optimized) *optimized = A->optimized ? 1 : 0;
+    if (opts) *opts = A->plan_opts;
+    return MXS_OK;
 }
 
 mxs_status mxs_split_parts(mxs_mat H, mxs_mat *band, mxs_mat *rest)
@@ -523,7 +587,7 @@ mxs_status mxs_set_impl(mxs_mat A, int32_t impl, void *stream)
     if (!A) return MXS_ERR_INVALID_ARG;
     if (is_split(A)) return MXS_ERR_UNSUPPORTED;
     return guarded([&] {
-        mxs_status st = ensure_plan(A, S(stream));
+        mxs_status st = need_plan(A);
         if (st != MXS_OK) return st;
         std::lock_guard<std::mutex> lk(A->mu);
         if (!impl_ok(A, impl)) return MXS_ERR_UNSUPPORTED;
@@ -536,8 +600,9 @@ mxs_status mxs_get_impl(mxs_mat A, int32_t *impl, void *stream)
 {
     if (!A || !impl) return MXS_ERR_INVALID_ARG;
     if (is_split(A)) return MXS_ERR_UNSUPPORTED;
+    (void)stream;
     return guarded([&] {
-        mxs_status st = ensure_plan(A, S(stream));
+        mxs_status st = need_plan(A);
         if (st == MXS_OK) *impl = A->impl;
         return st;
     });
@@ -553,7 +618,7 @@ mxs_status mxs_tune(mxs_mat A, const void *x, void *y, int32_t reps, int32_t *im
     if (overlaps(x, es * A->ncols, y, es * A->nrows)) return MXS_ERR_INVALID_ARG;
     return guarded([&] {
         hipStream_t s = S(stream);
-        mxs_status st = ensure_plan(A, s);
+        mxs_status st = need_plan(A);
         if (st != MXS_OK) return st;
         std::lock_guard<std::mutex> lk(A->mu);
         return tune(A, x, y, reps, impl, ms, s);
@@ -567,10 +632,33 @@ mxs_status mxs_spmv(mxs_mat A, const void *x, void *y, void *stream)
     if ((A->ncols > 0 && !x) || (A->nrows > 0 && !y)) return MXS_ERR_INVALID_ARG;
     if (overlaps(x, es * A->ncols, y, es * A->nrows)) return MXS_ERR_INVALID_ARG;
     return guarded([&] {
-        hipStream_t s = S(stream);
-        mxs_status st = ensure_plan(A, s);
+        mxs_status st = need_plan(A);
         if (st != MXS_OK) return st;
-        return spmv_launch(A, x, y, nullptr, nullptr, s);
+        return spmv_launch(A, x, y, nullptr, nullptr, S(stream));
+    });
+}
+
+mxs_status mxs_spmv_scratch_size(mxs_mat A, size_t *bytes)
+{
+    if (!A || !bytes) return MXS_ERR_INVALID_ARG;
+    if (!A->optimized) return MXS_ERR_NO_PLAN;
+    *bytes = spmv_scratch_bytes(A);
+    return MXS_OK;
+}
+
+mxs_status mxs_spmv_ws(mxs_mat A, const void *x, void *y, void *scratch, size_t bytes, void *stream)
+{
+    if (!A) return MXS_ERR_INVALID_ARG;
+    const size_t es = dsize(A->dtype);
+    if ((A->ncols > 0 && !x) || (A->nrows > 0 && !y)) return MXS_ERR_INVALID_ARG;
+    if (overlaps(x, es * A->ncols, y, es * A->nrows)) return MXS_ERR_INVALID_ARG;
+    if (!A->optimized) return MXS_ERR_NO_PLAN;
+    const size_t need = spmv_scratch_bytes(A);
+    if (bytes < need || (need > 0 && !scratch)) return MXS_ERR_INVALID_ARG;
+    if (scratch && (overlaps(scratch, need, x, es * A->ncols) || overlaps(scratch, need, y, es * A->nrows)))
+        return MXS_ERR_INVALID_ARG;
+    return guarded([&] {
+        return spmv_launch(A, x, y, nullptr, nullptr, S(stream), need > 0 ? scratch : nullptr);
     });
 }
 
@@ -627,8 +715,8 @@ mxs_status mxs_cg_solve(mxs_mat A, mxs_mat A32, const double *b, double *x, cons
         return MXS_ERR_INVALID_ARG;
     return guarded([&] {
         hipStream_t s = S(stream);
-        mxs_status st = ensure_plan(A, s);
-        if (st == MXS_OK && opts->mixed) st = ensure_plan(A32, s);
+        mxs_status st = need_plan(A);
+        if (st == MXS_OK && opts->mixed) st = need_plan(A32);
         if (st != MXS_OK) return st;
         if (A->nrows == 0) {
             *res = mxs_cg_result{};
@@ -642,13 +730,33 @@ mxs_status mxs_cg_solve(mxs_mat A, mxs_mat A32, const double *b, double *x, cons
 // ---------------------------------------------------------------------------
 // HPCG's preconditioner
 // ---------------------------------------------------------------------------
-mxs_status mxs_mg_create(int32_t n, int32_t levels, mxs_mg *out, void *stream)
+static mxs_status mg_shape_ok(int32_t n, int32_t levels)
 {
-    if (!out || n < 1 || levels < 1 || levels > 12) return MXS_ERR_INVALID_ARG;
+    if (n < 1 || levels < 1 || levels > 12) return MXS_ERR_INVALID_ARG;
     if (n % (1 << (levels - 1)) != 0) return MXS_ERR_INVALID_ARG;
     if ((int64_t)n * n * n > INT32_MAX || mxs_stencil_nnz(n, 27) > INT32_MAX)
         return MXS_ERR_UNSUPPORTED;
-    return guarded([&] { return mg_create(n, levels, out, S(stream)); });
+    return MXS_OK;
+}
+
+mxs_status mxs_mg_size(int32_t n, int32_t levels, size_t *bytes)
+{
+    if (!bytes) return MXS_ERR_INVALID_ARG;
+    const mxs_status st = mg_shape_ok(n, levels);
+    if (st != MXS_OK) return st;
+    return guarded([&] {
+        *bytes = mg_bytes(n, levels);
+        return *bytes > 0 ? MXS_OK : MXS_ERR_UNSUPPORTED;
+    });
+}
+
+mxs_status mxs_mg_create(int32_t n, int32_t levels, void *workspace, size_t bytes, mxs_mg *out,
+                         void *stream)
+{
+    if (!out || !workspace || (uintptr_t)workspace % kPlanAlign != 0) return MXS_ERR_INVALID_ARG;
+    const mxs_status st = mg_shape_ok(n, levels);
+    if (st != MXS_OK) return st;
+    return guarded([&] { return mg_create(n, levels, workspace, bytes, out, S(stream)); });
 }
 
 mxs_status mxs_mg_destroy(mxs_mg M)
@@ -709,7 +817,7 @@ mxs_status mxs_pcg_solve(mxs_mg M, mxs_mat A, const double *b, double *x, const 
     if (workspace_bytes < pcg_workspace_bytes(n)) return MXS_ERR_INVALID_ARG;
     return guarded([&] {
         hipStream_t s = S(stream);
-        mxs_status st = ensure_plan(A, s);
+        mxs_status st = need_plan(A);
         if (st != MXS_OK) return st;
         return pcg_solve(M, A, b, x, opts, res, workspace, workspace_bytes, s);
     });

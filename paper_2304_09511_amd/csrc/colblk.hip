@@ -15,6 +15,7 @@
 #include "common.h"
 
 #include <algorithm>
+#include <vector>
 
 namespace mxs {
 
@@ -50,6 +51,45 @@ __global__ void colblk_far_kernel(const int32_t *__restrict__ irp, const int32_t
         for (int w = 0; w < 256 / kWave; ++w) t += red[w];
         atomicAdd(far, t);
     }
+}
+
+// The same count from sorted COO arrays: entry k's predecessor in its row
+// is entry k-1 when that holds the same row id.
+__global__ void colblk_far_coo_kernel(const int32_t *__restrict__ ai, const int32_t *__restrict__ aj,
+                                      int64_t nnz, int64_t half, int32_t lpl,
+                                      unsigned long long *__restrict__ far)
+{
+    __shared__ unsigned long long red[256 / kWave];
+    unsigned long long c = 0;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nnz;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = ai[k], j = aj[k];
+        const int32_t prev_line = k > 0 && ai[k - 1] == ai[k] ? aj[k - 1] / lpl : -1;
+        c += (uint64_t)((j - r >= half || r - j >= half) && aj[k] / lpl != prev_line);
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) c += __shfl_xor(c, off, kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < 256 / kWave; ++w) t += red[w];
+        atomicAdd(far, t);
+    }
+}
+
+// cnt[b] += entries with columns in block b (K <= kColBlkMax blocks of width cb).
+__global__ void colblk_hist_kernel(const int32_t *__restrict__ aj, int64_t nnz, int32_t cb, int K,
+                                   unsigned long long *__restrict__ cnt)
+{
+    __shared__ unsigned int h[kColBlkMax];
+    for (int b = threadIdx.x; b < K; b += blockDim.x) h[b] = 0u;
+    __syncthreads();
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nnz;
+         k += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&h[aj[k] / cb], 1u);
+    __syncthreads();
+    for (int b = threadIdx.x; b < K; b += blockDim.x)
+        if (h[b]) atomicAdd(&cnt[b], (unsigned long long)h[b]);
 }
 
 // cnt[b*nrows + r] = entries of row r in column block b (cnt zeroed first).
@@ -99,104 +139,87 @@ __global__ void colblk_fill_kernel(const int32_t *__restrict__ irp, const int32_
 }
 
 static uint32_t row_grid(int32_t nrows) { return (uint32_t)std::clamp<int64_t>(((int64_t)nrows + 255) / 256, 1, 16384); }
+static uint32_t entry_grid(int64_t nnz) { return (uint32_t)std::clamp<int64_t>((nnz + 255) / 256, 1, 4096); }
 
-// Builds the blocks of COO or CSR matrix A when x exceeds kColBlkMinX bytes
-// and at least half of the entries are scattered (colblk_far_kernel).  Optional: without memory for the copy the matrix keeps its
-// other implementations.  The blocks are part handles owned by A.
-static mxs_status colblk_make(mxs_mat_s *A, const int32_t *irp, hipStream_t s)
+// Column blocks of COO or CSR matrix A, laid out in the plan when x has at
+// least kColBlkMinX bytes and at least half of the entries are scattered
+// (not for parts, nor with MXS_PLAN_NO_COLBLK).  irp: A's row pointers in
+// the build pass (CSR: its own; COO: a temporary of the plan).  The blocks
+// are part handles owned by A, each with its own tiles and carries.
+mxs_status colblk_plan(mxs_mat_s *A, const int32_t *irp, PlanCtx &c, hipStream_t s)
 {
     const int64_t xb = (int64_t)A->ncols * (int64_t)dsize(A->dtype);
+    if ((A->fmt != MXS_COO && A->fmt != MXS_CSR) || A->sub || A->part || A->nnz == 0 ||
+        A->nrows == 0 || xb < kColBlkMinX || (c.opts & MXS_PLAN_NO_COLBLK))
+        return MXS_OK;
     const int K = (int)std::min<int64_t>((xb + kColBlkX - 1) / kColBlkX, kColBlkMax);
     const int32_t cb = (int32_t)(((int64_t)A->ncols + K - 1) / K);
     const int32_t n = A->nrows;
     const bool coo = A->fmt == MXS_COO;
 
-    unsigned long long *far = nullptr;
-    MXS_HIP(hipMallocAsync((void **)&far, sizeof(unsigned long long), s));
-    mxs_status st = fill_bytes0(far, sizeof(unsigned long long), s);
-    if (st == MXS_OK) {
-        colblk_far_kernel<<<row_grid(n), 256, 0, s>>>(irp, A->idx1, n, cb / 2,
-                                                      (int32_t)(128 / dsize(A->dtype)), far);
-        st = launch_status();
-    }
-    unsigned long long h_far = 0;
-    if (st == MXS_OK && hipMemcpyAsync(&h_far, far, sizeof h_far, hipMemcpyDeviceToHost, s) != hipSuccess)
-        st = MXS_ERR_HIP;
-    (void)hipFreeAsync(far, s);
+    // measured in both passes: scattered entries, entries per block
+    auto *cnt = (unsigned long long *)c.counters(); // [0] scattered, [1 + b] block b
+    if (!cnt) return MXS_ERR_INVALID_ARG;
+    mxs_status st = fill_bytes0(cnt, sizeof(unsigned long long) * ((size_t)K + 1), s);
+    if (st != MXS_OK) return st;
+    const int32_t lpl = (int32_t)(128 / dsize(A->dtype));
+    if (coo)
+        colblk_far_coo_kernel<<<entry_grid(A->nnz), 256, 0, s>>>(A->idx0, A->idx1, A->nnz, cb / 2, lpl, cnt);
+    else
+        colblk_far_kernel<<<row_grid(n), 256, 0, s>>>(irp, A->idx1, n, cb / 2, lpl, cnt);
+    colblk_hist_kernel<<<entry_grid(A->nnz), 256, 0, s>>>(A->idx1, A->nnz, cb, K, cnt + 1);
+    MXS_HIP(hipGetLastError());
+    std::vector<unsigned long long> h((size_t)K + 1);
+    MXS_HIP(hipMemcpyAsync(h.data(), cnt, sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost, s));
     MXS_HIP(hipStreamSynchronize(s));
-    if (st != MXS_OK) return st;
-    if (2 * (int64_t)h_far < A->nnz) return MXS_OK;
-
-    // the copy: CSR keeps K row-pointer arrays, then the columns, then the
-    // values; COO keeps the row ids, columns and values (its block row
-    // pointers are only needed here)
-    const size_t np = (size_t)K * ((size_t)n + 1);
-    const size_t nidx = (coo ? 0 : np) + (size_t)A->nnz * (coo ? 2 : 1); // int32 words
-    const size_t vbase = (nidx * sizeof(int32_t) + 255) / 256 * 256;      // values 256-byte aligned
-    void *buf = nullptr;
-    if (hipMalloc(&buf, vbase + (size_t)A->nnz * dsize(A->dtype)) != hipSuccess) {
-        (void)hipGetLastError();
-        return MXS_OK;
-    }
-    int32_t *cnt = nullptr, *tmp_bip = nullptr;
-    if (hipMallocAsync((void **)&cnt, sizeof(int32_t) * (size_t)K * n, s) != hipSuccess ||
-        (coo && hipMallocAsync((void **)&tmp_bip, sizeof(int32_t) * np, s) != hipSuccess)) {
-        (void)hipGetLastError();
-        if (cnt) (void)hipFreeAsync(cnt, s);
-        (void)hipStreamSynchronize(s);
-        (void)hipFree(buf);
-        return MXS_OK;
-    }
-    A->owned.push_back(buf);
-    int32_t *bip = coo ? tmp_bip : (int32_t *)buf;
-    int32_t *oi = coo ? (int32_t *)buf : nullptr;
-    int32_t *oj = coo ? oi + A->nnz : bip + np;
-    void *ov = (char *)buf + vbase;
-    auto free_tmp = [&] {
-        if (tmp_bip) (void)hipFreeAsync(tmp_bip, s);
-        tmp_bip = nullptr;
-    };
-    st = fill_bytes0(cnt, sizeof(int32_t) * (size_t)K * n, s);
-    if (st == MXS_OK) {
-        colblk_count_kernel<<<row_grid(n), 256, 0, s>>>(irp, A->idx1, n, cb, cnt);
-        st = launch_status();
-    }
-    for (int b = 0; b < K && st == MXS_OK; ++b)
-        st = scan_i32(cnt + (size_t)b * n, bip + (size_t)b * ((size_t)n + 1), n, s);
-    (void)hipFreeAsync(cnt, s);
-    std::vector<int32_t> tot((size_t)K, 0);
-    for (int b = 0; b < K && st == MXS_OK; ++b)
-        if (hipMemcpyAsync(&tot[(size_t)b], bip + (size_t)b * ((size_t)n + 1) + n, sizeof(int32_t),
-                           hipMemcpyDeviceToHost, s) != hipSuccess)
-            st = MXS_ERR_HIP;
-    if (st == MXS_OK && hipStreamSynchronize(s) != hipSuccess) st = MXS_ERR_HIP;
+    if (2 * (int64_t)h[0] < A->nnz) return MXS_OK;
     std::vector<int64_t> off((size_t)K + 1, 0);
-    for (int b = 0; b < K; ++b) off[(size_t)b + 1] = off[(size_t)b] + tot[(size_t)b];
-    if (st == MXS_OK && off[(size_t)K] != A->nnz) st = MXS_ERR_INVALID_ARG; // the counts cover every entry
-    if (st != MXS_OK) {
-        free_tmp();
-        return st;
-    }
+    for (int b = 0; b < K; ++b) off[(size_t)b + 1] = off[(size_t)b] + (int64_t)h[(size_t)b + 1];
+    if (off[(size_t)K] != A->nnz) return MXS_ERR_INVALID_ARG; // the counts cover every entry
 
-    int64_t *boff = nullptr;
-    if (hipMallocAsync((void **)&boff, sizeof(int64_t) * ((size_t)K + 1), s) != hipSuccess ||
-        hipMemcpyAsync(boff, off.data(), sizeof(int64_t) * ((size_t)K + 1), hipMemcpyHostToDevice, s) !=
-            hipSuccess)
-        st = MXS_ERR_HIP;
-    if (st == MXS_OK) {
-        if (A->dtype == MXS_F64)
-            colblk_fill_kernel<double><<<row_grid(n), 256, 0, s>>>(irp, A->idx1, (const double *)A->vals,
-                                                                 n, cb, bip, boff, oi, oj, (double *)ov);
-        else
-            colblk_fill_kernel<float><<<row_grid(n), 256, 0, s>>>(irp, A->idx1, (const float *)A->vals,
-                                                                n, cb, bip, boff, oi, oj, (float *)ov);
-        st = launch_status();
+    // kept: CSR has K row-pointer arrays, then the columns, then the values;
+    // COO the row ids, columns and values (its block row pointers are only
+    // needed while the copy is cut)
+    const size_t np = (size_t)K * ((size_t)n + 1);
+    int32_t *bip_keep = coo ? nullptr : (int32_t *)c.keep(sizeof(int32_t) * np);
+    int32_t *oi = coo ? (int32_t *)c.keep(sizeof(int32_t) * (size_t)A->nnz) : nullptr;
+    int32_t *oj = (int32_t *)c.keep(sizeof(int32_t) * (size_t)A->nnz);
+    void *ov = c.keep((size_t)A->nnz * dsize(A->dtype));
+    // temporaries: entries per (block, row), COO's block row pointers, block
+    // offsets and the scan's partial sums
+    const size_t mark = c.mark();
+    int32_t *rc = (int32_t *)c.tmp(sizeof(int32_t) * (size_t)K * n);
+    int32_t *bip = coo ? (int32_t *)c.tmp(sizeof(int32_t) * np) : bip_keep;
+    auto *boff = (int64_t *)c.tmp(sizeof(int64_t) * ((size_t)K + 1));
+    void *sws = c.tmp(scan_ws_bytes(n));
+    if (c.build) {
+        st = fill_bytes0(rc, sizeof(int32_t) * (size_t)K * n, s);
+        if (st == MXS_OK) {
+            colblk_count_kernel<<<row_grid(n), 256, 0, s>>>(irp, A->idx1, n, cb, rc);
+            st = launch_status();
+        }
+        for (int b = 0; b < K && st == MXS_OK; ++b)
+            st = scan_i32_ws(rc + (size_t)b * n, bip + (size_t)b * ((size_t)n + 1), n, sws, s);
+        if (st == MXS_OK &&
+            hipMemcpyAsync(boff, off.data(), sizeof(int64_t) * ((size_t)K + 1), hipMemcpyHostToDevice, s) !=
+                hipSuccess)
+            st = MXS_ERR_HIP;
+        if (st == MXS_OK) {
+            if (A->dtype == MXS_F64)
+                colblk_fill_kernel<double><<<row_grid(n), 256, 0, s>>>(
+                    irp, A->idx1, (const double *)A->vals, n, cb, bip, boff, oi, oj, (double *)ov);
+            else
+                colblk_fill_kernel<float><<<row_grid(n), 256, 0, s>>>(
+                    irp, A->idx1, (const float *)A->vals, n, cb, bip, boff, oi, oj, (float *)ov);
+            st = launch_status();
+        }
+        // off[] is a host array read by the copy above: wait for it
+        if (hipStreamSynchronize(s) != hipSuccess && st == MXS_OK) st = MXS_ERR_HIP;
+        if (st != MXS_OK) return st;
     }
-    if (boff) (void)hipFreeAsync(boff, s);
-    free_tmp();
-    if (hipStreamSynchronize(s) != hipSuccess && st == MXS_OK) st = MXS_ERR_HIP;
-    if (st != MXS_OK) return st;
+    c.release(mark);
 
+    // the blocks: handles of A's format over their parts of the copy
     std::vector<mxs_mat_s *> blk;
     for (int b = 0; b < K && st == MXS_OK; ++b) {
         auto *B = new mxs_mat_s;
@@ -204,38 +227,24 @@ static mxs_status colblk_make(mxs_mat_s *A, const int32_t *irp, hipStream_t s)
         B->dtype = A->dtype;
         B->nrows = A->nrows;
         B->ncols = A->ncols;
-        B->nnz = tot[(size_t)b];
-        B->idx0 = coo ? oi + off[(size_t)b] : bip + (size_t)b * ((size_t)n + 1);
-        B->idx1 = oj + off[(size_t)b];
-        B->vals = (const char *)ov + off[(size_t)b] * (int64_t)dsize(A->dtype);
+        B->nnz = off[(size_t)b + 1] - off[(size_t)b];
+        if (c.build) {
+            B->idx0 = coo ? oi + off[(size_t)b] : bip + (size_t)b * ((size_t)n + 1);
+            B->idx1 = oj + off[(size_t)b];
+            B->vals = (const char *)ov + off[(size_t)b] * (int64_t)dsize(A->dtype);
+        }
         B->device = A->device;
         B->part = true;
+        B->sub = true;
         blk.push_back(B);
-        st = build_plan(B, s);
+        st = plan_walk(B, c, s);
     }
-    if (st != MXS_OK) {
+    if (st != MXS_OK || !c.build) {
         for (auto *B : blk) release(B);
         return st;
     }
     A->cblk = std::move(blk);
     return MXS_OK;
-}
-
-mxs_status colblk_build(mxs_mat_s *A, hipStream_t s)
-{
-    const int64_t xb = (int64_t)A->ncols * (int64_t)dsize(A->dtype);
-    if ((A->fmt != MXS_COO && A->fmt != MXS_CSR) || A->part || A->nnz == 0 || A->nrows == 0 ||
-        xb < kColBlkMinX)
-        return MXS_OK;
-    if (A->fmt == MXS_CSR) return colblk_make(A, A->idx0, s);
-    // COO: row pointers from the sorted row ids, for the build only
-    int32_t *irp = nullptr;
-    MXS_HIP(hipMallocAsync((void **)&irp, sizeof(int32_t) * ((size_t)A->nrows + 1), s));
-    mxs_status st = coo_irp_launch(A->nnz, A->nrows, A->idx0, irp, s);
-    if (st == MXS_OK) st = colblk_make(A, irp, s);
-    (void)hipFreeAsync(irp, s);
-    if (hipStreamSynchronize(s) != hipSuccess && st == MXS_OK) st = MXS_ERR_HIP;
-    return st;
 }
 
 }  // namespace mxs

@@ -161,7 +161,10 @@ struct mxs_mat_s {
     bool colblk = false;       // the active implementation runs them
     mxs_mat_s *band = nullptr; // HDC: the DIA band (owned by this handle)
     mxs_mat_s *rest = nullptr; // HDC: the COO or CSR remainder (owned)
-    bool part = false;         // the band or remainder of a split (its parent owns it)
+    bool part = false;         // owned by another handle or a hierarchy (not destroyable)
+    bool sub = false;          // a split's band or remainder, or a column block: its plan
+                               // is laid out inside its parent's
+    unsigned plan_opts = 0;    // options of the current plan (mxs_optimize)
     // ELL: ndiag = slots per row.  SELL: idx0 = columns, idx1 = perm,
     // sell_cs = slice offsets, slots = sell_cs[nslices], sigma = sort window.
     const int64_t *sell_cs = nullptr;
@@ -172,6 +175,61 @@ struct mxs_mat_s {
 inline bool is_split(const mxs_mat_s *A) { return A->fmt == MXS_HDC || A->fmt == MXS_HYB; }
 
 namespace mxs {
+// ---------------------------------------------------------------------------
+// Plan memory (mxs_plan_size, mxs_optimize)
+// ---------------------------------------------------------------------------
+// A plan is laid out twice by the same code: a sizing pass, in which nothing
+// is written and every take only counts bytes, and a build pass into the
+// caller's workspace.  What the layout depends on (the longest row, the
+// count of scattered entries, entries per column block) is measured in both
+// passes with a few device counters (`tiny`), so both passes take the same
+// arrays in the same order.  Workspace layout:
+//   [arrays the plan keeps][tiny counters][temporaries of the build]
+// The temporaries are dead once mxs_optimize returns.
+constexpr size_t kPlanAlign = 256;
+constexpr size_t kTinyBytes = 4096;
+
+struct PlanCtx {
+    unsigned opts = 0;
+    bool build = false;        // false: the sizing pass (nothing is written)
+    char *keep_base = nullptr; // build pass: where kept arrays go
+    size_t keep_used = 0;
+    char *tmp_base = nullptr;  // build pass: temporaries
+    size_t tmp_used = 0, tmp_peak = 0;
+    void *tiny = nullptr;      // kTinyBytes of device counters, both passes (nullptr: none)
+    bool tiny_used = false;
+
+    static size_t up(size_t b) { return (b + kPlanAlign - 1) / kPlanAlign * kPlanAlign; }
+    // an array the plan keeps
+    void *keep(size_t bytes)
+    {
+        keep_used = up(keep_used);
+        void *p = build ? keep_base + keep_used : nullptr;
+        keep_used += bytes;
+        return p;
+    }
+    // a temporary, given back with release(mark())
+    void *tmp(size_t bytes)
+    {
+        tmp_used = up(tmp_used);
+        void *p = build ? tmp_base + tmp_used : nullptr;
+        tmp_used += bytes;
+        tmp_peak = tmp_used > tmp_peak ? tmp_used : tmp_peak;
+        return p;
+    }
+    size_t mark() const { return tmp_used; }
+    void release(size_t m) { tmp_used = m; }
+    // device counters of a measurement taken in both passes (nullptr: the
+    // caller's workspace is too small to hold them)
+    void *counters()
+    {
+        tiny_used = true;
+        return tiny;
+    }
+    // workspace bytes of the layout
+    size_t total() const { return up(keep_used) + (tiny_used ? kTinyBytes : 0) + tmp_peak; }
+};
+
 // One grid of the multigrid hierarchy (mg.hip).
 struct MgLevel {
     int32_t n = 0, rows = 0;  // grid edge, rows = n^3
@@ -189,9 +247,8 @@ struct MgLevel {
 }  // namespace mxs
 
 struct mxs_mg_s {
-    std::vector<mxs::MgLevel> lv; // finest first
+    std::vector<mxs::MgLevel> lv; // finest first; arrays in the caller's workspace
     int device = 0;
-    std::vector<void *> owned;
 };
 
 
@@ -308,7 +365,9 @@ __device__ __forceinline__ void cg_finish_sigma(CgState *st, double sigma)
 // *done != 0; `dot` (nullable, square A only) fuses sum_i y_i*x_i into the
 // epilogue and launches the finish kernel that applies cg_finish_sigma.
 mxs_status spmv_launch(const mxs_mat_s *A, const void *x, void *y, const int *done,
-                       const DotSink *dot, hipStream_t s);
+                       const DotSink *dot, hipStream_t s, void *carry = nullptr);
+// `carry` (nullable): where the tile kernels put the partial sums of rows
+// that span tiles, spmv_scratch_bytes(A) bytes; nullptr: the plan's own.
 // p.Ap (n = nrows) reduced into `dot` as the COO path and the timed CG path do.
 mxs_status dot_sigma_launch(int64_t n, mxs_dtype t, const void *a, const void *b, const int *done,
                             const DotSink *dot, hipStream_t s);
@@ -316,7 +375,12 @@ mxs_status dot_sigma_launch(int64_t n, mxs_dtype t, const void *a, const void *b
 int64_t spmv_dot_parts(const mxs_mat_s *A);
 // Capacity of every partials array (workgroups of any reducing launch).
 constexpr int64_t kMaxParts = 1 << 18;
-mxs_status build_plan(mxs_mat_s *A, hipStream_t s);
+// Lays out (sizing pass) or builds (build pass) A's plan; see PlanCtx.
+mxs_status plan_walk(mxs_mat_s *A, PlanCtx &c, hipStream_t s);
+// Forgets A's plan (and its parts' and column blocks'); the memory is the caller's.
+void plan_reset(mxs_mat_s *A);
+// Bytes of the scratch mxs_spmv_ws takes for A's carries (0 when none).
+size_t spmv_scratch_bytes(const mxs_mat_s *A);
 // spmv.hip: the SpMV implementations of a format and the choice among them.
 int32_t impl_count(const mxs_mat_s *A);
 bool impl_ok(const mxs_mat_s *A, int32_t impl);
@@ -325,7 +389,7 @@ mxs_status tune(mxs_mat_s *A, const void *x, void *y, int32_t reps, int32_t *imp
                 double *ms, hipStream_t s); // syncs
 // spmv.hip: y += A x for a COO or CSR handle (the remainder of a split).
 mxs_status spmv_acc_launch(const mxs_mat_s *A, const void *x, void *y, const int *done,
-                           hipStream_t s);
+                           hipStream_t s, void *carry = nullptr);
 
 // split.hip
 mxs_status split_size(const mxs_mat_s *A, double min_fill, int32_t *band_ndiag, int64_t *rest_nnz,
@@ -338,6 +402,9 @@ mxs_status split(const mxs_mat_s *A, double min_fill, mxs_format rest_fmt, int32
 // out[i] = sum_{k<i} in[k] for i in [0, n]; out has n+1 entries (the total
 // last).  Fails with MXS_ERR_INDEX_RANGE if the total exceeds INT32_MAX.
 mxs_status scan_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t s);
+// The same with its temporaries in the caller's ws[scan_ws_bytes(n)] (syncs).
+size_t scan_ws_bytes(int64_t n);
+mxs_status scan_i32_ws(const int32_t *in, int32_t *out, int64_t n, void *ws, hipStream_t s);
 mxs_status fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 mxs_status fill_bytes0(void *p, size_t bytes, hipStream_t s);
 
@@ -398,11 +465,18 @@ int64_t ell_grid(int32_t nrows, bool dot);
 
 // Frees a handle, its parts and the device memory it owns (api.hip).
 void release(mxs_mat_s *A);
-// colblk.hip: COO and CSR column blocks (built by mxs_optimize when they apply).
-mxs_status colblk_build(mxs_mat_s *A, hipStream_t s);
+// colblk.hip: COO and CSR column blocks (laid out by the plan when they apply);
+// irp: A's row pointers (CSR: its own; COO: a build-pass temporary, else nullptr).
+mxs_status colblk_plan(mxs_mat_s *A, const int32_t *irp, PlanCtx &c, hipStream_t s);
+
+// ell.hip: longest row of row pointers irp into *K, with `counter` one device int.
+mxs_status longest_row_with(int32_t nrows, const int32_t *irp, int *counter, int32_t *K,
+                            hipStream_t s); // syncs
 
 // mg.hip: HPCG's multigrid preconditioner.
-mxs_status mg_create(int32_t n, int32_t levels, mxs_mg_s **out, hipStream_t s); // syncs
+size_t mg_bytes(int32_t n, int32_t levels); // workspace of the hierarchy (0: unsupported)
+mxs_status mg_create(int32_t n, int32_t levels, void *ws, size_t bytes, mxs_mg_s **out,
+                     hipStream_t s); // syncs
 void mg_release(mxs_mg_s *M);
 mxs_status symgs_launch(const mxs_mg_s *M, int32_t level, const double *r, double *x,
                         hipStream_t s);
@@ -416,6 +490,10 @@ mxs_status pcg_solve(const mxs_mg_s *M, const mxs_mat_s *A, const double *b, dou
 // gen.hip
 mxs_status stencil_coo(int32_t n, int32_t points, double diag, double offdiag, int32_t *ai,
                        int32_t *aj, void *av, mxs_dtype t, hipStream_t s);
+// The same with its temporaries in ws[stencil_ws_bytes(n)].
+size_t stencil_ws_bytes(int32_t n);
+mxs_status stencil_coo_ws(int32_t n, int32_t points, double diag, double offdiag, int32_t *ai,
+                          int32_t *aj, void *av, mxs_dtype t, void *ws, hipStream_t s);
 
 // mlp.hip
 mxs_status mlp_inputs(const double *raw, int32_t n, const float *mu, const float *sd,

@@ -63,10 +63,8 @@ __global__ void row_len_max_kernel(int32_t nrows, const int32_t *__restrict__ ir
     if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(out, m);
 }
 
-static mxs_status longest_row(int32_t nrows, const int32_t *irp, int32_t *K, hipStream_t s)
+mxs_status longest_row_with(int32_t nrows, const int32_t *irp, int *d, int32_t *K, hipStream_t s)
 {
-    int *d = nullptr;
-    MXS_HIP(hipMallocAsync((void **)&d, sizeof(int), s));
     mxs_status st = fill_bytes0(d, sizeof(int), s);
     if (st == MXS_OK && nrows > 0) {
         row_len_max_kernel<<<grid_of(nrows, 4096), 256, 0, s>>>(nrows, irp, d);
@@ -75,9 +73,18 @@ static mxs_status longest_row(int32_t nrows, const int32_t *irp, int32_t *K, hip
     int h = 0;
     if (st == MXS_OK && hipMemcpyAsync(&h, d, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess)
         st = MXS_ERR_HIP;
-    (void)hipFreeAsync(d, s);
-    if (st == MXS_OK && hipStreamSynchronize(s) != hipSuccess) st = MXS_ERR_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess && st == MXS_OK) st = MXS_ERR_HIP;
     *K = h;
+    return st;
+}
+
+static mxs_status longest_row(int32_t nrows, const int32_t *irp, int32_t *K, hipStream_t s)
+{
+    int *d = nullptr;
+    MXS_HIP(hipMallocAsync((void **)&d, sizeof(int), s));
+    const mxs_status st = longest_row_with(nrows, irp, d, K, s);
+    (void)hipFreeAsync(d, s);
+    if (hipStreamSynchronize(s) != hipSuccess && st == MXS_OK) return MXS_ERR_HIP;
     return st;
 }
 

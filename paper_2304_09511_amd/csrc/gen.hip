@@ -61,18 +61,29 @@ __global__ void stencil_write_kernel(int32_t n, int32_t points, T diag, T offdia
     }
 }
 
-mxs_status stencil_coo(int32_t n, int32_t points, double diag, double offdiag, int32_t *ai,
-                       int32_t *aj, void *av, mxs_dtype t, hipStream_t s)
+static size_t up256(size_t b) { return (b + 255) / 256 * 256; }
+
+size_t stencil_ws_bytes(int32_t n)
+{
+    const int64_t N = (int64_t)n * n * n;
+    return up256(sizeof(int32_t) * (size_t)N) + up256(sizeof(int32_t) * ((size_t)N + 1)) +
+           scan_ws_bytes(N);
+}
+
+// The generator with its temporaries (row lengths, their scan) in
+// ws[stencil_ws_bytes(n)].
+mxs_status stencil_coo_ws(int32_t n, int32_t points, double diag, double offdiag, int32_t *ai,
+                          int32_t *aj, void *av, mxs_dtype t, void *ws, hipStream_t s)
 {
     const int64_t N = (int64_t)n * n * n;
     if (N == 0) return MXS_OK;
-    int32_t *cnt = nullptr, *pos = nullptr;
-    MXS_HIP(hipMallocAsync((void **)&cnt, sizeof(int32_t) * (size_t)N, s));
-    MXS_HIP(hipMallocAsync((void **)&pos, sizeof(int32_t) * ((size_t)N + 1), s));
+    auto *cnt = (int32_t *)ws;
+    auto *pos = (int32_t *)((char *)ws + up256(sizeof(int32_t) * (size_t)N));
+    void *sws = (char *)pos + up256(sizeof(int32_t) * ((size_t)N + 1));
     const uint32_t g = (uint32_t)std::min<int64_t>((N + 255) / 256, 65536);
     stencil_count_kernel<<<g, 256, 0, s>>>(n, points, cnt);
     MXS_HIP(hipGetLastError());
-    mxs_status st = scan_i32(cnt, pos, N, s);
+    mxs_status st = scan_i32_ws(cnt, pos, N, sws, s);
     if (st == MXS_OK) {
         if (t == MXS_F64)
             stencil_write_kernel<double><<<g, 256, 0, s>>>(n, points, diag, offdiag, pos, ai, aj,
@@ -82,8 +93,18 @@ mxs_status stencil_coo(int32_t n, int32_t points, double diag, double offdiag, i
                                                           pos, ai, aj, (float *)av);
         st = launch_status();
     }
-    MXS_HIP(hipFreeAsync(cnt, s));
-    MXS_HIP(hipFreeAsync(pos, s));
+    return st;
+}
+
+mxs_status stencil_coo(int32_t n, int32_t points, double diag, double offdiag, int32_t *ai,
+                       int32_t *aj, void *av, mxs_dtype t, hipStream_t s)
+{
+    const int64_t N = (int64_t)n * n * n;
+    if (N == 0) return MXS_OK;
+    void *ws = nullptr;
+    MXS_HIP(hipMallocAsync(&ws, stencil_ws_bytes(n), s));
+    const mxs_status st = stencil_coo_ws(n, points, diag, offdiag, ai, aj, av, t, ws, s);
+    MXS_HIP(hipFreeAsync(ws, s));
     return st;
 }
 

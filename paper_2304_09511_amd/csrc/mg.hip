@@ -25,6 +25,7 @@
 #include "common.h"
 
 #include <algorithm>
+#include <cstdio>
 
 namespace mxs {
 
@@ -234,37 +235,94 @@ __global__ void mg_prolong_kernel(const int32_t *__restrict__ order, const doubl
 static uint32_t blocks(int64_t n, int nt = kMgNT) { return (uint32_t)std::max<int64_t>(1, (n + nt - 1) / nt); }
 
 // ---------------------------------------------------------------------------
-// Hierarchy
+// Hierarchy: every array lives in the caller's workspace, laid out by a
+// sizing pass (closed forms, no device work) and then built by the same code
+// (see PlanCtx).
 // ---------------------------------------------------------------------------
-static mxs_status take(mxs_mg_s *M, void **p, size_t bytes)
+// Neighbours along one axis of coordinate t on an n-point edge, t included.
+static int along(int32_t t, int32_t n) { return 1 + (t > 0 ? 1 : 0) + (t < n - 1 ? 1 : 0); }
+
+// Sum over the slices of a level of their widths (the longest row's
+// off-diagonal count, from the stencil's row lengths), in colour order.
+static int64_t slice_total(int32_t n)
 {
-    *p = nullptr;
-    if (bytes == 0) return MXS_OK;
-    const hipError_t e = hipMalloc(p, bytes);
-    if (e != hipSuccess) return e == hipErrorOutOfMemory ? MXS_ERR_OUT_OF_MEMORY : note_hip_error(e, "hipMalloc");
-    M->owned.push_back(*p);
-    return MXS_OK;
+    int64_t total = 0;
+    for (int c = 0; c < kColours; ++c) {
+        const int px = c & 1, py = (c >> 1) & 1, pz = (c >> 2) & 1;
+        int k = 0, w = 0;
+        for (int32_t z = pz; z < n; z += 2)
+            for (int32_t y = py; y < n; y += 2)
+                for (int32_t x = px; x < n; x += 2) {
+                    w = std::max(w, along(x, n) * along(y, n) * along(z, n) - 1);
+                    if (++k == kSlice) {
+                        total += w;
+                        k = 0;
+                        w = 0;
+                    }
+                }
+        if (k > 0) total += w;
+    }
+    return total;
 }
 
-static mxs_status build_level(mxs_mg_s *M, MgLevel &L, int32_t n, bool vectors, hipStream_t s)
+static mxs_status build_level(mxs_mg_s *M, MgLevel &L, int32_t n, bool vectors, PlanCtx &c,
+                              hipStream_t s)
 {
+    L = MgLevel{};
     L.n = n;
     const int64_t rows64 = (int64_t)n * n * n;
     const int64_t nnz = (3 * (int64_t)n - 2) * (3 * (int64_t)n - 2) * (3 * (int64_t)n - 2);
     if (rows64 > INT32_MAX || nnz > INT32_MAX) return MXS_ERR_UNSUPPORTED;
     L.rows = (int32_t)rows64;
-    mxs_status st;
+    // colour order (closed form) and slices
+    ColourGeom g{};
+    g.n = n;
+    const int32_t h[2] = {(n + 1) / 2, n / 2};
+    g.coff[0] = 0;
+    for (int c2 = 0; c2 < kColours; ++c2)
+        g.coff[c2 + 1] = g.coff[c2] + h[c2 & 1] * h[(c2 >> 1) & 1] * h[(c2 >> 2) & 1];
+    std::copy(g.coff, g.coff + kColours + 1, L.coff);
+    int32_t nsl = 0;
+    for (int c2 = 0; c2 < kColours; ++c2) {
+        L.sfirst[c2] = nsl;
+        nsl += (L.coff[c2 + 1] - L.coff[c2] + kSlice - 1) / kSlice;
+    }
+    L.sfirst[kColours] = nsl;
+    L.nslices = nsl;
+    const int64_t total = slice_total(n);
+    const size_t entries = (size_t)kSlice * (size_t)total;
+
+    // kept: the operator in CSR, the colour order, the slices, the diagonal,
+    // and on coarse levels their right-hand side and correction
+    auto *irp = (int32_t *)c.keep(sizeof(int32_t) * ((size_t)L.rows + 1));
+    auto *aj = (int32_t *)c.keep(sizeof(int32_t) * (size_t)nnz);
+    auto *av = (double *)c.keep(sizeof(double) * (size_t)nnz);
+    L.order = (int32_t *)c.keep(sizeof(int32_t) * (size_t)L.rows);
+    L.soff = (int64_t *)c.keep(sizeof(int64_t) * ((size_t)nsl + 1));
+    L.col = (int32_t *)c.keep(sizeof(int32_t) * entries);
+    L.val = (double *)c.keep(sizeof(double) * entries);
+    L.diag = (double *)c.keep(sizeof(double) * (size_t)L.rows);
+    if (vectors) {
+        L.r = (double *)c.keep(sizeof(double) * (size_t)L.rows);
+        L.z = (double *)c.keep(sizeof(double) * (size_t)L.rows);
+    }
+    // temporaries: row ids, the generator's, slice widths and their scan, a
+    // flag.  The next level's are taken only after this level's build has
+    // synchronised, so the region is handed back at once.
+    const size_t mark = c.mark();
+    auto *ai = (int32_t *)c.tmp(sizeof(int32_t) * (size_t)nnz);
+    void *gws = c.tmp(stencil_ws_bytes(n));
+    auto *dev_sfirst = (int32_t *)c.tmp(sizeof(int32_t) * (kColours + 1));
+    auto *width = (int32_t *)c.tmp(sizeof(int32_t) * ((size_t)nsl + 1));
+    auto *wscan = (int32_t *)c.tmp(sizeof(int32_t) * ((size_t)nsl + 1));
+    auto *flags = (int *)c.tmp(sizeof(int));
+    void *sws = c.tmp(scan_ws_bytes(nsl));
+    c.release(mark);
+    if (!c.build) return MXS_OK;
+
     // the operator: 27-point stencil, 26 on the diagonal and -1 off it, in CSR
-    int32_t *irp, *aj;
-    double *av;
-    if ((st = take(M, (void **)&irp, sizeof(int32_t) * ((size_t)L.rows + 1))) != MXS_OK) return st;
-    if ((st = take(M, (void **)&aj, sizeof(int32_t) * (size_t)nnz)) != MXS_OK) return st;
-    if ((st = take(M, (void **)&av, sizeof(double) * (size_t)nnz)) != MXS_OK) return st;
-    int32_t *ai = nullptr;
-    MXS_HIP(hipMallocAsync((void **)&ai, sizeof(int32_t) * (size_t)nnz, s));
-    st = stencil_coo(n, 27, 26.0, -1.0, ai, aj, av, MXS_F64, s);
+    mxs_status st = stencil_coo_ws(n, 27, 26.0, -1.0, ai, aj, av, MXS_F64, gws, s);
     if (st == MXS_OK) st = coo_irp_launch(nnz, L.rows, ai, irp, s);
-    (void)hipFreeAsync(ai, s);
     if (st != MXS_OK) return st;
     auto *A = new mxs_mat_s;
     A->fmt = MXS_CSR;
@@ -278,57 +336,30 @@ static mxs_status build_level(mxs_mg_s *M, MgLevel &L, int32_t n, bool vectors, 
     A->part = true;
     L.A = A;
 
-    // colour order (closed form)
-    ColourGeom g{};
-    g.n = n;
-    const int32_t h[2] = {(n + 1) / 2, n / 2};
-    g.coff[0] = 0;
-    for (int c = 0; c < kColours; ++c)
-        g.coff[c + 1] = g.coff[c] + h[c & 1] * h[(c >> 1) & 1] * h[(c >> 2) & 1];
-    std::copy(g.coff, g.coff + kColours + 1, L.coff);
-    if ((st = take(M, (void **)&L.order, sizeof(int32_t) * (size_t)L.rows)) != MXS_OK) return st;
     mg_order_kernel<<<std::min<uint32_t>(blocks(L.rows), 65536), kMgNT, 0, s>>>(g, L.order);
     if ((st = launch_status()) != MXS_OK) return st;
-
-    // slices
-    int32_t nsl = 0;
-    for (int c = 0; c < kColours; ++c) {
-        L.sfirst[c] = nsl;
-        nsl += (L.coff[c + 1] - L.coff[c] + kSlice - 1) / kSlice;
-    }
-    L.sfirst[kColours] = nsl;
-    L.nslices = nsl;
-    int32_t *dev_sfirst = nullptr, *width = nullptr, *wscan = nullptr;
-    int *flags = nullptr;
-    if ((st = take(M, (void **)&dev_sfirst, sizeof(int32_t) * (kColours + 1))) != MXS_OK) return st;
     MXS_HIP(hipMemcpyAsync(dev_sfirst, L.sfirst, sizeof(int32_t) * (kColours + 1),
                            hipMemcpyHostToDevice, s));
-    if ((st = take(M, (void **)&L.soff, sizeof(int64_t) * ((size_t)nsl + 1))) != MXS_OK) return st;
-    MXS_HIP(hipMallocAsync((void **)&width, sizeof(int32_t) * ((size_t)nsl + 1), s));
-    MXS_HIP(hipMallocAsync((void **)&wscan, sizeof(int32_t) * ((size_t)nsl + 1), s));
-    MXS_HIP(hipMallocAsync((void **)&flags, sizeof(int), s));
-    auto cleanup = [&] {
-        (void)hipFreeAsync(width, s);
-        (void)hipFreeAsync(wscan, s);
-        (void)hipFreeAsync(flags, s);
-    };
     mg_width_kernel<<<blocks(nsl), kMgNT, 0, s>>>(g, dev_sfirst, L.order, irp, nsl, width);
     st = launch_status();
-    if (st == MXS_OK) st = scan_i32(width, wscan, nsl, s);
+    if (st == MXS_OK) st = scan_i32_ws(width, wscan, nsl, sws, s);
     if (st == MXS_OK) {
         mg_slice_offsets_kernel<<<blocks(nsl + 1), kMgNT, 0, s>>>(wscan, nsl, L.soff);
         st = launch_status();
     }
-    int32_t total = 0;
-    if (st == MXS_OK && hipMemcpyAsync(&total, wscan + nsl, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess)
+    int32_t dev_total = 0;
+    if (st == MXS_OK && hipMemcpyAsync(&dev_total, wscan + nsl, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess)
         st = MXS_ERR_HIP;
     if (st == MXS_OK && hipStreamSynchronize(s) != hipSuccess) st = MXS_ERR_HIP;
-    const size_t entries = (size_t)kSlice * (size_t)total;
-    if (st == MXS_OK) st = take(M, (void **)&L.col, sizeof(int32_t) * entries);
-    if (st == MXS_OK) st = take(M, (void **)&L.val, sizeof(double) * entries);
-    if (st == MXS_OK) st = take(M, (void **)&L.diag, sizeof(double) * (size_t)L.rows);
+    if (st != MXS_OK) return st;
+    if (dev_total != total) { // the slices' size was laid out from the closed form
+        snprintf(g_last_error, sizeof g_last_error,
+                 "multigrid level %d: slice widths sum to %d on the device, %lld laid out", n,
+                 dev_total, (long long)total);
+        return MXS_ERR_HIP;
+    }
     // lanes past a colour's last row are never read; zero them anyway
-    if (st == MXS_OK) st = fill_bytes0(L.col, sizeof(int32_t) * entries, s);
+    st = fill_bytes0(L.col, sizeof(int32_t) * entries, s);
     if (st == MXS_OK) st = fill_bytes0(L.val, sizeof(double) * entries, s);
     if (st == MXS_OK) st = fill_bytes0(flags, sizeof(int), s);
     if (st == MXS_OK) {
@@ -339,36 +370,55 @@ static mxs_status build_level(mxs_mg_s *M, MgLevel &L, int32_t n, bool vectors, 
     int hf = 0;
     if (st == MXS_OK && hipMemcpyAsync(&hf, flags, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess)
         st = MXS_ERR_HIP;
-    cleanup();
     if (st == MXS_OK && hipStreamSynchronize(s) != hipSuccess) st = MXS_ERR_HIP;
     if (st != MXS_OK) return st;
     if (hf) return MXS_ERR_INVALID_ARG; // no such row in the stencil: a build fault
-    if (vectors) {
-        if ((st = take(M, (void **)&L.r, sizeof(double) * (size_t)L.rows)) != MXS_OK) return st;
-        if ((st = take(M, (void **)&L.z, sizeof(double) * (size_t)L.rows)) != MXS_OK) return st;
-    }
     return MXS_OK;
 }
 
 void mg_release(mxs_mg_s *M)
 {
     if (!M) return;
-    // the level operators' arrays belong to the hierarchy; plans that
-    // mxs_optimize or mxs_tune built on them belong to the operators
+    // the level operators' arrays are in the caller's workspace; plans built
+    // on them are the caller's too
     for (auto &L : M->lv) release(L.A);
-    for (void *p : M->owned)
-        if (p) (void)hipFree(p);
     delete M;
 }
 
-mxs_status mg_create(int32_t n, int32_t levels, mxs_mg_s **out, hipStream_t s)
+static mxs_status mg_walk(mxs_mg_s *M, int32_t n, int32_t levels, PlanCtx &c, hipStream_t s)
 {
+    M->lv.resize((size_t)levels);
+    for (int32_t l = 0; l < levels; ++l) {
+        const mxs_status st = build_level(M, M->lv[(size_t)l], n >> l, l > 0, c, s);
+        if (st != MXS_OK) return st;
+    }
+    return MXS_OK;
+}
+
+size_t mg_bytes(int32_t n, int32_t levels)
+{
+    mxs_mg_s M;
+    PlanCtx c;
+    if (mg_walk(&M, n, levels, c, nullptr) != MXS_OK) return 0;
+    return c.total();
+}
+
+mxs_status mg_create(int32_t n, int32_t levels, void *ws, size_t bytes, mxs_mg_s **out, hipStream_t s)
+{
+    PlanCtx z;
+    {
+        mxs_mg_s sizing;
+        const mxs_status st = mg_walk(&sizing, n, levels, z, s);
+        if (st != MXS_OK) return st;
+    }
+    if (bytes < z.total()) return MXS_ERR_INVALID_ARG;
     auto *M = new mxs_mg_s;
     (void)hipGetDevice(&M->device);
-    M->lv.resize((size_t)levels);
-    mxs_status st = MXS_OK;
-    for (int32_t l = 0; l < levels && st == MXS_OK; ++l)
-        st = build_level(M, M->lv[(size_t)l], n >> l, l > 0, s);
+    PlanCtx c;
+    c.build = true;
+    c.keep_base = (char *)ws;
+    c.tmp_base = (char *)ws + PlanCtx::up(z.keep_used);
+    mxs_status st = mg_walk(M, n, levels, c, s);
     if (st != MXS_OK) {
         (void)hipStreamSynchronize(s);
         mg_release(M);

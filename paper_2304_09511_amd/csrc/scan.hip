@@ -102,13 +102,18 @@ __global__ __launch_bounds__(kScanNT) void scan_tiles(const int32_t *__restrict_
     }
 }
 
-mxs_status scan_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t s)
+size_t scan_ws_bytes(int64_t n)
 {
     const int64_t ntiles = std::max<int64_t>((n + kScanTile - 1) / kScanTile, 1);
-    long long *sums = nullptr;
-    int *ovf = nullptr;
-    MXS_HIP(hipMallocAsync((void **)&sums, sizeof(long long) * (size_t)ntiles, s));
-    MXS_HIP(hipMallocAsync((void **)&ovf, sizeof(int), s));
+    return sizeof(long long) * (size_t)ntiles + 256;
+}
+
+// The scan with its temporaries (tile sums, overflow flag) in ws[scan_ws_bytes(n)].
+mxs_status scan_i32_ws(const int32_t *in, int32_t *out, int64_t n, void *ws, hipStream_t s)
+{
+    const int64_t ntiles = std::max<int64_t>((n + kScanTile - 1) / kScanTile, 1);
+    long long *sums = (long long *)ws;
+    int *ovf = (int *)((char *)ws + sizeof(long long) * (size_t)ntiles);
     scan_tile_sums<<<(uint32_t)ntiles, kScanNT, 0, s>>>(in, n, sums);
     MXS_HIP(hipGetLastError());
     scan_tile_offsets<<<1, kScanNT, 0, s>>>(sums, ntiles, out, n, ovf);
@@ -119,10 +124,18 @@ mxs_status scan_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t s)
     }
     int h_ovf = 0;
     MXS_HIP(hipMemcpyAsync(&h_ovf, ovf, sizeof(int), hipMemcpyDeviceToHost, s));
-    MXS_HIP(hipFreeAsync(sums, s));
-    MXS_HIP(hipFreeAsync(ovf, s));
     MXS_HIP(hipStreamSynchronize(s));
     return h_ovf ? MXS_ERR_INDEX_RANGE : MXS_OK;
+}
+
+mxs_status scan_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t s)
+{
+    void *ws = nullptr;
+    MXS_HIP(hipMallocAsync(&ws, scan_ws_bytes(n), s));
+    const mxs_status st = scan_i32_ws(in, out, n, ws, s);
+    (void)hipFreeAsync(ws, s);
+    if (hipStreamSynchronize(s) != hipSuccess && st == MXS_OK) return MXS_ERR_HIP;
+    return st;
 }
 
 __global__ void fill_i32_kernel(int32_t *__restrict__ p, int32_t v, int64_t n)

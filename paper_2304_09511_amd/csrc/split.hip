@@ -313,6 +313,7 @@ mxs_status split(const mxs_mat_s *A, double min_fill, mxs_format rest_fmt, int32
     h->ndiag = m.ndiag;
     h->device = A->device;
     band->part = rest->part = true;
+    band->sub = rest->sub = true;
     h->band = band;
     h->rest = rest;
     *out = h;

@@ -32,9 +32,6 @@
 #ifndef MXS_DIA_WIN
 #define MXS_DIA_WIN 0 // 1: stage the x windows of interior DIA blocks in LDS
 #endif
-#ifndef MXS_DIA_BLOCKED
-#define MXS_DIA_BLOCKED 1 // keep a row-blocked copy of the DIA values in the plan
-#endif
 #ifndef MXS_DIA_RPT64
 #define MXS_DIA_RPT64 1
 #endif
@@ -1179,68 +1176,69 @@ int64_t spmv_dot_parts(const mxs_mat_s *A)
     return n;
 }
 
-static mxs_status build_csr_plan(mxs_mat_s *A, hipStream_t s)
+// CSR plan: the entry tiles (first owned row and flags per tile) and the
+// carries mxs_spmv uses; the ELL copy when rows have near-equal lengths (at
+// most 5% padding; not for parts, nor with MXS_PLAN_NO_ELL); the column
+// blocks (colblk.hip).
+static mxs_status csr_plan(mxs_mat_s *A, PlanCtx &c, hipStream_t s)
 {
     const int tile = csr_tile(A->dtype);
     const int64_t nt = (A->nnz + tile - 1) / tile;
-    A->csr.ntiles = nt;
-    if (nt == 0) return MXS_OK;
+    CsrPlan P{};
+    P.ntiles = nt;
+    if (nt == 0) {
+        if (c.build) A->csr = P;
+        return MXS_OK;
+    }
     // default: a thread per row when rows outnumber entries two to one
-    A->csr.rowwise = (int64_t)A->nrows > 2 * A->nnz;
-    int32_t *buf = nullptr;
-    // tile_row [nt+1], tile_info [nt], then one flag
-    MXS_HIP(hipMalloc((void **)&buf, sizeof(int32_t) * (2 * (size_t)nt + 2)));
-    A->owned.push_back(buf);
-    int32_t *tile_row = buf, *info = buf + nt + 1;
-    int *flag = nullptr;
-    MXS_HIP(hipMallocAsync((void **)&flag, sizeof(int), s));
-    mxs_status st = fill_i32(flag, 0, 1, s);
-    if (st != MXS_OK) return st;
-    const uint32_t g = (uint32_t)((nt + 1 + 255) / 256);
-    const int ext = A->dtype == MXS_F64 ? CsrCfg<double>::EXT : CsrCfg<float>::EXT;
-    csr_tile_rows_kernel<<<g, 256, 0, s>>>(A->idx0, A->nrows, nt, tile, tile_row);
-    csr_tile_info_kernel<<<g, 256, 0, s>>>(A->idx0, tile_row, A->nnz, nt, tile, ext, info, flag);
-    if (A->nrows > 0)
-        csr_long_rows_kernel<<<(uint32_t)(((int64_t)A->nrows + 255) / 256), 256, 0, s>>>(
-            A->idx0, A->nrows, tile, info);
-    MXS_HIP(hipGetLastError());
-    int any = 0;
-    MXS_HIP(hipMemcpyAsync(&any, flag, sizeof(int), hipMemcpyDeviceToHost, s));
-    MXS_HIP(hipFreeAsync(flag, s));
-    MXS_HIP(hipStreamSynchronize(s));
-    A->csr.tile_row = tile_row;
-    A->csr.tile_info = info;
-    A->csr.fixup = any != 0;
-    void *carry = nullptr;
-    MXS_HIP(hipMalloc(&carry, 2 * (size_t)nt * dsize(A->dtype)));
-    A->owned.push_back(carry);
-    A->csr.carry = carry;
+    P.rowwise = (int64_t)A->nrows > 2 * A->nnz;
+    // tile_row [nt+1], tile_info [nt]
+    int32_t *buf = (int32_t *)c.keep(sizeof(int32_t) * (2 * (size_t)nt + 1));
+    void *carry = c.keep(2 * (size_t)nt * dsize(A->dtype));
+    int *flag = (int *)c.counters();
+    if (!flag) return MXS_ERR_INVALID_ARG; // no room for the measurement
+    if (c.build) {
+        int32_t *tile_row = buf, *info = buf + nt + 1;
+        mxs_status st = fill_i32(flag, 0, 1, s);
+        if (st != MXS_OK) return st;
+        const uint32_t g = (uint32_t)((nt + 1 + 255) / 256);
+        const int ext = A->dtype == MXS_F64 ? CsrCfg<double>::EXT : CsrCfg<float>::EXT;
+        csr_tile_rows_kernel<<<g, 256, 0, s>>>(A->idx0, A->nrows, nt, tile, tile_row);
+        csr_tile_info_kernel<<<g, 256, 0, s>>>(A->idx0, tile_row, A->nnz, nt, tile, ext, info, flag);
+        if (A->nrows > 0)
+            csr_long_rows_kernel<<<(uint32_t)(((int64_t)A->nrows + 255) / 256), 256, 0, s>>>(
+                A->idx0, A->nrows, tile, info);
+        MXS_HIP(hipGetLastError());
+        int any = 0;
+        MXS_HIP(hipMemcpyAsync(&any, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+        MXS_HIP(hipStreamSynchronize(s));
+        P.tile_row = tile_row;
+        P.tile_info = info;
+        P.fixup = any != 0;
+        P.carry = carry;
+    }
     // ELL copy for rows of near-equal length: lanes of a wave then hold
     // neighbouring rows, and their gathers of x neighbouring addresses
-    int32_t K = 0;
-    const mxs_status st_w = ell_width(A, &K, s);
-    if (st_w != MXS_OK && st_w != MXS_ERR_DIA_TOO_SPARSE) return st_w;
-    if (st_w == MXS_OK && K > 0 && (double)K * A->nrows <= 1.05 * (double)A->nnz) {
-        const size_t slots = (size_t)K * A->nrows;
-        const size_t vbase = (slots * sizeof(int32_t) + 255) / 256 * 256; // values 256-byte aligned
-        void *buf = nullptr;
-        // the copy is optional: without memory for it, the entry tiles run
-        if (hipMalloc(&buf, vbase + slots * dsize(A->dtype)) != hipSuccess) {
-            (void)hipGetLastError();
-        } else {
-            A->owned.push_back(buf);
-            int32_t *col = (int32_t *)buf;
-            void *val = (char *)buf + vbase;
-            mxs_status st_b = ell_build(A, K, col, val, s);
-            if (st_b != MXS_OK) return st_b;
-            MXS_HIP(hipStreamSynchronize(s));
-            A->csr.ell_k = K;
-            A->csr.ell_col = col;
-            A->csr.ell_val = val;
+    if (!A->sub && !(c.opts & MXS_PLAN_NO_ELL)) {
+        int32_t K = 0;
+        mxs_status st = longest_row_with(A->nrows, A->idx0, flag, &K, s);
+        if (st != MXS_OK) return st;
+        if (K > 0 && (double)K * A->nrows <= 1.05 * (double)A->nnz) {
+            const size_t slots = (size_t)K * A->nrows;
+            int32_t *col = (int32_t *)c.keep(slots * sizeof(int32_t));
+            void *val = c.keep(slots * dsize(A->dtype));
+            if (c.build) {
+                st = ell_build(A, K, col, val, s);
+                if (st != MXS_OK) return st;
+                P.ell_k = K;
+                P.ell_col = col;
+                P.ell_val = val;
+            }
         }
     }
+    if (c.build) A->csr = P;
     // column blocks for scattered columns over a large x
-    return colblk_build(A, s);
+    return colblk_plan(A, A->idx0, c, s);
 }
 
 // Row-blocked copy: out[(b*nd + d)*R + r] = av[d*nrows + b*R + r] (0 past the last row).
@@ -1258,20 +1256,25 @@ __global__ void dia_block_copy_kernel(const T *__restrict__ av, int32_t nrows, i
     }
 }
 
-// x windows of interior DIA blocks (see dia_spmv_kernel).
-static mxs_status build_dia_plan(mxs_mat_s *A, hipStream_t s)
+// DIA plan: the x windows of interior blocks (see dia_spmv_kernel) and,
+// with MXS_PLAN_DIA_BLOCKED, a row-blocked copy of the values.
+static mxs_status dia_plan(mxs_mat_s *A, PlanCtx &c, hipStream_t s)
 {
+    DiaPlan P{};
     const int nd = A->ndiag;
-    if (nd == 0) return MXS_OK;
+    if (nd == 0 || A->nrows == 0) {
+        if (c.build) A->dia = P;
+        return MXS_OK;
+    }
     std::vector<int32_t> off(nd);
     MXS_HIP(hipMemcpyAsync(off.data(), A->idx0, sizeof(int32_t) * nd, hipMemcpyDeviceToHost, s));
     MXS_HIP(hipStreamSynchronize(s));
-    A->dia.first_off = off[0];
-    A->dia.last_off = off[nd - 1];
+    P.first_off = off[0];
+    P.last_off = off[nd - 1];
     bool tri = nd % 3 == 0;
     for (int t = 0; tri && t < nd / 3; ++t)
         tri = off[3 * t + 1] == off[3 * t] + 1 && off[3 * t + 2] == off[3 * t] + 2;
-    A->dia.triples = tri ? 1 : 0;
+    P.triples = tri ? 1 : 0;
     const int R = kDiaNT * (A->dtype == MXS_F64 ? DiaCfg<double>::RPT : DiaCfg<float>::RPT);
     std::vector<int32_t> runs, pos(nd);
     int64_t total = 0;
@@ -1287,19 +1290,12 @@ static mxs_status build_dia_plan(mxs_mat_s *A, hipStream_t s)
             d0 = d;
         }
     }
-#if MXS_DIA_BLOCKED
-    if (dia_blocks(A) * R <= (int64_t)A->nrows + A->nrows / 8) { // padding stays small
+    // the row-blocked copy, on request, when its padding stays small
+    if ((c.opts & MXS_PLAN_DIA_BLOCKED) && dia_blocks(A) * R <= (int64_t)A->nrows + A->nrows / 8) {
         const int64_t nb = dia_blocks(A);
         const size_t elems = (size_t)nb * nd * R;
-        void *blk = nullptr;
-        // the copy is optional: without memory for it, the diagonal-major
-        // values are read
-        if (hipMalloc(&blk, elems * dsize(A->dtype)) != hipSuccess) {
-            (void)hipGetLastError();
-            blk = nullptr;
-        }
-        if (blk) {
-            A->owned.push_back(blk);
+        void *blk = c.keep(elems * dsize(A->dtype));
+        if (c.build) {
             const uint32_t g = (uint32_t)std::min<int64_t>(((int64_t)elems + 255) / 256, 65536);
             if (A->dtype == MXS_F64)
                 dia_block_copy_kernel<double><<<g, 256, 0, s>>>((const double *)A->vals, A->nrows, nd, R,
@@ -1308,26 +1304,27 @@ static mxs_status build_dia_plan(mxs_mat_s *A, hipStream_t s)
                 dia_block_copy_kernel<float><<<g, 256, 0, s>>>((const float *)A->vals, A->nrows, nd, R,
                                                                (int64_t)elems, (float *)blk);
             MXS_HIP(hipGetLastError());
-            A->dia.blk = blk;
+            P.blk = blk;
         }
     }
-#endif
     const int64_t nruns = (int64_t)runs.size() / 3;
     // windows only when they fit and save at least a quarter of the x loads
     const bool use = MXS_DIA_WIN && nd <= kDiaStage && nruns <= kDiaMaxRuns &&
                      total <= kDiaWinMax && 4 * total <= 3 * (int64_t)nd * R;
-    if (!use) return MXS_OK;
-    int32_t *dev = nullptr;
-    MXS_HIP(hipMalloc((void **)&dev, sizeof(int32_t) * ((size_t)nd + runs.size())));
-    A->owned.push_back(dev);
-    MXS_HIP(hipMemcpyAsync(dev, pos.data(), sizeof(int32_t) * nd, hipMemcpyHostToDevice, s));
-    MXS_HIP(hipMemcpyAsync(dev + nd, runs.data(), sizeof(int32_t) * runs.size(),
-                           hipMemcpyHostToDevice, s));
-    MXS_HIP(hipStreamSynchronize(s));
-    A->dia.pos = dev;
-    A->dia.runs = dev + nd;
-    A->dia.nruns = (int32_t)nruns;
-    A->dia.lds_elems = (int32_t)total;
+    if (use) {
+        int32_t *dev = (int32_t *)c.keep(sizeof(int32_t) * ((size_t)nd + runs.size()));
+        if (c.build) {
+            MXS_HIP(hipMemcpyAsync(dev, pos.data(), sizeof(int32_t) * nd, hipMemcpyHostToDevice, s));
+            MXS_HIP(hipMemcpyAsync(dev + nd, runs.data(), sizeof(int32_t) * runs.size(),
+                                   hipMemcpyHostToDevice, s));
+            MXS_HIP(hipStreamSynchronize(s));
+            P.pos = dev;
+            P.runs = dev + nd;
+            P.nruns = (int32_t)nruns;
+            P.lds_elems = (int32_t)total;
+        }
+    }
+    if (c.build) A->dia = P;
     return MXS_OK;
 }
 
@@ -1341,31 +1338,31 @@ __global__ void tile_rows_max_kernel(const int32_t *__restrict__ tile_row, int64
 
 
 // COO plan: the CSR tiling derived from the row ids through a temporary row
-// pointer array (freed here), kept when every tile owns at most kCooRowsMax
-// rows; otherwise the segmented-scan tiles.
-static mxs_status build_coo_plan(mxs_mat_s *A, hipStream_t s)
+// pointer array, usable when every tile owns at most kCooRowsMax rows;
+// otherwise the segmented-scan tiles.  One carry array serves either.
+static mxs_status coo_plan(mxs_mat_s *A, PlanCtx &c, hipStream_t s)
 {
-    A->coo = CooPlan{};
-    if (A->nnz == 0) return MXS_OK;
+    CooPlan P{};
+    if (A->nnz == 0) {
+        if (c.build) A->coo = P;
+        return MXS_OK;
+    }
     const int tile = csr_tile(A->dtype);
     const int64_t nt = (A->nnz + tile - 1) / tile;
-    int32_t *irp = nullptr;
-    int *flags = nullptr; // [0] any carry, [1] most rows in a tile
-    MXS_HIP(hipMallocAsync((void **)&irp, sizeof(int32_t) * ((size_t)A->nrows + 1), s));
-    MXS_HIP(hipMallocAsync((void **)&flags, 2 * sizeof(int), s));
-    int32_t *buf = nullptr;
-    if (hipMalloc((void **)&buf, sizeof(int32_t) * (2 * (size_t)nt + 1)) != hipSuccess) {
-        (void)hipFreeAsync(irp, s);
-        (void)hipFreeAsync(flags, s);
-        (void)hipStreamSynchronize(s);
-        return MXS_ERR_OUT_OF_MEMORY;
-    }
-    A->owned.push_back(buf);
-    int32_t *tile_row = buf, *info = buf + nt + 1;
-    mxs_status st = coo_irp_launch(A->nnz, A->nrows, A->idx0, irp, s);
-    if (st == MXS_OK) st = fill_i32(flags, 0, 2, s);
-    int h[2] = {0, 0};
-    if (st == MXS_OK) {
+    const int64_t nt_seg = (A->nnz + kCooTile - 1) / kCooTile;
+    int32_t *buf = (int32_t *)c.keep(sizeof(int32_t) * (2 * (size_t)nt + 1));
+    // carries of either implementation (two values per tile)
+    void *carry = c.keep(2 * (size_t)std::max(nt, nt_seg) * dsize(A->dtype));
+    int *flags = (int *)c.counters(); // [0] any carry, [1] most rows in a tile
+    if (!flags) return MXS_ERR_INVALID_ARG;
+    // row pointers of the sorted row ids, for the build only
+    const size_t mark = c.mark();
+    int32_t *irp = (int32_t *)c.tmp(sizeof(int32_t) * ((size_t)A->nrows + 1));
+    if (c.build) {
+        int32_t *tile_row = buf, *info = buf + nt + 1;
+        mxs_status st = coo_irp_launch(A->nnz, A->nrows, A->idx0, irp, s);
+        if (st == MXS_OK) st = fill_i32(flags, 0, 2, s);
+        if (st != MXS_OK) return st;
         const uint32_t g = (uint32_t)((nt + 1 + 255) / 256);
         const int ext = A->dtype == MXS_F64 ? CsrCfg<double>::EXT : CsrCfg<float>::EXT;
         csr_tile_rows_kernel<<<g, 256, 0, s>>>(irp, A->nrows, nt, tile, tile_row);
@@ -1374,29 +1371,23 @@ static mxs_status build_coo_plan(mxs_mat_s *A, hipStream_t s)
             csr_long_rows_kernel<<<(uint32_t)(((int64_t)A->nrows + 255) / 256), 256, 0, s>>>(
                 irp, A->nrows, tile, info);
         tile_rows_max_kernel<<<g, 256, 0, s>>>(tile_row, nt, flags + 1);
-        st = launch_status();
-        if (st == MXS_OK &&
-            hipMemcpyAsync(h, flags, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess)
-            st = MXS_ERR_HIP;
+        MXS_HIP(hipGetLastError());
+        int h[2] = {0, 0};
+        MXS_HIP(hipMemcpyAsync(h, flags, sizeof(h), hipMemcpyDeviceToHost, s));
+        MXS_HIP(hipStreamSynchronize(s));
+        P.rows_ok = h[1] <= kCooRowsMax;
+        P.tile_row = tile_row;
+        P.tile_info = info;
+        P.fixup = h[0] != 0;
+        P.nt_rows = nt;
+        P.nt_seg = nt_seg;
+        P.carry_rows = P.carry_seg = carry;
+        A->coo = P;
     }
-    (void)hipFreeAsync(irp, s);
-    (void)hipFreeAsync(flags, s);
-    MXS_HIP(hipStreamSynchronize(s));
-    if (st != MXS_OK) return st;
-    A->coo.rows_ok = h[1] <= kCooRowsMax;
-    A->coo.tile_row = tile_row;
-    A->coo.tile_info = info;
-    A->coo.fixup = h[0] != 0;
-    A->coo.nt_rows = nt;
-    A->coo.nt_seg = (A->nnz + kCooTile - 1) / kCooTile;
-    // carries of either implementation (two values per tile)
-    const int64_t nc = std::max(A->coo.nt_rows, A->coo.nt_seg);
-    void *carry = nullptr;
-    MXS_HIP(hipMalloc(&carry, 2 * (size_t)nc * dsize(A->dtype)));
-    A->owned.push_back(carry);
-    A->coo.carry_rows = A->coo.carry_seg = carry;
-    // column blocks for scattered columns over a large x
-    return colblk_build(A, s);
+    // column blocks for scattered columns over a large x (cut with irp)
+    const mxs_status st = colblk_plan(A, irp, c, s);
+    c.release(mark);
+    return st;
 }
 
 // ---------------------------------------------------------------------------
@@ -1516,25 +1507,52 @@ mxs_status tune(mxs_mat_s *A, const void *x, void *y, int32_t reps, int32_t *imp
     return MXS_OK;
 }
 
-mxs_status build_plan(mxs_mat_s *A, hipStream_t s)
+mxs_status plan_walk(mxs_mat_s *A, PlanCtx &c, hipStream_t s)
 {
-    if (A->optimized) return MXS_OK;
     mxs_status st = MXS_OK;
     if (is_split(A)) {
-        st = build_plan(A->band, s);
-        if (st == MXS_OK) st = build_plan(A->rest, s);
+        st = plan_walk(A->band, c, s);
+        if (st == MXS_OK) st = plan_walk(A->rest, c, s);
     } else if (A->fmt == MXS_CSR) {
-        st = build_csr_plan(A, s);
+        st = csr_plan(A, c, s);
     } else if (A->fmt == MXS_DIA) {
-        st = build_dia_plan(A, s);
+        st = dia_plan(A, c, s);
     } else if (A->fmt == MXS_COO) {
-        st = build_coo_plan(A, s);
+        st = coo_plan(A, c, s);
     }
-    if (st == MXS_OK) {
+    if (st == MXS_OK && c.build) {
         if (!is_split(A)) set_impl(A, default_impl(A));
+        A->plan_opts = c.opts;
         A->optimized = true;
     }
     return st;
+}
+
+void plan_reset(mxs_mat_s *A)
+{
+    if (!A) return;
+    plan_reset(A->band);
+    plan_reset(A->rest);
+    for (mxs_mat_s *B : A->cblk) release(B);
+    A->cblk.clear();
+    A->colblk = false;
+    A->csr = CsrPlan{};
+    A->coo = CooPlan{};
+    A->dia = DiaPlan{};
+    A->optimized = false;
+    A->impl = -1;
+    A->plan_opts = 0;
+}
+
+size_t spmv_scratch_bytes(const mxs_mat_s *A)
+{
+    if (is_split(A)) return spmv_scratch_bytes(A->rest); // the band (DIA, ELL) has no carries
+    size_t b = 0;
+    if (A->fmt == MXS_CSR) b = 2 * (size_t)A->csr.ntiles * dsize(A->dtype);
+    if (A->fmt == MXS_COO) b = 2 * (size_t)std::max(A->coo.nt_rows, A->coo.nt_seg) * dsize(A->dtype);
+    // column blocks run one after the other on one stream: one region serves all
+    for (const mxs_mat_s *B : A->cblk) b = std::max(b, spmv_scratch_bytes(B));
+    return b;
 }
 
 template <typename T>
@@ -1558,7 +1576,7 @@ mxs_status dot_sigma_launch(int64_t n, mxs_dtype t, const void *a, const void *b
 
 template <typename T>
 static mxs_status spmv_typed(const mxs_mat_s *A, const T *x, T *y, const int *done,
-                             const DotSink *dot, hipStream_t s, int acc)
+                             const DotSink *dot, hipStream_t s, int acc, void *carry)
 {
     if (A->nrows == 0) return MXS_OK;
     uint32_t grid = 0;
@@ -1569,7 +1587,8 @@ static mxs_status spmv_typed(const mxs_mat_s *A, const T *x, T *y, const int *do
     if (A->colblk) {
         // column blocks: the first writes y (unless accumulating), the rest add to it
         for (size_t b = 0; b < A->cblk.size(); ++b) {
-            const mxs_status st = spmv_typed<T>(A->cblk[b], x, y, done, nullptr, s, acc || b > 0 ? 1 : 0);
+            const mxs_status st =
+                spmv_typed<T>(A->cblk[b], x, y, done, nullptr, s, acc || b > 0 ? 1 : 0, carry);
             if (st != MXS_OK) return st;
         }
         if (dot) return dot_sigma_typed<T>(A->nrows, x, y, done, dot, s);
@@ -1613,20 +1632,21 @@ static mxs_status spmv_typed(const mxs_mat_s *A, const T *x, T *y, const int *do
         }
         spmv_grid<T>(A, dot != nullptr, &grid, &per);
         const int32_t *tr = A->csr.tile_row, *ti = A->csr.tile_info;
+        T *cr = (T *)(carry ? carry : A->csr.carry);
         auto kern = dot ? (A->csr.gx ? csr_spmv_kernel<T, true, true> : csr_spmv_kernel<T, true, false>)
                         : (A->csr.gx ? csr_spmv_kernel<T, false, true> : csr_spmv_kernel<T, false, false>);
         kern<<<grid, 256, 0, s>>>(A->idx0, A->idx1, (const T *)A->vals, x, y, tr, ti, A->nnz, nt, per,
-                                  (T *)A->csr.carry, done, dot ? parts : nullptr, acc);
+                                  cr, done, dot ? parts : nullptr, acc);
         MXS_HIP(hipGetLastError());
         nparts = grid;
         if (A->csr.fixup) {
             const uint32_t fg = fixup_grid(nt);
             if (dot)
-                csr_fixup_kernel<T, true><<<fg, 256, 0, s>>>(A->idx0, tr, ti, (const T *)A->csr.carry,
+                csr_fixup_kernel<T, true><<<fg, 256, 0, s>>>(A->idx0, tr, ti, cr,
                                                              x, y, A->nnz, nt, csr_tile(A->dtype),
                                                              done, parts + grid, acc);
             else
-                csr_fixup_kernel<T, false><<<fg, 256, 0, s>>>(A->idx0, tr, ti, (const T *)A->csr.carry,
+                csr_fixup_kernel<T, false><<<fg, 256, 0, s>>>(A->idx0, tr, ti, cr,
                                                               x, y, A->nnz, nt, csr_tile(A->dtype),
                                                               done, nullptr, acc);
             MXS_HIP(hipGetLastError());
@@ -1659,22 +1679,23 @@ static mxs_status spmv_typed(const mxs_mat_s *A, const T *x, T *y, const int *do
             if (!acc) fill_kernel<T><<<fill_g, 256, 0, s>>>(y, T(0), A->nrows, done);
         } else {
             spmv_grid<T>(A, false, &grid, &per);
+            T *cr = (T *)(carry ? carry : A->coo.carry);
             if (A->coo.rows) {
                 coo_rows_kernel<T><<<grid, 256, 0, s>>>(A->idx0, A->idx1, (const T *)A->vals, x, y,
                                                         A->coo.tile_row, A->coo.tile_info, A->nnz,
-                                                        nt, per, (T *)A->coo.carry, done, acc);
+                                                        nt, per, cr, done, acc);
                 MXS_HIP(hipGetLastError());
                 if (A->coo.fixup)
                     coo_rows_fixup_kernel<T><<<(uint32_t)((nt + 255) / 256), 256, 0, s>>>(
-                        A->idx0, A->coo.tile_row, A->coo.tile_info, (const T *)A->coo.carry, y,
+                        A->idx0, A->coo.tile_row, A->coo.tile_info, cr, y,
                         A->nnz, nt, csr_tile(A->dtype), done, acc);
             } else {
                 coo_spmv_kernel<T><<<grid, kCooNT, 0, s>>>(A->nnz, A->nrows, A->idx0, A->idx1,
                                                            (const T *)A->vals, x, y,
-                                                           (T *)A->coo.carry, nt, per, done, acc);
+                                                           cr, nt, per, done, acc);
                 MXS_HIP(hipGetLastError());
                 coo_fixup_kernel<T><<<(uint32_t)((nt + 255) / 256), 256, 0, s>>>(
-                    A->nnz, A->idx0, (const T *)A->coo.carry, y, nt, done, acc);
+                    A->nnz, A->idx0, cr, y, nt, done, acc);
             }
         }
         MXS_HIP(hipGetLastError());
@@ -1700,27 +1721,27 @@ static mxs_status spmv_typed(const mxs_mat_s *A, const T *x, T *y, const int *do
 }
 
 mxs_status spmv_acc_launch(const mxs_mat_s *A, const void *x, void *y, const int *done,
-                           hipStream_t s)
+                           hipStream_t s, void *carry)
 {
     if (A->fmt != MXS_COO && A->fmt != MXS_CSR) return MXS_ERR_UNSUPPORTED;
     if (A->dtype == MXS_F64)
-        return spmv_typed<double>(A, (const double *)x, (double *)y, done, nullptr, s, 1);
-    return spmv_typed<float>(A, (const float *)x, (float *)y, done, nullptr, s, 1);
+        return spmv_typed<double>(A, (const double *)x, (double *)y, done, nullptr, s, 1, carry);
+    return spmv_typed<float>(A, (const float *)x, (float *)y, done, nullptr, s, 1, carry);
 }
 
 mxs_status spmv_launch(const mxs_mat_s *A, const void *x, void *y, const int *done,
-                       const DotSink *dot, hipStream_t s)
+                       const DotSink *dot, hipStream_t s, void *carry)
 {
     if (is_split(A)) {
         // the band (DIA) or ELL part writes every row; the remainder adds onto it
-        mxs_status st = spmv_launch(A->band, x, y, done, nullptr, s);
-        if (st == MXS_OK && A->rest->nnz > 0) st = spmv_acc_launch(A->rest, x, y, done, s);
+        mxs_status st = spmv_launch(A->band, x, y, done, nullptr, s, carry);
+        if (st == MXS_OK && A->rest->nnz > 0) st = spmv_acc_launch(A->rest, x, y, done, s, carry);
         if (st == MXS_OK && dot) st = dot_sigma_launch(A->nrows, A->dtype, y, x, done, dot, s);
         return st;
     }
     if (A->dtype == MXS_F64)
-        return spmv_typed<double>(A, (const double *)x, (double *)y, done, dot, s, 0);
-    return spmv_typed<float>(A, (const float *)x, (float *)y, done, dot, s, 0);
+        return spmv_typed<double>(A, (const double *)x, (double *)y, done, dot, s, 0, carry);
+    return spmv_typed<float>(A, (const float *)x, (float *)y, done, dot, s, 0, carry);
 }
 
 }  // namespace mxs

@@ -90,17 +90,26 @@ def test_create_rejects_bad_arguments_on_host(lib):
 
 def test_calls_reject_null_handles_and_bad_enums(lib):
     assert lib.mxs_spmv(None, FAKE, FAKE, None) == -1
-    assert lib.mxs_optimize(None, None) == -1
+    assert lib.mxs_optimize(None, 0, None, 0, None) == -1
+    assert lib.mxs_plan_size(None, 0, FAKE, None) == -1
+    assert lib.mxs_plan_info(None, None, None) == -1
+    assert lib.mxs_spmv_scratch_size(None, FAKE) == -1
+    assert lib.mxs_spmv_ws(None, FAKE, FAKE, FAKE, 64, None) == -1
     assert lib.mxs_impl_count(None) == 0
     assert lib.mxs_split_parts(None, None, None) == -1
     assert lib.mxs_sell_size(None, 1, None, None, None) == -1
     assert lib.mxs_to_sell(None, 1, FAKE, FAKE, FAKE, FAKE, FAKE, None) == -1
     assert lib.mxs_hyb_size(None, -1, None, None, None) == -1
     assert lib.mxs_to_hyb(None, -1, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, None) == -1
-    assert lib.mxs_mg_create(8, 2, None, None) == -1          # no output pointer
-    assert lib.mxs_mg_create(6, 3, FAKE, None) == -1          # 6 not divisible by 4
-    assert lib.mxs_mg_create(8, 13, FAKE, None) == -1
-    assert lib.mxs_mg_create(2048, 1, FAKE, None) == -10      # rows beyond int32
+    assert lib.mxs_mg_create(8, 2, FAKE, 1 << 20, None, None) == -1   # no output pointer
+    assert lib.mxs_mg_create(8, 2, None, 1 << 20, FAKE, None) == -1   # no workspace
+    assert lib.mxs_mg_create(8, 2, C.c_void_p(0x1010), 1 << 20, FAKE, None) == -1  # misaligned
+    assert lib.mxs_mg_create(6, 3, FAKE, 1 << 20, FAKE, None) == -1   # 6 not divisible by 4
+    assert lib.mxs_mg_create(8, 13, FAKE, 1 << 20, FAKE, None) == -1
+    assert lib.mxs_mg_create(2048, 1, FAKE, 1 << 20, FAKE, None) == -10  # rows beyond int32
+    assert lib.mxs_mg_size(8, 2, None) == -1
+    assert lib.mxs_mg_size(6, 3, FAKE) == -1
+    assert lib.mxs_mg_size(2048, 1, FAKE) == -10
     assert lib.mxs_mg_destroy(None) == 0
     assert lib.mxs_mg_level(None, 0, None, None) == -1
     assert lib.mxs_symgs(None, 0, FAKE, FAKE, None) == -1
@@ -157,3 +166,26 @@ def test_one_hip_runtime_whatever_the_import_order():
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.split() == ["1", "1"], out.stdout
+
+
+def test_multigrid_workspace_size_closed_form(lib):
+    """mxs_mg_size is host arithmetic: per level the CSR operator, colour
+    order, slice offsets, sliced off-diagonal entries (slice widths from the
+    stencil's row lengths), diagonal and, below the finest level, two
+    vectors; plus the build's temporaries.  It grows with n and levels and is
+    bounded below by the operators' and slices' bytes."""
+    sizes = {}
+    for n, L in ((8, 1), (8, 2), (16, 4), (128, 4)):
+        b = C.c_size_t()
+        assert lib.mxs_mg_size(n, L, C.byref(b)) == 0
+        sizes[(n, L)] = b.value
+        low = 0
+        for l in range(L):
+            m = n >> l
+            nnz, rows = (3 * m - 2) ** 3, m ** 3
+            # CSR operator (12 bytes an entry) and the slices (off-diagonal
+            # entries, 12 bytes each, at least) and the diagonal
+            low += 12 * nnz + 4 * (rows + 1) + 12 * (nnz - rows) + 8 * rows + (16 * rows if l else 0)
+        assert b.value >= low, (n, L, b.value, low)
+        assert b.value <= 1.2 * low + (1 << 20), (n, L, b.value, low)
+    assert sizes[(8, 1)] < sizes[(8, 2)] < sizes[(16, 4)] < sizes[(128, 4)]

@@ -24,7 +24,9 @@ def to_dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def build(mxs, a, fmt):
+def build(mxs, a, fmt, opts=None):
+    """The matrix in `fmt` with a plan; DIA with its row-blocked copy (an
+    opt-in of the plan), so that every implementation is reachable."""
     A = mxs.Matrix.coo(a.nrows, a.ncols, a.ai, a.aj, a.av)
     if fmt != "coo":
         try:
@@ -33,7 +35,9 @@ def build(mxs, a, fmt):
             if e.status == -5:
                 return None
             raise
-    return A.optimize()
+    if opts is None:
+        opts = mxs.PLAN_DIA_BLOCKED if fmt == "dia" else 0
+    return A.optimize(opts)
 
 
 def applicable(mxs, A):
@@ -99,7 +103,8 @@ def test_every_impl_integer_data_bit_exact(gpu, name, fmt):
 
 def test_applicability_rules(gpu):
     """COO row tiles need at most 512 rows per tile; DIA id 0 needs offsets in
-    runs of three, ids 0 and 1 the row-blocked copy."""
+    runs of three, ids 0 and 1 the row-blocked copy, which only a plan asked
+    for it makes; CSR id 3 needs the ELL copy, which a plan can leave out."""
     mxs = gpu
     sparse = dict(CASES)["empty_rows"]   # 10,000 rows, 100 live: one tile owns them all
     # (defaults read before applicable(), which leaves its last id active)
@@ -113,6 +118,14 @@ def test_applicability_rules(gpu):
     C = build(mxs, sparse, "csr")
     assert C.impl == 1 and applicable(mxs, C) == [0, 1, 2, 5]  # rows > 2 nnz: a thread per row
     assert build(mxs, wl.stencil(16), "csr").impl == 0
+    # the default plan has no row-blocked DIA copy: the diagonal-major kernel
+    D = build(mxs, wl.stencil(16), "dia", opts=0)
+    assert D.impl == 2 and applicable(mxs, D) == [2]
+    # rows of near-equal length get the ELL copy unless the plan leaves it out
+    E = build(mxs, wl.stencil(48), "csr")
+    assert E.impl == 3 and 3 in applicable(mxs, E)
+    E2 = build(mxs, wl.stencil(48), "csr", opts=mxs.PLAN_NO_ELL)
+    assert E2.impl == 0 and 3 not in applicable(mxs, E2)
     for B in (A, S):
         with pytest.raises(mxs.MxsError) as e:
             B.impl = B.impl_count()

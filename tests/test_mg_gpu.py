@@ -128,11 +128,17 @@ def test_mg_argument_checks(gpu):
     import ctypes as C
     mxs = gpu
     lib = mxs.load()
+    import torch
     h = C.c_void_p()
-    assert lib.mxs_mg_create(6, 3, C.byref(h), None) == -1       # 6 not divisible by 4
-    assert lib.mxs_mg_create(8, 0, C.byref(h), None) == -1
-    assert lib.mxs_mg_create(0, 1, C.byref(h), None) == -1
-    assert lib.mxs_mg_create(2048, 1, C.byref(h), None) == -10   # beyond int32 rows
+    b = C.c_size_t()
+    assert lib.mxs_mg_size(8, 2, C.byref(b)) == 0
+    ws = torch.empty(b.value, dtype=torch.uint8, device="cuda")
+    assert lib.mxs_mg_create(6, 3, mxs._ptr(ws), b.value, C.byref(h), None) == -1  # 6 not divisible by 4
+    assert lib.mxs_mg_create(8, 0, mxs._ptr(ws), b.value, C.byref(h), None) == -1
+    assert lib.mxs_mg_create(0, 1, mxs._ptr(ws), b.value, C.byref(h), None) == -1
+    assert lib.mxs_mg_create(2048, 1, mxs._ptr(ws), b.value, C.byref(h), None) == -10  # beyond int32 rows
+    assert lib.mxs_mg_create(8, 2, mxs._ptr(ws), b.value - 1, C.byref(h), None) == -1  # too small
+    assert h.value is None
     M = mxs.Multigrid(8, 2)
     x = to_dev(np.zeros(512))
     assert lib.mxs_symgs(M.handle, 2, mxs._ptr(x), mxs._ptr(to_dev(np.zeros(512))), None) == -1

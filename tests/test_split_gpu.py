@@ -197,6 +197,7 @@ def test_split_parts_every_impl_pair_matches_oracle(gpu, rest):
     mxs = gpu
     a = banded_noise(30000, seed=7)
     H = mxs.Matrix.coo(a.nrows, a.ncols, a.ai, a.aj, a.av).split(0.5, rest)
+    H.optimize(mxs.PLAN_DIA_BLOCKED)   # the band's row-blocked copy: every DIA implementation
     band, part = H.parts()
     assert band.format == mxs.DIA and band.ndiag == H.ndiag
     assert part.format == mxs.FORMATS[rest] and part.nnz == H._keep[3].numel()
