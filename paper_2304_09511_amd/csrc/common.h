@@ -72,6 +72,13 @@ struct CgState {
     long long nupd;  // updates made
     int noupd;       // 0 only while an update is pending (update kernels run)
     int last;        // the pending update is the last allowed (iteration cap)
+    // plain CG whose r.r is reduced inside the direction update
+    // (cg_rho_p_kernel): that launch may not write rho while its workgroups
+    // read it, so it leaves the new value here and the next finish of p.Ap
+    // moves it into rho
+    double rho_next;
+    int rho_pend;    // 1: rho_next holds the new rho
+    int pad2;
 };
 
 // Where a fused dot product of an SpMV epilogue goes: one partial per
@@ -346,6 +353,10 @@ constexpr int kFinNT = 1024;
 // breakdown when sigma <= 0 or not finite.
 __device__ __forceinline__ void cg_finish_sigma(CgState *st, double sigma)
 {
+    if (st->rho_pend) {
+        st->rho = st->rho_next;
+        st->rho_pend = 0;
+    }
     st->sigma = sigma;
     st->iters += 1;
     if (!(sigma > 0.0) || !__builtin_isfinite(sigma)) {

@@ -566,9 +566,11 @@ __global__ __launch_bounds__(256) void ell_spmv_kernel(int32_t nrows, int32_t K,
     double dpart = 0.0;
     const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
     for (int64_t i = b * 256 + threadIdx.x; i < nrows; i += (int64_t)gridDim.x * 256) {
+        // the fused dot's x value first: its load overlaps the row's
+        const T xi = DOT ? x[i] : T(0);
         const T yi = padded_row_sum(col, val, i, nrows, K, x);
         y[i] = yi;
-        if (DOT) dpart += (double)yi * (double)x[i];
+        if (DOT) dpart += (double)yi * (double)xi;
     }
     if (DOT) {
         const double bs = block_sum<256>(dpart, red);
@@ -594,11 +596,13 @@ __global__ __launch_bounds__(256) void sell_spmv_kernel(int32_t nrows, int64_t n
         const int64_t sl = p / kSellC;
         const int64_t base = cs[sl];
         const int32_t w = (int32_t)((cs[sl + 1] - base) / kSellC);
+        // the row id (and the fused dot's x value) first: their loads overlap the row's
+        const int32_t i = p < nrows ? perm[p] : 0;
+        const T xi = DOT && p < nrows ? x[i] : T(0);
         const T yi = padded_row_sum(col, val, base + p % kSellC, (int64_t)kSellC, w, x);
         if (p < nrows) {
-            const int32_t i = perm[p];
             y[i] = yi;
-            if (DOT) dpart += (double)yi * (double)x[i];
+            if (DOT) dpart += (double)yi * (double)xi;
         }
     }
     if (DOT) {

@@ -612,6 +612,14 @@ __global__ __launch_bounds__(256) void dia_spmv_kernel(
         // iff the first and the last one do.
         const bool interior = staged && ndiag > 0 && row0 + ROWS <= nrows &&
                               row0 + first_off >= 0 && row0 + ROWS - 1 + last_off < ncols;
+        // x at the block's own rows for the fused dot, loaded now so that its
+        // latency hides under the diagonals' loads (square A: row < ncols)
+        T xself[RPT];
+        if (DOT) {
+#pragma unroll
+            for (int r = 0; r < RPT; ++r)
+                xself[r] = x[min(row0 + r * NT + tid, (int64_t)min(nrows, ncols) - 1)];
+        }
         // value of diagonal d for the block's local row li is a_blk[d*dstride + li]
         const T *__restrict__ a_blk = blocked ? av + b * (int64_t)ndiag * ROWS : av + row0;
         const int64_t dstride = blocked ? (int64_t)ROWS : (int64_t)nrows;
@@ -772,7 +780,7 @@ __global__ __launch_bounds__(256) void dia_spmv_kernel(
 #else
                 y[i] = sum[r];
 #endif
-                if (DOT) dpart += (double)sum[r] * (double)x[i];
+                if (DOT) dpart += (double)sum[r] * (double)xself[r];
             }
         }
     }
@@ -792,6 +800,8 @@ __global__ __launch_bounds__(256) void dia_spmv_kernel(
 // as 0 by the tile that sees the gap, so y needs no separate clearing.
 // ===========================================================================
 constexpr int kCooNT = 256;
+constexpr int kCooGapQ = 32;      // long runs of empty rows a tile queues for its workgroup
+constexpr int kCooShortGap = 64;  // runs up to this long are zeroed by the thread that meets them
 constexpr int kCooIPT = MXS_COO_IPT;
 constexpr int kCooTile = kCooNT * kCooIPT;
 
@@ -849,14 +859,31 @@ __global__ __launch_bounds__(256) void coo_spmv_kernel(
     __shared__ T sval[PADDED];
     __shared__ int sh[NT / kWave];
     __shared__ T sv[NT / kWave];
+    // runs of empty rows longer than kCooShortGap, zeroed by the whole
+    // workgroup after the tile (a thread zeroes shorter runs, and long ones
+    // that find the queue full, itself)
+    __shared__ int32_t gap_lo[kCooGapQ], gap_hi[kCooGapQ];
+    __shared__ int gap_n;
     if (done && *done) return;
     const int tid = threadIdx.x;
     const int64_t g = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t t_lo = g * per, t_hi = min(ntiles, t_lo + per);
+    auto zero_rows = [&](int32_t lo, int32_t hi) {
+        if (hi - lo > kCooShortGap) {
+            const int q = atomicAdd(&gap_n, 1);
+            if (q < kCooGapQ) {
+                gap_lo[q] = lo;
+                gap_hi[q] = hi;
+                return;
+            }
+        }
+        for (int32_t z = lo; z < hi; ++z) y[z] = T(0);
+    };
 
     for (int64_t tile = t_lo; tile < t_hi; ++tile) {
         const int64_t k0 = tile * TILE;
         const int n = (int)min((int64_t)TILE, nnz - k0);
+        if (tid == 0) gap_n = 0; // read after the barriers below
         {
             // Unconditional loads (the last tile clamps to its final entry) so
             // they issue back to back: rows, columns, values, then x gathers.
@@ -909,8 +936,7 @@ __global__ __launch_bounds__(256) void coo_spmv_kernel(
                     if (tile_cont && pr == first_row) carry[2 * tile] = s;
                     else y[pr] = acc ? y[pr] + s : s;
                 }
-                if (!acc)
-                    for (int32_t z = pr + 1; z < rw; ++z) y[z] = T(0); // rows without entries
+                if (!acc && rw > pr + 1) zero_rows(pr + 1, rw); // rows without entries
                 s = T(0);
             }
             s += sval[coo_pad(j)];
@@ -924,10 +950,13 @@ __global__ __launch_bounds__(256) void coo_spmv_kernel(
             } else {
                 if (is_cont) carry[2 * tile] = s;
                 else y[last] = acc ? y[last] + s : s;
-                if (k0 + n == nnz && !acc)
-                    for (int32_t z = last + 1; z < nrows; ++z) y[z] = T(0);
+                if (k0 + n == nnz && !acc && nrows > last + 1) zero_rows(last + 1, nrows);
             }
         }
+        __syncthreads();
+        const int ng = min(gap_n, kCooGapQ);
+        for (int q = 0; q < ng; ++q)
+            for (int32_t z = gap_lo[q] + tid; z < gap_hi[q]; z += NT) y[z] = T(0);
         __syncthreads();
     }
 }
