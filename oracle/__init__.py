@@ -58,10 +58,16 @@ class use_library:
 
 
 def _load(path: str | None = None):
+    """The oracle library; ORACLE_LIB names another build of it (the
+    sanitizer run of the pins uses that)."""
     global _lib
     if path is not None:
         return _bind(C.CDLL(path))
     if _lib is None:
+        other = os.environ.get("ORACLE_LIB")
+        if other:
+            _lib = _bind(C.CDLL(other))
+            return _lib
         if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
             build()
         _lib = _bind(C.CDLL(_LIB_PATH))
