@@ -161,6 +161,22 @@ def cg_runs(torch, mxs, mats, rtol, label):
     return res, bn
 
 
+def cg16_run(torch, mxs):
+    """GPU FP64 CG to 1e-9 on the 16^3 stencil (DIA), time to tolerance after
+    a warm-up solve: the GPU side of the oracle's 16^3 CG timing."""
+    A = mxs.stencil(16, fmt="dia").optimize()
+    b = mxs.spmv(A, torch.ones(A.nrows, dtype=torch.float64, device="cuda"))
+    ws = mxs.cg_workspace(A)
+    mxs.cg_solve(A, b, rtol=1e-9, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, x, r = mxs.cg_solve(A, b, rtol=1e-9, workspace=ws)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) * 1e3
+    A.close()
+    return {"status": st, "iters": r["iters"], "time_to_tol_ms": round(t, 3), "format": "dia"}
+
+
 def padded_bytes(A, nnz, s=8):
     """Algorithmic bytes of an ELL or SELL SpMV: the entries (column and
     value; padding slots are the format's overhead, not the operation's),
@@ -200,25 +216,29 @@ def other_formats(torch, mxs, coo, x, y, label):
     return out
 
 
+# colour order of a symmetric sweep (mxs.h): forward over colours 1, ..., 7, 0,
+# backward over the reverse without repeating colour 0
+SWEEP_PASSES = (1, 2, 3, 4, 5, 6, 7, 0, 7, 6, 5, 4, 3, 2, 1)
+
+
 def symgs_bytes(nn):
     """Algorithmic bytes of one symmetric sweep on the nn^3 stencil: every
     colour pass reads its rows' off-diagonal entries (4-byte column, 8-byte
     value), diagonal, right-hand side and row id, writes their x, and reads
-    x once; 15 passes (the backward sweep repeats no colour)."""
-    import oracle as orc
+    x once; 15 passes (the backward sweep repeats no colour).  A point's
+    colour is the parity of its coordinates, (ix&1) + 2(iy&1) + 4(iz&1)."""
     rows = nn ** 3
-    col = orc.grid_colours(nn)
-    # off-diagonal entries per row of the 27-point stencil: (product of
-    # neighbours in range along each axis) - 1
     i = np.arange(rows)
     ax = [i % nn, (i // nn) % nn, i // (nn * nn)]
+    col = (ax[0] & 1) + 2 * (ax[1] & 1) + 4 * (ax[2] & 1)
+    # off-diagonal entries per row of the 27-point stencil: (product of
+    # neighbours in range along each axis) - 1
     span = np.ones(rows, np.int64)
     for a in ax:
         span *= 1 + (a > 0) + (a < nn - 1)
     offd = span - 1
     total = 0
-    passes = list(orc.COLOUR_SWEEP) + list(reversed(orc.COLOUR_SWEEP[:-1]))
-    for c in passes:
+    for c in SWEEP_PASSES:
         sel = col == c
         total += int(offd[sel].sum()) * 12 + int(sel.sum()) * (8 + 8 + 4 + 8) + rows * 8
     return total
@@ -358,18 +378,7 @@ def mixed_vs_fp64(torch, mxs, n, fmts=("dia", "csr")):
     return out
 
 
-def cpu_baseline(orc, coo_host, nbytes, budget_s=12.0):
-    """The oracle's COO SpMV (single thread) on this host, repeated for about
-    `budget_s` seconds."""
-    ai, aj, av, nrows = coo_host
-    x = np.random.Generator(np.random.PCG64(1)).uniform(-1, 1, nrows)
-    times = []
-    t_end = time.perf_counter() + budget_s
-    while time.perf_counter() < t_end or len(times) < 3:
-        t0 = time.perf_counter()
-        orc.coo_spmv(nrows, ai, aj, av, x)
-        times.append(time.perf_counter() - t0)
-    med = statistics.median(times)
+def host_cpu():
     try:
         cores = len(os.sched_getaffinity(0))
     except Exception:
@@ -382,10 +391,58 @@ def cpu_baseline(orc, coo_host, nbytes, budget_s=12.0):
                 break
     except OSError:
         pass
+    return cores, model
+
+
+def cpu_baseline(orc, coo_host, nbytes, budget_s=8.0, gpu_cg=None):
+    """The oracle on this host, one thread: its COO SpMV (Algorithm 1)
+    repeated for about `budget_s` seconds on the benchmark's matrix, and its
+    FP64 CG to 1e-9 on the 16^3 and 128^3 stencils (b = A*1, x0 = 0) beside
+    the GPU's CG on the same problem; the 192^3 FP64 CG comes from the stored
+    oracle run with the CPU it ran on."""
+    import workloads as wl
+    ai, aj, av, nrows = coo_host
+    x = np.random.Generator(np.random.PCG64(1)).uniform(-1, 1, nrows)
+    times = []
+    t_end = time.perf_counter() + budget_s
+    while time.perf_counter() < t_end or len(times) < 3:
+        t0 = time.perf_counter()
+        orc.coo_spmv(nrows, ai, aj, av, x)
+        times.append(time.perf_counter() - t0)
+    med = statistics.median(times)
+    cores, model = host_cpu()
+    cg = {}
+    for n, coo in ((16, None), (128, (ai, aj, av))):
+        if coo is None:
+            a = wl.stencil(n)
+            cai, caj, cav = a.ai, a.aj, a.av
+        else:
+            cai, caj, cav = coo
+        b = orc.coo_spmv(n ** 3, cai, caj, cav, np.ones(n ** 3))
+        t0 = time.perf_counter()
+        st, xo, it, rel, true_rel = orc.cg(n ** 3, cai, caj, cav, b, None, 1e-9, 20000)
+        t = time.perf_counter() - t0
+        rec = {"status": st, "iters": it, "time_to_tol_ms": round(t * 1e3, 2),
+               "true_rel_resid": true_rel}
+        g = (gpu_cg or {}).get(n)
+        if g:
+            rec["gpu_time_to_tol_ms"] = g["time_to_tol_ms"]
+            rec["gpu_iters"] = g["iters"]
+            rec["gpu_format"] = g["format"]
+            rec["speedup_gpu_over_oracle"] = round(rec["time_to_tol_ms"] / g["time_to_tol_ms"], 1)
+        cg[f"stencil{n}_tol1e-9"] = rec
+    g192 = load_golden("cg_stencil192_tol1e-10")
+    if g192 is not None:
+        cg["stencil192_tol1e-10"] = {
+            "status": g192["status"], "iters": g192["iters"],
+            "time_to_tol_ms": round(1e3 * g192["oracle_seconds"], 1),
+            "source": "tests/golden/cg_stencil192_tol1e-10.json (stored oracle run, one thread of "
+                      "the build container's CPU, not this host)"}
     return {"value": round(nbytes / med / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
             "sample": f"oracle COO SpMV (Algorithm 1, FP64, single thread) on the same 128^3 "
-                      f"stencil, {len(times)} calls in {sum(times):.1f} s, median {med * 1e3:.1f} ms/call",
-            "host_cores_available": cores, "host_cpu": model}
+                      f"stencil, {len(times)} calls in {sum(times):.1f} s, median {med * 1e3:.1f} ms/call; "
+                      f"oracle FP64 CG to 1e-9 on the 16^3 and 128^3 stencils",
+            "host_cores_available": cores, "host_cpu": model, "cg": cg}
 
 
 GOLDEN = os.path.join(ROOT, "tests", "golden")
@@ -411,6 +468,45 @@ def compare_golden(section, name, x_by_fmt=None):
                          "inner_iters": g.get("inner_iters"), "true_rel_resid": g["true_rel_resid"],
                          "source": f"tests/golden/{name}.json"}
     return g
+
+
+def csr_arrays_line(torch, mxs, A, x, y, nbytes):
+    """CSR's entry-tile kernel, which reads the CSR arrays themselves (the
+    default implementation may read a plan copy instead): protocol timing
+    against CSR's algorithmic bytes; the default is restored afterwards."""
+    default = A.impl
+    A.impl = 0
+    tc = time_calls(torch, lambda: mxs.spmv(A, x, y))
+    A.impl = default
+    med = tc["median_ms"] * 1e-3
+    return {"implementation": "entry_tiles", "kernel": "csr_spmv_kernel",
+            "protocol_10x100_median_us": round(med * 1e6, 2), "algorithmic_bytes": nbytes,
+            "GBps": round(nbytes / med / 1e9, 1), "frac_of_peak": round(nbytes / med / 1e9 / PEAK_HBM_GBS, 4)}
+
+
+def fp32_lines(torch, mxs, mats, fp64_bytes):
+    """The FP32 SpMVs of the mixed solvers (values rounded to FP32, FP32 x and
+    y) on the same stencil: protocol timing against the FP32 algorithmic
+    bytes (s = 4)."""
+    out = {}
+    n = mats["csr"].nrows
+    x32 = (torch.rand(n, dtype=torch.float64, device="cuda") * 2 - 1).float()
+    y32 = torch.empty(n, dtype=torch.float32, device="cuda")
+    for f in FORMATS:
+        B = mats[f].cast(mxs.F32)
+        B.optimize()
+        nb = algorithmic_bytes(B, f, s=4)
+        tc = time_calls(torch, lambda: mxs.spmv(B, x32, y32))
+        med = tc["median_ms"] * 1e-3
+        names = mxs.Matrix.IMPL_NAMES[B.format]
+        out[f] = {"us_per_call": round(med * 1e6, 2), "algorithmic_bytes": nb,
+                  "GBps": round(nb / med / 1e9, 1), "frac_of_peak": round(nb / med / 1e9 / PEAK_HBM_GBS, 4),
+                  "bytes_vs_fp64": round(nb / fp64_bytes[f], 3), "implementation": names[B.impl],
+                  "kernel": KERNEL_NAMES[f][B.impl]}
+        log(f"[bench]   fp32 {f}: {out[f]['us_per_call']} us, {out[f]['GBps']} GB/s "
+            f"({100 * out[f]['frac_of_peak']:.1f}%)")
+        B.close()
+    return out
 
 
 def impl_report(mxs, A, x, y, reps=20):
@@ -635,7 +731,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-irregular", action="store_true")
     ap.add_argument("--no-selector", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=8.0)
     ap.add_argument("--pmc", choices=FORMATS + ("symgs", "zipf-csr0", "zipf-csr4", "zipf-coo0", "zipf-coo2"), default=None)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -709,7 +805,18 @@ def main():
 
     for f in FORMATS:
         per[f]["implementations"] = impl_report(mxs, mats[f], x, ys[f])
+        d = per[f]["implementations"]["default_id"]
+        per[f]["implementation"] = per[f]["implementations"]["default"]
+        per[f]["kernel"] = KERNEL_NAMES[f][d]
         log(f"[bench]   {f} implementations (median us): {per[f]['implementations']['median_us']}")
+    if per["csr"]["kernel"] == "ell_spmv_kernel":
+        # the default reads the plan's ELL copy
+        per["csr"]["note"] = ("the default implementation runs ell_spmv_kernel over the plan's ELL copy "
+                              "(rows of near-equal length); algorithmic_bytes are the CSR operation's; "
+                              "csr_arrays_kernel is the kernel that reads the CSR arrays")
+    per["csr"]["csr_arrays_kernel"] = csr_arrays_line(torch, mxs, mats["csr"], x, ys["csr"], bytes_f["csr"])
+    log(f"[bench]   csr entry tiles (CSR arrays): {per['csr']['csr_arrays_kernel']}")
+    out_fp32 = fp32_lines(torch, mxs, mats, bytes_f)
 
     out_other = other_formats(torch, mxs, mats["coo"], x, ys["coo"], f"stencil{args.n}")
 
@@ -732,12 +839,13 @@ def main():
                                   f"FP64 values 26/-1, int32 indices), resident in HBM; one step = one "
                                   f"SpMV in each of COO, CSR, DIA",
                       "x": "U[-1,1) seed 1", "formats": list(FORMATS)},
-           "per_format": per, "other_formats": out_other, "roofline": roofline}
+           "per_format": per, "fp32_spmv": out_fp32, "other_formats": out_other, "roofline": roofline}
 
     if not args.no_cg:
         out["cg"], _ = cg_runs(torch, mxs, mats, 1e-9, f"{args.n}^3")
         out["cg"]["config"] = f"b = A*1, x0 = 0, unpreconditioned CG to 1e-9 (||r_k|| / ||r_0||)"
         compare_golden(out["cg"], f"cg_stencil{args.n}_tol1e-9")
+        out["cg16"] = cg16_run(torch, mxs)
     if not args.no_pcg:
         out["pcg_mg"] = pcg_runs(torch, mxs, args.n, 4, 1e-9, mats)
     for A in mats.values():
@@ -752,7 +860,14 @@ def main():
         out["selector"] = selector_eval(torch, mxs)
     if not args.no_cpu:
         import oracle as orc
-        out["cpu_baseline"] = cpu_baseline(orc, (ai, aj, av, n), bytes_f["coo"], args.cpu_seconds)
+        gpu_cg = {}
+        if "cg" in out:
+            best = min(FORMATS, key=lambda f: out["cg"][f]["time_to_tol_ms"])
+            gpu_cg[args.n] = dict(out["cg"][best], format=best)
+        if "cg16" in out:
+            gpu_cg[16] = out["cg16"]
+        out["cpu_baseline"] = cpu_baseline(orc, (ai, aj, av, n), bytes_f["coo"], args.cpu_seconds,
+                                           gpu_cg=gpu_cg)
         log(f"[bench] CPU oracle: {out['cpu_baseline']['value']} GB/s ({out['cpu_baseline']['sample']})")
         out["parity_vs_oracle"] = parity_checks(orc, checks)
         bad = {k: v for k, v in out["parity_vs_oracle"].items() if not v <= 1e-12}
