@@ -615,16 +615,21 @@ def irregular_runs(torch, mxs, checks):
     return out
 
 
-def selector_eval(torch, mxs, n_live=40):
-    """The committed selector on its 500 held-out matrices (stored timings),
+def selector_eval(torch, mxs, n_live=100):
+    """The committed selector on its 700 held-out matrices (stored timings;
+    also per group of families, with each format's label count and recall),
     and live on a seeded sample of them re-timed on this GPU: accuracy, mean
     regret against the run-first tuner, the always-CSR baseline, and the
     selection cost of each."""
     from paper_2304_09511_amd import selector as S
     model = S.Selector.load(str(S.MODEL_PATH))
     recs, F, T, y = S.load_dataset(str(S.DATA_PATH))
-    tr, te = S.split(len(recs), 1500)
-    out = {"stored_held_out": S.evaluate(model, F[te], T[te])}
+    tr, te = S.dataset_split(len(recs))
+    base, ext = te[te < S.N_BASE], te[te >= S.N_BASE]
+    out = {"stored_held_out": S.evaluate(model, F[te], T[te]),
+           "stored_held_out_base_families": S.evaluate(model, F[base], T[base]),
+           "stored_held_out_further_families": S.evaluate(model, F[ext], T[ext]) if ext.size else None,
+           "labels_per_format_all": {f: int((y == k).sum()) for k, f in enumerate(S.FORMATS)}}
     pick = np.sort(np.random.Generator(np.random.PCG64(12)).choice(te, n_live, replace=False))
     Tl, choice, t_model, t_tuner = [], [], [], []
     for i in pick:
@@ -697,8 +702,13 @@ def pmc_mode(args):
             mxs.spmv(A, x, y)
         args.pmc = fmt
     else:
+        # a stencil format with its default implementation, or csr0: CSR's
+        # entry tiles (the kernel that reads the CSR arrays)
         mats = build_matrices(mxs, args.n)
-        A = mats[args.pmc]
+        A = mats[args.pmc[:3]]
+        if args.pmc == "csr0":
+            A.impl = 0
+        args.pmc = args.pmc[:3]
         x = torch.from_numpy(np.random.Generator(np.random.PCG64(1)).uniform(-1, 1, A.ncols)).cuda()
         y = torch.empty(A.nrows, dtype=torch.float64, device="cuda")
         for _ in range(args.steps):
@@ -732,7 +742,8 @@ def main():
     ap.add_argument("--no-irregular", action="store_true")
     ap.add_argument("--no-selector", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=8.0)
-    ap.add_argument("--pmc", choices=FORMATS + ("symgs", "zipf-csr0", "zipf-csr4", "zipf-coo0", "zipf-coo2"), default=None)
+    ap.add_argument("--pmc", choices=FORMATS + ("csr0", "symgs", "zipf-csr0", "zipf-csr4", "zipf-coo0", "zipf-coo2"),
+                    default=None)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "

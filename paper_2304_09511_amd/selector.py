@@ -18,11 +18,11 @@ ELL, SELL-64-1 (slices of 64 rows, no sorting), HYB (ELL part plus COO
 remainder) and HDC (the diagonals at least half full as a DIA band plus a
 COO remainder, the local/remote split of Table III on one GPU).
 
-The dataset builder labels synthetic matrices (5 families, rows log-uniform
+The dataset builder labels synthetic matrices (8 families, rows log-uniform
 in [1e4, 1e7]) by the tuner's timings; labels are written as JSON lines and
 the builder resumes an interrupted file.
 
-    python -m paper_2304_09511_amd.selector label --n 2000 --out labels.jsonl
+    python -m paper_2304_09511_amd.selector label --n 3200 --out labels.jsonl
     python -m paper_2304_09511_amd.selector train --data labels.jsonl --out model.json
 """
 from __future__ import annotations
@@ -44,6 +44,11 @@ DATA_DIR = pathlib.Path(__file__).resolve().parent / "selector_data"
 DATA_PATH = DATA_DIR / "labels.jsonl"
 MODEL_PATH = DATA_DIR / "model.json"
 FAMILIES = ("stencil7", "stencil27", "banded", "zipf", "block")
+# matrices 2000 onward: a band with scattered entries (uniform, or gathered
+# in a few long rows), hypersparse matrices (most rows empty), and rows of
+# near-equal length at random columns near the diagonal with a few long rows
+EXT_FAMILIES = ("bandscatter", "hypersparse", "windowed")
+N_BASE, N_TOTAL = 2000, 3200
 FORMATS = ("coo", "csr", "dia", "ell", "sell", "hyb", "hdc")
 # equal medians: the general-purpose format first, the two-part ones last
 TIE_ORDER = ("csr", "dia", "ell", "sell", "coo", "hyb", "hdc")
@@ -134,9 +139,11 @@ def exhaustive_select(A_coo, reps=10, warm=3):
 # Dataset
 # ---------------------------------------------------------------------------
 def matrix_spec(i, seed=4):
-    """Family, row count and seed of dataset matrix i (400 per family)."""
+    """Family, row count and seed of dataset matrix i (400 per family):
+    the five base families cycle over matrices 0-1999, the two further ones
+    over 2000-2799."""
     g = np.random.Generator(np.random.PCG64([seed, i]))
-    fam = FAMILIES[i % len(FAMILIES)]
+    fam = FAMILIES[i % len(FAMILIES)] if i < N_BASE else EXT_FAMILIES[(i - N_BASE) % len(EXT_FAMILIES)]
     rows = int(round(10 ** g.uniform(4.0, 7.0)))
     spec = {"i": i, "family": fam, "seed": int(g.integers(1, 2 ** 31 - 1))}
     if fam.startswith("stencil"):
@@ -145,8 +152,17 @@ def matrix_spec(i, seed=4):
         spec["nblockrows"] = max(1, rows // 8)
     else:
         spec["rows"] = rows
-        if fam == "banded":
+        if fam in ("banded", "bandscatter"):
             spec["ndiag"] = int(g.integers(3, 65))
+        if fam == "bandscatter":
+            spec["frac"] = float(10 ** g.uniform(-3.0, math.log10(0.4)))
+            spec["concentrated"] = bool(g.integers(0, 2))
+        if fam == "hypersparse":
+            spec["per_row"] = float(10 ** g.uniform(math.log10(0.02), math.log10(0.5)))
+        if fam == "windowed":
+            spec["length"] = int(g.integers(4, 33))
+            spec["width"] = int(10 ** g.uniform(2.0, 4.7))
+            spec["tail_frac"] = float(10 ** g.uniform(-2.0, math.log10(0.5)))
     return spec
 
 
@@ -162,6 +178,14 @@ def generate_arrays(spec, device="cuda"):
         return wl.device_banded(spec["rows"], spec["ndiag"], 2000, spec["seed"], device=device)
     if fam == "zipf":
         return wl.device_zipf_rows(spec["rows"], spec["seed"], device=device)
+    if fam == "bandscatter":
+        return wl.device_banded_scatter(spec["rows"], spec["ndiag"], 2000, spec["frac"],
+                                        spec["concentrated"], spec["seed"], device=device)
+    if fam == "hypersparse":
+        return wl.device_hypersparse(spec["rows"], spec["per_row"], spec["seed"], device=device)
+    if fam == "windowed":
+        return wl.device_windowed_rows(spec["rows"], spec["length"], spec["width"], spec["tail_frac"],
+                                       spec["seed"], device=device)
     return wl.device_block_random(spec["nblockrows"], spec["seed"], device=device)
 
 
@@ -220,6 +244,19 @@ def load_dataset(path):
 def split(n, n_train, seed=4):
     perm = np.random.Generator(np.random.PCG64(seed)).permutation(n)
     return np.sort(perm[:n_train]), np.sort(perm[n_train:])
+
+
+def dataset_split(n):
+    """Training and held-out indices of the first n matrices: the base
+    matrices' fixed 1,500 / 500 split, and three quarters / one quarter of
+    the further families' (seed 5)."""
+    tr, te = split(min(n, N_BASE), min(n, N_BASE) * 3 // 4)
+    if n > N_BASE:
+        m = n - N_BASE
+        etr, ete = split(m, m * 3 // 4, seed=5)
+        tr = np.concatenate([tr, N_BASE + etr])
+        te = np.concatenate([te, N_BASE + ete])
+    return tr, te
 
 
 def regret(T, choice):
@@ -362,38 +399,47 @@ def select_format(A, model=None):
 
 
 def evaluate(model, F, T):
-    """Accuracy, mean regret of the model and of always-CSR, on rows of F/T."""
+    """Accuracy, mean regret of the model and of always-CSR, and per format
+    the labels (fastest) and the recall of the model on them, on rows of F/T."""
     feas = np.isfinite(T)
     choice = model.predict(F, feas)
     best = np.array([FORMATS.index(best_format(dict(zip(FORMATS, t)))) for t in T])
+    per = {}
+    for k, f in enumerate(FORMATS):
+        sel = best == k
+        per[f] = {"labels": int(sel.sum()),
+                  "recall": None if not sel.any() else float(np.mean(choice[sel] == k))}
     return {"n": int(F.shape[0]), "accuracy": float(np.mean(choice == best)),
             "mean_regret": regret(T, choice), "always_csr_regret": regret(T, np.ones(len(T), int)),
-            "exhaustive_cost_x_one_spmv": float(len(FORMATS))}
+            "exhaustive_cost_x_one_spmv": float(len(FORMATS)), "per_format": per}
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
     a = sub.add_parser("label")
-    a.add_argument("--n", type=int, default=2000)
+    a.add_argument("--n", type=int, default=N_TOTAL)
     a.add_argument("--out", required=True)
     a.add_argument("--seed", type=int, default=4)
     b = sub.add_parser("train")
     b.add_argument("--data", required=True)
     b.add_argument("--out", required=True)
     b.add_argument("--epochs", type=int, default=300)
-    b.add_argument("--train", type=int, default=1500)
     args = ap.parse_args(argv)
     mxs.load()
     if args.cmd == "label":
         label_dataset(args.n, args.out, args.seed)
     else:
         recs, F, T, y = load_dataset(args.data)
-        tr, te = split(len(recs), min(args.train, len(recs) - 1))
+        tr, te = dataset_split(len(recs))
         model = Selector().fit(F[tr], y[tr], epochs=args.epochs)
         model.save(args.out)
+        base = te[te < N_BASE]
+        ext = te[te >= N_BASE]
         print(json.dumps({"train": evaluate(model, F[tr], T[tr]),
-                          "held_out": evaluate(model, F[te], T[te])}))
+                          "held_out": evaluate(model, F[te], T[te]),
+                          "held_out_base_families": evaluate(model, F[base], T[base]),
+                          "held_out_further_families": evaluate(model, F[ext], T[ext]) if ext.size else None}))
 
 
 if __name__ == "__main__":

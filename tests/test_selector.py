@@ -11,11 +11,13 @@ from paper_2304_09511_amd import selector as S
 
 
 def test_dataset_spec_is_deterministic_and_balanced():
-    specs = [S.matrix_spec(i) for i in range(2000)]
-    assert specs == [S.matrix_spec(i) for i in range(2000)]
+    specs = [S.matrix_spec(i) for i in range(S.N_TOTAL)]
+    assert S.N_TOTAL == S.N_BASE + 400 * len(S.EXT_FAMILIES)
+    assert specs == [S.matrix_spec(i) for i in range(S.N_TOTAL)]
     fams = [s["family"] for s in specs]
-    for f in S.FAMILIES:
+    for f in S.FAMILIES + S.EXT_FAMILIES:
         assert fams.count(f) == 400
+    assert set(fams[:S.N_BASE]) == set(S.FAMILIES)
     rows = []
     for s in specs:
         if s["family"].startswith("stencil"):
@@ -24,8 +26,15 @@ def test_dataset_spec_is_deterministic_and_balanced():
             rows.append(8 * s["nblockrows"])
         else:
             rows.append(s["rows"])
-            if s["family"] == "banded":
+            if s["family"] in ("banded", "bandscatter"):
                 assert 3 <= s["ndiag"] <= 64
+            if s["family"] == "bandscatter":
+                assert 0.001 <= s["frac"] <= 0.4 and isinstance(s["concentrated"], bool)
+            if s["family"] == "hypersparse":
+                assert 0.02 <= s["per_row"] <= 0.5
+            if s["family"] == "windowed":
+                assert 4 <= s["length"] <= 32 and 100 <= s["width"] <= 50200
+                assert 0.01 <= s["tail_frac"] <= 0.5
     rows = np.array(rows)
     assert rows.min() >= 9000 and rows.max() <= 10_100_000
     # log-uniform: about a third of the matrices in each decade
@@ -51,6 +60,44 @@ def test_split_is_a_partition():
     tr, te = S.split(2000, 1500)
     assert len(tr) == 1500 and len(te) == 500
     assert np.array_equal(np.sort(np.concatenate([tr, te])), np.arange(2000))
+    # the whole set: the base matrices keep that split, the further families
+    # split three to one
+    tr2, te2 = S.dataset_split(S.N_TOTAL)
+    assert len(tr2) == 2400 and len(te2) == 800
+    assert np.array_equal(np.sort(np.concatenate([tr2, te2])), np.arange(S.N_TOTAL))
+    assert np.array_equal(tr2[tr2 < S.N_BASE], tr) and np.array_equal(te2[te2 < S.N_BASE], te)
+
+
+@pytest.mark.parametrize("concentrated", [False, True])
+def test_band_scatter_and_hypersparse_generators(concentrated):
+    """Canonical COO (sorted, distinct, in range); the band keeps every
+    in-range slot of its offsets; scattered entries add about frac of the
+    band's count, gathered in at most 1% of the rows when concentrated."""
+    import torch
+    N = 30000
+    nr, nc, ai, aj, av = wl.device_banded_scatter(N, 9, 300, 0.2, concentrated, seed=11, device="cpu")
+    b_nr, _, b_ai, b_aj, _ = wl.device_banded(N, 9, 300, 11, device="cpu")
+    key = ai.long() * nc + aj.long()
+    assert bool((key[1:] > key[:-1]).all()) and nr == nc == N
+    bkey = b_ai.long() * N + b_aj.long()
+    assert bool(torch.isin(bkey, key).all())
+    extra = key.numel() - bkey.numel()
+    assert 0.15 * bkey.numel() <= extra <= 0.2 * bkey.numel()
+    off = ~torch.isin(key, bkey)
+    if concentrated:
+        assert torch.unique(ai[off]).numel() <= N // 100
+    nr, nc, ai, aj, av = wl.device_hypersparse(N, 0.3, seed=12, device="cpu")
+    key = ai.long() * nc + aj.long()
+    assert bool((key[1:] > key[:-1]).all())
+    assert 0.29 * N <= key.numel() <= 0.3 * N and av.numel() == key.numel()
+    nr, nc, ai, aj, av = wl.device_windowed_rows(N, 12, 500, 0.1, seed=13, device="cpu")
+    key = ai.long() * nc + aj.long()
+    assert bool((key[1:] > key[:-1]).all())
+    lens = torch.bincount(ai.long(), minlength=N)
+    # the body: at most length + 1 entries a row outside the long rows
+    assert int(torch.quantile(lens.double(), 0.9)) <= 13 and int(lens.max()) > 13
+    body = (aj.long() - ai.long()).abs() <= 500
+    assert float(body.double().mean()) > 0.85
 
 
 def test_he_init_layout_and_scale():
@@ -117,7 +164,7 @@ def test_committed_labels_are_consistent():
     if not path.exists():
         pytest.skip("no labelled dataset committed")
     recs, F, T, y = S.load_dataset(str(path))
-    assert len(recs) == 2000 and [r["i"] for r in recs] == list(range(2000))
+    assert len(recs) == S.N_TOTAL and [r["i"] for r in recs] == list(range(S.N_TOTAL))
     for r in recs:
         t = {f: (math.inf if r["times_ms"][f] is None else r["times_ms"][f]) for f in S.FORMATS}
         assert r["label"] == S.best_format(t)

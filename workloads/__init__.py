@@ -409,3 +409,69 @@ def device_banded_noise(N: int, ndiag: int, max_offset: int, noise: int, seed: i
     first[1:] = key[1:] != key[:-1]
     key, val = key[first], val[first]
     return N, N, (key // N).to(torch.int32), (key % N).to(torch.int32), val.contiguous()
+
+
+def device_banded_scatter(N: int, ndiag: int, max_offset: int, frac: float, concentrated: bool,
+                          seed: int, device="cuda", dtype=None):
+    """A banded matrix (device_banded) plus round(frac * band entries)
+    entries at random positions, N(0,1) values, sorted by (row, column); a
+    position already on the band keeps the band's value.  Uniform positions,
+    or (concentrated) rows drawn from a random 1% of the rows: long rows over
+    a short-row band."""
+    import torch
+    dtype = dtype or torch.float64
+    nr, nc, ai, aj, av = device_banded(N, ndiag, max_offset, seed, device=device, dtype=dtype)
+    noise = int(round(frac * ai.numel()))
+    g = _tgen(seed + 7, device)
+    if concentrated:
+        pool = torch.randperm(N, generator=g, device=device)[:max(1, N // 100)]
+        ni = pool[torch.randint(0, pool.numel(), (noise,), generator=g, device=device)]
+    else:
+        ni = torch.randint(0, N, (noise,), generator=g, device=device, dtype=torch.int64)
+    nj = torch.randint(0, N, (noise,), generator=g, device=device, dtype=torch.int64)
+    nv = torch.randn(noise, generator=g, device=device, dtype=dtype)
+    key = torch.cat([ai.long() * N + aj.long(), ni.long() * N + nj])
+    val = torch.cat([av, nv])
+    key, order = torch.sort(key, stable=True)
+    val = val[order]
+    first = torch.ones_like(key, dtype=torch.bool)
+    first[1:] = key[1:] != key[:-1]
+    key, val = key[first], val[first]
+    return N, N, (key // N).to(torch.int32), (key % N).to(torch.int32), val.contiguous()
+
+
+def device_hypersparse(N: int, per_row: float, seed: int, device="cuda", dtype=None):
+    """About per_row * N entries (fewer rows than entries' worth: most rows
+    empty when per_row < 1) at distinct uniform random positions of an N x N
+    matrix, N(0,1) values, sorted by (row, column)."""
+    import torch
+    dtype = dtype or torch.float64
+    g = _tgen(seed, device)
+    m = max(1, int(round(per_row * N)))
+    key = torch.randint(0, N * N, (m,), generator=g, device=device, dtype=torch.int64)
+    key = torch.unique(key)
+    val = torch.randn(key.numel(), generator=g, device=device, dtype=dtype)
+    return N, N, (key // N).to(torch.int32), (key % N).to(torch.int32), val.contiguous()
+
+
+def device_windowed_rows(N: int, length: int, width: int, tail_frac: float, seed: int,
+                         device="cuda", dtype=None):
+    """Rows of near-equal length (length - 1 to length + 1 entries, fewer
+    where columns collide) at uniform random columns within `width` of the
+    diagonal, plus round(tail_frac * entries) entries at random columns in
+    a random 1% of the rows (a few long rows over an ELL-friendly body);
+    N(0,1) values, sorted by (row, column), distinct."""
+    import torch
+    dtype = dtype or torch.float64
+    g = _tgen(seed, device)
+    lens = length + torch.randint(-1, 2, (N,), generator=g, device=device)
+    lens = lens.clamp(min=1)
+    ai = torch.repeat_interleave(torch.arange(N, device=device, dtype=torch.int64), lens)
+    aj = (ai + torch.randint(-width, width + 1, (ai.numel(),), generator=g, device=device)).clamp(0, N - 1)
+    tail = int(round(tail_frac * ai.numel()))
+    pool = torch.randperm(N, generator=g, device=device)[:max(1, N // 100)]
+    ti = pool[torch.randint(0, pool.numel(), (tail,), generator=g, device=device)]
+    tj = torch.randint(0, N, (tail,), generator=g, device=device, dtype=torch.int64)
+    key = torch.unique(torch.cat([ai * N + aj, ti * N + tj]))
+    val = torch.randn(key.numel(), generator=g, device=device, dtype=dtype)
+    return N, N, (key // N).to(torch.int32), (key % N).to(torch.int32), val.contiguous()
