@@ -108,6 +108,32 @@ def test_stencil128_spmv_full_vector(gpu, stencil128):
         assert rel_maxnorm(y, ref) <= 1e-12, fmt
 
 
+def test_stencil128_every_implementation_full_vector(gpu, stencil128):
+    """Every SpMV implementation of COO, CSR and DIA (DIA planned with its
+    row-blocked copy, so that all three are reachable) at the benchmark's
+    size, the whole vector against the oracle."""
+    a, mats = stencil128
+    x = wl.uniform_vector(a.ncols, seed=2)
+    ref = orc.coo_spmv(a.nrows, a.ai, a.aj, a.av, x)
+    xd = to_dev(x)
+    D = mats["coo"].convert("dia").optimize(gpu.PLAN_DIA_BLOCKED)
+    for fmt, B in (("coo", mats["coo"]), ("csr", mats["csr"]), ("dia", D)):
+        default = B.impl
+        ran = []
+        for i in range(B.impl_count()):
+            try:
+                B.impl = i
+            except gpu.MxsError as e:
+                assert e.status == -10
+                continue
+            y = gpu.spmv(B, xd).cpu().numpy()
+            assert rel_maxnorm(y, ref) <= 1e-12, (fmt, i)
+            ran.append(i)
+        B.impl = default
+        assert {"coo": {0, 1}, "csr": {0, 1, 2, 3, 5}, "dia": {0, 1, 2}}[fmt] <= set(ran), (fmt, ran)
+    D.close()
+
+
 def test_stencil128_spmv_integer_data_bit_exact(gpu, stencil128):
     a, mats = stencil128
     x = wl.integer_vector(a.ncols, seed=4)
