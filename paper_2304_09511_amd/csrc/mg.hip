@@ -45,6 +45,16 @@ __device__ __forceinline__ T ld_slice(const T *p)
     if constexpr (STREAM) return __builtin_nontemporal_load(p);
     else return *p;
 }
+// Workgroup index of the cycle's kernels: with a grid of a multiple of 8
+// workgroups, XCD j (workgroups j, j + 8, ...) takes the j-th eighth of the
+// rows in colour order, that is the same z-slab of the grid in every
+// colour's pass, so the neighbour values a pass reads were mostly written by
+// the previous pass through the same L2.
+__device__ __forceinline__ int32_t mg_block()
+{
+    return gridDim.x % kNumXcd ? (int32_t)blockIdx.x : (int32_t)xcd_remap(blockIdx.x, gridDim.x);
+}
+
 // sweep order of the colours: coarse points (colour 0) last
 constexpr int kSweep[kColours] = {1, 2, 3, 4, 5, 6, 7, 0};
 
@@ -154,7 +164,7 @@ __global__ __launch_bounds__(kMgNT) void symgs_colour_kernel(
     int32_t p0, int32_t nrows_c, int32_t s0, const int *__restrict__ done)
 {
     if (done && *done) return;
-    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t t = mg_block() * blockDim.x + threadIdx.x;
     if (t >= nrows_c) return;
     const int32_t s = s0 + t / kSlice;
     const int lane = t % kSlice;
@@ -196,7 +206,7 @@ __global__ __launch_bounds__(kMgNT) void mg_start_kernel(const int32_t *__restri
                                                          const int *__restrict__ done)
 {
     if (done && *done) return;
-    for (int32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < rows; p += gridDim.x * blockDim.x) {
+    for (int32_t p = mg_block() * blockDim.x + threadIdx.x; p < rows; p += gridDim.x * blockDim.x) {
         const int32_t i = order[p];
         z[i] = p >= q0 && p < q1 ? r[i] / diag[p] : 0.0;
     }
@@ -210,7 +220,7 @@ __global__ __launch_bounds__(kMgNT) void mg_restrict_kernel(
     int32_t nc, double *__restrict__ rc, const int *__restrict__ done)
 {
     if (done && *done) return;
-    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t t = mg_block() * blockDim.x + threadIdx.x;
     if (t >= nc) return;
     const int32_t s = t / kSlice;
     const int lane = t % kSlice;
@@ -228,11 +238,13 @@ __global__ void mg_prolong_kernel(const int32_t *__restrict__ order, const doubl
                                   int32_t nc, double *__restrict__ z, const int *__restrict__ done)
 {
     if (done && *done) return;
-    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t t = mg_block() * blockDim.x + threadIdx.x;
     if (t < nc) z[order[t]] += zc[t];
 }
 
 static uint32_t blocks(int64_t n, int nt = kMgNT) { return (uint32_t)std::max<int64_t>(1, (n + nt - 1) / nt); }
+// grid of the cycle's kernels: a multiple of 8 workgroups (see mg_block)
+static uint32_t xblocks(int64_t n, int nt) { return pad_grid(blocks(n, nt)); }
 
 // ---------------------------------------------------------------------------
 // Hierarchy: every array lives in the caller's workspace, laid out by a
@@ -439,7 +451,7 @@ static void colour_pass(const MgLevel &L, int c, const double *r, double *x,
     const bool big = L.rows >= kBigRows;
     const int nt = big ? 256 : 64;
     auto kern = big ? symgs_colour_kernel<16, true> : symgs_colour_kernel<32, false>;
-    kern<<<blocks(nr, nt), nt, 0, s>>>(L.order, L.soff, L.col, L.val, L.diag, r, x, p0, nr,
+    kern<<<xblocks(nr, nt), nt, 0, s>>>(L.order, L.soff, L.col, L.val, L.diag, r, x, p0, nr,
                                        L.sfirst[c], done);
 }
 
@@ -453,7 +465,7 @@ static mxs_status symgs_level(const MgLevel &L, const double *r, double *x, bool
 {
     if (zero_start) {
         const int c = kSweep[0];
-        mg_start_kernel<<<std::min<uint32_t>(blocks(L.rows, 256), 8192), 256, 0, s>>>(
+        mg_start_kernel<<<std::min<uint32_t>(xblocks(L.rows, 256), 8192), 256, 0, s>>>(
             L.order, L.diag, r, x, L.rows, L.coff[c], L.coff[c + 1], done);
     }
     for (int k = zero_start ? 1 : 0; k < kColours; ++k) colour_pass(L, kSweep[k], r, x, done, s);
@@ -476,11 +488,11 @@ static mxs_status vcycle(const mxs_mg_s *M, size_t l, const double *r, double *z
     const MgLevel &C = M->lv[l + 1];
     const int32_t nc = L.coff[1]; // colour-0 rows = coarse rows
     const int nt = L.rows >= kBigRows ? 256 : 64;
-    mg_restrict_kernel<<<blocks(nc, nt), nt, 0, s>>>(L.order, L.soff, L.col, L.val, L.diag, r, z, nc,
+    mg_restrict_kernel<<<xblocks(nc, nt), nt, 0, s>>>(L.order, L.soff, L.col, L.val, L.diag, r, z, nc,
                                                      C.r, done);
     if ((st = launch_status()) != MXS_OK) return st;
     if ((st = vcycle(M, l + 1, C.r, C.z, done, s)) != MXS_OK) return st;
-    mg_prolong_kernel<<<blocks(nc, nt), nt, 0, s>>>(L.order, C.z, nc, z, done);
+    mg_prolong_kernel<<<xblocks(nc, nt), nt, 0, s>>>(L.order, C.z, nc, z, done);
     if ((st = launch_status()) != MXS_OK) return st;
     return symgs_level(L, r, z, false, done, s);
 }
