@@ -615,6 +615,90 @@ def irregular_runs(torch, mxs, checks):
     return out
 
 
+def device_facts(torch):
+    """What the device reports about itself (names, counts, sizes)."""
+    pr = torch.cuda.get_device_properties(0)
+    out = {"name": pr.name, "arch": getattr(pr, "gcnArchName", None),
+           "compute_units": pr.multi_processor_count, "hbm_bytes": pr.total_memory,
+           "wavefront": getattr(pr, "warp_size", None)}
+    l2 = getattr(pr, "L2_cache_size", None)
+    if l2:
+        out["l2_bytes_reported"] = l2
+    return out
+
+
+def stream_reference(torch, mxs, mib=512, reps=10):
+    """Bandwidth of plain streams on this device, for scale beside the SpMV
+    figures: a device copy (torch, reads and writes `mib` MiB each way) and a
+    read-only stream (the library's dot product of two `mib` MiB FP64
+    vectors).  Median of `reps` timed calls after two warm-ups."""
+    n = mib * 2 ** 20 // 8
+    a = torch.rand(n, dtype=torch.float64, device="cuda")
+    b = torch.rand(n, dtype=torch.float64, device="cuda")
+    c = torch.empty_like(a)
+
+    def med(fn):
+        for _ in range(2):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ts = []
+        for _ in range(reps):
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1) * 1e-3)
+        return statistics.median(ts)
+    t_copy = med(lambda: c.copy_(a))
+    t_read = med(lambda: mxs.dot(a, b))
+    out = {"copy_GBps": round(2 * n * 8 / t_copy / 1e9, 1), "copy_bytes_each_way": n * 8,
+           "read_stream_GBps": round(2 * n * 8 / t_read / 1e9, 1), "read_stream_bytes": 2 * n * 8,
+           "read_stream_kernel": "dot_partials_kernel (mxs_dot)",
+           "timing": f"median of {reps} calls, HIP events around each"}
+    del a, b, c
+    torch.cuda.empty_cache()
+    return out
+
+
+def conversion_costs(torch, mxs, coo, spmv_ms, reps=3):
+    """Runtime format switching has a price (Section IV): wall time of each
+    conversion from the 128^3 COO handle (and back), and of building each
+    format's plan (mxs_optimize), in ms and in SpMVs of the target format.
+    Matrix.convert includes its host-synchronous sizing call and the
+    allocation of the new arrays from torch's caching allocator."""
+    def wall(fn):
+        r = fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+            del r
+        return statistics.median(ts) * 1e3
+    out = {}
+    csr = coo.convert("csr")
+    dia = coo.convert("dia")
+    for name, fn, tgt in (("coo_to_csr", lambda: coo.convert("csr"), "csr"),
+                          ("coo_to_dia", lambda: coo.convert("dia"), "dia"),
+                          ("csr_to_coo", lambda: csr.convert("coo"), "coo"),
+                          ("csr_to_dia", lambda: csr.convert("dia"), "dia"),
+                          ("dia_to_csr", lambda: dia.convert("csr"), "csr"),
+                          ("dia_to_coo", lambda: dia.convert("coo"), "coo")):
+        ms = wall(fn)
+        out[name] = {"ms": round(ms, 3), "spmv_equivalents": round(ms / spmv_ms[tgt], 1)}
+    for name, A, tgt in (("optimize_csr", csr, "csr"), ("optimize_dia", dia, "dia"),
+                         ("optimize_coo", coo, "coo")):
+        ms = wall(lambda A=A: A.optimize())
+        out[name] = {"ms": round(ms, 3), "spmv_equivalents": round(ms / spmv_ms[tgt], 1)}
+    csr.close()
+    dia.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def selector_eval(torch, mxs, n_live=100):
     """The committed selector on its 700 held-out matrices (stored timings;
     also per group of families, with each format's label count and recall),
@@ -831,6 +915,16 @@ def main():
 
     out_other = other_formats(torch, mxs, mats["coo"], x, ys["coo"], f"stencil{args.n}")
 
+    # scale: plain streams on the same device, and what switching formats costs
+    stream = stream_reference(torch, mxs)
+    for f in FORMATS:
+        per[f]["frac_of_read_stream"] = round(per[f]["protocol_10x100"]["GBps"] / stream["read_stream_GBps"], 4)
+    log(f"[bench] streams: copy {stream['copy_GBps']} GB/s, read {stream['read_stream_GBps']} GB/s")
+    conv = conversion_costs(torch, mxs, mats["coo"],
+                            {f: per[f]["protocol_10x100"]["median_ms"] * 1e-3 for f in FORMATS})
+    conv_s = ", ".join(f"{k} {v['ms']}" for k, v in conv.items())
+    log(f"[bench] conversions and plans (ms): {conv_s}")
+
     # dominant kernel of the step and its roofline
     dom = max(FORMATS, key=lambda f: per[f]["us_per_call"])
     achieved = bytes_f[dom] / (per[dom]["us_per_call"] * 1e-6) / 1e9
@@ -850,7 +944,8 @@ def main():
                                   f"FP64 values 26/-1, int32 indices), resident in HBM; one step = one "
                                   f"SpMV in each of COO, CSR, DIA",
                       "x": "U[-1,1) seed 1", "formats": list(FORMATS)},
-           "per_format": per, "fp32_spmv": out_fp32, "other_formats": out_other, "roofline": roofline}
+           "per_format": per, "fp32_spmv": out_fp32, "other_formats": out_other, "roofline": roofline,
+           "device": device_facts(torch), "stream_reference": stream, "conversion": conv}
 
     if not args.no_cg:
         out["cg"], _ = cg_runs(torch, mxs, mats, 1e-9, f"{args.n}^3")

@@ -74,15 +74,53 @@ struct Aux {
 // ---------------------------------------------------------------------------
 // Reductions
 // ---------------------------------------------------------------------------
-template <typename T>
+// Per-workgroup partials of a.b.  VEC (both 16-byte aligned): each thread
+// loads kVU 16-byte vectors of each array (non-temporal) before adding, then
+// the scalar tail of n mod (16/sizeof(T)); a fixed order per thread.
+template <typename T, bool VEC>
 __global__ __launch_bounds__(kVNT) void dot_kernel(int64_t n, const T *__restrict__ a,
                                                    const T *__restrict__ b, double *partials)
 {
     __shared__ double red[kVNT / kWave];
     double s = 0.0;
-    VEC_LOOP(i, n) s += (double)a[i] * (double)b[i];
+    int64_t tail = 0;
+    if constexpr (VEC) {
+        using V = V16<T>;
+        constexpr int W = 16 / sizeof(T);
+        const int64_t nv = n / W;
+        const V *__restrict__ av = (const V *)a;
+        const V *__restrict__ bv = (const V *)b;
+        for (int64_t v0 = (int64_t)blockIdx.x * kVNT * kVU + threadIdx.x; v0 < nv;
+             v0 += (int64_t)gridDim.x * kVNT * kVU) {
+            V as[kVU], bs[kVU];
+#pragma unroll
+            for (int u = 0; u < kVU; ++u) {
+                const int64_t v = min(v0 + (int64_t)u * kVNT, nv - 1); // in range; sums masked
+                as[u] = __builtin_nontemporal_load(&av[v]);
+                bs[u] = __builtin_nontemporal_load(&bv[v]);
+            }
+#pragma unroll
+            for (int u = 0; u < kVU; ++u)
+                if (v0 + (int64_t)u * kVNT < nv)
+#pragma unroll
+                    for (int w = 0; w < W; ++w) s += (double)as[u][w] * (double)bs[u][w];
+        }
+        tail = nv * W;
+    }
+    for (int64_t i = tail + (int64_t)blockIdx.x * kVNT + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kVNT)
+        s += (double)a[i] * (double)b[i];
     const double bs = block_sum<kVNT>(s, red);
     if (threadIdx.x == 0) partials[blockIdx.x] = bs;
+}
+
+template <typename T>
+static void dot_partials(int64_t n, const T *a, const T *b, double *parts, uint32_t g, hipStream_t s)
+{
+    if (al16(a) && al16(b))
+        dot_kernel<T, true><<<g, kVNT, 0, s>>>(n, a, b, parts);
+    else
+        dot_kernel<T, false><<<g, kVNT, 0, s>>>(n, a, b, parts);
 }
 
 // *out = sum of the partials (single workgroup)
@@ -101,9 +139,9 @@ mxs_status dot_launch(int64_t n, mxs_dtype t, const void *a, const void *b, doub
     double *parts = nullptr;
     MXS_HIP(hipMallocAsync((void **)&parts, sizeof(double) * g, s));
     if (t == MXS_F64)
-        dot_kernel<double><<<g, kVNT, 0, s>>>(n, (const double *)a, (const double *)b, parts);
+        dot_partials<double>(n, (const double *)a, (const double *)b, parts, g, s);
     else
-        dot_kernel<float><<<g, kVNT, 0, s>>>(n, (const float *)a, (const float *)b, parts);
+        dot_partials<float>(n, (const float *)a, (const float *)b, parts, g, s);
     MXS_HIP(hipGetLastError());
     total_kernel<<<1, kFinNT, 0, s>>>(parts, g, result);
     MXS_HIP(hipGetLastError());
@@ -163,9 +201,9 @@ mxs_status dot_noalloc_launch(int64_t n, mxs_dtype t, const void *a, const void 
     // every workgroup writes its own partial and the total reads exactly g:
     // nothing in the array needs clearing between calls
     if (t == MXS_F64)
-        dot_kernel<double><<<g, kVNT, 0, s>>>(n, (const double *)a, (const double *)b, parts);
+        dot_partials<double>(n, (const double *)a, (const double *)b, parts, g, s);
     else
-        dot_kernel<float><<<g, kVNT, 0, s>>>(n, (const float *)a, (const float *)b, parts);
+        dot_partials<float>(n, (const float *)a, (const float *)b, parts, g, s);
     MXS_HIP(hipGetLastError());
     total_kernel<<<1, kFinNT, 0, s>>>(parts, g, result);
     MXS_HIP(hipGetLastError());
