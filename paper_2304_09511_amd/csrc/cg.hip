@@ -716,6 +716,7 @@ __global__ __launch_bounds__(kFinNT) void ru_resid_finish_kernel(const double *_
             else st->beta = r32sq / st->rho;
             st->rho = r32sq;
             st->rmax = sqrt(r32sq);
+            st->done = 0;
         }
     }
 }
@@ -733,7 +734,10 @@ __global__ __launch_bounds__(kFinNT) void ru_rho_finish_kernel(const double *__r
         st->rr = rr;
         const bool cap = st->iters >= st->maxit;
         if (rn <= st->delta * st->rmax || rn <= st->thresh) {
+            // update pending: done = 2 parks the iteration kernels until
+            // the residual replacement has run (it resets done)
             st->noupd = 0;
+            st->done = 2;
             st->last = cap ? 1 : 0;
             st->nupd += 1;
         } else if (cap) {
@@ -959,6 +963,70 @@ mxs_status enqueue_ru_iteration(const mxs_mat_s *A, const mxs_mat_s *A32, int64_
     return tm.mark();
 }
 
+// The reliable-update loop without the update kernels in every iteration:
+// one FP32 CG step (SpMV with p.q, x/r update, r.r finish, direction) ...
+mxs_status enqueue_ru_step(const mxs_mat_s *A32, int64_t n, float *d32, float *r32, float *p32,
+                           float *q32, double *parts, CgState *st, hipStream_t s)
+{
+    mxs_status e;
+    const DotSink ds{parts, st};
+    const uint32_t g32 = vec_grid(n, 4);
+    if ((e = spmv_launch(A32, p32, q32, &st->done, &ds, s)) != MXS_OK) return e;
+    cg_xr_kernel<float, true, true><<<g32, kVNT, 0, s>>>(n, d32, r32, p32, q32, parts, st);
+    ru_rho_finish_kernel<<<1, kFinNT, 0, s>>>(parts, g32, st);
+    cg_p_kernel<float><<<g32, kVNT, 0, s>>>(n, r32, p32, st);
+    return launch_status();
+}
+
+// ... and, enqueued by the host when a step left an update pending (done =
+// 2; the steps after it returned at entry), the residual replacement and
+// the direction update of the step that asked for it.
+mxs_status enqueue_ru_update(const mxs_mat_s *A, int64_t n, const double *b, double *x, double *q64,
+                             float *d32, float *r32, float *p32, double *parts, CgState *st,
+                             hipStream_t s)
+{
+    mxs_status e;
+    const uint32_t g = vec_grid(n);
+    const uint32_t g32 = vec_grid(n, 4);
+    ru_apply_kernel<false><<<g, kVNT, 0, s>>>(n, x, d32, st);
+    if ((e = launch_status()) != MXS_OK) return e;
+    if ((e = spmv_launch(A, x, q64, &st->noupd, nullptr, s)) != MXS_OK) return e;
+    ru_resid_kernel<false><<<g, kVNT, 0, s>>>(n, b, x, q64, r32, nullptr, nullptr, parts, st);
+    ru_resid_finish_kernel<false><<<1, kFinNT, 0, s>>>(parts, g, st);
+    cg_p_kernel<float><<<g32, kVNT, 0, s>>>(n, r32, p32, st);
+    return launch_status();
+}
+
+// Runs reliable-update steps in chunks of `every`, reading the state after
+// each chunk: done = 1 ends the loop, done = 2 (an update pending) has the
+// update enqueued before the next chunk.  A chunk that meets an update
+// wastes its remaining steps (each returns at entry), against four
+// launches per step saved on the steps without one.
+template <typename Step, typename Upd>
+mxs_status run_ru_loop(const CgState *st, int64_t maxit, int32_t every, CgState *host, hipStream_t s,
+                       Step &&step, Upd &&upd)
+{
+    const int64_t C = std::max<int32_t>(every, 1);
+    MXS_HIP(hipMemcpyAsync(host, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+    MXS_HIP(hipStreamSynchronize(s));
+    int64_t launched = 0, updates = 0;
+    while (host->done != 1 && launched < maxit + C * (updates + 2)) {
+        if (host->done == 2) {
+            mxs_status e = upd();
+            if (e != MXS_OK) return e;
+            ++updates;
+        }
+        for (int64_t c = 0; c < C; ++c) {
+            mxs_status e = step();
+            if (e != MXS_OK) return e;
+        }
+        launched += C;
+        MXS_HIP(hipMemcpyAsync(host, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+        MXS_HIP(hipStreamSynchronize(s));
+    }
+    return MXS_OK;
+}
+
 // ||a - c||^2 (c may be null; w = a - c when non-null) into *out.
 mxs_status norm2(int64_t n, const double *a, const double *c, double *w, double *parts,
                  double *out, hipStream_t s)
@@ -1045,11 +1113,20 @@ mxs_status cg_solve(const mxs_mat_s *A, const mxs_mat_s *A32, const double *b, d
         ru_resid_kernel<true><<<g, kVNT, 0, s>>>(n, b, x, w.q, w.r32, w.p32, w.d32, w.parts, w.st32);
         ru_resid_finish_kernel<true><<<1, kFinNT, 0, s>>>(w.parts, g, w.st32);
         MXS_HIP(hipGetLastError());
-        if (o->maxit > 0) {
+        if (o->maxit > 0 && tm.on) {
+            // timed: every iteration with its (mostly idle) update kernels
             if ((e = run_loop(w.st32, o->maxit, o->check_every, tm, host, s, [&] {
                      return enqueue_ru_iteration(A, A32, n, b, x, w.q, w.d32, w.r32, w.p32, w.q32,
                                                  w.parts, w.st32, tm, s);
                  })) != MXS_OK)
+                return e;
+        } else if (o->maxit > 0) {
+            if ((e = run_ru_loop(
+                     w.st32, o->maxit, o->check_every, host, s,
+                     [&] { return enqueue_ru_step(A32, n, w.d32, w.r32, w.p32, w.q32, w.parts, w.st32, s); },
+                     [&] {
+                         return enqueue_ru_update(A, n, b, x, w.q, w.d32, w.r32, w.p32, w.parts, w.st32, s);
+                     })) != MXS_OK)
                 return e;
         } else {
             MXS_HIP(hipMemcpyAsync(host, w.st32, sizeof(CgState), hipMemcpyDeviceToHost, s));
