@@ -327,21 +327,21 @@ template <int NT>
 __device__ __forceinline__ double reduce_partials(const double *__restrict__ partials, int64_t n,
                                                   double *smem)
 {
-    // thread t sums partials t, t + NT, ... in eight interleaved accumulators
-    // (eight independent loads in flight), then the fixed combination below
+    // thread t sums partials t, t + NT, ... in eight interleaved accumulators,
+    // eight loads in flight per round; the last round is masked, its loads
+    // still issued together (a partial round summed one load at a time cost a
+    // dependent round trip per partial), then the fixed combination below
     constexpr int U = 8;
     double acc[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) acc[u] = 0.0;
-    int64_t i = threadIdx.x;
-    for (; i + (int64_t)(U - 1) * NT < n; i += (int64_t)U * NT) {
+    for (int64_t i = threadIdx.x; i < n; i += (int64_t)U * NT) {
         double v[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = partials[i + (int64_t)u * NT];
+        for (int u = 0; u < U; ++u) v[u] = i + (int64_t)u * NT < n ? partials[i + (int64_t)u * NT] : 0.0;
 #pragma unroll
         for (int u = 0; u < U; ++u) acc[u] += v[u];
     }
-    for (; i < n; i += NT) acc[0] += partials[i];
     const double v = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     return block_sum<NT>(v, smem);
 }
