@@ -253,7 +253,8 @@ __global__ void cg_state_init(CgState *st, double rtol, long long maxit)
     st->last = 0;
     st->rho_next = 0.0;
     st->rho_pend = 0;
-    st->pad2 = 0;
+    st->rmax_pend = 0;
+    st->rmax_next = 0.0;
 }
 
 // r = b - q (q = A x0), p = r, partials of r.r; flags NaN/Inf in b or x0.
@@ -751,6 +752,88 @@ __global__ __launch_bounds__(kFinNT) void ru_rho_finish_kernel(const double *__r
     }
 }
 
+// The end of a reliable-update step in one launch (as cg_rho_p_kernel for
+// plain CG): every workgroup sums the r.r partials of the x/r update in
+// index order, takes the same decision as ru_rho_finish_kernel (an update
+// pending, the cap, or beta = r.r / rho) and, when the step goes on,
+// updates p = r + beta p.  Workgroup 0 records the scalars; the new rho and
+// rmax go to rho_next / rmax_next, moved in by the next p.q finish, since
+// the other workgroups read rho and rmax during this launch.
+__global__ __launch_bounds__(kVNT) void ru_rho_p_kernel(int64_t n, const float *__restrict__ r,
+                                                        float *__restrict__ p,
+                                                        const double *__restrict__ partials,
+                                                        int64_t nparts, CgState *st)
+{
+    __shared__ double red[kVNT / kWave];
+    __shared__ double bc;
+    if (st->done) return;
+    const int64_t vb = vec_block<>();
+    using V = V16<float>;
+    constexpr int W = 4;
+    const int64_t nv = n / W;
+    const V *__restrict__ rv = (const V *)r;
+    V *__restrict__ pv = (V *)p;
+    const int64_t v0 = vb * kVNT * kVU + threadIdx.x;
+    V rs[kVU], ps[kVU];
+    if (v0 < nv) {
+#pragma unroll
+        for (int u = 0; u < kVU; ++u) {
+            const int64_t v = min(v0 + (int64_t)u * kVNT, nv - 1);
+            rs[u] = rv[v];
+            ps[u] = pv[v];
+        }
+    }
+    const double rr0 = reduce_partials<kVNT>(partials, nparts, red);
+    if (threadIdx.x == 0) bc = rr0;
+    __syncthreads();
+    const double rr = bc, rn = sqrt(rr), rmax = st->rmax, rho = st->rho;
+    const bool cap = st->iters >= st->maxit;
+    const bool upd = rn <= st->delta * rmax || rn <= st->thresh;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->rr = rr;
+        if (upd) {
+            st->noupd = 0;
+            st->done = 2;
+            st->last = cap ? 1 : 0;
+            st->nupd += 1;
+        } else if (cap) {
+            st->status = (int)MXS_NOT_CONVERGED;
+            st->done = 1;
+        } else {
+            st->rmax_next = rn > rmax ? rn : rmax;
+            st->rmax_pend = 1;
+            st->beta = rr / rho;
+            st->rho_next = rr;
+            st->rho_pend = 1;
+        }
+    }
+    if (upd || cap) return;
+    const float b = (float)(rr / rho);
+    if (v0 < nv) {
+#pragma unroll
+        for (int u = 0; u < kVU; ++u) {
+            const int64_t v = v0 + (int64_t)u * kVNT;
+            if (v < nv) pv[v] = rs[u] + b * ps[u];
+        }
+    }
+    for (int64_t w0 = v0 + (int64_t)gridDim.x * kVNT * kVU; w0 < nv; w0 += (int64_t)gridDim.x * kVNT * kVU) {
+        V rt[kVU], pt[kVU];
+#pragma unroll
+        for (int u = 0; u < kVU; ++u) {
+            const int64_t v = min(w0 + (int64_t)u * kVNT, nv - 1);
+            rt[u] = rv[v];
+            pt[u] = pv[v];
+        }
+#pragma unroll
+        for (int u = 0; u < kVU; ++u) {
+            const int64_t v = w0 + (int64_t)u * kVNT;
+            if (v < nv) pv[v] = rt[u] + b * pt[u];
+        }
+    }
+    for (int64_t i = nv * W + vb * kVNT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVNT)
+        p[i] = r[i] + b * p[i];
+}
+
 // x += fp64(d); d = 0 -- when an update is pending, or always with FORCE
 // (the final fold after the loop).
 template <bool FORCE>
@@ -973,8 +1056,12 @@ mxs_status enqueue_ru_step(const mxs_mat_s *A32, int64_t n, float *d32, float *r
     const uint32_t g32 = vec_grid(n, 4);
     if ((e = spmv_launch(A32, p32, q32, &st->done, &ds, s)) != MXS_OK) return e;
     cg_xr_kernel<float, true, true><<<g32, kVNT, 0, s>>>(n, d32, r32, p32, q32, parts, st);
-    ru_rho_finish_kernel<<<1, kFinNT, 0, s>>>(parts, g32, st);
-    cg_p_kernel<float><<<g32, kVNT, 0, s>>>(n, r32, p32, st);
+    if (g32 <= kFoldParts) {
+        ru_rho_p_kernel<<<g32, kVNT, 0, s>>>(n, r32, p32, parts, g32, st);
+    } else {
+        ru_rho_finish_kernel<<<1, kFinNT, 0, s>>>(parts, g32, st);
+        cg_p_kernel<float><<<g32, kVNT, 0, s>>>(n, r32, p32, st);
+    }
     return launch_status();
 }
 

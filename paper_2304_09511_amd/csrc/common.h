@@ -78,7 +78,8 @@ struct CgState {
     // moves it into rho
     double rho_next;
     int rho_pend;    // 1: rho_next holds the new rho
-    int pad2;
+    int rmax_pend;   // 1: rmax_next holds the new rmax (reliable updates, same reason)
+    double rmax_next;
 };
 
 // Where a fused dot product of an SpMV epilogue goes: one partial per
@@ -356,6 +357,10 @@ __device__ __forceinline__ void cg_finish_sigma(CgState *st, double sigma)
     if (st->rho_pend) {
         st->rho = st->rho_next;
         st->rho_pend = 0;
+    }
+    if (st->rmax_pend) {
+        st->rmax = st->rmax_next;
+        st->rmax_pend = 0;
     }
     st->sigma = sigma;
     st->iters += 1;
