@@ -212,6 +212,28 @@ def test_reliable_update_statuses_and_polling(gpu):
     with pytest.raises(gpu.MxsError) as e:
         gpu.cg_solve(A, b, mixed="ru", A32=A32, delta=1.5)
     assert e.value.status == -1
+    # the timed solve launches the update kernels in every step (idle unless
+    # an update is due), the untimed one only when a step asks for an update:
+    # the same kernels in the same order on the device, so the same result
+    for delta in (0.1, 0.5):
+        for every in (1, 5):
+            st_u, x_u, r_u = gpu.cg_solve(A, b, rtol=1e-11, mixed="ru", A32=A32, delta=delta,
+                                          check_every=every)
+            st_t, x_t, r_t = gpu.cg_solve(A, b, rtol=1e-11, mixed="ru", A32=A32, delta=delta,
+                                          check_every=every, timing=True)
+            assert st_u == st_t == 0
+            assert r_u["outer_iters"] >= 1
+            assert (r_u["iters"], r_u["outer_iters"]) == (r_t["iters"], r_t["outer_iters"])
+            assert torch.equal(x_u, x_t)
+    # the cap reached on a step that also asks for an update (its update is
+    # the last one), and on one that does not
+    for maxit in range(1, 12):
+        st_u, x_u, r_u = gpu.cg_solve(A, b, rtol=1e-30, mixed="ru", A32=A32, delta=0.5, maxit=maxit)
+        st_t, x_t, r_t = gpu.cg_solve(A, b, rtol=1e-30, mixed="ru", A32=A32, delta=0.5, maxit=maxit,
+                                      timing=True)
+        assert st_u == st_t == 1 and r_u["iters"] == r_t["iters"] == maxit
+        assert r_u["outer_iters"] == r_t["outer_iters"]
+        assert torch.equal(x_u, x_t)
     # indefinite: p.Ap = 0 at the first step
     ind = wl.Coo(2, 2, np.array([0, 1], np.int32), np.array([0, 1], np.int32), np.array([1.0, -1.0]))
     I = build(gpu, ind, "csr")
