@@ -849,13 +849,22 @@ def main():
     step_bytes = sum(bytes_f.values())
 
     # outputs of this exact configuration, checked against the oracle in the
-    # CPU leg below
+    # CPU leg below; and the 16^3 stencil (x ~ U[-1,1), seed 1) in each format
     checks = []
     ai, aj, av = mats["coo"].export()
     x_host = x.cpu().numpy()
     for f in FORMATS:
         y = mxs.spmv(mats[f], x, ys[f]).cpu().numpy()
         checks.append({"name": f"stencil{args.n}/{f}", "coo": (n, ai, aj, av), "x": x_host, "y": y})
+    small = build_matrices(mxs, 16)
+    n16 = small["coo"].nrows
+    x16 = np.random.Generator(np.random.PCG64(1)).uniform(-1, 1, n16)
+    c16 = small["coo"].export()
+    for f in FORMATS:
+        y16 = mxs.spmv(small[f], torch.from_numpy(x16).cuda()).cpu().numpy()
+        checks.append({"name": f"stencil16/{f}", "coo": (n16, *c16), "x": x16, "y": y16})
+    for A in small.values():
+        A.close()
 
     # ---- timed region: K steps, one SpMV per format per step ----
     ev = {f: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
