@@ -314,8 +314,8 @@ mxs_status mxs_dot(int64_t n, mxs_dtype dtype, const void *a, const void *b, dou
  * (64 KiB) that the library keeps on each GPU it runs on until the process
  * ends, instead of a buffer allocated per call.  A call that would need more
  * partials than the array holds is refused with MXS_ERR_UNSUPPORTED (detail
- * in mxs_last_error); the grid is capped below that, so no n is refused
- * today.  Calls that overlap on one GPU (different streams, or threads
+ * in mxs_last_error); the grid is capped at the array's size, so no n is
+ * refused today.  Calls that overlap on one GPU (different streams, or threads
  * without ordering) share the array and race; calls on one stream are
  * ordered.  The first call on a device looks up the array's address there. */
 mxs_status mxs_dot_noalloc(int64_t n, mxs_dtype dtype, const void *a, const void *b,
