@@ -27,7 +27,7 @@
 #define MXS_CSR_IPT64 8
 #endif
 #ifndef MXS_CSR_IPT32
-#define MXS_CSR_IPT32 16
+#define MXS_CSR_IPT32 12
 #endif
 #ifndef MXS_DIA_WIN
 #define MXS_DIA_WIN 0 // 1: stage the x windows of interior DIA blocks in LDS
