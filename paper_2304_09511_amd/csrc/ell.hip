@@ -25,7 +25,11 @@
 namespace mxs {
 
 constexpr int kSellC = 64; // slice height: one wavefront
-constexpr int kPadU = 8;   // slots a lane loads at once in SpMV
+// slots a lane loads at once in SpMV: 16 in FP64, 8 in FP32 (measured at
+// 128^3: FP64 ELL 124.0 us against 125.0 with 8, FP32 76.7 us against 80.0
+// with 16)
+template <typename T>
+constexpr int kPadU = sizeof(T) == 8 ? 16 : 8;
 
 template <typename T>
 __device__ __forceinline__ T ld_nt(const T *p)
@@ -527,7 +531,7 @@ mxs_status padded_to_rows(const mxs_mat_s *A, mxs_format dst, int32_t *idx0, int
 // ---------------------------------------------------------------------------
 // SpMV
 // ---------------------------------------------------------------------------
-// kPadU slots per step, loads of a step issued together; slots past the
+// kPadU<T> slots per step, loads of a step issued together; slots past the
 // width read nothing, padding slots (column -1) gather nothing.
 template <typename T>
 __device__ __forceinline__ T padded_row_sum(const int32_t *__restrict__ col, const T *__restrict__ val,
@@ -535,19 +539,19 @@ __device__ __forceinline__ T padded_row_sum(const int32_t *__restrict__ col, con
                                             const T *__restrict__ x)
 {
     T sum = T(0);
-    for (int32_t k = 0; k < w; k += kPadU) {
-        int32_t c[kPadU];
-        T v[kPadU], xv[kPadU];
+    for (int32_t k = 0; k < w; k += kPadU<T>) {
+        int32_t c[kPadU<T>];
+        T v[kPadU<T>], xv[kPadU<T>];
 #pragma unroll
-        for (int u = 0; u < kPadU; ++u) {
+        for (int u = 0; u < kPadU<T>; ++u) {
             const bool in = k + u < w;
             c[u] = in ? ld_nt(&col[pos + (int64_t)(k + u) * stride]) : -1;
             v[u] = in ? ld_nt(&val[pos + (int64_t)(k + u) * stride]) : T(0);
         }
 #pragma unroll
-        for (int u = 0; u < kPadU; ++u) xv[u] = c[u] >= 0 ? x[c[u]] : T(0);
+        for (int u = 0; u < kPadU<T>; ++u) xv[u] = c[u] >= 0 ? x[c[u]] : T(0);
 #pragma unroll
-        for (int u = 0; u < kPadU; ++u)
+        for (int u = 0; u < kPadU<T>; ++u)
             if (c[u] >= 0) sum += v[u] * xv[u];
     }
     return sum;
