@@ -101,6 +101,7 @@ struct CsrPlan {
     int32_t *tile_info = nullptr; // [ntiles] overflow length and carry flags
     void *carry = nullptr;       // [2*ntiles] head / tail pieces of rows too long to finish
     int64_t ntiles = 0;
+    int32_t tile = 0;            // entries per tile (256 threads x entries per thread)
     bool fixup = false;          // some row reaches past its owner's overflow window
     bool rowwise = false;        // a thread per row (default when rows outnumber entries 2:1)
     bool gx = false;             // entry tiles, x gathered per row from LDS-staged columns

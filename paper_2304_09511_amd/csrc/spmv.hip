@@ -29,6 +29,9 @@
 #ifndef MXS_CSR_IPT32
 #define MXS_CSR_IPT32 10
 #endif
+#ifndef MXS_CSR_IPT_MANY
+#define MXS_CSR_IPT_MANY 8 // CSR tiles owning more rows than the LDS-staged path takes
+#endif
 #ifndef MXS_COO_IPT64
 #define MXS_COO_IPT64 8
 #endif
@@ -297,7 +300,8 @@ __device__ __forceinline__ void reduce_tile_rows(int nr, bool queue, int32_t *lo
 // row.  Lanes then gather x for neighbouring rows at the same position in
 // their rows, which for banded matrices are neighbouring addresses: fewer
 // cache lines per gather instruction than gathering in entry order.
-template <typename T, bool DOT, bool GX>
+// IPTT: entries per thread of the plan's tiles (csr_plan_ipt).
+template <typename T, bool DOT, bool GX, int IPTT>
 __global__ __launch_bounds__(256) MXS_CSR_ATTR void csr_spmv_kernel(
     const int32_t *__restrict__ irp, const int32_t *__restrict__ aj, const T *__restrict__ av,
     const T *__restrict__ x, T *__restrict__ y, const int32_t *__restrict__ tile_row,
@@ -305,7 +309,7 @@ __global__ __launch_bounds__(256) MXS_CSR_ATTR void csr_spmv_kernel(
     T *__restrict__ carry, const int *__restrict__ done, double *__restrict__ partials, int acc)
 {
     using C = CsrCfg<T>;
-    constexpr int NT = C::NT, IPT = C::IPT, TILE = C::TILE, EXT = C::EXT, RMAX = C::RMAX;
+    constexpr int NT = C::NT, IPT = IPTT, TILE = NT * IPTT, EXT = C::EXT, RMAX = C::RMAX;
     static_assert(EXT == NT, "one overflow entry per thread");
     __shared__ T prod[TILE + EXT]; // products, or the values when GX
     __shared__ int32_t scol[GX ? TILE + EXT : 1];
@@ -1191,7 +1195,18 @@ static int64_t dia_blocks(const mxs_mat_s *A)
     return (A->nrows + rows - 1) / rows;
 }
 
-static int csr_tile(mxs_dtype t) { return t == MXS_F64 ? CsrCfg<double>::TILE : CsrCfg<float>::TILE; }
+// Entries per thread of a CSR matrix's tiles: CsrCfg's (10) while a tile
+// would own at most RMAX rows on average (the LDS-staged path; 127.2 us
+// against 129.4 us with 8 on the 128^3 stencil), else MXS_CSR_IPT_MANY (8;
+// the 4M-row Zipf matrix's column blocks, about two entries per row: 715
+// against 778 us with 10).
+static int csr_plan_ipt(const mxs_mat_s *A)
+{
+    const int wide = A->dtype == MXS_F64 ? CsrCfg<double>::IPT : CsrCfg<float>::IPT;
+    const double rows_per_tile = (double)A->nrows * (CsrCfg<double>::NT * wide) /
+                                 (double)std::max<int64_t>(A->nnz, 1);
+    return rows_per_tile <= CsrCfg<double>::RMAX ? wide : MXS_CSR_IPT_MANY;
+}
 static int coo_tile(mxs_dtype t) { return t == MXS_F64 ? CooCfg<double>::TILE : CooCfg<float>::TILE; }
 
 // One workgroup per block/tile.  A fused dot writes one partial per
@@ -1203,7 +1218,7 @@ static void spmv_grid(const mxs_mat_s *A, bool dot, uint32_t *grid, int64_t *per
     const int64_t nblk = A->fmt == MXS_CSR ? A->csr.ntiles
                          : A->fmt == MXS_DIA ? dia_blocks(A) : A->coo.ntiles;
 #if MXS_PERSIST
-    int64_t cap = A->fmt == MXS_CSR ? resident_workgroups(csr_spmv_kernel<T, false, false>, 256)
+    int64_t cap = A->fmt == MXS_CSR ? resident_workgroups(csr_spmv_kernel<T, false, false, CsrCfg<T>::IPT>, 256)
                   : A->fmt == MXS_DIA ? resident_workgroups(dia_spmv_kernel<T, false>, kDiaNT)
                                       : resident_workgroups(coo_spmv_kernel<T>, kCooNT);
 #else
@@ -1237,10 +1252,11 @@ int64_t spmv_dot_parts(const mxs_mat_s *A)
 // blocks (colblk.hip).
 static mxs_status csr_plan(mxs_mat_s *A, PlanCtx &c, hipStream_t s)
 {
-    const int tile = csr_tile(A->dtype);
+    const int tile = CsrCfg<double>::NT * csr_plan_ipt(A);
     const int64_t nt = (A->nnz + tile - 1) / tile;
     CsrPlan P{};
     P.ntiles = nt;
+    P.tile = tile;
     if (nt == 0) {
         if (c.build) A->csr = P;
         return MXS_OK;
@@ -1688,8 +1704,12 @@ static mxs_status spmv_typed(const mxs_mat_s *A, const T *x, T *y, const int *do
         spmv_grid<T>(A, dot != nullptr, &grid, &per);
         const int32_t *tr = A->csr.tile_row, *ti = A->csr.tile_info;
         T *cr = (T *)(carry ? carry : A->csr.carry);
-        auto kern = dot ? (A->csr.gx ? csr_spmv_kernel<T, true, true> : csr_spmv_kernel<T, true, false>)
-                        : (A->csr.gx ? csr_spmv_kernel<T, false, true> : csr_spmv_kernel<T, false, false>);
+        constexpr int W = CsrCfg<T>::IPT, M = MXS_CSR_IPT_MANY;
+        const bool wide = A->csr.tile == CsrCfg<T>::NT * W;
+        auto kern = wide ? (dot ? (A->csr.gx ? csr_spmv_kernel<T, true, true, W> : csr_spmv_kernel<T, true, false, W>)
+                                : (A->csr.gx ? csr_spmv_kernel<T, false, true, W> : csr_spmv_kernel<T, false, false, W>))
+                         : (dot ? (A->csr.gx ? csr_spmv_kernel<T, true, true, M> : csr_spmv_kernel<T, true, false, M>)
+                                : (A->csr.gx ? csr_spmv_kernel<T, false, true, M> : csr_spmv_kernel<T, false, false, M>));
         kern<<<grid, 256, 0, s>>>(A->idx0, A->idx1, (const T *)A->vals, x, y, tr, ti, A->nnz, nt, per,
                                   cr, done, dot ? parts : nullptr, acc);
         MXS_HIP(hipGetLastError());
@@ -1698,11 +1718,11 @@ static mxs_status spmv_typed(const mxs_mat_s *A, const T *x, T *y, const int *do
             const uint32_t fg = fixup_grid(nt);
             if (dot)
                 csr_fixup_kernel<T, true><<<fg, 256, 0, s>>>(A->idx0, tr, ti, cr,
-                                                             x, y, A->nnz, nt, csr_tile(A->dtype),
+                                                             x, y, A->nnz, nt, A->csr.tile,
                                                              done, parts + grid, acc);
             else
                 csr_fixup_kernel<T, false><<<fg, 256, 0, s>>>(A->idx0, tr, ti, cr,
-                                                              x, y, A->nnz, nt, csr_tile(A->dtype),
+                                                              x, y, A->nnz, nt, A->csr.tile,
                                                               done, nullptr, acc);
             MXS_HIP(hipGetLastError());
             nparts += fg;
