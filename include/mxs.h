@@ -348,7 +348,11 @@ typedef struct {
     int32_t max_outer;   /* mixed = 1: at most this many corrections */
     double inner_rtol;   /* mixed = 1: inner solves stop at ||r|| <= inner_rtol*||r_0|| */
     int32_t check_every; /* host reads the device convergence flag every this many
-                            iterations (>= 1); iterations past convergence are no-ops */
+                            iterations (>= 1); iterations past convergence are no-ops.
+                            mixed = 2 without timing: the host also enqueues a residual
+                            replacement when it reads that one is pending (the steps
+                            after the one that asked for it return at entry until
+                            then); the result does not depend on check_every */
     int32_t timing;      /* 1: time SpMV, dot and vector-update kernels with events
                             (mixed = 2 counts its FP64 updates as vector updates) */
     double ru_delta;     /* mixed = 2: update factor in [0, 1] */
