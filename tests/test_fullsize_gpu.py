@@ -267,6 +267,40 @@ def test_stencil192_reliable_updates_match_oracle(gpu, stencil192, fmt, delta):
     check_solution(x, 192, 1e-10, r["true_rel_resid"], g, f"ru {fmt} {delta}")
 
 
+def test_reliable_updates_large_grid_untimed_equals_timed(gpu):
+    """Above 8.4M rows the FP32 vector grid has more than 2,048 workgroups and
+    a reliable-update step ends with a finish kernel and a separate direction
+    update instead of the folded one: that step, in the loop that enqueues
+    the residual replacement only when asked, against the loop that launches
+    the update kernels in every step (the timed solve) - the same kernels
+    in the same order on the device, so the same iterations, updates and x,
+    bit for bit; converged, with x within the conditioning bound of 1 (b =
+    A*1: the kappa inequality and max |x - 1| <= 2 kappa tol, as above).
+    Stencil 208^3 (8,998,912 rows), DIA."""
+    import torch
+    n = 208
+    A = gpu.stencil(n, fmt="dia").optimize()
+    A32 = A.cast(gpu.F32).optimize()
+    b = gpu.spmv(A, torch.ones(A.nrows, dtype=torch.float64, device="cuda"))
+    ws = gpu.cg_workspace(A, mixed=True)
+    kw = dict(rtol=1e-10, maxit=20000, mixed="ru", A32=A32, delta=0.1, workspace=ws)
+    st_u, x_u, r_u = gpu.cg_solve(A, b, **kw)
+    st_t, x_t, r_t = gpu.cg_solve(A, b, timing=True, **kw)
+    print(f"[ru208] iters {r_u['iters']} updates {r_u['outer_iters']}", flush=True)
+    assert st_u == st_t == 0 and r_u["true_rel_resid"] <= 1e-10
+    assert (r_u["iters"], r_u["outer_iters"]) == (r_t["iters"], r_t["outer_iters"])
+    assert r_u["outer_iters"] >= 2
+    assert torch.equal(x_u, x_t)
+    kappa = stencil_kappa(n)
+    e = x_u - 1.0
+    rel2 = float(torch.linalg.vector_norm(e) / math.sqrt(x_u.numel()))
+    assert rel2 <= kappa * r_u["true_rel_resid"] * 1.01 + 1e-14, (rel2, kappa)
+    assert float(e.abs().max()) <= 2 * kappa * 1e-10, float(e.abs().max())
+    A.close()
+    A32.close()
+    torch.cuda.empty_cache()
+
+
 def test_near_int32_entry_limit_all_formats(gpu):
     """A ragged tridiagonal matrix (2, -1, -1) with 2^29 + 7 rows: 1.61e9
     entries, close to the int32 entry limit, built on the device.  Integer x,
