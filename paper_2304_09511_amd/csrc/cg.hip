@@ -1014,8 +1014,11 @@ mxs_status run_loop(const CgState *st, int64_t maxit, int32_t every, Timer &tm, 
     return MXS_OK;
 }
 
-// One reliable-update iteration: the FP32 CG step, then the update kernels
-// (no-ops unless this step asked for an update), then the next direction.
+// One reliable-update iteration as the timed solve runs it: the FP32 CG
+// step, then the update kernels (no-ops unless this step asked for an
+// update), then the next direction; the untimed solve runs enqueue_ru_step
+// and, only when asked, enqueue_ru_update (the same kernels in the same
+// order on the device).
 mxs_status enqueue_ru_iteration(const mxs_mat_s *A, const mxs_mat_s *A32, int64_t n,
                                 const double *b, double *x, double *q64, float *d32, float *r32,
                                 float *p32, float *q32, double *parts, CgState *st, Timer &tm,
