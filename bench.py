@@ -830,8 +830,7 @@ def main():
                     default=None)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(see DESIGN.md for how the SpMV/CG path would shard)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
     if args.pmc:
         return pmc_mode(args)
