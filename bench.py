@@ -437,7 +437,7 @@ def cpu_baseline(orc, coo_host, nbytes, budget_s=8.0, gpu_cg=None):
             "status": g192["status"], "iters": g192["iters"],
             "time_to_tol_ms": round(1e3 * g192["oracle_seconds"], 1),
             "source": "tests/golden/cg_stencil192_tol1e-10.json (stored oracle run, one thread of "
-                      "the build container's CPU, not this host)"}
+                      "the CPU of the machine that wrote the stored runs, not this host)"}
     return {"value": round(nbytes / med / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
             "sample": f"oracle COO SpMV (Algorithm 1, FP64, single thread) on the same 128^3 "
                       f"stencil, {len(times)} calls in {sum(times):.1f} s, median {med * 1e3:.1f} ms/call; "
