@@ -174,11 +174,14 @@ def test_tune_argument_checks(gpu):
                         None, None, None) == UNSUPPORTED
 
 
+@pytest.mark.parametrize("points,n", [(27, 12), (7, 14)])
 @pytest.mark.parametrize("fmt", ["coo", "csr", "dia"])
-def test_cg_with_every_impl_matches_oracle(gpu, fmt):
-    """The fused SpMV + p.Ap of each implementation inside CG."""
+def test_cg_with_every_impl_matches_oracle(gpu, fmt, points, n):
+    """The fused SpMV + p.Ap of each implementation inside CG; the 27-point
+    stencil's CSR tiles take 10 entries per thread, the 7-point stencil's 8
+    (more rows per tile than the LDS-staged path holds at 10)."""
     mxs = gpu
-    a = wl.stencil(12)
+    a = wl.stencil(n, points=points)
     b = orc.coo_spmv(a.nrows, a.ai, a.aj, a.av, np.ones(a.ncols))
     st_o, x_o, it_o, _, _ = orc.cg(a.nrows, a.ai, a.aj, a.av, b, tol=1e-10, maxit=2000)
     A = build(mxs, a, fmt)
@@ -189,18 +192,24 @@ def test_cg_with_every_impl_matches_oracle(gpu, fmt):
         assert np.max(np.abs(x.cpu().numpy() - x_o)) <= 1e-8, i
 
 
-def long_rows(seed, ncols=30000, integer=False, dtype=np.float64):
+def long_rows(seed, ncols=30000, integer=False, dtype=np.float64, pad_short=0):
     """Short rows (0-10 entries) around runs of long rows: 40 rows of 65
     entries (a tile then owns about 32 long rows), lengths at the wave path's
-    threshold (64, 65, 66) and at the FP64 tile and extension edges (2,047 to
-    2,305), and rows of up to 5,000 entries that span tiles."""
+    threshold (64, 65, 66) and at the tile and extension edges of each tile
+    size (2,048 and 2,560 entries, 3,072 for COO's FP32 tiles, each plus 256),
+    and rows of up to 5,000 entries that span tiles.  pad_short: that many
+    more rows of 0-2 entries at the end (CSR tiles then own too many rows
+    for the LDS-staged path and take 8 entries per thread instead of 10)."""
     g = wl.rng(seed)
     lens = list(g.integers(0, 11, 300))
     lens += [65] * 40 + list(g.integers(0, 11, 50))
     for L in (64, 65, 66, 100, 127, 128, 129, 300, 1000, 2000, 2047, 2048, 2049,
-              2303, 2304, 2305, 2500, 4095, 4096, 4097, 4999, 5000):
+              2303, 2304, 2305, 2500, 2559, 2560, 2561, 2815, 2816, 2817, 3071, 3072, 3073,
+              3327, 3328, 3329, 4095, 4096, 4097, 4999, 5000):
         lens += [int(L)] + list(g.integers(0, 11, int(g.integers(1, 40))))
     lens += [65, 66, 64, 200] * 20 + list(g.integers(0, 11, 200))
+    if pad_short:
+        lens += list(g.integers(0, 3, pad_short))
     L = np.array(lens, np.int64)
     ai = np.repeat(np.arange(L.size, dtype=np.int32), L)
     aj = wl._distinct_sorted_columns(g, ai, L, ncols)
@@ -217,11 +226,16 @@ def wave_path_ids(mxs, fmt):
     return {"coo": [0], "csr": [0, 2]}[fmt]
 
 
+@pytest.mark.parametrize("pad_short", [0, 40000])
 @pytest.mark.parametrize("fmt", ["coo", "csr"])
 @pytest.mark.parametrize("dtype", ["f64", "f32", "int"])
-def test_long_rows_reduced_by_waves(gpu, fmt, dtype):
+def test_long_rows_reduced_by_waves(gpu, fmt, dtype, pad_short):
+    if fmt == "coo" and pad_short:
+        pytest.skip("COO's row tiles do not apply to tiles owning more than 512 rows "
+                    "(the segmented tiles take them, tested with the other implementations)")
     mxs = gpu
-    a = long_rows(5, integer=dtype == "int", dtype=np.float32 if dtype == "f32" else np.float64)
+    a = long_rows(5, integer=dtype == "int", dtype=np.float32 if dtype == "f32" else np.float64,
+                  pad_short=pad_short)
     print(f"[long rows] {fmt} {dtype} {a.nrows} rows nnz={a.nnz}", flush=True)
     A = build(mxs, a, fmt)
     x = (wl.integer_vector(a.ncols, seed=3) if dtype == "int"
