@@ -75,6 +75,7 @@ def source_sha(path=None):
 
 
 MG_SRC = os.path.join(ROOT, "paper_2304_09511_amd", "csrc", "mg.hip")
+ELL_SRC = os.path.join(ROOT, "paper_2304_09511_amd", "csrc", "ell.hip")
 
 
 def symgs_traffic_from_profile(n):
@@ -91,16 +92,17 @@ def symgs_traffic_from_profile(n):
     return float(m_b.group(1))
 
 
-def traffic_from_profile(fmt, workload_tag):
+def traffic_from_profile(fmt, workload_tag, src=None):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source."""
+    was taken on the current kernel source (`src`: the kernel's file,
+    spmv.hip by default)."""
     path = os.path.join(ROOT, "profiles", f"{fmt}_spmv_{workload_tag}_pmc.txt")
     if not os.path.exists(path):
         return None
     text = open(path).read()
     m_sha = re.search(r"^source_sha256_16:\s*(\w+)", text, re.M)
     m_b = re.search(r"^hbm_bytes_per_launch:\s*([0-9.eE+]+)", text, re.M)
-    if not m_sha or not m_b or m_sha.group(1) != source_sha():
+    if not m_sha or not m_b or m_sha.group(1) != source_sha(src):
         return None
     return float(m_b.group(1))
 
@@ -499,10 +501,14 @@ def fp32_lines(torch, mxs, mats, fp64_bytes):
         tc = time_calls(torch, lambda: mxs.spmv(B, x32, y32))
         med = tc["median_ms"] * 1e-3
         names = mxs.Matrix.IMPL_NAMES[B.format]
+        kern = KERNEL_NAMES[f][B.impl]
+        traffic = traffic_from_profile(f"{f}_fp32", f"stencil{round(n ** (1 / 3))}",
+                                       ELL_SRC if kern.startswith("ell") else None)
         out[f] = {"us_per_call": round(med * 1e6, 2), "algorithmic_bytes": nb,
                   "GBps": round(nb / med / 1e9, 1), "frac_of_peak": round(nb / med / 1e9 / PEAK_HBM_GBS, 4),
                   "bytes_vs_fp64": round(nb / fp64_bytes[f], 3), "implementation": names[B.impl],
-                  "kernel": KERNEL_NAMES[f][B.impl]}
+                  "kernel": kern, "traffic": traffic,
+                  "traffic_over_algorithmic": None if traffic is None else round(traffic / nb, 4)}
         log(f"[bench]   fp32 {f}: {out[f]['us_per_call']} us, {out[f]['GBps']} GB/s "
             f"({100 * out[f]['frac_of_peak']:.1f}%)")
         B.close()
@@ -766,6 +772,7 @@ def pmc_mode(args):
 
     import paper_2304_09511_amd as mxs
     mxs.load()
+    value_bytes = 8
     if args.pmc == "symgs":
         M = mxs.Multigrid(args.n, 4)
         r = torch.from_numpy(np.random.Generator(np.random.PCG64(1)).uniform(-1, 1, args.n ** 3)).cuda()
@@ -786,15 +793,23 @@ def pmc_mode(args):
             mxs.spmv(A, x, y)
         args.pmc = fmt
     else:
-        # a stencil format with its default implementation, or csr0: CSR's
-        # entry tiles (the kernel that reads the CSR arrays)
+        # a stencil format with its default implementation, csr0: CSR's
+        # entry tiles (the kernel that reads the CSR arrays), or <fmt>32: the
+        # FP32 copy of a format (values rounded, FP32 x and y) as the mixed
+        # solvers run it
         mats = build_matrices(mxs, args.n)
         A = mats[args.pmc[:3]]
+        fp32 = args.pmc.endswith("32")
+        if fp32:
+            A = A.cast(mxs.F32).optimize()
+            value_bytes = 4
         if args.pmc == "csr0":
             A.impl = 0
         args.pmc = args.pmc[:3]
         x = torch.from_numpy(np.random.Generator(np.random.PCG64(1)).uniform(-1, 1, A.ncols)).cuda()
-        y = torch.empty(A.nrows, dtype=torch.float64, device="cuda")
+        if fp32:
+            x = x.float()
+        y = torch.empty(A.nrows, dtype=x.dtype, device="cuda")
         for _ in range(args.steps):
             mxs.spmv(A, x, y)
     # calibration: a plain copy of 1 GiB (reads 1 GiB, writes 1 GiB)
@@ -808,7 +823,7 @@ def pmc_mode(args):
                           "copy_bytes_each_way": src.numel() * 8,
                           "source_sha256_16": source_sha(MG_SRC)}))
         return
-    print(json.dumps({"pmc": args.pmc, "bytes_per_launch": algorithmic_bytes(A, args.pmc),
+    print(json.dumps({"pmc": args.pmc, "bytes_per_launch": algorithmic_bytes(A, args.pmc, s=value_bytes),
                       "copy_bytes_each_way": src.numel() * 8, "source_sha256_16": source_sha()}))
 
 
@@ -826,7 +841,8 @@ def main():
     ap.add_argument("--no-irregular", action="store_true")
     ap.add_argument("--no-selector", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=8.0)
-    ap.add_argument("--pmc", choices=FORMATS + ("csr0", "symgs", "zipf-csr0", "zipf-csr4", "zipf-coo0", "zipf-coo2"),
+    ap.add_argument("--pmc", choices=FORMATS + ("csr0", "symgs", "zipf-csr0", "zipf-csr4", "zipf-coo0", "zipf-coo2",
+                                                "coo32", "csr32", "dia32"),
                     default=None)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
