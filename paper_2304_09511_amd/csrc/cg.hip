@@ -305,6 +305,9 @@ __global__ __launch_bounds__(kFinNT) void start_finish_kernel(const double *__re
 // x += alpha p; r -= alpha q; with FUSED, partials of r.r.  VEC (all four
 // vectors 16-byte aligned): each thread loads kVU 16-byte vectors of every
 // array before any arithmetic, then the scalar tail of n mod (16/sizeof(T)).
+// x (touched by no other kernel of the loop) and q (dead after this) go
+// through non-temporal loads and stores, leaving the caches to p, r and
+// the matrix (CG at 128^3: 22.87 -> 22.54 ms DIA).
 template <typename T, bool FUSED, bool VEC>
 __global__ __launch_bounds__(kVNT) void cg_xr_kernel(int64_t n, T *__restrict__ x,
                                                      T *__restrict__ r, const T *__restrict__ p,
@@ -331,10 +334,10 @@ __global__ __launch_bounds__(kVNT) void cg_xr_kernel(int64_t n, T *__restrict__ 
 #pragma unroll
             for (int u = 0; u < kVU; ++u) {
                 const int64_t v = min(v0 + (int64_t)u * kVNT, nv - 1); // in range; stores masked
-                xs[u] = xv[v];
+                xs[u] = __builtin_nontemporal_load(&xv[v]);
                 rs[u] = rv[v];
                 ps[u] = pv[v];
-                qs[u] = qv[v];
+                qs[u] = __builtin_nontemporal_load(&qv[v]);
             }
 #pragma unroll
             for (int u = 0; u < kVU; ++u) {
@@ -342,7 +345,7 @@ __global__ __launch_bounds__(kVNT) void cg_xr_kernel(int64_t n, T *__restrict__ 
                 if (v < nv) {
                     const V xn = xs[u] + a * ps[u];
                     const V rn = rs[u] - a * qs[u];
-                    xv[v] = xn;
+                    __builtin_nontemporal_store(xn, &xv[v]);
                     rv[v] = rn;
                     if (FUSED)
 #pragma unroll
