@@ -573,7 +573,9 @@ __global__ __launch_bounds__(256) void ell_spmv_kernel(int32_t nrows, int32_t K,
         // the fused dot's x value first: its load overlaps the row's
         const T xi = DOT ? x[i] : T(0);
         const T yi = padded_row_sum(col, val, i, nrows, K, x);
-        y[i] = yi;
+        // y is read next by another kernel after a full vector pass: store it
+        // past the caches
+        __builtin_nontemporal_store(yi, &y[i]);
         if (DOT) dpart += (double)yi * (double)xi;
     }
     if (DOT) {
