@@ -659,7 +659,7 @@ def stream_reference(torch, mxs, mib=512, reps=10):
     t_read = med(lambda: mxs.dot(a, b))
     out = {"copy_GBps": round(2 * n * 8 / t_copy / 1e9, 1), "copy_bytes_each_way": n * 8,
            "read_stream_GBps": round(2 * n * 8 / t_read / 1e9, 1), "read_stream_bytes": 2 * n * 8,
-           "read_stream_kernel": "dot_partials_kernel (mxs_dot)",
+           "read_stream_kernel": "dot_kernel (mxs_dot: two arrays read together, plus its finish kernel)",
            "timing": f"median of {reps} calls, HIP events around each"}
     del a, b, c
     torch.cuda.empty_cache()
