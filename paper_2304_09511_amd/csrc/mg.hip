@@ -55,6 +55,12 @@ __device__ __forceinline__ int32_t mg_block()
     return gridDim.x % kNumXcd ? (int32_t)blockIdx.x : (int32_t)xcd_remap(blockIdx.x, gridDim.x);
 }
 
+// The cycle's kernels read their convergence flag from here when they are
+// given none, so that the flag's load needs no test of the pointer first and
+// goes out with the kernel's other first loads.
+__device__ const int kNoFlag = 0;
+__device__ __forceinline__ int flag_of(const int *done) { return *(done ? done : &kNoFlag); }
+
 // sweep order of the colours: coarse points (colour 0) last
 constexpr int kSweep[kColours] = {1, 2, 3, 4, 5, 6, 7, 0};
 
@@ -163,16 +169,21 @@ __global__ __launch_bounds__(kMgNT) void symgs_colour_kernel(
     const double *__restrict__ diag, const double *__restrict__ r, double *__restrict__ x,
     int32_t p0, int32_t nrows_c, int32_t s0, const int *__restrict__ done)
 {
-    if (done && *done) return;
+    const int stop = flag_of(done);
     const int32_t t = mg_block() * blockDim.x + threadIdx.x;
     if (t >= nrows_c) return;
     const int32_t s = s0 + t / kSlice;
     const int lane = t % kSlice;
     const int32_t i = order[p0 + t];
+    const int64_t base = soff[s];
+    const int32_t w = (int32_t)((soff[s + 1] - base) / kSlice);
+    const double dg = diag[p0 + t];
+    // The convergence flag is tested with the loads above in flight (i and w
+    // are never negative: testing them keeps those loads ahead of the
+    // branch), so the flag costs the pass no round trip of its own.
+    if (stop | (i < 0) | (w < 0)) return;
     double sum = r[i];
     {
-        const int64_t base = soff[s];
-        const int32_t w = (int32_t)((soff[s + 1] - base) / kSlice);
         const int32_t *__restrict__ cs = col + base + lane;
         const double *__restrict__ vs = val + base + lane;
         // U entries per step, all loads of a step issued together; entries
@@ -192,7 +203,7 @@ __global__ __launch_bounds__(kMgNT) void symgs_colour_kernel(
             for (int u = 0; u < U; ++u) sum -= vu[u] * xu[u];
         }
     }
-    x[i] = sum / diag[p0 + t];
+    x[i] = sum / dg;
 }
 
 // The first colour pass of a sweep from z = 0 with the zeroing folded in:
@@ -205,10 +216,14 @@ __global__ __launch_bounds__(kMgNT) void mg_start_kernel(const int32_t *__restri
                                                          int32_t q0, int32_t q1,
                                                          const int *__restrict__ done)
 {
-    if (done && *done) return;
+    const int stop = flag_of(done);
     for (int32_t p = mg_block() * blockDim.x + threadIdx.x; p < rows; p += gridDim.x * blockDim.x) {
         const int32_t i = order[p];
-        z[i] = p >= q0 && p < q1 ? r[i] / diag[p] : 0.0;
+        const bool first = p >= q0 && p < q1;
+        const double dg = first ? diag[p] : 1.0;
+        // the flag with the row's loads in flight (i is never negative)
+        if (stop | (i < 0)) return;
+        z[i] = first ? r[i] / dg : 0.0;
     }
 }
 
@@ -219,7 +234,7 @@ __global__ __launch_bounds__(kMgNT) void mg_restrict_kernel(
     const double *__restrict__ diag, const double *__restrict__ r, const double *__restrict__ z,
     int32_t nc, double *__restrict__ rc, const int *__restrict__ done)
 {
-    if (done && *done) return;
+    const int stop = flag_of(done);
     const int32_t t = mg_block() * blockDim.x + threadIdx.x;
     if (t >= nc) return;
     const int32_t s = t / kSlice;
@@ -227,7 +242,10 @@ __global__ __launch_bounds__(kMgNT) void mg_restrict_kernel(
     const int32_t i = order[t];
     const int64_t base = soff[s];
     const int32_t w = (int32_t)((soff[s + 1] - base) / kSlice);
-    double az = diag[t] * z[i];
+    const double dg = diag[t];
+    // the flag with the loads above in flight (i and w are never negative)
+    if (stop | (i < 0) | (w < 0)) return;
+    double az = dg * z[i];
     for (int32_t k = 0; k < w; ++k)
         az += val[base + (int64_t)k * kSlice + lane] * z[col[base + (int64_t)k * kSlice + lane]];
     rc[t] = r[i] - az;
@@ -237,9 +255,14 @@ __global__ __launch_bounds__(kMgNT) void mg_restrict_kernel(
 __global__ void mg_prolong_kernel(const int32_t *__restrict__ order, const double *__restrict__ zc,
                                   int32_t nc, double *__restrict__ z, const int *__restrict__ done)
 {
-    if (done && *done) return;
+    const int stop = flag_of(done);
     const int32_t t = mg_block() * blockDim.x + threadIdx.x;
-    if (t < nc) z[order[t]] += zc[t];
+    if (t >= nc) return;
+    const int32_t i = order[t];
+    const double c = zc[t];
+    // the flag with the loads above in flight (i is never negative)
+    if (stop | (i < 0)) return;
+    z[i] += c;
 }
 
 static uint32_t blocks(int64_t n, int nt = kMgNT) { return (uint32_t)std::max<int64_t>(1, (n + nt - 1) / nt); }
