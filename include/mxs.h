@@ -245,8 +245,8 @@ mxs_status mxs_plan_info(mxs_mat A, int32_t *optimized, unsigned *opts);
  *           row   3: a lane per row over an ELL copy made by mxs_optimize
  *           (applicable when that copy adds at most 5% slots)
  *        4: column blocks: mxs_optimize splits the entries by column range
- *           into K full-height CSR blocks whose part of x fits one XCD's
- *           4 MiB L2 (K = ceil(x bytes / 4 MiB), at most 32) and runs them
+ *           into K full-height CSR blocks whose part of x about fits one
+ *           XCD's 4 MiB L2 (K = ceil(x bytes / 6 MiB), at most 32) and runs them
  *           in turn, the first writing y and the others adding to it
  *           (applicable when x is at least 8 MiB and at least half of the
  *           entries lie half a block or more from the diagonal and read x

@@ -5,11 +5,11 @@
 // (uniformly scattered columns, say), nearly every gather misses L2 and the
 // SpMV is bound by gather transactions, not by the matrix stream.
 // mxs_optimize then splits the entries by column range into K full-height
-// matrices of the same format whose x ranges fit one L2 each: block b holds,
+// matrices of the same format whose x ranges about fit one L2 each: block b holds,
 // row by row, the entries with columns in [b*cb, (b+1)*cb), in their
 // original order.  The blocks run in turn with the format's tile kernels,
 // the first writing y and the others adding to it, so all gathers of a pass
-// fall in one L2-sized window of x.  The cost: a second copy of the entries
+// fall in one window of x of about an L2's size.  The cost: a second copy of the entries
 // (with row ids for COO, K row-pointer arrays for CSR) and K passes over y.
 // Per row the sum is the row's block sums added in block order.
 #include "common.h"
@@ -19,7 +19,12 @@
 
 namespace mxs {
 
-constexpr int64_t kColBlkX = 4ll << 20;     // bytes of x per block (one XCD's L2)
+// Bytes of x per block: blocks of up to 6 MiB, a little more than one XCD's
+// 4 MiB L2, measured best (4M-row Zipf matrix: CSR 678 us with 6 blocks,
+// 691 with 7, 716 with 8, 719 with 5; 8M rows: 1,645 against 1,880 us with
+// 4 MiB blocks): a pass over y and the row pointers fewer outweighs the
+// gathers that a window past the L2's size sends on to the MALL.
+constexpr int64_t kColBlkX = 6ll << 20;
 constexpr int64_t kColBlkMinX = 8ll << 20;  // x smaller than this: no blocks
 constexpr int kColBlkMax = 32;
 

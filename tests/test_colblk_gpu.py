@@ -45,15 +45,15 @@ def build(mxs, a, fmt):
 
 
 CASES = {
-    # x 8.8 MB: 3 blocks; rows of 3 to 5,000 entries spread over all blocks
+    # x 8.8 MB: 2 blocks; rows of 3 to 5,000 entries spread over both blocks
     "zipf_1.1M": lambda: wl.zipf_rows(1_100_000, seed=21),
-    # x 12 MB: 3 blocks, 6 uniform columns per row
+    # x 12 MB: 2 blocks, 6 uniform columns per row
     "uniform_1.5M": lambda: fixed_rows(1_500_000, 1_500_000, 6, seed=22),
-    # wide: 300,000 rows, x 24 MB (6 blocks)
+    # wide: 300,000 rows, x 24 MB (4 blocks)
     "wide_300k_x_3M": lambda: fixed_rows(300_000, 3_000_000, 12, seed=23),
-    # x 160 MB: the block count is capped at 32 (5 MB of x per block)
-    "very_wide_100k_x_20M": lambda: fixed_rows(100_000, 20_000_000, 8, seed=30),
-    # columns only in the first half: the last two of four blocks are empty
+    # x 208 MB: the block count is capped at 32 (6.5 MB of x per block)
+    "very_wide_100k_x_26M": lambda: fixed_rows(100_000, 26_000_000, 8, seed=30),
+    # columns only in the first half: the last of three blocks is empty
     "left_half_2M": lambda: fixed_rows(2_000_000, 2_000_000, 4, seed=24, hi=1_000_000),
     # columns only in the second half: the first block (which writes y) is empty
     "right_half_2M": lambda: fixed_rows(2_000_000, 2_000_000, 4, seed=25, lo=1_000_000),
