@@ -32,6 +32,9 @@
 #ifndef MXS_CSR_IPT_MANY
 #define MXS_CSR_IPT_MANY 8 // CSR tiles owning more rows than the LDS-staged path takes
 #endif
+#ifndef MXS_CSR_IPT_SPARSE
+#define MXS_CSR_IPT_SPARSE 4 // CSR tiles of rows shorter than five entries on average
+#endif
 #ifndef MXS_COO_IPT64
 #define MXS_COO_IPT64 8
 #endif
@@ -1197,15 +1200,19 @@ static int64_t dia_blocks(const mxs_mat_s *A)
 
 // Entries per thread of a CSR matrix's tiles: CsrCfg's (10) while a tile
 // would own at most RMAX rows on average (the LDS-staged path; 127.2 us
-// against 129.4 us with 8 on the 128^3 stencil), else MXS_CSR_IPT_MANY (8;
-// the 4M-row Zipf matrix's column blocks, about two entries per row: 715
-// against 778 us with 10).
+// against 129.4 us with 8 on the 128^3 stencil); MXS_CSR_IPT_SPARSE (4)
+// past 2 RMAX rows, rows of fewer than five entries (the 4M-row Zipf
+// matrix's 6 column blocks, 2.7 entries per row: 649 against 679 us with 8;
+// 0.5 random entries per row on 800,000 rows 13.9 against 19.2 us; 3 per
+// row near the diagonal 50.6 against 52.4 us); MXS_CSR_IPT_MANY (8) between
+// (6 per row near the diagonal: 88.8 against 94.0 us with 4).
 static int csr_plan_ipt(const mxs_mat_s *A)
 {
     const int wide = A->dtype == MXS_F64 ? CsrCfg<double>::IPT : CsrCfg<float>::IPT;
     const double rows_per_tile = (double)A->nrows * (CsrCfg<double>::NT * wide) /
                                  (double)std::max<int64_t>(A->nnz, 1);
-    return rows_per_tile <= CsrCfg<double>::RMAX ? wide : MXS_CSR_IPT_MANY;
+    if (rows_per_tile <= CsrCfg<double>::RMAX) return wide;
+    return rows_per_tile <= 2 * CsrCfg<double>::RMAX ? MXS_CSR_IPT_MANY : MXS_CSR_IPT_SPARSE;
 }
 static int coo_tile(mxs_dtype t) { return t == MXS_F64 ? CooCfg<double>::TILE : CooCfg<float>::TILE; }
 
@@ -1704,12 +1711,14 @@ static mxs_status spmv_typed(const mxs_mat_s *A, const T *x, T *y, const int *do
         spmv_grid<T>(A, dot != nullptr, &grid, &per);
         const int32_t *tr = A->csr.tile_row, *ti = A->csr.tile_info;
         T *cr = (T *)(carry ? carry : A->csr.carry);
-        constexpr int W = CsrCfg<T>::IPT, M = MXS_CSR_IPT_MANY;
-        const bool wide = A->csr.tile == CsrCfg<T>::NT * W;
-        auto kern = wide ? (dot ? (A->csr.gx ? csr_spmv_kernel<T, true, true, W> : csr_spmv_kernel<T, true, false, W>)
-                                : (A->csr.gx ? csr_spmv_kernel<T, false, true, W> : csr_spmv_kernel<T, false, false, W>))
-                         : (dot ? (A->csr.gx ? csr_spmv_kernel<T, true, true, M> : csr_spmv_kernel<T, true, false, M>)
-                                : (A->csr.gx ? csr_spmv_kernel<T, false, true, M> : csr_spmv_kernel<T, false, false, M>));
+        constexpr int W = CsrCfg<T>::IPT, M = MXS_CSR_IPT_MANY, P = MXS_CSR_IPT_SPARSE;
+        const int ipt = A->csr.tile / CsrCfg<T>::NT;
+        auto kern = ipt == W ? (dot ? (A->csr.gx ? csr_spmv_kernel<T, true, true, W> : csr_spmv_kernel<T, true, false, W>)
+                                    : (A->csr.gx ? csr_spmv_kernel<T, false, true, W> : csr_spmv_kernel<T, false, false, W>))
+                  : ipt == M ? (dot ? (A->csr.gx ? csr_spmv_kernel<T, true, true, M> : csr_spmv_kernel<T, true, false, M>)
+                                    : (A->csr.gx ? csr_spmv_kernel<T, false, true, M> : csr_spmv_kernel<T, false, false, M>))
+                             : (dot ? (A->csr.gx ? csr_spmv_kernel<T, true, true, P> : csr_spmv_kernel<T, true, false, P>)
+                                    : (A->csr.gx ? csr_spmv_kernel<T, false, true, P> : csr_spmv_kernel<T, false, false, P>));
         kern<<<grid, 256, 0, s>>>(A->idx0, A->idx1, (const T *)A->vals, x, y, tr, ti, A->nnz, nt, per,
                                   cr, done, dot ? parts : nullptr, acc);
         MXS_HIP(hipGetLastError());
