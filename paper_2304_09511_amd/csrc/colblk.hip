@@ -241,6 +241,7 @@ mxs_status colblk_plan(mxs_mat_s *A, const int32_t *irp, PlanCtx &c, hipStream_t
         B->device = A->device;
         B->part = true;
         B->sub = true;
+        B->cblk_part = true;
         blk.push_back(B);
         st = plan_walk(B, c, s);
     }

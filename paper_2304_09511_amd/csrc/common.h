@@ -138,6 +138,7 @@ struct CooPlan {
     int32_t *tile_info = nullptr; // [nt_rows]
     bool fixup = false;           // some row is longer than its owner's window
     int64_t nt_rows = 0, nt_seg = 0;
+    int32_t seg_tile = 0;         // entries per segmented tile
     void *carry_rows = nullptr, *carry_seg = nullptr;
 };
 
@@ -173,6 +174,7 @@ struct mxs_mat_s {
     bool part = false;         // owned by another handle or a hierarchy (not destroyable)
     bool sub = false;          // a split's band or remainder, or a column block: its plan
                                // is laid out inside its parent's
+    bool cblk_part = false;    // a column block (its columns scattered by construction)
     unsigned plan_opts = 0;    // options of the current plan (mxs_optimize)
     // ELL: ndiag = slots per row.  SELL: idx0 = columns, idx1 = perm,
     // sell_cs = slice offsets, slots = sell_cs[nslices], sigma = sort window.

@@ -67,6 +67,9 @@
 #ifndef MXS_COO_IPT
 #define MXS_COO_IPT 4
 #endif
+#ifndef MXS_COO_IPT_SCATTER
+#define MXS_COO_IPT_SCATTER 1 // segmented-scan tiles of a column block (see coo_plan)
+#endif
 #ifndef MXS_PERSIST
 #define MXS_PERSIST 0 // 1: at most one resident wave of workgroups, each over a run of blocks
 #endif
@@ -835,9 +838,9 @@ constexpr int kCooNT = 256;
 constexpr int kCooGapQ = 32;      // long runs of empty rows a tile queues for its workgroup
 constexpr int kCooShortGap = 64;  // runs up to this long are zeroed by the thread that meets them
 constexpr int kCooIPT = MXS_COO_IPT;
-constexpr int kCooTile = kCooNT * kCooIPT;
 
-__device__ __forceinline__ int coo_pad(int j) { return j + j / kCooIPT; }
+template <int IPT>
+__device__ __forceinline__ int coo_pad(int j) { return j + j / IPT; }
 
 template <typename T>
 struct SegPair {
@@ -879,13 +882,14 @@ __device__ SegPair<T> block_seg_excl_scan(SegPair<T> x, int *sh, T *sv)
     return seg_combine<T>(pre, {eh, ev});
 }
 
-template <typename T>
+// IPT: entries per thread of the plan's segmented tiles (coo_plan).
+template <typename T, int IPT>
 __global__ __launch_bounds__(256) void coo_spmv_kernel(
     int64_t nnz, int32_t nrows, const int32_t *__restrict__ ai, const int32_t *__restrict__ aj,
     const T *__restrict__ av, const T *__restrict__ x, T *__restrict__ y, T *__restrict__ carry,
     int64_t ntiles, int64_t per, const int *__restrict__ done, int acc)
 {
-    constexpr int NT = kCooNT, IPT = kCooIPT, TILE = kCooTile;
+    constexpr int NT = kCooNT, TILE = NT * IPT;
     constexpr int PADDED = TILE + TILE / IPT;
     __shared__ int32_t srow[PADDED];
     __shared__ T sval[PADDED];
@@ -936,8 +940,8 @@ __global__ __launch_bounds__(256) void coo_spmv_kernel(
             for (int e = 0; e < IPT; ++e) {
                 const int j = e * NT + tid;
                 if (j < n) {
-                    srow[coo_pad(j)] = row[e];
-                    sval[coo_pad(j)] = val[e] * xv[e];
+                    srow[coo_pad<IPT>(j)] = row[e];
+                    sval[coo_pad<IPT>(j)] = val[e] * xv[e];
                 }
             }
         }
@@ -950,19 +954,19 @@ __global__ __launch_bounds__(256) void coo_spmv_kernel(
         // pass 1: this thread's run as a (head seen, tail sum) pair
         SegPair<T> mine = {0, T(0)};
         for (int j = b0; j < b1; ++j) {
-            const int32_t pr = j == 0 ? prev_row : srow[coo_pad(j - 1)];
-            if (srow[coo_pad(j)] != pr) {
+            const int32_t pr = j == 0 ? prev_row : srow[coo_pad<IPT>(j - 1)];
+            if (srow[coo_pad<IPT>(j)] != pr) {
                 mine.h = 1;
                 mine.v = T(0);
             }
-            mine.v += sval[coo_pad(j)];
+            mine.v += sval[coo_pad<IPT>(j)];
         }
         const SegPair<T> cin = block_seg_excl_scan<T, NT>(mine, sh, sv);
         // pass 2: emit every segment that closes inside this run
         T s = cin.v;
         for (int j = b0; j < b1; ++j) {
-            const int32_t rw = srow[coo_pad(j)];
-            const int32_t pr = j == 0 ? prev_row : srow[coo_pad(j - 1)];
+            const int32_t rw = srow[coo_pad<IPT>(j)];
+            const int32_t pr = j == 0 ? prev_row : srow[coo_pad<IPT>(j - 1)];
             if (rw != pr) {
                 if (j > 0) {
                     if (tile_cont && pr == first_row) carry[2 * tile] = s;
@@ -971,11 +975,11 @@ __global__ __launch_bounds__(256) void coo_spmv_kernel(
                 if (!acc && rw > pr + 1) zero_rows(pr + 1, rw); // rows without entries
                 s = T(0);
             }
-            s += sval[coo_pad(j)];
+            s += sval[coo_pad<IPT>(j)];
         }
         if (b0 < n && b1 == n) {
             // the thread holding the tile's last entry closes or hands over its segment
-            const int32_t last = srow[coo_pad(n - 1)];
+            const int32_t last = srow[coo_pad<IPT>(n - 1)];
             const bool is_cont = tile_cont && last == first_row;
             if (next_row == last) {
                 carry[2 * tile + (is_cont ? 0 : 1)] = s;
@@ -1129,9 +1133,8 @@ __global__ void coo_rows_fixup_kernel(const int32_t *__restrict__ ai,
 template <typename T>
 __global__ void coo_fixup_kernel(int64_t nnz, const int32_t *__restrict__ ai,
                                  const T *__restrict__ carry, T *__restrict__ y, int64_t ntiles,
-                                 const int *__restrict__ done, int acc)
+                                 int32_t TILE, const int *__restrict__ done, int acc)
 {
-    constexpr int TILE = kCooTile;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ntiles) return;
     if (done && *done) return;
@@ -1227,7 +1230,7 @@ static void spmv_grid(const mxs_mat_s *A, bool dot, uint32_t *grid, int64_t *per
 #if MXS_PERSIST
     int64_t cap = A->fmt == MXS_CSR ? resident_workgroups(csr_spmv_kernel<T, false, false, CsrCfg<T>::IPT>, 256)
                   : A->fmt == MXS_DIA ? resident_workgroups(dia_spmv_kernel<T, false>, kDiaNT)
-                                      : resident_workgroups(coo_spmv_kernel<T>, kCooNT);
+                                      : resident_workgroups(coo_spmv_kernel<T, kCooIPT>, kCooNT);
 #else
     int64_t cap = INT64_MAX / 2;
 #endif
@@ -1427,7 +1430,13 @@ static mxs_status coo_plan(mxs_mat_s *A, PlanCtx &c, hipStream_t s)
     }
     const int tile = coo_tile(A->dtype);
     const int64_t nt = (A->nnz + tile - 1) / tile;
-    const int64_t nt_seg = (A->nnz + kCooTile - 1) / kCooTile;
+    // segmented tiles: 4 entries per thread, 1 for a column block, whose
+    // gathers of x are scattered by construction (the 4M-row Zipf matrix's
+    // 6 COO blocks: 677 against 737 us; 3 entries per row near the diagonal,
+    // a matrix for the segmented kernel without blocks, lose with 1: 90.3
+    // against 77.1 us)
+    const int32_t seg_tile = kCooNT * (A->cblk_part ? MXS_COO_IPT_SCATTER : kCooIPT);
+    const int64_t nt_seg = (A->nnz + seg_tile - 1) / seg_tile;
     int32_t *buf = (int32_t *)c.keep(sizeof(int32_t) * (2 * (size_t)nt + 1));
     // carries of either implementation (two values per tile)
     void *carry = c.keep(2 * (size_t)std::max(nt, nt_seg) * dsize(A->dtype));
@@ -1459,6 +1468,7 @@ static mxs_status coo_plan(mxs_mat_s *A, PlanCtx &c, hipStream_t s)
         P.fixup = h[0] != 0;
         P.nt_rows = nt;
         P.nt_seg = nt_seg;
+        P.seg_tile = seg_tile;
         P.carry_rows = P.carry_seg = carry;
         A->coo = P;
     }
@@ -1774,12 +1784,13 @@ static mxs_status spmv_typed(const mxs_mat_s *A, const T *x, T *y, const int *do
                         A->idx0, A->coo.tile_row, A->coo.tile_info, cr, y,
                         A->nnz, nt, coo_tile(A->dtype), done, acc);
             } else {
-                coo_spmv_kernel<T><<<grid, kCooNT, 0, s>>>(A->nnz, A->nrows, A->idx0, A->idx1,
-                                                           (const T *)A->vals, x, y,
-                                                           cr, nt, per, done, acc);
+                auto kern = A->coo.seg_tile == kCooNT * kCooIPT ? coo_spmv_kernel<T, kCooIPT>
+                                                                : coo_spmv_kernel<T, MXS_COO_IPT_SCATTER>;
+                kern<<<grid, kCooNT, 0, s>>>(A->nnz, A->nrows, A->idx0, A->idx1, (const T *)A->vals,
+                                             x, y, cr, nt, per, done, acc);
                 MXS_HIP(hipGetLastError());
                 coo_fixup_kernel<T><<<(uint32_t)((nt + 255) / 256), 256, 0, s>>>(
-                    A->nnz, A->idx0, cr, y, nt, done, acc);
+                    A->nnz, A->idx0, cr, y, nt, A->coo.seg_tile, done, acc);
             }
         }
         MXS_HIP(hipGetLastError());
