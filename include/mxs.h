@@ -248,7 +248,8 @@ mxs_status mxs_plan_info(mxs_mat A, int32_t *optimized, unsigned *opts);
  *           into K full-height CSR blocks whose part of x about fits one
  *           XCD's 4 MiB L2 (K = ceil(x bytes / 6 MiB), at most 32) and runs them
  *           in turn, the first writing y and the others adding to it
- *           (applicable when x is at least 8 MiB and at least half of the
+ *           (applicable when x is at least 8 MiB, the rows hold at least
+ *           three entries on average, and at least half of the
  *           entries lie half a block or more from the diagonal and read x
  *           from another 128-byte line than the row's previous entry; the copy
  *           takes as much memory as the entries, plus K row-pointer arrays

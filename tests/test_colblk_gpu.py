@@ -121,12 +121,15 @@ def test_column_blocks_fp32(gpu, fmt):
 @pytest.mark.parametrize("fmt", ["csr", "coo"])
 def test_column_blocks_not_built_where_they_do_not_apply(gpu, fmt):
     """Near-diagonal entries (banded), dense 8 x 8 blocks at random block
-    columns (far from the diagonal, but eight entries to a line of x) or an
-    x below 8 MiB: no blocks, their id refused, defaults as before."""
+    columns (far from the diagonal, but eight entries to a line of x), an
+    x below 8 MiB, or scattered rows of two entries (x of 16 MB, but fewer
+    than three entries per row): no blocks, their id refused, defaults as
+    before."""
     mxs = gpu
     for a in (wl.banded(1_500_000, ndiag=11, max_offset=2000, seed=3),
               wl.block_random(200_000, seed=31),
-              fixed_rows(900_000, 900_000, 6, seed=28)):
+              fixed_rows(900_000, 900_000, 6, seed=28),
+              fixed_rows(2_000_000, 2_000_000, 2, seed=32)):
         C = build(mxs, a, fmt)
         assert C.impl != COLBLK[fmt]
         with pytest.raises(mxs.MxsError) as e:
