@@ -20,10 +20,11 @@
 namespace mxs {
 
 // Bytes of x per block: blocks of up to 6 MiB, a little more than one XCD's
-// 4 MiB L2, measured best (4M-row Zipf matrix: CSR 678 us with 6 blocks,
-// 691 with 7, 716 with 8, 719 with 5; 8M rows: 1,645 against 1,880 us with
-// 4 MiB blocks): a pass over y and the row pointers fewer outweighs the
-// gathers that a window past the L2's size sends on to the MALL.
+// 4 MiB L2, measured best (4M-row Zipf matrix, CSR blocks of 2,048-entry
+// tiles: 678 us with 6 blocks, 691 with 7, 716 with 8, 719 with 5; 8M rows:
+// 1,645 against 1,880 us with 4 MiB blocks): a pass over y and the row
+// pointers fewer outweighs the gathers that a window past the L2's size
+// sends on to the MALL.
 constexpr int64_t kColBlkX = 6ll << 20;
 constexpr int64_t kColBlkMinX = 8ll << 20;  // x smaller than this: no blocks
 constexpr int64_t kColBlkMinPerRow = 3;     // fewer entries per row on average: no blocks
