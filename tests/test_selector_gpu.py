@@ -302,8 +302,8 @@ def test_device_dataset_generators_match_oracle_features(gpu):
 
 def test_trained_selector_beats_always_csr(gpu):
     """On the committed labelled set (timings of this GPU): the selector
-    trained on the 2,100 training matrices has held-out mean regret at most
-    5 % and below the always-CSR baseline's, on all 700 held-out matrices and
+    trained on the 2,400 training matrices has held-out mean regret at most
+    5 % and below the always-CSR baseline's, on all 800 held-out matrices and
     on each group of families; every one of the seven formats is the fastest
     for some matrix of the set."""
     from paper_2304_09511_amd import selector as S
